@@ -1,0 +1,302 @@
+"""Seeded synthetic inputs for the Biot parallel-in-time solver.
+
+This module produces *inputs only*: mesh coordinates and connectivity, boundary
+flags, the boundary facets that carry a load, per-element material fields and the
+time profile of the load.  It contains none of the solver's arithmetic (no element
+matrices, no Lame conversion, no time stepping), so both the device path and the
+independent CPU reference can consume the same inputs without sharing any of the
+method.
+
+Mesh conventions (the paper's experiments use uniform right-triangle grids on the
+unit square, Sec. 4.1):
+  * 2D: an N x N grid of squares, node (i, j) has id j*(N+1)+i and sits at
+    (i/N, j/N); every square is split along its (i,j)->(i+1,j+1) diagonal, so
+    refining N -> 2N is the midpoint (red) refinement the paper describes.
+  * 3D (not in the paper): an N^3 grid of cubes, node (i,j,k) has id
+    (k*(N+1)+j)*(N+1)+i; every cube is split into the six Kuhn tetrahedra that
+    share its (0,0,0)->(1,1,1) diagonal, which is conforming and nested under 2:1
+    refinement.
+
+Boundary flags are a per-node bit mask: bit d (d < dim) fixes displacement
+component d to zero, bit dim fixes the pressure to zero.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+U_BITS_2D = 0b011
+P_BIT_2D = 0b100
+
+
+# ----------------------------------------------------------------------------
+# meshes
+# ----------------------------------------------------------------------------
+def square_mesh(n: int):
+    """Structured right-triangle mesh of the unit square with n cells per side.
+
+    Returns (xyz float64 [(n+1)^2, 2], conn int32 [2 n^2, 3]); triangles are
+    counter-clockwise.  Triangle 2*(j*n+i) is the lower-right one of square
+    (i, j), triangle 2*(j*n+i)+1 the upper-left one.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    i, j = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="xy")
+    xyz = np.stack([i.ravel() / n, j.ravel() / n], axis=1).astype(np.float64)
+    ci, cj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    ci = ci.ravel()
+    cj = cj.ravel()
+    v00 = cj * (n + 1) + ci
+    v10 = v00 + 1
+    v01 = v00 + (n + 1)
+    v11 = v01 + 1
+    lower = np.stack([v00, v10, v11], axis=1)
+    upper = np.stack([v00, v11, v01], axis=1)
+    conn = np.empty((2 * n * n, 3), dtype=np.int32)
+    conn[0::2] = lower
+    conn[1::2] = upper
+    return xyz, conn
+
+
+# the six axis orders that define the Kuhn simplices of a cube
+_KUHN_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def cube_mesh(n: int):
+    """Structured Kuhn tetrahedral mesh of the unit cube with n cells per side.
+
+    Returns (xyz float64 [(n+1)^3, 3], conn int32 [6 n^3, 4]).  Each tetrahedron
+    walks from the cube's (0,0,0) corner to its (1,1,1) corner one axis at a
+    time; vertex order is fixed so that every tetrahedron has positive volume.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    m = n + 1
+    g = np.arange(m)
+    k, j, i = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([i.ravel() / n, j.ravel() / n, k.ravel() / n], axis=1).astype(np.float64)
+    c = np.arange(n)
+    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
+    base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)
+    tets = []
+    for perm in _KUHN_PERMS:
+        verts = [base.copy()]
+        cur = base.copy()
+        for ax in perm:
+            cur = cur.copy()
+            cur[:, ax] += 1
+            verts.append(cur)
+        ids = [(v[:, 2] * m + v[:, 1]) * m + v[:, 0] for v in verts]
+        t = np.stack(ids, axis=1)
+        # orientation: sign of the permutation decides the handedness
+        sign = _perm_sign(perm)
+        if sign < 0:
+            t = t[:, [0, 2, 1, 3]]
+        tets.append(t)
+    # interleave so that the 6 tets of one cube are contiguous
+    conn = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int32)
+    return xyz, conn
+
+
+def _perm_sign(p):
+    p = list(p)
+    s = 1
+    for a in range(len(p)):
+        for b in range(a + 1, len(p)):
+            if p[a] > p[b]:
+                s = -s
+    return s
+
+
+# ----------------------------------------------------------------------------
+# Terzaghi-type boundary data on the unit square / cube
+# ----------------------------------------------------------------------------
+def terzaghi_flags(xyz: np.ndarray) -> np.ndarray:
+    """Per-node Dirichlet bit mask for the consolidation column.
+
+    Fixed base (all displacement components zero on the bottom face), roller
+    sides (the normal displacement component zero on the lateral faces), drained
+    top (pressure zero on the top face).  Corners take the union.
+    """
+    dim = xyz.shape[1]
+    up = dim - 1  # vertical axis
+    tol = 1e-12
+    flags = np.zeros(xyz.shape[0], dtype=np.uint8)
+    bottom = xyz[:, up] < tol
+    top = xyz[:, up] > 1 - tol
+    flags[bottom] |= np.uint8((1 << dim) - 1)
+    for ax in range(dim - 1):
+        side = (xyz[:, ax] < tol) | (xyz[:, ax] > 1 - tol)
+        flags[side] |= np.uint8(1 << ax)
+    flags[top] |= np.uint8(1 << dim)
+    return flags
+
+
+def top_facets(n: int, dim: int) -> np.ndarray:
+    """Boundary facets of the top face (y=1 in 2D, z=1 in 3D) as node tuples."""
+    if dim == 2:
+        j = n
+        i = np.arange(n)
+        a = j * (n + 1) + i
+        return np.stack([a, a + 1], axis=1).astype(np.int32)
+    m = n + 1
+    k = n
+    j, i = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    v00 = (k * m + j.ravel()) * m + i.ravel()
+    v10 = v00 + 1
+    v01 = v00 + m
+    v11 = v01 + 1
+    # each top square is the face of two Kuhn tets: split along (0,0)->(1,1)
+    t1 = np.stack([v00, v10, v11], axis=1)
+    t2 = np.stack([v00, v11, v01], axis=1)
+    return np.concatenate([t1, t2], axis=0).astype(np.int32)
+
+
+def step_load_profile(n_steps: int, magnitude: float = 1.0) -> np.ndarray:
+    """Load multiplier per time level: zero at t=0, `magnitude` for every step n>=1."""
+    c = np.full(n_steps + 1, magnitude, dtype=np.float64)
+    c[0] = 0.0
+    return c
+
+
+# ----------------------------------------------------------------------------
+# material fields
+# ----------------------------------------------------------------------------
+def smoothed_gaussian_cells(n: int, seed: int, ell: float) -> np.ndarray:
+    """Unit-variance smooth Gaussian field on the n x n cells of the unit square.
+
+    White noise per cell from numpy's PCG64 (`default_rng(seed)`), convolved with
+    exp(-r^2 / (2 ell^2)) by a zero-padded FFT, then shifted and scaled to zero
+    sample mean and unit sample standard deviation.  Returned as [n*n] in cell
+    order j*n+i.
+    """
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n, n))
+    h = 1.0 / n
+    m = 2 * n
+    d = np.minimum(np.arange(m), m - np.arange(m)) * h
+    kern = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * ell * ell))
+    pad = np.zeros((m, m))
+    pad[:n, :n] = w
+    z = np.real(np.fft.ifft2(np.fft.fft2(pad) * np.fft.fft2(kern)))[:n, :n]
+    z = (z - z.mean()) / z.std()
+    return z.ravel()
+
+
+def lognormal_perm_2d(n: int, seed: int, k_mean: float = 1e-2, sigma: float = 1.0,
+                      ell: float = 0.1) -> np.ndarray:
+    """Per-element permeability exp(log k_mean + sigma z), z the smooth cell field;
+    both triangles of a square share the square's value."""
+    z = smoothed_gaussian_cells(n, seed, ell)
+    k_cell = np.exp(np.log(k_mean) + sigma * z)
+    return np.repeat(k_cell, 2)
+
+
+def uniform_young(n_elems: int, seed: int, lo: float = 5e3, hi: float = 2e4) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=n_elems)
+
+
+# ----------------------------------------------------------------------------
+# a complete problem description
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Problem:
+    """Everything the solver needs, as plain arrays (inputs only)."""
+    dim: int
+    grid_n: int                 # cells per side of the structured grid
+    xyz: np.ndarray             # [n_nodes, dim] float64
+    conn: np.ndarray            # [n_elems, dim+1] int32
+    flags: np.ndarray           # [n_nodes] uint8 Dirichlet bit mask (homogeneous values)
+    young: np.ndarray           # [n_elems] E
+    poisson: np.ndarray         # [n_elems] nu
+    perm: np.ndarray            # [n_elems] K (permeability / viscosity)
+    alpha: float                # Biot-Willis coefficient
+    stab_h: float               # mesh size entering the stabilization parameter
+    facets: np.ndarray          # [n_facets, dim] boundary facets carrying a traction
+    traction: np.ndarray        # [n_facets, dim] traction vector per facet
+    load_coef: np.ndarray       # [n_steps+1] multiplier of the traction at each time level
+    n_steps: int
+    dt: float
+
+    @property
+    def n_nodes(self) -> int:
+        return self.xyz.shape[0]
+
+    @property
+    def n_elems(self) -> int:
+        return self.conn.shape[0]
+
+    @property
+    def n_dof(self) -> int:
+        return self.n_nodes * (self.dim + 1)
+
+
+def terzaghi_problem(n: int, n_steps: int, dim: int = 2, dt: Optional[float] = None,
+                     young=1e4, poisson=0.3, perm=1e-2, alpha: float = 1.0,
+                     load: float = 1.0) -> Problem:
+    """Consolidation column: unit top load, drained top, fixed base, roller sides.
+
+    `young`, `poisson` and `perm` may be scalars or per-element arrays.
+    """
+    if dim == 2:
+        xyz, conn = square_mesh(n)
+    elif dim == 3:
+        xyz, conn = cube_mesh(n)
+    else:
+        raise ValueError("dim must be 2 or 3")
+    ne = conn.shape[0]
+    facets = top_facets(n, dim)
+    tr = np.zeros((facets.shape[0], dim))
+    tr[:, dim - 1] = -load
+    return Problem(
+        dim=dim, grid_n=n, xyz=xyz, conn=conn, flags=terzaghi_flags(xyz),
+        young=np.broadcast_to(np.asarray(young, dtype=np.float64), (ne,)).copy(),
+        poisson=np.broadcast_to(np.asarray(poisson, dtype=np.float64), (ne,)).copy(),
+        perm=np.broadcast_to(np.asarray(perm, dtype=np.float64), (ne,)).copy(),
+        alpha=float(alpha), stab_h=1.0 / n, facets=facets, traction=tr,
+        load_coef=step_load_profile(n_steps), n_steps=n_steps,
+        dt=(1.0 / n_steps) if dt is None else float(dt))
+
+
+def heterogeneous_problem(n: int, n_steps: int, field_seed: int = 2, young_seed: int = 102,
+                          sigma: float = 1.0, ell: float = 0.1) -> Problem:
+    """Consolidation column with a log-normal permeability field and uniform-random E."""
+    k = lognormal_perm_2d(n, field_seed, 1e-2, sigma, ell)
+    e = uniform_young(2 * n * n, young_seed)
+    return terzaghi_problem(n, n_steps, young=e, perm=k)
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+def small_terzaghi() -> Problem:
+    """16 x 16 square, 289 nodes, 867 unknowns, 32 steps of dt = 1/32."""
+    return terzaghi_problem(16, 32)
+
+
+def large_terzaghi() -> Problem:
+    """256 x 256 square, 66,049 nodes, 198,147 unknowns, 512 steps of dt = 1/512."""
+    return terzaghi_problem(256, 512)
+
+
+def large_heterogeneous() -> Problem:
+    """256 x 256 square, log-normal permeability, E ~ U[5e3, 2e4], 512 steps."""
+    return heterogeneous_problem(256, 512)
+
+
+def batched_samples(count: int = 64, seed: int = 3):
+    """(grid n, n_steps, field seed) for independent samples of uneven size."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.choice(np.array([32, 48, 64, 96, 128]), size=count)
+    steps = rng.choice(np.arange(128, 513, 16), size=count)
+    return [(int(sizes[i]), int(steps[i]), 3000 + i) for i in range(count)]
+
+
+def sensor_nodes(problem: Problem, count: int = 64, seed: int = 42) -> np.ndarray:
+    """Distinct nodes whose pressure is free (not on the drained face)."""
+    free = np.nonzero((problem.flags & (1 << problem.dim)) == 0)[0]
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(free, size=count, replace=False)).astype(np.int32)

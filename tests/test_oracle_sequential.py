@@ -1,0 +1,149 @@
+"""Pins of the oracle's sequential backward-Euler solve (eq. (fullysystem)).
+
+* dense brute force of the whole space-time block-bidiagonal system;
+* the exact steady state of the consolidation column (linear, hence in P1);
+* Terzaghi's series solution (rates, not digits);
+* the trigonometric manufactured solution of Sec. 4.1 against Table 1
+  (soft pins: magnitudes within 20 %, ratios near 4 per halving of h).
+"""
+import numpy as np
+import pytest
+
+from paper_2310_10430_amd import workloads as W
+from oracle import analytic, fem, sequential as seq
+
+
+def test_dense_space_time_brute_force():
+    """Assemble [AA; -A' AA; ...] densely and solve it with LAPACK."""
+    pb = W.heterogeneous_problem(3, 5, field_seed=7, young_seed=8)
+    pb.dt = 0.05
+    orc = seq.BiotOracle(pb)
+    X = orc.solve_sequential()
+    fr = orc.free
+    AA = orc.AA.toarray()[np.ix_(fr, fr)]
+    Ap = orc.Ap.toarray()[np.ix_(fr, fr)]
+    nf = len(fr)
+    N = pb.n_steps
+    M = np.zeros((N * nf, N * nf))
+    rhs = np.zeros(N * nf)
+    for n in range(N):
+        M[n * nf:(n + 1) * nf, n * nf:(n + 1) * nf] = AA
+        if n > 0:
+            M[n * nf:(n + 1) * nf, (n - 1) * nf:n * nf] = -Ap
+        rhs[n * nf:(n + 1) * nf] = orc.load(n + 1)[fr]
+    Xd = np.linalg.solve(M, rhs).reshape(N, nf)
+    scale = np.abs(Xd).max(axis=0).max()
+    assert np.abs(X[1:, fr] - Xd).max() < 1e-12 * scale
+
+
+def test_small_terzaghi_reaches_exact_steady_state():
+    """u_y = -y/(lambda+2mu), u_x = 0, p = 0 is in the P1 space; with
+    dt = 1/32 the slowest mode decays by ~0.09 per step, so the last step
+    equals it to rounding."""
+    pb = W.small_terzaghi()
+    orc = seq.BiotOracle(pb)
+    Y = orc.trajectory_node_major(orc.solve_sequential())
+    lam, mu = fem.lame(1e4, 0.3)
+    uy = -pb.xyz[:, 1] / (lam + 2 * mu)
+    assert np.abs(Y[-1, :, 1] - uy).max() < 1e-12 * np.abs(uy).max()
+    assert np.abs(Y[-1, :, 0]).max() < 1e-12 * np.abs(uy).max()
+    assert np.abs(Y[-1, :, 2]).max() < 1e-12
+
+
+def test_backward_error_per_step():
+    pb = W.heterogeneous_problem(32, 8)
+    orc = seq.BiotOracle(pb)
+    X = orc.solve_sequential()
+    R = orc.space_time_residual(X)
+    for n in range(1, pb.n_steps + 1):
+        b = orc.rhs(n, X[n - 1])
+        den = abs(orc.AA).max() * np.abs(X[n]).max() + np.abs(b).max()
+        assert np.abs(R[n - 1]).max() < 1e-14 * den
+
+
+def test_terzaghi_series_convergence():
+    """With K = 1/(lambda+2mu) (c_v = 1) the column consolidates over t ~ 1;
+    the discrete pressure approaches the series as h and dt are refined."""
+    lam, mu = fem.lame(1e4, 0.3)
+    kc = 1.0 / (lam + 2 * mu)
+    T = 0.1
+    errs = []
+    for n, ns in [(16, 16), (32, 64), (64, 256)]:
+        pb = W.terzaghi_problem(n, ns, dt=T / ns, perm=kc)
+        orc = seq.BiotOracle(pb)
+        Y = orc.trajectory_node_major(orc.solve_sequential())
+        pe = analytic.terzaghi_pressure(pb.xyz[:, 1], T, 1.0)
+        errs.append(np.abs(Y[-1, :, 2] - pe).max())
+    assert errs[0] < 0.02 and errs[2] < 1e-3
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] / errs[2] > 8
+
+
+def test_terzaghi_series_initial_and_limits():
+    """Series sanity: p(y, 0+) = q inside, p = 0 at the drained top, and the
+    displacement at the top tends to -q/(lambda+2mu)."""
+    y = np.linspace(0.05, 0.95, 7)
+    assert np.allclose(analytic.terzaghi_pressure(y, 1e-9, 1.0, terms=20000), 1.0, atol=2e-3)
+    assert abs(analytic.terzaghi_pressure(np.array([1.0]), 0.3, 1.0)[0]) < 1e-12
+    assert abs(analytic.terzaghi_displacement(np.array([1.0]), 50.0, 1.0, 3.0, 1.0)[0] + 0.2) < 1e-12
+
+
+def test_dunavant_rule_degree_four():
+    xyz = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    conn = np.array([[0, 1, 2]])
+    pts, w, _ = analytic.tri_quadrature(xyz, conn)
+    x, y = pts[0, :, 0], pts[0, :, 1]
+    from math import factorial
+    for a in range(5):
+        for b in range(5 - a):
+            exact = factorial(a) * factorial(b) / factorial(a + b + 2)
+            assert abs(np.sum(w[0] * x ** a * y ** b) - exact) < 1e-13
+
+
+@pytest.mark.slow
+def test_manufactured_solution_table1_space():
+    """Table 1 (tau = 1/1024, t = 1): L2 errors of p 0.02180 / 0.00592 / 0.00152
+    at h = 1/16, 1/32, 1/64.  Digits depend on quadrature and the norm's
+    evaluation, so they are soft pins (20 %); the ratios approach 4."""
+    paper = {16: 0.02180138, 32: 0.00592069, 64: 0.00152259}
+    errs = {}
+    for n in (16, 32, 64):
+        pb, X = analytic.mms_solve(n, 1 / 1024, 1024)
+        errs[n] = analytic.l2_error_p(pb, X, 1.0)
+        assert abs(errs[n] / paper[n] - 1) < 0.2
+    r1 = errs[16] / errs[32]
+    r2 = errs[32] / errs[64]
+    assert 3.5 < r1 < 4.2 and 3.7 < r2 < 4.2
+
+
+def test_manufactured_solution_table1_time():
+    """Table 1 (h = 1/128, t = 1): errors shrink by ~2 per halving of tau at
+    large tau (0.00556, 0.00256, 0.00126 at tau = 1/2, 1/4, 1/8)."""
+    paper = {2: 0.00556048, 4: 0.00255742, 8: 0.00126302}
+    errs = {}
+    for nt in (2, 4, 8):
+        pb, X = analytic.mms_solve(128, 1.0 / nt, nt)
+        errs[nt] = analytic.l2_error_p(pb, X, 1.0)
+        assert abs(errs[nt] / paper[nt] - 1) < 0.2
+    assert 1.8 < errs[2] / errs[4] < 2.5
+    assert 1.8 < errs[4] / errs[8] < 2.3
+
+
+def test_printed_source_sign_is_inconsistent():
+    """With the source term exactly as printed, the error stalls near 0.04 under
+    refinement instead of falling like h^2 (reading of g)."""
+    g_ok = analytic.mms_source
+    try:
+        def printed(x, y, t, alpha, K):
+            pi = np.pi
+            return (3 * alpha * pi * np.sin(t) * (np.cos(3 * pi * x) * np.sin(3 * pi * y)
+                                                  - np.sin(3 * pi * x) * np.cos(3 * pi * y))
+                    + 18 * K * pi ** 2 * np.cos(t) * np.cos(3 * pi * x) * np.cos(3 * pi * y))
+        analytic.mms_source = printed
+        pb, X = analytic.mms_solve(32, 1 / 256, 256)
+        e_printed = analytic.l2_error_p(pb, X, 1.0)
+    finally:
+        analytic.mms_source = g_ok
+    pb, X = analytic.mms_solve(32, 1 / 256, 256)
+    e_ok = analytic.l2_error_p(pb, X, 1.0)
+    assert e_printed > 5 * e_ok
