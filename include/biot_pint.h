@@ -1,0 +1,212 @@
+/*
+ * biot_pint -- preconditioned parallel-in-time solver for the quasi-static
+ * two-field Biot model on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the inverted time-stepping iteration of Zhou, Gu, Ju and Xing,
+ * "A Parallel-in-time Method Based on Preconditioner for Biot's Model"
+ * (arXiv 2310.10430):
+ *   - Sec. 2.2, eq. (diseq1)/(fullysystem): stabilized P1-P1 finite elements
+ *     and backward Euler give, per time step n,
+ *         AA X^n = A' X^{n-1} + f^n,
+ *         AA = [A  B; B' -S],  S = tau C_K + C_beta,  A' = [0 0; B' -C_beta],
+ *         f^n = [F^n; -tau G^n];
+ *   - Sec. 3.1, eqs. (p1)/(p2): block preconditioners P1 = [A 0; B' -S_p],
+ *     P2 = [A 0; 0 -S_p] with the approximate Schur complement
+ *     S_p = (tau + beta/K) C;
+ *   - Sec. 3.2, Alg. 2 and Alg. 3: the outer loop iterates
+ *         X^{n,m} = X^{n,m-1} + omega P^{-1}(A' X^{n-1,m} + f^n - AA X^{n,m-1})
+ *     over all time steps, starting from X^{n,0} = 0; Alg. 4 runs the
+ *     iterations as a pipeline ("wavefront") lagging one step each.
+ * The two inner solves with A and S_p inside P are each replaced by one
+ * geometric-multigrid V-cycle (Galerkin coarse operators on the nested
+ * structured meshes, Chebyshev smoothing preconditioned by node-block Jacobi,
+ * dense solve on the coarsest level).  The fixed point of the iteration is the
+ * backward-Euler trajectory.
+ *
+ * Conventions
+ *   - Every function returns BIOT_OK (0) or a negative error code; the message
+ *     of the last error on a handle is available from biot_last_error().
+ *     No C++ exception crosses this interface.
+ *   - Host arrays passed in are only read during the call (they are copied).
+ *   - Device memory is owned by the caller: the library computes how much it
+ *     needs (biot_workspace_size) and the caller binds one buffer of that size
+ *     (biot_bind).  The library never allocates or frees device memory.
+ *   - All device work is enqueued on the stream given to biot_bind.  Calls that
+ *     return host values synchronize that stream; the others do not.
+ *   - Degrees of freedom are node-major: dof = node*(dim+1) + c with
+ *     c = 0..dim-1 the displacement components and c = dim the pressure.  A
+ *     trajectory is [n_steps+1][n_nodes][dim+1] doubles; row 0 is X^0.
+ *   - Prescribed (Dirichlet) values are homogeneous: flagged dofs are zero.
+ *   - Meshes must be the structured unit-square (2D, right triangles split
+ *     along (i,j)->(i+1,j+1)) or unit-cube (3D, Kuhn tetrahedra) grids with
+ *     lexicographic node numbering; grid_n gives the cells per side.
+ *
+ * Calls on one handle must not overlap; different handles are independent.
+ */
+#ifndef BIOT_PINT_H
+#define BIOT_PINT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BIOT_OK 0
+#define BIOT_EINVAL (-1)        /* bad argument or mesh                        */
+#define BIOT_ENOMEM (-2)        /* workspace too small                          */
+#define BIOT_EHIP (-3)          /* a HIP runtime call failed                    */
+#define BIOT_EDIVERGED (-4)     /* residual became non-finite or grew too much  */
+#define BIOT_ENOTCONVERGED (-5) /* max_sweeps reached above tolerance           */
+#define BIOT_ESTATE (-6)        /* call out of order (e.g. not bound yet)       */
+
+#define BIOT_SCHED_JACOBI 0     /* every step couples to the previous sweep     */
+#define BIOT_SCHED_WAVEFRONT 1  /* Alg. 2 order: step n couples to step n-1 of  */
+                                /* the same sweep; `depth` sweeps per pass run  */
+                                /* as a pipeline (Alg. 4)                       */
+#define BIOT_PRECOND_P1 1       /* eq. (p1), block lower triangular             */
+#define BIOT_PRECOND_P2 2       /* eq. (p2), block diagonal                     */
+
+typedef struct biot_handle biot_handle;
+
+/* Mesh and boundary description (Sec. 2.1 boundary conditions). */
+typedef struct {
+  int32_t dim;               /* 2 or 3                                          */
+  int32_t n_nodes;           /* (grid_n+1)^dim                                  */
+  int32_t n_elems;           /* simplices                                       */
+  int32_t grid_n;            /* cells per side of the structured grid (>= 1)    */
+  const double* xyz;         /* [n_nodes][dim], node (i,j,k) at (i,j,k)/grid_n  */
+  const int32_t* conn;       /* [n_elems][dim+1], positively oriented           */
+  const uint8_t* dirichlet;  /* [n_nodes]; bit c<dim: u_c = 0, bit dim: p = 0   */
+} biot_mesh;
+
+/* Materials per element (Sec. 2.1: Lame parameters from E and nu). */
+typedef struct {
+  const double* young;    /* [n_elems] Young's modulus E > 0                      */
+  const double* poisson;  /* [n_elems] Poisson ratio, -1 < nu < 0.5                */
+  const double* perm;     /* [n_elems] K = permeability / viscosity >= 0           */
+  const double* beta;     /* [n_elems] stabilization parameter, or NULL for         */
+                          /* beta_e = alpha^2 stab_h^2 / (4 (lambda_e + 2 mu_e))     */
+  double alpha;           /* Biot-Willis coefficient                               */
+  double stab_h;          /* mesh size entering the default beta                    */
+} biot_materials;
+
+/* Surface load: constant traction per boundary facet, scaled per time level. */
+typedef struct {
+  int32_t n_facets;            /* may be 0                                       */
+  const int32_t* facet_nodes;  /* [n_facets][dim]                                */
+  const double* traction;      /* [n_facets][dim]                                */
+  const double* coef;          /* [n_steps+1]: multiplier c(n); f^n = c(n) F     */
+} biot_load;
+
+typedef struct {
+  int32_t schedule;     /* BIOT_SCHED_*  (default JACOBI)                          */
+  int32_t depth;        /* wavefront: sweeps per pass = iterations in flight (8)   */
+  int32_t precond;      /* BIOT_PRECOND_* (default P1)                             */
+  int32_t cheb_degree;  /* Chebyshev smoother degree per smoothing call (2)        */
+  double cheb_ratio;    /* smoother interval [lmax/ratio, lmax] (4)                */
+  double lmax_safety;   /* factor on the power-iteration estimate of lmax (1.1)    */
+  int32_t power_iters;  /* power iterations for lmax per level (20)                */
+  int32_t max_batch;    /* Jacobi: columns per launch, <= 0 for all steps (0)      */
+  double omega;         /* damping of the outer update (0.6)                       */
+} biot_options;
+
+typedef struct {
+  int32_t sweeps;       /* outer sweeps performed                                  */
+  int32_t converged;    /* 1 if rel_resid <= rtol                                  */
+  double rel_resid_u;   /* max_n ||r_u^n|| / max_n ||b_u^n||                       */
+  double rel_resid_p;   /* max_n ||r_p^n|| / max_n ||b_p^n||                       */
+  double seconds;       /* wall time of the call                                   */
+} biot_stats;
+
+typedef struct {
+  int32_t dim, n_nodes, n_steps, n_levels;
+  int32_t level_cells[16];   /* cells per side per multigrid level                */
+  int32_t level_nodes[16];   /* nodes per level                                    */
+  int32_t slots;             /* node-blocked ELL slots per node (7 in 2D, 15 in 3D) */
+  double lmax_A[16];         /* spectral bounds used by the smoothers (with safety) */
+  double lmax_S[16];
+  uint64_t workspace_bytes;
+} biot_info_t;
+
+/* Fills *opt with the defaults listed above. */
+int biot_default_options(biot_options* opt);
+
+/* Assembles the step matrix, the coupling, the load and the multigrid
+ * hierarchy on the host (FP64).  dt = tau > 0, n_steps >= 1.  On success
+ * *out is a new handle that must be released with biot_destroy(). */
+int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_load* load,
+                double dt, int32_t n_steps, const biot_options* opt, biot_handle** out);
+
+/* Device bytes the handle needs (operators, two trajectories, work vectors). */
+int biot_workspace_size(const biot_handle* h, uint64_t* bytes);
+
+/* Binds caller-owned device memory (>= biot_workspace_size bytes, 256-byte
+ * aligned) and the HIP stream (hipStream_t, NULL for the default stream),
+ * uploads the operators and sets the trajectory to zero. */
+int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* hip_stream);
+
+/* X^{n} = 0 for all n (the initial iterate of Alg. 2; X^0 = 0). */
+int biot_reset(biot_handle* h);
+
+/* n_sweeps outer sweeps.  JACOBI: each sweep updates every step from the
+ * previous sweep.  WAVEFRONT: n_sweeps must be a multiple of depth; each pass
+ * of `depth` Gauss-Seidel-in-time sweeps runs as N+depth-1 pipelined waves. */
+int biot_sweep(biot_handle* h, int32_t n_sweeps);
+
+/* Space-time residual of the current trajectory: for every step n >= 1 the
+ * squared norms [||r_u||^2, ||r_p||^2, ||b_u||^2, ||b_p||^2] of
+ * r = A' X^{n-1} + f^n - AA X^n and b = A' X^{n-1} + f^n, written to
+ * norms[n_steps][4] (host).  Synchronizes the stream. */
+int biot_residual_norms(biot_handle* h, double* norms);
+
+/* Sweeps until max(rel_resid_u, rel_resid_p) <= rtol (checked every
+ * `check_every` sweeps) or max_sweeps.  Returns BIOT_ENOTCONVERGED if the
+ * tolerance was not met, BIOT_EDIVERGED on non-finite residuals.  stats may be
+ * NULL.  Synchronizes the stream. */
+int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t check_every,
+                      biot_stats* stats);
+
+/* Copies steps n0..n1-1 of the trajectory to dst ([n1-n0][n_nodes][dim+1]),
+ * a device pointer if dst_on_device else host (host copies synchronize). */
+int biot_get_trajectory(biot_handle* h, int32_t n0, int32_t n1, double* dst, int32_t dst_on_device);
+
+/* Overwrites steps n0..n1-1 of the trajectory (warm start / resume). */
+int biot_set_trajectory(biot_handle* h, int32_t n0, int32_t n1, const double* src,
+                        int32_t src_on_device);
+
+/* Y = AA X for ncols device columns [ncols][n_nodes][dim+1] (diagnostic). */
+int biot_apply_operator(biot_handle* h, const double* X, double* Y, int32_t ncols);
+
+/* Z = P^{-1} R with the multigrid inner solves, for ncols device columns. */
+int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols);
+
+int biot_get_info(const biot_handle* h, biot_info_t* info);
+
+/* Message of the last failed call on h (or of the last failed biot_create when
+ * h is NULL).  Valid until the next call on the same handle. */
+/* Host copies of the operators of multigrid level `level` as assembled by
+ * biot_create (after the boundary conditions), in the node-blocked layout:
+ *   nbr [W][nn]           neighbour node of each slot (slot 0 = the node)
+ *   A   [W][dim*dim][nn]  displacement blocks, entry a*dim+b
+ *   S   [W][nn]           tau C_K + C_beta (coarse levels: Galerkin products)
+ * and, for level 0 only,
+ *   B   [W][dim][nn]      matrix of -b(v,q): u-row, p-column
+ *   Bt  [W][dim][nn]      its transpose: p-row, u-column
+ *   Cb  [W][nn]           C_beta
+ *   F   [nn][dim+1]       load for a unit multiplier.
+ * Any pointer may be NULL.  Sizes follow biot_get_info (W = slots). */
+int biot_export_level(const biot_handle* h, int32_t level, int32_t* nbr, double* A, double* S,
+                      double* B, double* Bt, double* Cb, double* F);
+
+const char* biot_last_error(const biot_handle* h);
+
+const char* biot_version(void);
+
+void biot_destroy(biot_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIOT_PINT_H */

@@ -1,0 +1,119 @@
+"""ctypes declarations of the C ABI in include/biot_pint.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbiot_pint.so")
+
+BIOT_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDIVERGED", -5: "ENOTCONVERGED", -6: "ESTATE"}
+SCHED = {"jacobi": 0, "wavefront": 1}
+PRECOND = {"P1": 1, "P2": 2}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_up = C.POINTER(C.c_uint8)
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int32), ("n_elems", C.c_int32),
+                ("grid_n", C.c_int32), ("xyz", _dp), ("conn", _ip), ("dirichlet", _up)]
+
+
+class Materials(C.Structure):
+    _fields_ = [("young", _dp), ("poisson", _dp), ("perm", _dp), ("beta", _dp),
+                ("alpha", C.c_double), ("stab_h", C.c_double)]
+
+
+class Load(C.Structure):
+    _fields_ = [("n_facets", C.c_int32), ("facet_nodes", _ip), ("traction", _dp), ("coef", _dp)]
+
+
+class Options(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("depth", C.c_int32), ("precond", C.c_int32),
+                ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
+                ("lmax_safety", C.c_double), ("power_iters", C.c_int32),
+                ("max_batch", C.c_int32), ("omega", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("converged", C.c_int32), ("rel_resid_u", C.c_double),
+                ("rel_resid_p", C.c_double), ("seconds", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int32), ("n_steps", C.c_int32),
+                ("n_levels", C.c_int32), ("level_cells", C.c_int32 * 16),
+                ("level_nodes", C.c_int32 * 16), ("slots", C.c_int32),
+                ("lmax_A", C.c_double * 16), ("lmax_S", C.c_double * 16),
+                ("workspace_bytes", C.c_uint64)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "biot_default_options": (C.c_int, [C.POINTER(Options)]),
+    "biot_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Materials), C.POINTER(Load), C.c_double,
+                              C.c_int32, C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "biot_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "biot_bind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]),
+    "biot_reset": (C.c_int, [C.c_void_p]),
+    "biot_sweep": (C.c_int, [C.c_void_p, C.c_int32]),
+    "biot_residual_norms": (C.c_int, [C.c_void_p, _dp]),
+    "biot_solve_to_tol": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_int32, C.POINTER(Stats)]),
+    "biot_get_trajectory": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
+    "biot_set_trajectory": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
+    "biot_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "biot_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "biot_get_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "biot_export_level": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "biot_last_error": (C.c_char_p, [C.c_void_p]),
+    "biot_version": (C.c_char_p, []),
+    "biot_destroy": (None, [C.c_void_p]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load libbiot_pint.so from the package directory; raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python __graft_entry__.py` "
+                           "(build()) to compile the HIP library")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+class BiotError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(lib, rc, handle=None):
+    if rc != BIOT_OK:
+        msg = lib.biot_last_error(handle)
+        raise BiotError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def dptr(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def iptr(a):
+    return a.ctypes.data_as(_ip)
+
+
+def uptr(a):
+    return a.ctypes.data_as(_up)

@@ -1,0 +1,685 @@
+// HIP kernels (gfx950) of the preconditioned inverted time-stepping sweep.
+//
+// Every kernel processes a batch of columns (time steps / iterations) at once.
+// A thread owns one node and a tile of CT columns: the node's matrix blocks
+// are loaded once per slot and applied to all CT columns, so the operator is
+// read once per column tile while the column data streams through.  The grid
+// is (column tiles, node blocks) with the column tile fastest, so the
+// workgroups that share a node block -- and its matrix rows -- are dispatched
+// back to back and hit in L2/MALL.
+//
+// Layouts (see setup.hpp): operator values [slot][entry][node]; state columns
+// node-major [node][u_x, u_y, (u_z), p]; multigrid work vectors node-major
+// [node][comp], one contiguous vector per column of the batch.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace biot {
+namespace {
+
+constexpr int CT = 4;  // columns per thread
+
+__constant__ int c_off2[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
+                                 {0, -1, 0}, {1, 1, 0}, {-1, -1, 0}};
+__constant__ int c_off3[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
+                                  {0, 0, 1},  {0, 0, -1}, {1, 1, 0},   {-1, -1, 0}, {1, 0, 1},
+                                  {-1, 0, -1}, {0, 1, 1}, {0, -1, -1}, {1, 1, 1},  {-1, -1, -1}};
+
+template <int DIM>
+__device__ inline void node_coords(int id, int m, int& i, int& j, int& k) {
+  i = id % m;
+  j = (id / m) % m;
+  k = DIM == 2 ? 0 : id / (m * m);
+}
+template <int DIM>
+__device__ inline int node_id(int i, int j, int k, int m) {
+  return DIM == 2 ? j * m + i : (k * m + j) * m + i;
+}
+
+// Deterministic block sum of Q values per thread (wave64 shuffles, then LDS
+// across the 4 waves in a fixed order).  Result valid in thread 0.
+template <int Q>
+__device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    v[q] = x;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lds[wave * Q + q] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = ((lds[q] + lds[Q + q]) + lds[2 * Q + q]) + lds[3 * Q + q];
+}
+
+// ---------------------------------------------------------------------------
+// fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1}, norms, and the
+// first (pointwise) Chebyshev step of the displacement V-cycle
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
+                                                     const ColDesc* __restrict__ cols, int nc,
+                                                     double* __restrict__ ru,
+                                                     double* __restrict__ rp,
+                                                     double* __restrict__ xa,
+                                                     double* __restrict__ d, double inv_theta,
+                                                     double* __restrict__ partials, int pstride) {
+  constexpr int D1 = DIM + 1;
+  __shared__ double lds[4 * 4 * CT];
+  const int nn = L.nn;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  const int c0 = blockIdx.x * CT;
+  const bool active = v < nn;
+  const double* xc[CT];
+  const double* xp[CT];
+  double coef[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int c = min(c0 + t, nc - 1);
+    xc[t] = cols[c].xcur;
+    xp[t] = cols[c].xprev;
+    coef[t] = cols[c].coef;
+  }
+  double au[CT][DIM], ap[CT], bp[CT];
+  double Fu[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(v) * D1 + a] : 0.0;
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) au[t][a] = coef[t] * Fu[a];
+    ap[t] = 0.0;
+    bp[t] = 0.0;
+  }
+  if (active) {
+    for (int s = 0; s < L.W; ++s) {
+      const int w = L.nbr[size_t(s) * nn + v];
+      double Ab[DIM * DIM], Bb[DIM], Btb[DIM];
+#pragma unroll
+      for (int e = 0; e < DIM * DIM; ++e) Ab[e] = L.A[(size_t(s) * DIM * DIM + e) * nn + v];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        Bb[c] = F.B[(size_t(s) * DIM + c) * nn + v];
+        Btb[c] = F.Bt[(size_t(s) * DIM + c) * nn + v];
+      }
+      const double Sv = L.S[size_t(s) * nn + v];
+      const double Cbv = F.Cb[size_t(s) * nn + v];
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        double xw[D1], xpw[D1];
+#pragma unroll
+        for (int k = 0; k < D1; ++k) {
+          xw[k] = xc[t][size_t(w) * D1 + k];
+          xpw[k] = xp[t][size_t(w) * D1 + k];
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          double acc = Bb[a] * xw[DIM];
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) acc += Ab[a * DIM + b] * xw[b];
+          au[t][a] -= acc;
+        }
+        double btc = 0.0, btp = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+          btc += Btb[c] * xw[c];
+          btp += Btb[c] * xpw[c];
+        }
+        const double coup = btp - Cbv * xpw[DIM];
+        bp[t] += coup;
+        ap[t] += coup - btc + Sv * xw[DIM];
+      }
+    }
+    double Di[DIM * DIM];
+    if (xa) {
+#pragma unroll
+      for (int e = 0; e < DIM * DIM; ++e) Di[e] = L.Ainv[size_t(e) * nn + v];
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      if (c0 + t >= nc) break;
+      const size_t cu = size_t(c0 + t) * nn * DIM;
+      if (ru) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = au[t][a];
+        rp[size_t(c0 + t) * nn + v] = ap[t];
+      }
+      if (xa) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          double z = 0.0;
+#pragma unroll
+          for (int b = 0; b < DIM; ++b) z += Di[a * DIM + b] * au[t][b];
+          z *= inv_theta;
+          xa[cu + size_t(v) * DIM + a] = z;
+          d[cu + size_t(v) * DIM + a] = z;
+        }
+      }
+    }
+  }
+  if (partials) {
+    double q[4 * CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      double su = 0.0, sb = 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        su += au[t][a] * au[t][a];
+        const double ba = coef[t] * Fu[a];
+        sb += ba * ba;
+      }
+      q[4 * t + 0] = active ? su : 0.0;
+      q[4 * t + 1] = active ? ap[t] * ap[t] : 0.0;
+      q[4 * t + 2] = active ? sb : 0.0;
+      q[4 * t + 3] = active ? bp[t] * bp[t] : 0.0;
+    }
+    block_sum<4 * CT>(q, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        if (c0 + t >= nc) break;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          partials[(size_t(c0 + t) * pstride + blockIdx.y) * 4 + k] = q[4 * t + k];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev step on one level:  d <- c1 d + c2 D^{-1}(b - K xin);  xout = xin + d
+// ---------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, int isA, const double* __restrict__ b,
+                                                 const double* __restrict__ xin,
+                                                 double* __restrict__ xout, double* __restrict__ d,
+                                                 int nc, double c1, double c2) {
+  const int nn = L.nn;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const int c0 = blockIdx.x * CT;
+  const double* K = isA ? L.A : L.S;
+  const double* Dg = isA ? L.Ainv : L.Sinv;
+  const size_t stride = size_t(nn) * C;
+  double acc[CT][C];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(v) * C;
+#pragma unroll
+    for (int a = 0; a < C; ++a) acc[t][a] = b[base + a];
+  }
+  for (int s = 0; s < L.W; ++s) {
+    const int w = L.nbr[size_t(s) * nn + v];
+    double blk[C * C];
+#pragma unroll
+    for (int e = 0; e < C * C; ++e) blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(w) * C;
+      double xw[C];
+#pragma unroll
+      for (int k = 0; k < C; ++k) xw[k] = xin[base + k];
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * xw[k];
+        acc[t][a] -= s2;
+      }
+    }
+  }
+  double Di[C * C];
+#pragma unroll
+  for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    if (c0 + t >= nc) break;
+    const size_t base = size_t(c0 + t) * stride + size_t(v) * C;
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      double z = 0.0;
+#pragma unroll
+      for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[t][k];
+      const double dn = (c1 != 0.0 ? c1 * d[base + a] : 0.0) + c2 * z;
+      d[base + a] = dn;
+      xout[base + a] = xin[base + a] + dn;
+    }
+  }
+}
+
+// r = b - K x on one level
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
+                                                           const double* __restrict__ b,
+                                                           const double* __restrict__ x,
+                                                           double* __restrict__ r, int nc) {
+  const int nn = L.nn;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const int c0 = blockIdx.x * CT;
+  const double* K = isA ? L.A : L.S;
+  const size_t stride = size_t(nn) * C;
+  double acc[CT][C];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(v) * C;
+#pragma unroll
+    for (int a = 0; a < C; ++a) acc[t][a] = b[base + a];
+  }
+  for (int s = 0; s < L.W; ++s) {
+    const int w = L.nbr[size_t(s) * nn + v];
+    double blk[C * C];
+#pragma unroll
+    for (int e = 0; e < C * C; ++e) blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(w) * C;
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[base + k];
+        acc[t][a] -= s2;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    if (c0 + t >= nc) break;
+    const size_t base = size_t(c0 + t) * stride + size_t(v) * C;
+#pragma unroll
+    for (int a = 0; a < C; ++a) r[base + a] = acc[t][a];
+  }
+}
+
+// coarse b = P' r_fine (P1 interpolation transpose, masked), plus the first
+// Chebyshev step of the coarse level when it is not the coarsest
+template <int DIM, int C>
+__global__ __launch_bounds__(kBlock) void k_restrict(LevelDev Lf, LevelDev Lc, int isA,
+                                                     const double* __restrict__ rf,
+                                                     double* __restrict__ bc,
+                                                     double* __restrict__ xa,
+                                                     double* __restrict__ d, double inv_theta,
+                                                     int nc) {
+  constexpr int W = DIM == 2 ? 7 : 15;
+  const int I = blockIdx.y * kBlock + threadIdx.x;
+  if (I >= Lc.nn) return;
+  const int c = blockIdx.x;
+  const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
+  int ci, cj, ck;
+  node_coords<DIM>(I, mc, ci, cj, ck);
+  const uint8_t fc = Lc.fixed[I];
+  const int bit0 = isA ? 0 : DIM;
+  const size_t sf = size_t(Lf.nn) * C, sc = size_t(Lc.nn) * C;
+  double acc[C];
+#pragma unroll
+  for (int a = 0; a < C; ++a) acc[a] = 0.0;
+#pragma unroll
+  for (int s = 0; s < W; ++s) {
+    const int* o = DIM == 2 ? c_off2[s] : c_off3[s];
+    const int fi = 2 * ci + o[0], fj = 2 * cj + o[1], fk = 2 * ck + o[2];
+    if (fi < 0 || fi >= mf || fj < 0 || fj >= mf || fk < 0 || fk >= mf) continue;
+    const int f = node_id<DIM>(fi, fj, fk, mf);
+    const double wgt = s == 0 ? 1.0 : 0.5;
+    const uint8_t ff = Lf.fixed[f];
+#pragma unroll
+    for (int a = 0; a < C; ++a)
+      if (!((ff >> (bit0 + a)) & 1)) acc[a] += wgt * rf[size_t(c) * sf + size_t(f) * C + a];
+  }
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    if ((fc >> (bit0 + a)) & 1) acc[a] = 0.0;
+    bc[size_t(c) * sc + size_t(I) * C + a] = acc[a];
+  }
+  if (xa) {
+    const double* Dg = isA ? Lc.Ainv : Lc.Sinv;
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      double z = 0.0;
+#pragma unroll
+      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + I] * acc[k];
+      z *= inv_theta;
+      xa[size_t(c) * sc + size_t(I) * C + a] = z;
+      d[size_t(c) * sc + size_t(I) * C + a] = z;
+    }
+  }
+}
+
+// xf_out = xf_in + P xc (P1 interpolation, masked)
+template <int DIM, int C>
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelDev Lf, LevelDev Lc, int isA,
+                                                    const double* __restrict__ xin,
+                                                    const double* __restrict__ xc,
+                                                    double* __restrict__ xout, int nc) {
+  const int f = blockIdx.y * kBlock + threadIdx.x;
+  if (f >= Lf.nn) return;
+  const int c = blockIdx.x;
+  const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
+  int i, j, k;
+  node_coords<DIM>(f, mf, i, j, k);
+  const int ai = i >> 1, aj = j >> 1, ak = k >> 1;
+  const int oi = i & 1, oj = j & 1, ok = k & 1;
+  const int p0 = node_id<DIM>(ai, aj, ak, mc);
+  const bool two = (oi | oj | ok) != 0;
+  const int p1 = two ? node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
+  const double w = two ? 0.5 : 1.0;
+  const int bit0 = isA ? 0 : DIM;
+  const uint8_t ff = Lf.fixed[f], f0 = Lc.fixed[p0], f1 = Lc.fixed[p1];
+  const size_t sf = size_t(Lf.nn) * C, sc = size_t(Lc.nn) * C;
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    double add = 0.0;
+    if (!((ff >> (bit0 + a)) & 1)) {
+      if (!((f0 >> (bit0 + a)) & 1)) add += w * xc[size_t(c) * sc + size_t(p0) * C + a];
+      if (two && !((f1 >> (bit0 + a)) & 1)) add += w * xc[size_t(c) * sc + size_t(p1) * C + a];
+    }
+    const size_t idx = size_t(c) * sf + size_t(f) * C + a;
+    xout[idx] = xin[idx] + add;
+  }
+}
+
+// coarsest level: x = M^{-1} b with the dense inverse, one workgroup per column
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ Minv,
+                                                         const double* __restrict__ b,
+                                                         double* __restrict__ x) {
+  extern __shared__ double sb[];
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += kBlock) sb[i] = b[size_t(c) * n + i];
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += kBlock) {
+    double acc = 0.0;
+    const double* row = Minv + size_t(r) * n;
+    for (int j = 0; j < n; ++j) acc += row[j] * sb[j];
+    x[size_t(c) * n + r] = acc;
+  }
+}
+
+// pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), and the first
+// Chebyshev step of the pressure V-cycle
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1,
+                                                   const double* __restrict__ zu,
+                                                   const double* __restrict__ rp,
+                                                   double* __restrict__ t_out,
+                                                   double* __restrict__ xa,
+                                                   double* __restrict__ d, double inv_theta,
+                                                   int nc) {
+  const int nn = L.nn;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const int c0 = blockIdx.x * CT;
+  double acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = -rp[size_t(min(c0 + t, nc - 1)) * nn + v];
+  if (p1) {
+    for (int s = 0; s < L.W; ++s) {
+      const int w = L.nbr[size_t(s) * nn + v];
+      double Btb[DIM];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) Btb[c] = F.Bt[(size_t(s) * DIM + c) * nn + v];
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        const size_t base = size_t(min(c0 + t, nc - 1)) * nn * DIM + size_t(w) * DIM;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[t] += Btb[c] * zu[base + c];
+      }
+    }
+  }
+  const double si = L.Sinv[v];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    if (c0 + t >= nc) break;
+    const size_t idx = size_t(c0 + t) * nn + v;
+    t_out[idx] = acc[t];
+    const double z = si * acc[t] * inv_theta;
+    xa[idx] = z;
+    d[idx] = z;
+  }
+}
+
+// X^{n,m} = X^{n,m-1} + omega [z_u; z_p]
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_update(int nn, const ColDesc* __restrict__ cols,
+                                                   const double* __restrict__ zu,
+                                                   const double* __restrict__ zp, double omega) {
+  constexpr int D1 = DIM + 1;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const int c = blockIdx.x;
+  const double* xc = cols[c].xcur;
+  double* xo = cols[c].xout;
+  double* xo2 = cols[c].xout2;
+  double out[D1];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    out[a] = xc[size_t(v) * D1 + a] + omega * zu[(size_t(c) * nn + v) * DIM + a];
+  out[DIM] = xc[size_t(v) * D1 + DIM] + omega * zp[size_t(c) * nn + v];
+#pragma unroll
+  for (int a = 0; a < D1; ++a) xo[size_t(v) * D1 + a] = out[a];
+  if (xo2)
+#pragma unroll
+    for (int a = 0; a < D1; ++a) xo2[size_t(v) * D1 + a] = out[a];
+}
+
+// per-column sums of the block partials in a fixed order
+__global__ __launch_bounds__(kBlock) void k_reduce_norms(const double* __restrict__ partials,
+                                                         int nblk, int pstride,
+                                                         double* __restrict__ norms) {
+  __shared__ double lds[16];
+  const int c = blockIdx.x;
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] += partials[(size_t(c) * pstride + b) * 4 + k];
+  block_sum<4>(q, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) norms[size_t(c) * 4 + k] = q[k];
+}
+
+// Y = AA X (test/diagnostic path)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply_operator(LevelDev L, FineDev F,
+                                                           const double* __restrict__ X,
+                                                           double* __restrict__ Y) {
+  constexpr int D1 = DIM + 1;
+  const int nn = L.nn;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const int c = blockIdx.x;
+  const double* x = X + size_t(c) * nn * D1;
+  double yu[DIM] = {}, yp = 0.0;
+  for (int s = 0; s < L.W; ++s) {
+    const int w = L.nbr[size_t(s) * nn + v];
+    double xw[D1];
+#pragma unroll
+    for (int k = 0; k < D1; ++k) xw[k] = x[size_t(w) * D1 + k];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      double acc = F.B[(size_t(s) * DIM + a) * nn + v] * xw[DIM];
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) acc += L.A[(size_t(s) * DIM * DIM + a * DIM + b) * nn + v] * xw[b];
+      yu[a] += acc;
+    }
+    double acc = -L.S[size_t(s) * nn + v] * xw[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) acc += F.Bt[(size_t(s) * DIM + a) * nn + v] * xw[a];
+    yp += acc;
+  }
+  double* y = Y + size_t(c) * nn * D1;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) y[size_t(v) * D1 + a] = yu[a];
+  y[size_t(v) * D1 + DIM] = yp;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_unpack(int nn, const double* __restrict__ X,
+                                                   double* __restrict__ ru,
+                                                   double* __restrict__ rp) {
+  constexpr int D1 = DIM + 1;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const size_t c = blockIdx.x;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) ru[(c * nn + v) * DIM + a] = X[(c * nn + v) * D1 + a];
+  rp[c * nn + v] = X[(c * nn + v) * D1 + DIM];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_pack(int nn, const double* __restrict__ zu,
+                                                 const double* __restrict__ zp,
+                                                 double* __restrict__ Z) {
+  constexpr int D1 = DIM + 1;
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const size_t c = blockIdx.x;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) Z[(c * nn + v) * D1 + a] = zu[(c * nn + v) * DIM + a];
+  Z[(c * nn + v) * D1 + DIM] = zp[c * nn + v];
+}
+
+// first Chebyshev step from a zero iterate: xa = d = D^{-1} b / theta
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_pre1(LevelDev L, int isA, const double* __restrict__ b,
+                                                 double* __restrict__ xa, double* __restrict__ d,
+                                                 double inv_theta) {
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= L.nn) return;
+  const size_t base = size_t(blockIdx.x) * L.nn * C + size_t(v) * C;
+  const double* Dg = isA ? L.Ainv : L.Sinv;
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    double z = 0.0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + v] * b[base + k];
+    z *= inv_theta;
+    xa[base + a] = z;
+    d[base + a] = z;
+  }
+}
+
+inline dim3 tiled_grid(int nc, int nn) { return dim3((nc + CT - 1) / CT, num_node_blocks(nn)); }
+inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
+
+}  // namespace
+
+void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
+                     double* ru, double* rp, double* xa, double* d, double inv_theta,
+                     double* partials, int pstride, hipStream_t st) {
+  if (dim == 2)
+    hipLaunchKernelGGL(k_residual<2>, tiled_grid(nc, L.nn), dim3(kBlock), 0, st, L, F, cols, nc,
+                       ru, rp, xa, d, inv_theta, partials, pstride);
+  else
+    hipLaunchKernelGGL(k_residual<3>, tiled_grid(nc, L.nn), dim3(kBlock), 0, st, L, F, cols, nc,
+                       ru, rp, xa, d, inv_theta, partials, pstride);
+}
+
+void launch_cheb(int comps, const LevelDev& L, bool is_A, const double* b, const double* xin,
+                 double* xout, double* d, int nc, double c1, double c2, hipStream_t st) {
+  dim3 g = tiled_grid(nc, L.nn);
+  switch (comps) {
+    case 1: hipLaunchKernelGGL(k_cheb<1>, g, dim3(kBlock), 0, st, L, int(is_A), b, xin, xout, d, nc, c1, c2); break;
+    case 2: hipLaunchKernelGGL(k_cheb<2>, g, dim3(kBlock), 0, st, L, int(is_A), b, xin, xout, d, nc, c1, c2); break;
+    default: hipLaunchKernelGGL(k_cheb<3>, g, dim3(kBlock), 0, st, L, int(is_A), b, xin, xout, d, nc, c1, c2); break;
+  }
+}
+
+void launch_level_residual(int comps, const LevelDev& L, bool is_A, const double* b,
+                           const double* x, double* r, int nc, hipStream_t st) {
+  dim3 g = tiled_grid(nc, L.nn);
+  switch (comps) {
+    case 1: hipLaunchKernelGGL(k_level_residual<1>, g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc); break;
+    case 2: hipLaunchKernelGGL(k_level_residual<2>, g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc); break;
+    default: hipLaunchKernelGGL(k_level_residual<3>, g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc); break;
+  }
+}
+
+void launch_restrict(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
+                     const double* rf, double* bc, double* xa_c, double* d_c, double inv_theta_c,
+                     int nc, hipStream_t st) {
+  dim3 g = col_grid(nc, Lc.nn);
+  if (dim == 2) {
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
+    else hipLaunchKernelGGL((k_restrict<2, 2>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
+  } else {
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<3, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
+    else hipLaunchKernelGGL((k_restrict<3, 3>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
+  }
+}
+
+void launch_prolong(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
+                    const double* xf_in, const double* xc, double* xf_out, int nc, hipStream_t st) {
+  dim3 g = col_grid(nc, Lf.nn);
+  if (dim == 2) {
+    if (comps == 1) hipLaunchKernelGGL((k_prolong<2, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
+    else hipLaunchKernelGGL((k_prolong<2, 2>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
+  } else {
+    if (comps == 1) hipLaunchKernelGGL((k_prolong<3, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
+    else hipLaunchKernelGGL((k_prolong<3, 3>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
+  }
+}
+
+void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, int nc,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_solve, dim3(nc), dim3(kBlock), size_t(n) * sizeof(double), st, n,
+                     Minv, b, x);
+}
+
+void launch_pstage(int dim, const LevelDev& L, const FineDev& F, bool p1, const double* zu,
+                   const double* rp, double* t, double* xa, double* d, double inv_theta, int nc,
+                   hipStream_t st) {
+  dim3 g = tiled_grid(nc, L.nn);
+  if (dim == 2)
+    hipLaunchKernelGGL(k_pstage<2>, g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc);
+  else
+    hipLaunchKernelGGL(k_pstage<3>, g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc);
+}
+
+void launch_update(int dim, int nn, const ColDesc* cols, const double* zu, const double* zp,
+                   double omega, int nc, hipStream_t st) {
+  dim3 g = col_grid(nc, nn);
+  if (dim == 2) hipLaunchKernelGGL(k_update<2>, g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
+  else hipLaunchKernelGGL(k_update<3>, g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
+}
+
+void launch_reduce_norms(const double* partials, int nblk, int pstride, double* norms, int nc,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_norms, dim3(nc), dim3(kBlock), 0, st, partials, nblk, pstride, norms);
+}
+
+void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const double* X,
+                           double* Y, int nc, hipStream_t st) {
+  dim3 g = col_grid(nc, L.nn);
+  if (dim == 2) hipLaunchKernelGGL(k_apply_operator<2>, g, dim3(kBlock), 0, st, L, F, X, Y);
+  else hipLaunchKernelGGL(k_apply_operator<3>, g, dim3(kBlock), 0, st, L, F, X, Y);
+}
+
+void launch_unpack(int dim, int nn, const double* X, double* ru, double* rp, int nc, hipStream_t st) {
+  dim3 g = col_grid(nc, nn);
+  if (dim == 2) hipLaunchKernelGGL(k_unpack<2>, g, dim3(kBlock), 0, st, nn, X, ru, rp);
+  else hipLaunchKernelGGL(k_unpack<3>, g, dim3(kBlock), 0, st, nn, X, ru, rp);
+}
+
+void launch_pre1(int comps, const LevelDev& L, bool is_A, const double* b, double* xa, double* d,
+                 double inv_theta, int nc, hipStream_t st) {
+  dim3 g = col_grid(nc, L.nn);
+  switch (comps) {
+    case 1: hipLaunchKernelGGL(k_pre1<1>, g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, inv_theta); break;
+    case 2: hipLaunchKernelGGL(k_pre1<2>, g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, inv_theta); break;
+    default: hipLaunchKernelGGL(k_pre1<3>, g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, inv_theta); break;
+  }
+}
+
+void launch_pack(int dim, int nn, const double* zu, const double* zp, double* Z, int nc,
+                 hipStream_t st) {
+  dim3 g = col_grid(nc, nn);
+  if (dim == 2) hipLaunchKernelGGL(k_pack<2>, g, dim3(kBlock), 0, st, nn, zu, zp, Z);
+  else hipLaunchKernelGGL(k_pack<3>, g, dim3(kBlock), 0, st, nn, zu, zp, Z);
+}
+
+}  // namespace biot

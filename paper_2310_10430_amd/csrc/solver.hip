@@ -1,0 +1,694 @@
+// Runtime of the Biot parallel-in-time solver and its C ABI (include/biot_pint.h).
+//
+// Schedules (Sec. 3.2 and 3.3 of the paper):
+//   JACOBI     one sweep updates all N_time steps at once from the previous
+//              sweep's trajectory; batches of steps are columns of one launch.
+//   WAVEFRONT  Alg. 2's Gauss-Seidel-in-time order run as the pipeline of
+//              Alg. 4: `depth` iterations are in flight, slot s working on step
+//              w - s at wall step w.  Each slot keeps a ping-pong pair of
+//              columns, so no slot reads what another writes in the same wave.
+// One unit (step n, iteration m) is
+//   r   = c(n) F + A' X^{n-1} - AA X^{n,m-1}                  (k_residual)
+//   z_u = V_A(r_u)                                            (multigrid V-cycle)
+//   t   = B' z_u - r_p   (P1)   or   -r_p   (P2)              (k_pstage)
+//   z_p = V_S(t)                                              (multigrid V-cycle)
+//   X^{n,m} = X^{n,m-1} + omega [z_u; z_p]                    (k_update)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/biot_pint.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+using namespace biot;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Field {  // work vectors of one V-cycle family per level
+  std::vector<double*> b, x0, x1, d, r;
+};
+
+struct ChebCoef {
+  double theta = 0, delta = 0, sigma = 0;
+};
+
+}  // namespace
+
+struct biot_handle {
+  std::string err;
+  HostProblem P;
+  biot_options opt{};
+  int dim = 2, D1 = 3, nn = 0, N = 0, nlev = 0;
+  int ncmax = 0;  // batch capacity (columns)
+  size_t col = 0; // doubles per state column
+  // device state
+  bool bound = false;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  uint64_t ws_need = 0;
+  std::vector<LevelDev> L;
+  FineDev F{};
+  double* coarseA = nullptr;
+  double* coarseS = nullptr;
+  double* T[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* slots = nullptr;
+  Field fa, fs;
+  double* rp = nullptr;
+  double* partials = nullptr;
+  int nblk = 0;
+  double* norms = nullptr;
+  ColDesc* desc_jac[2] = {nullptr, nullptr};
+  ColDesc* desc_k4[2] = {nullptr, nullptr};
+  ColDesc* desc_wave[2] = {nullptr, nullptr};
+  std::vector<int> wave_off, wave_cnt;
+  std::vector<ChebCoef> chA, chS;
+  // host copies of the descriptor tables (uploaded at bind)
+  std::vector<ColDesc> h_jac[2], h_k4[2], h_wave[2];
+};
+
+namespace {
+
+int fail(biot_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(h, BIOT_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+#define LAUNCHCHK(h)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return fail(h, BIOT_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// bump allocator over the workspace; with base == nullptr it only counts bytes
+struct Bump {
+  char* base;
+  uint64_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~uint64_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += uint64_t(count) * sizeof(T);
+    return p;
+  }
+};
+
+void plan(biot_handle* h, char* base) {
+  Bump b{base};
+  const int dim = h->dim;
+  h->L.assign(h->nlev, LevelDev{});
+  for (int l = 0; l < h->nlev; ++l) {
+    const HostLevel& H = h->P.levels[l];
+    LevelDev& D = h->L[l];
+    D.nn = H.nn;
+    D.W = H.W;
+    D.n_cells = H.n_cells;
+    D.nbr = b.take<int32_t>(H.nbr.size());
+    D.A = b.take<double>(H.A.size());
+    D.S = b.take<double>(H.S.size());
+    D.Ainv = b.take<double>(H.Ainv.size());
+    D.Sinv = b.take<double>(H.Sinv.size());
+    D.fixed = b.take<uint8_t>(H.fixed.size());
+  }
+  const HostLevel& H0 = h->P.levels[0];
+  h->F.B = b.take<double>(H0.B.size());
+  h->F.Bt = b.take<double>(H0.Bt.size());
+  h->F.Cb = b.take<double>(H0.Cb.size());
+  h->F.F = b.take<double>(h->P.F.size());
+  h->coarseA = b.take<double>(h->P.coarseAinv.size());
+  h->coarseS = b.take<double>(h->P.coarseSinv.size());
+  const size_t traj = size_t(h->N + 1) * h->col;
+  h->T[0] = b.take<double>(traj);
+  h->T[1] = b.take<double>(traj);
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
+    h->slots = b.take<double>(size_t(2) * h->opt.depth * h->col);
+  const int nc = h->ncmax;
+  for (Field* f : {&h->fa, &h->fs}) {
+    const int C = (f == &h->fa) ? dim : 1;
+    f->b.assign(h->nlev, nullptr);
+    f->x0.assign(h->nlev, nullptr);
+    f->x1.assign(h->nlev, nullptr);
+    f->d.assign(h->nlev, nullptr);
+    f->r.assign(h->nlev, nullptr);
+    for (int l = 0; l < h->nlev; ++l) {
+      const size_t n = size_t(nc) * h->P.levels[l].nn * C;
+      f->b[l] = b.take<double>(n);
+      f->x0[l] = b.take<double>(n);
+      f->x1[l] = b.take<double>(n);
+      f->d[l] = b.take<double>(n);
+      f->r[l] = b.take<double>(n);
+    }
+  }
+  h->rp = b.take<double>(size_t(nc) * h->nn);
+  h->nblk = num_node_blocks(h->nn);
+  h->partials = b.take<double>(size_t(std::max(nc, h->N)) * h->nblk * 4);
+  h->norms = b.take<double>(size_t(h->N) * 4);
+  for (int c = 0; c < 2; ++c) {
+    h->desc_jac[c] = b.take<ColDesc>(h->N);
+    h->desc_k4[c] = b.take<ColDesc>(h->N);
+    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
+      h->desc_wave[c] = b.take<ColDesc>(size_t(h->N) * h->opt.depth);
+  }
+  h->ws_need = b.off + 256;
+}
+
+void build_tables(biot_handle* h) {
+  const size_t col = h->col;
+  for (int c = 0; c < 2; ++c) {
+    double* Tin = h->T[c];
+    double* Tout = h->T[1 - c];
+    h->h_jac[c].resize(h->N);
+    h->h_k4[c].resize(h->N);
+    for (int n = 1; n <= h->N; ++n) {
+      ColDesc d{};
+      d.xcur = Tin + n * col;
+      d.xprev = Tin + (n - 1) * col;
+      d.xout = Tout + n * col;
+      d.xout2 = nullptr;
+      d.coef = h->P.coef[n];
+      d.step = n;
+      h->h_jac[c][n - 1] = d;
+      d.xout = nullptr;
+      h->h_k4[c][n - 1] = d;
+    }
+    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) {
+      const int D = h->opt.depth;
+      auto slot = [&](int s, int parity) { return h->slots + (size_t(parity) * D + s) * col; };
+      h->h_wave[c].clear();
+      h->wave_off.clear();
+      h->wave_cnt.clear();
+      for (int w = 1; w <= h->N + D - 1; ++w) {
+        h->wave_off.push_back(int(h->h_wave[c].size()));
+        int cnt = 0;
+        for (int s = 0; s < D; ++s) {
+          const int n = w - s;
+          if (n < 1 || n > h->N) continue;
+          ColDesc d{};
+          d.xcur = s == 0 ? Tin + n * col : slot(s - 1, (w - 1) & 1);
+          d.xprev = n == 1 ? Tin : slot(s, (w - 1) & 1);
+          d.xout = slot(s, w & 1);
+          d.xout2 = s == D - 1 ? Tout + n * col : nullptr;
+          d.coef = h->P.coef[n];
+          d.step = n;
+          h->h_wave[c].push_back(d);
+          ++cnt;
+        }
+        h->wave_cnt.push_back(cnt);
+      }
+    }
+  }
+}
+
+ChebCoef cheb_of(double lmax, double ratio) {
+  ChebCoef c;
+  const double lmin = lmax / ratio;
+  c.theta = 0.5 * (lmax + lmin);
+  c.delta = 0.5 * (lmax - lmin);
+  c.sigma = c.theta / c.delta;
+  return c;
+}
+
+// One V-cycle for field A (is_A) or S on level l for nc columns.  On entry b[l]
+// holds the right-hand side and, unless l is the coarsest level, x0[l]/d[l]
+// hold the first Chebyshev step.  Returns the buffer with the result.
+int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out) {
+  Field& f = is_A ? h->fa : h->fs;
+  const int C = is_A ? h->dim : 1;
+  const int last = h->nlev - 1;
+  hipStream_t st = h->st;
+  if (l == last) {
+    launch_coarse_solve(h->P.levels[l].nn * C, is_A ? h->coarseA : h->coarseS, f.b[l], f.x0[l], nc, st);
+    LAUNCHCHK(h);
+    *out = f.x0[l];
+    return BIOT_OK;
+  }
+  const ChebCoef& cc = is_A ? h->chA[l] : h->chS[l];
+  const int deg = h->opt.cheb_degree;
+  double* cur = f.x0[l];
+  double* oth = f.x1[l];
+  // pre-smoothing: the first step was done by the producer of b[l]
+  double rho = 1.0 / cc.sigma;
+  for (int j = 2; j <= deg; ++j) {
+    const double rn = 1.0 / (2.0 * cc.sigma - rho);
+    launch_cheb(C, h->L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho, 2.0 * rn / cc.delta, st);
+    LAUNCHCHK(h);
+    rho = rn;
+    std::swap(cur, oth);
+  }
+  launch_level_residual(C, h->L[l], is_A, f.b[l], cur, f.r[l], nc, st);
+  LAUNCHCHK(h);
+  const bool coarse_last = (l + 1 == last);
+  const ChebCoef* cn = coarse_last ? nullptr : (is_A ? &h->chA[l + 1] : &h->chS[l + 1]);
+  launch_restrict(h->dim, C, h->L[l], h->L[l + 1], is_A, f.r[l], f.b[l + 1],
+                  coarse_last ? nullptr : f.x0[l + 1], coarse_last ? nullptr : f.d[l + 1],
+                  coarse_last ? 0.0 : 1.0 / cn->theta, nc, st);
+  LAUNCHCHK(h);
+  double* xc = nullptr;
+  int rc = vcycle(h, is_A, l + 1, nc, &xc);
+  if (rc) return rc;
+  launch_prolong(h->dim, C, h->L[l], h->L[l + 1], is_A, cur, xc, oth, nc, st);
+  LAUNCHCHK(h);
+  std::swap(cur, oth);
+  // post-smoothing: deg steps, restarting the recurrence
+  launch_cheb(C, h->L[l], is_A, f.b[l], cur, oth, f.d[l], nc, 0.0, 1.0 / cc.theta, st);
+  LAUNCHCHK(h);
+  std::swap(cur, oth);
+  rho = 1.0 / cc.sigma;
+  for (int j = 2; j <= deg; ++j) {
+    const double rn = 1.0 / (2.0 * cc.sigma - rho);
+    launch_cheb(C, h->L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho, 2.0 * rn / cc.delta, st);
+    LAUNCHCHK(h);
+    rho = rn;
+    std::swap(cur, oth);
+  }
+  *out = cur;
+  return BIOT_OK;
+}
+
+bool level0_smoothed(const biot_handle* h) { return h->nlev > 1; }
+
+// P^{-1} applied to the batch whose residual is in fa.b[0] (r_u) and rp (r_p);
+// the first Chebyshev step of V_A has been written by the producer.
+int precond_batch(biot_handle* h, int nc, double** zu, double** zp) {
+  int rc = vcycle(h, true, 0, nc, zu);
+  if (rc) return rc;
+  const bool sm = level0_smoothed(h);
+  launch_pstage(h->dim, h->L[0], h->F, h->opt.precond == BIOT_PRECOND_P1, *zu, h->rp, h->fs.b[0],
+                h->fs.x0[0], h->fs.d[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc, h->st);
+  LAUNCHCHK(h);
+  return vcycle(h, false, 0, nc, zp);
+}
+
+// one unit for every column of a descriptor batch
+int unit_batch(biot_handle* h, const ColDesc* cols, int nc, double* partials, double* norms_out) {
+  const bool sm = level0_smoothed(h);
+  launch_residual(h->dim, h->L[0], h->F, cols, nc, h->fa.b[0], h->rp, sm ? h->fa.x0[0] : nullptr,
+                  h->fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0, partials, h->nblk, h->st);
+  LAUNCHCHK(h);
+  double *zu = nullptr, *zp = nullptr;
+  int rc = precond_batch(h, nc, &zu, &zp);
+  if (rc) return rc;
+  launch_update(h->dim, h->nn, cols, zu, zp, h->opt.omega, nc, h->st);
+  LAUNCHCHK(h);
+  if (partials && norms_out) {
+    launch_reduce_norms(partials, h->nblk, h->nblk, norms_out, nc, h->st);
+    LAUNCHCHK(h);
+  }
+  return BIOT_OK;
+}
+
+int jacobi_sweep(biot_handle* h) {
+  ColDesc* tab = h->desc_jac[h->cur];
+  for (int n0 = 0; n0 < h->N; n0 += h->ncmax) {
+    const int nc = std::min(h->ncmax, h->N - n0);
+    int rc = unit_batch(h, tab + n0, nc, nullptr, nullptr);
+    if (rc) return rc;
+  }
+  h->cur = 1 - h->cur;
+  return BIOT_OK;
+}
+
+int wavefront_pass(biot_handle* h) {
+  ColDesc* tab = h->desc_wave[h->cur];
+  for (size_t w = 0; w < h->wave_off.size(); ++w) {
+    int rc = unit_batch(h, tab + h->wave_off[w], h->wave_cnt[w], nullptr, nullptr);
+    if (rc) return rc;
+  }
+  h->cur = 1 - h->cur;
+  return BIOT_OK;
+}
+
+// global space-time residual norms of the current trajectory into h->norms
+int global_residual(biot_handle* h) {
+  ColDesc* tab = h->desc_k4[h->cur];
+  const int chunk = std::max(h->ncmax, 1);
+  for (int n0 = 0; n0 < h->N; n0 += chunk) {
+    const int nc = std::min(chunk, h->N - n0);
+    launch_residual(h->dim, h->L[0], h->F, tab + n0, nc, nullptr, nullptr, nullptr, nullptr, 0.0,
+                    h->partials, h->nblk, h->st);
+    LAUNCHCHK(h);
+    launch_reduce_norms(h->partials, h->nblk, h->nblk, h->norms + size_t(n0) * 4, nc, h->st);
+    LAUNCHCHK(h);
+  }
+  return BIOT_OK;
+}
+
+void rel_resid(const std::vector<double>& nr, int N, double& ru, double& rp) {
+  double mu = 0, mp = 0, bu = 0, bp = 0;
+  bool bad = false;
+  for (int n = 0; n < N; ++n) {
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(nr[size_t(n) * 4 + k])) bad = true;
+    mu = std::max(mu, nr[size_t(n) * 4 + 0]);
+    mp = std::max(mp, nr[size_t(n) * 4 + 1]);
+    bu = std::max(bu, nr[size_t(n) * 4 + 2]);
+    bp = std::max(bp, nr[size_t(n) * 4 + 3]);
+  }
+  if (bad) {
+    ru = rp = NAN;
+    return;
+  }
+  ru = std::sqrt(mu) / std::max(std::sqrt(bu), 1e-300);
+  rp = std::sqrt(mp) / std::max(std::sqrt(bp), 1e-300);
+}
+
+int check_bound(biot_handle* h) {
+  if (!h) return BIOT_EINVAL;
+  if (!h->bound) return fail(h, BIOT_ESTATE, "workspace not bound");
+  return BIOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int biot_default_options(biot_options* o) {
+  if (!o) return BIOT_EINVAL;
+  o->schedule = BIOT_SCHED_JACOBI;
+  o->depth = 8;
+  o->precond = BIOT_PRECOND_P1;
+  o->cheb_degree = 2;
+  o->cheb_ratio = 4.0;
+  o->lmax_safety = 1.1;
+  o->power_iters = 20;
+  o->max_batch = 0;
+  o->omega = 0.6;
+  return BIOT_OK;
+}
+
+int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_load* load,
+                double dt, int32_t n_steps, const biot_options* opt, biot_handle** out) {
+  if (!out) return fail(nullptr, BIOT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mesh || !mat || !load) return fail(nullptr, BIOT_EINVAL, "NULL mesh, materials or load");
+  biot_options o;
+  biot_default_options(&o);
+  if (opt) o = *opt;
+  if (o.schedule != BIOT_SCHED_JACOBI && o.schedule != BIOT_SCHED_WAVEFRONT)
+    return fail(nullptr, BIOT_EINVAL, "unknown schedule");
+  if (o.precond != BIOT_PRECOND_P1 && o.precond != BIOT_PRECOND_P2)
+    return fail(nullptr, BIOT_EINVAL, "unknown preconditioner");
+  if (o.schedule == BIOT_SCHED_WAVEFRONT && (o.depth < 1 || o.depth > 4096))
+    return fail(nullptr, BIOT_EINVAL, "depth must be in 1..4096");
+  if (!(o.omega > 0.0) || !std::isfinite(o.omega)) return fail(nullptr, BIOT_EINVAL, "omega must be > 0");
+  if (o.power_iters < 1) return fail(nullptr, BIOT_EINVAL, "power_iters must be >= 1");
+  if (!(o.lmax_safety >= 1.0)) return fail(nullptr, BIOT_EINVAL, "lmax_safety must be >= 1");
+  biot_handle* h = new (std::nothrow) biot_handle();
+  if (!h) return fail(nullptr, BIOT_ENOMEM, "out of host memory");
+  h->opt = o;
+  MeshIn m{mesh->dim, mesh->n_nodes, mesh->n_elems, mesh->grid_n, mesh->xyz, mesh->conn, mesh->dirichlet};
+  MaterialsIn mi{mat->young, mat->poisson, mat->perm, mat->beta, mat->alpha, mat->stab_h};
+  LoadIn li{load->n_facets, load->facet_nodes, load->traction, load->coef};
+  HostOptions ho;
+  ho.cheb_degree = o.cheb_degree;
+  ho.cheb_ratio = o.cheb_ratio;
+  ho.lmax_safety = o.lmax_safety;
+  ho.power_iters = o.power_iters;
+  std::string e;
+  try {
+    e = build_problem(m, mi, li, dt, n_steps, ho, h->P);
+  } catch (const std::exception& ex) {
+    e = std::string("set-up failed: ") + ex.what();
+  }
+  if (!e.empty()) {
+    delete h;
+    return fail(nullptr, BIOT_EINVAL, e);
+  }
+  h->dim = h->P.dim;
+  h->D1 = h->dim + 1;
+  h->nn = h->P.nn;
+  h->N = n_steps;
+  h->nlev = int(h->P.levels.size());
+  if (h->nlev > 16) {
+    delete h;
+    return fail(nullptr, BIOT_EINVAL, "too many multigrid levels");
+  }
+  h->col = size_t(h->nn) * h->D1;
+  h->ncmax = o.schedule == BIOT_SCHED_WAVEFRONT
+                 ? std::max(o.depth, 1)
+                 : (o.max_batch > 0 ? std::min<int>(o.max_batch, n_steps) : n_steps);
+  h->chA.resize(h->nlev);
+  h->chS.resize(h->nlev);
+  for (int l = 0; l + 1 < h->nlev; ++l) {
+    h->chA[l] = cheb_of(h->P.levels[l].lmaxA, o.cheb_ratio);
+    h->chS[l] = cheb_of(h->P.levels[l].lmaxS, o.cheb_ratio);
+  }
+  plan(h, nullptr);
+  *out = h;
+  return BIOT_OK;
+}
+
+int biot_workspace_size(const biot_handle* h, uint64_t* bytes) {
+  if (!h || !bytes) return BIOT_EINVAL;
+  *bytes = h->ws_need;
+  return BIOT_OK;
+}
+
+int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
+  if (!h) return BIOT_EINVAL;
+  if (!device_ptr) return fail(h, BIOT_EINVAL, "device_ptr is NULL");
+  if (reinterpret_cast<uintptr_t>(device_ptr) % 256 != 0)
+    return fail(h, BIOT_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < h->ws_need) return fail(h, BIOT_ENOMEM, "workspace smaller than biot_workspace_size");
+  h->ws = static_cast<char*>(device_ptr);
+  h->st = static_cast<hipStream_t>(stream);
+  plan(h, h->ws);
+  build_tables(h);
+  hipStream_t st = h->st;
+  for (int l = 0; l < h->nlev; ++l) {
+    const HostLevel& H = h->P.levels[l];
+    const LevelDev& D = h->L[l];
+    HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(D.nbr), H.nbr.data(), H.nbr.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.A), H.A.data(), H.A.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.S), H.S.data(), H.S.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.Ainv), H.Ainv.data(), H.Ainv.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.Sinv), H.Sinv.data(), H.Sinv.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<uint8_t*>(D.fixed), H.fixed.data(), H.fixed.size(), hipMemcpyHostToDevice, st));
+  }
+  const HostLevel& H0 = h->P.levels[0];
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.B), H0.B.data(), H0.B.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.Bt), H0.Bt.data(), H0.Bt.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.Cb), H0.Cb.data(), H0.Cb.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.F), h->P.F.data(), h->P.F.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(h->coarseA, h->P.coarseAinv.data(), h->P.coarseAinv.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(h, hipMemcpyAsync(h->coarseS, h->P.coarseSinv.data(), h->P.coarseSinv.size() * 8, hipMemcpyHostToDevice, st));
+  for (int c = 0; c < 2; ++c) {
+    HIPCHK(h, hipMemcpyAsync(h->desc_jac[c], h->h_jac[c].data(), h->h_jac[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(h->desc_k4[c], h->h_k4[c].data(), h->h_k4[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
+    if (h->desc_wave[c])
+      HIPCHK(h, hipMemcpyAsync(h->desc_wave[c], h->h_wave[c].data(), h->h_wave[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
+  }
+  const size_t traj = size_t(h->N + 1) * h->col * 8;
+  HIPCHK(h, hipMemsetAsync(h->T[0], 0, traj, st));
+  HIPCHK(h, hipMemsetAsync(h->T[1], 0, traj, st));
+  if (h->slots) HIPCHK(h, hipMemsetAsync(h->slots, 0, size_t(2) * h->opt.depth * h->col * 8, st));
+  HIPCHK(h, hipStreamSynchronize(st));  // host sources must outlive the copies
+  h->cur = 0;
+  h->bound = true;
+  return BIOT_OK;
+}
+
+int biot_reset(biot_handle* h) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  const size_t traj = size_t(h->N + 1) * h->col * 8;
+  HIPCHK(h, hipMemsetAsync(h->T[0], 0, traj, h->st));
+  HIPCHK(h, hipMemsetAsync(h->T[1], 0, traj, h->st));
+  h->cur = 0;
+  return BIOT_OK;
+}
+
+int biot_sweep(biot_handle* h, int32_t n_sweeps) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (n_sweeps < 0) return fail(h, BIOT_EINVAL, "n_sweeps < 0");
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) {
+    if (n_sweeps % h->opt.depth != 0) return fail(h, BIOT_EINVAL, "wavefront: n_sweeps must be a multiple of depth");
+    for (int p = 0; p < n_sweeps / h->opt.depth; ++p)
+      if ((rc = wavefront_pass(h))) return rc;
+  } else {
+    for (int s = 0; s < n_sweeps; ++s)
+      if ((rc = jacobi_sweep(h))) return rc;
+  }
+  return BIOT_OK;
+}
+
+int biot_residual_norms(biot_handle* h, double* norms) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!norms) return fail(h, BIOT_EINVAL, "norms is NULL");
+  if ((rc = global_residual(h))) return rc;
+  HIPCHK(h, hipMemcpyAsync(norms, h->norms, size_t(h->N) * 4 * 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return BIOT_OK;
+}
+
+int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t check_every,
+                      biot_stats* stats) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!(rtol > 0) || max_sweeps < 0 || check_every < 1)
+    return fail(h, BIOT_EINVAL, "need rtol > 0, max_sweeps >= 0, check_every >= 1");
+  auto t0 = std::chrono::steady_clock::now();
+  int step = check_every;
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
+    step = ((check_every + h->opt.depth - 1) / h->opt.depth) * h->opt.depth;
+  std::vector<double> nr(size_t(h->N) * 4);
+  int done = 0;
+  double ru = 0, rp = 0;
+  bool conv = false;
+  double first = -1;
+  while (true) {
+    if ((rc = global_residual(h))) return rc;
+    HIPCHK(h, hipMemcpyAsync(nr.data(), h->norms, nr.size() * 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    rel_resid(nr, h->N, ru, rp);
+    if (!std::isfinite(ru) || !std::isfinite(rp)) {
+      rc = fail(h, BIOT_EDIVERGED, "non-finite residual");
+      break;
+    }
+    const double worst = std::max(ru, rp);
+    if (first < 0) first = worst;
+    if (worst <= rtol) {
+      conv = true;
+      break;
+    }
+    if (done > 0 && worst > 1e6 * std::max(first, 1e-300)) {
+      rc = fail(h, BIOT_EDIVERGED, "residual grew by more than 1e6");
+      break;
+    }
+    if (done >= max_sweeps) {
+      rc = fail(h, BIOT_ENOTCONVERGED, "max_sweeps reached above tolerance");
+      break;
+    }
+    const int k = std::min(step, max_sweeps - done);
+    const int kk = h->opt.schedule == BIOT_SCHED_WAVEFRONT ? ((k + h->opt.depth - 1) / h->opt.depth) * h->opt.depth : k;
+    int r2 = biot_sweep(h, kk);
+    if (r2) return r2;
+    done += kk;
+  }
+  if (stats) {
+    stats->sweeps = done;
+    stats->converged = conv ? 1 : 0;
+    stats->rel_resid_u = ru;
+    stats->rel_resid_p = rp;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return rc;
+}
+
+int biot_get_trajectory(biot_handle* h, int32_t n0, int32_t n1, double* dst, int32_t dst_on_device) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!dst || n0 < 0 || n1 > h->N + 1 || n0 > n1) return fail(h, BIOT_EINVAL, "bad range or NULL dst");
+  const size_t bytes = size_t(n1 - n0) * h->col * 8;
+  HIPCHK(h, hipMemcpyAsync(dst, h->T[h->cur] + size_t(n0) * h->col, bytes,
+                           dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
+  if (!dst_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
+  return BIOT_OK;
+}
+
+int biot_set_trajectory(biot_handle* h, int32_t n0, int32_t n1, const double* src, int32_t src_on_device) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!src || n0 < 0 || n1 > h->N + 1 || n0 > n1) return fail(h, BIOT_EINVAL, "bad range or NULL src");
+  const size_t bytes = size_t(n1 - n0) * h->col * 8;
+  for (int c = 0; c < 2; ++c)  // both buffers: X^0 must be the same in either
+    HIPCHK(h, hipMemcpyAsync(h->T[c] + size_t(n0) * h->col, src, bytes,
+                             src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
+  if (!src_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
+  return BIOT_OK;
+}
+
+int biot_apply_operator(biot_handle* h, const double* X, double* Y, int32_t ncols) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!X || !Y || ncols < 0) return fail(h, BIOT_EINVAL, "bad arguments");
+  if (ncols == 0) return BIOT_OK;
+  launch_apply_operator(h->dim, h->L[0], h->F, X, Y, ncols, h->st);
+  LAUNCHCHK(h);
+  return BIOT_OK;
+}
+
+int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!R || !Z || ncols < 0) return fail(h, BIOT_EINVAL, "bad arguments");
+  const bool sm = level0_smoothed(h);
+  for (int c0 = 0; c0 < ncols; c0 += h->ncmax) {
+    const int nc = std::min(h->ncmax, ncols - c0);
+    launch_unpack(h->dim, h->nn, R + size_t(c0) * h->col, h->fa.b[0], h->rp, nc, h->st);
+    LAUNCHCHK(h);
+    if (sm) {
+      launch_pre1(h->dim, h->L[0], true, h->fa.b[0], h->fa.x0[0], h->fa.d[0], 1.0 / h->chA[0].theta, nc, h->st);
+      LAUNCHCHK(h);
+    }
+    double *zu = nullptr, *zp = nullptr;
+    if ((rc = precond_batch(h, nc, &zu, &zp))) return rc;
+    launch_pack(h->dim, h->nn, zu, zp, Z + size_t(c0) * h->col, nc, h->st);
+    LAUNCHCHK(h);
+  }
+  return BIOT_OK;
+}
+
+int biot_get_info(const biot_handle* h, biot_info_t* info) {
+  if (!h || !info) return BIOT_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->dim = h->dim;
+  info->n_nodes = h->nn;
+  info->n_steps = h->N;
+  info->n_levels = h->nlev;
+  for (int l = 0; l < h->nlev && l < 16; ++l) {
+    info->level_cells[l] = h->P.levels[l].n_cells;
+    info->level_nodes[l] = h->P.levels[l].nn;
+    info->lmax_A[l] = h->P.levels[l].lmaxA;
+    info->lmax_S[l] = h->P.levels[l].lmaxS;
+  }
+  info->slots = h->P.levels[0].W;
+  info->workspace_bytes = h->ws_need;
+  return BIOT_OK;
+}
+
+int biot_export_level(const biot_handle* h, int32_t level, int32_t* nbr, double* A, double* S,
+                      double* B, double* Bt, double* Cb, double* F) {
+  if (!h || level < 0 || level >= h->nlev) return BIOT_EINVAL;
+  const HostLevel& H = h->P.levels[level];
+  if (nbr) std::memcpy(nbr, H.nbr.data(), H.nbr.size() * sizeof(int32_t));
+  if (A) std::memcpy(A, H.A.data(), H.A.size() * sizeof(double));
+  if (S) std::memcpy(S, H.S.data(), H.S.size() * sizeof(double));
+  if (level == 0) {
+    if (B) std::memcpy(B, H.B.data(), H.B.size() * sizeof(double));
+    if (Bt) std::memcpy(Bt, H.Bt.data(), H.Bt.size() * sizeof(double));
+    if (Cb) std::memcpy(Cb, H.Cb.data(), H.Cb.size() * sizeof(double));
+    if (F) std::memcpy(F, h->P.F.data(), h->P.F.size() * sizeof(double));
+  }
+  return BIOT_OK;
+}
+
+const char* biot_last_error(const biot_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+const char* biot_version(void) { return "biot_pint 0.1 (gfx950, FP64)"; }
+
+void biot_destroy(biot_handle* h) { delete h; }
+
+}  // extern "C"

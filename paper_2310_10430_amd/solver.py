@@ -1,0 +1,180 @@
+"""Python front end of the HIP library: argument marshalling and device memory.
+
+Every step of the solver runs in the HIP kernels of libbiot_pint.so; this module
+only converts a `workloads.Problem` into the C structures, allocates the device
+workspace as a torch tensor and passes torch's current stream.  It raises if the
+library is not built; there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
+                  cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None):
+    """biot_create on the host (no device work); returns (handle, options)."""
+    lib = _lib.load()
+    xyz = np.ascontiguousarray(problem.xyz, dtype=np.float64)
+    conn = np.ascontiguousarray(problem.conn, dtype=np.int32)
+    flags = np.ascontiguousarray(problem.flags, dtype=np.uint8)
+    young = np.ascontiguousarray(problem.young, dtype=np.float64)
+    pois = np.ascontiguousarray(problem.poisson, dtype=np.float64)
+    perm = np.ascontiguousarray(problem.perm, dtype=np.float64)
+    beta_a = None if beta is None else np.ascontiguousarray(beta, dtype=np.float64)
+    facets = np.ascontiguousarray(problem.facets, dtype=np.int32)
+    tr = np.ascontiguousarray(problem.traction, dtype=np.float64)
+    coef = np.ascontiguousarray(problem.load_coef, dtype=np.float64)
+    mesh = _lib.Mesh(problem.dim, problem.n_nodes, problem.n_elems, problem.grid_n,
+                     _lib.dptr(xyz), _lib.iptr(conn), _lib.uptr(flags))
+    mat = _lib.Materials(_lib.dptr(young), _lib.dptr(pois), _lib.dptr(perm),
+                         _lib.dptr(beta_a), float(problem.alpha), float(problem.stab_h))
+    load = _lib.Load(facets.shape[0], _lib.iptr(facets) if facets.size else None,
+                     _lib.dptr(tr) if tr.size else None, _lib.dptr(coef))
+    opt = _lib.Options()
+    lib.biot_default_options(C.byref(opt))
+    opt.schedule = _lib.SCHED[schedule]
+    opt.depth = depth
+    opt.precond = _lib.PRECOND[precond]
+    opt.cheb_degree = cheb_degree
+    opt.cheb_ratio = cheb_ratio
+    opt.lmax_safety = lmax_safety
+    opt.power_iters = power_iters
+    opt.max_batch = max_batch
+    opt.omega = omega
+    h = C.c_void_p()
+    _lib.check(lib, lib.biot_create(C.byref(mesh), C.byref(mat), C.byref(load),
+                                    float(problem.dt), problem.n_steps, C.byref(opt),
+                                    C.byref(h)), None)
+    return h, opt
+
+
+def handle_info(lib, h) -> dict:
+    inf = _lib.Info()
+    _lib.check(lib, lib.biot_get_info(h, C.byref(inf)), h)
+    L = inf.n_levels
+    return dict(dim=inf.dim, n_nodes=inf.n_nodes, n_steps=inf.n_steps, n_levels=L,
+                level_cells=list(inf.level_cells[:L]), level_nodes=list(inf.level_nodes[:L]),
+                slots=inf.slots, lmax_A=list(inf.lmax_A[:L]), lmax_S=list(inf.lmax_S[:L]),
+                workspace_bytes=int(inf.workspace_bytes))
+
+
+def export_level(lib, h, level: int) -> dict:
+    """Host copies of a level's node-blocked operators (see biot_export_level)."""
+    info = handle_info(lib, h)
+    nn = info["level_nodes"][level]
+    W = info["slots"]
+    d = info["dim"]
+    out = dict(nbr=np.zeros((W, nn), np.int32), A=np.zeros((W, d * d, nn)), S=np.zeros((W, nn)))
+    ptr = lambda a: C.c_void_p(a.ctypes.data)
+    if level == 0:
+        out.update(B=np.zeros((W, d, nn)), Bt=np.zeros((W, d, nn)), Cb=np.zeros((W, nn)),
+                   F=np.zeros((nn, d + 1)))
+        args = [ptr(out[k]) for k in ("nbr", "A", "S", "B", "Bt", "Cb", "F")]
+    else:
+        args = [ptr(out[k]) for k in ("nbr", "A", "S")] + [None] * 4
+    _lib.check(lib, lib.biot_export_level(h, level, *args), h)
+    return out
+
+
+class BiotSolver:
+    """Handle on one Biot problem bound to a GPU workspace."""
+
+    def __init__(self, problem, schedule: str = "jacobi", depth: int = 8, precond: str = "P1",
+                 omega: float = 0.6, cheb_degree: int = 2, cheb_ratio: float = 4.0,
+                 lmax_safety: float = 1.1, power_iters: int = 20, max_batch: int = 0,
+                 device: str = "cuda:0", beta=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("BiotSolver needs a ROCm GPU (torch.cuda is not available)")
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        h, opt = create_handle(problem, schedule=schedule, depth=depth, precond=precond,
+                               omega=omega, cheb_degree=cheb_degree, cheb_ratio=cheb_ratio,
+                               lmax_safety=lmax_safety, power_iters=power_iters,
+                               max_batch=max_batch, beta=beta)
+        self.problem = problem
+        self.dim = problem.dim
+        self.n_nodes = problem.n_nodes
+        self.n_steps = problem.n_steps
+        self.options = opt
+        lib = self.lib
+        self.h = h
+        nbytes = C.c_uint64()
+        self._check(lib.biot_workspace_size(h, C.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._check(lib.biot_bind(h, C.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
+                                  C.c_void_p(self.stream.cuda_stream)))
+
+    # ------------------------------------------------------------------
+    def _check(self, rc):
+        return _lib.check(self.lib, rc, self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.biot_destroy(self.h)
+            self.h = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def reset(self):
+        self._check(self.lib.biot_reset(self.h))
+
+    def sweep(self, n: int = 1):
+        self._check(self.lib.biot_sweep(self.h, int(n)))
+
+    def residual_norms(self) -> np.ndarray:
+        out = np.zeros((self.n_steps, 4))
+        self._check(self.lib.biot_residual_norms(self.h, _lib.dptr(out)))
+        return out
+
+    def solve_to_tol(self, rtol: float, max_sweeps: int = 1000, check_every: int = 4,
+                     raise_on_failure: bool = True) -> dict:
+        st = _lib.Stats()
+        rc = self.lib.biot_solve_to_tol(self.h, float(rtol), int(max_sweeps), int(check_every),
+                                        C.byref(st))
+        if rc != 0 and raise_on_failure:
+            self._check(rc)
+        return dict(sweeps=st.sweeps, converged=bool(st.converged), rel_resid_u=st.rel_resid_u,
+                    rel_resid_p=st.rel_resid_p, seconds=st.seconds, rc=rc)
+
+    def trajectory(self, n0: int = 0, n1: int | None = None) -> torch.Tensor:
+        n1 = self.n_steps + 1 if n1 is None else n1
+        out = torch.empty((n1 - n0, self.n_nodes, self.dim + 1), dtype=torch.float64,
+                          device=self.device)
+        self._check(self.lib.biot_get_trajectory(self.h, n0, n1, C.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def set_trajectory(self, X: torch.Tensor, n0: int = 0):
+        X = X.to(self.device, torch.float64).contiguous()
+        self._check(self.lib.biot_set_trajectory(self.h, n0, n0 + X.shape[0],
+                                                 C.c_void_p(X.data_ptr()), 1))
+
+    def apply_operator(self, X: torch.Tensor) -> torch.Tensor:
+        X = X.to(self.device, torch.float64).contiguous()
+        Y = torch.empty_like(X)
+        self._check(self.lib.biot_apply_operator(self.h, C.c_void_p(X.data_ptr()),
+                                                 C.c_void_p(Y.data_ptr()), X.shape[0]))
+        return Y
+
+    def apply_precond(self, R: torch.Tensor) -> torch.Tensor:
+        R = R.to(self.device, torch.float64).contiguous()
+        Z = torch.empty_like(R)
+        self._check(self.lib.biot_apply_precond(self.h, C.c_void_p(R.data_ptr()),
+                                                C.c_void_p(Z.data_ptr()), R.shape[0]))
+        return Z
+
+    def info(self) -> dict:
+        return handle_info(self.lib, self.h)

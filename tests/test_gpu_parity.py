@@ -1,0 +1,167 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Element-by-element comparisons on seeded inputs (node-major device layout vs
+the oracle's field-major vectors), at sizes that span several node blocks and
+column tiles with ragged tails:
+  * the step operator AA;
+  * one application of the block preconditioner P1/P2 with multigrid inner
+    solves (oracle.precond, oracle.gmg);
+  * one Jacobi-order sweep and one wavefront pass (oracle.inverted);
+  * the space-time residual norms;
+and the converged solve against sequential backward Euler (<= 1e-8 per field).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2310_10430_amd import workloads as W
+from oracle import fem, inverted, precond, sequential as seq
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a ROCm GPU", allow_module_level=True)
+
+from paper_2310_10430_amd.solver import BiotSolver  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _nm(X, orc):
+    return fem.field_to_node_major(X, orc.n_nodes, orc.dim)
+
+
+def _fm(Y):
+    return fem.node_to_field_major(Y)
+
+
+def _random_state(orc, ncols, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((ncols, orc.n_dof))
+    X[:, orc.fixed] = 0.0
+    # scale the fields like a physical state (u ~ 1e-4, p ~ 1)
+    X[:, : orc.nU] *= 1e-4
+    return X
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("n,dim", [(20, 2), (6, 3)])
+def test_step_operator(n, dim):
+    pb = W.heterogeneous_problem(n, 3) if dim == 2 else W.terzaghi_problem(n, 3, dim=3)
+    orc = seq.BiotOracle(pb)
+    X = _random_state(orc, 5, 1)
+    s = BiotSolver(pb)
+    Y = s.apply_operator(torch.from_numpy(_nm(X, orc))).cpu().numpy()
+    s.close()
+    Yo = (orc.AA @ X.T).T
+    Yo[:, orc.fixed] = 0.0
+    assert _rel(_fm(Y), Yo) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["P1", "P2"])
+@pytest.mark.parametrize("n", [16, 24])
+def test_block_preconditioner(kind, n):
+    pb = W.heterogeneous_problem(n, 3)
+    orc = seq.BiotOracle(pb)
+    P = precond.BlockPreconditioner(orc, kind, "gmg")
+    R = _random_state(orc, 7, 2)
+    R[:, orc.nU:] *= 1e-6
+    s = BiotSolver(pb, precond=kind, max_batch=5)     # ragged batches of 5 + 2
+    Z = _fm(s.apply_precond(torch.from_numpy(_nm(R, orc))).cpu().numpy())
+    s.close()
+    for c in range(R.shape[0]):
+        Zo = P.apply(R[c])
+        assert _rel(Z[c, : orc.nU], Zo[: orc.nU]) < 1e-11
+        assert _rel(Z[c, orc.nU:], Zo[orc.nU:]) < 1e-11
+
+
+def test_jacobi_sweep_matches_oracle():
+    pb = W.heterogeneous_problem(16, 9)
+    orc = seq.BiotOracle(pb)
+    P = precond.BlockPreconditioner(orc, "P1", "gmg")
+    X = _random_state(orc, pb.n_steps + 1, 3)
+    X[0] = 0.0
+    s = BiotSolver(pb, schedule="jacobi", omega=0.55, max_batch=4)
+    s.set_trajectory(torch.from_numpy(_nm(X, orc)))
+    s.sweep(2)
+    Xg = _fm(s.trajectory().cpu().numpy())
+    s.close()
+    Xo = X
+    for _ in range(2):
+        Xo, _ = inverted.sweep(orc, Xo, P, 0.55, "jacobi")
+    assert _rel(Xg[:, : orc.nU], Xo[:, : orc.nU]) < 1e-11
+    assert _rel(Xg[:, orc.nU:], Xo[:, orc.nU:]) < 1e-11
+
+
+@pytest.mark.parametrize("depth", [1, 3])
+def test_wavefront_pass_matches_oracle(depth):
+    pb = W.heterogeneous_problem(16, 7)
+    orc = seq.BiotOracle(pb)
+    P = precond.BlockPreconditioner(orc, "P1", "gmg")
+    X = _random_state(orc, pb.n_steps + 1, 4)
+    X[0] = 0.0
+    s = BiotSolver(pb, schedule="wavefront", depth=depth, omega=0.6)
+    s.set_trajectory(torch.from_numpy(_nm(X, orc)))
+    s.sweep(2 * depth)
+    Xg = _fm(s.trajectory().cpu().numpy())
+    s.close()
+    Xo = inverted.wavefront(orc, X, P, 0.6, depth)
+    Xo = inverted.wavefront(orc, Xo, P, 0.6, depth)
+    assert _rel(Xg[:, : orc.nU], Xo[:, : orc.nU]) < 1e-11
+    assert _rel(Xg[:, orc.nU:], Xo[:, orc.nU:]) < 1e-11
+
+
+def test_residual_norms_match_oracle():
+    pb = W.heterogeneous_problem(16, 6)
+    orc = seq.BiotOracle(pb)
+    X = _random_state(orc, pb.n_steps + 1, 5)
+    X[0] = 0.0
+    s = BiotSolver(pb)
+    s.set_trajectory(torch.from_numpy(_nm(X, orc)))
+    nr = s.residual_norms()
+    s.close()
+    for n in range(1, pb.n_steps + 1):
+        b, r = inverted.step_residual(orc, n, X[n - 1], X[n])
+        ref = inverted.norms(orc, b, r)
+        assert np.allclose(nr[n - 1], ref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("schedule,depth", [("jacobi", 1), ("wavefront", 4)])
+def test_small_terzaghi_solve_reaches_backward_euler(schedule, depth):
+    pb = W.small_terzaghi()
+    orc = seq.BiotOracle(pb)
+    Xs = orc.solve_sequential()
+    s = BiotSolver(pb, schedule=schedule, depth=depth, omega=0.6)
+    st = s.solve_to_tol(1e-11, max_sweeps=400, check_every=4)
+    Xg = _fm(s.trajectory().cpu().numpy())
+    s.close()
+    assert st["converged"]
+    err = seq.relative_field_errors(Xg, Xs, orc.n_nodes, orc.dim)
+    assert err["u"] < 1e-8 and err["p"] < 1e-8, (err, st)
+
+
+def test_sweeps_are_deterministic_and_resumable():
+    pb = W.heterogeneous_problem(16, 8)
+    s = BiotSolver(pb, omega=0.6)
+    s.sweep(6)
+    A = s.trajectory().clone()
+    s.reset()
+    s.sweep(3)
+    mid = s.trajectory().clone()
+    s.reset()
+    s.set_trajectory(mid)
+    s.sweep(3)
+    B = s.trajectory().clone()
+    s.close()
+    assert torch.equal(A, B)
+
+
+def test_wavefront_rejects_partial_pass():
+    pb = W.terzaghi_problem(8, 5)
+    s = BiotSolver(pb, schedule="wavefront", depth=3)
+    with pytest.raises(RuntimeError):
+        s.sweep(2)
+    s.close()

@@ -1,0 +1,155 @@
+"""CPU checks of the HIP library's host side (no GPU needed).
+
+* libbiot_pint.so loads and exports every function include/biot_pint.h declares;
+* the library's own FP64 assembly (C++) equals the oracle's independent numpy
+  assembly, operator by operator, after the boundary conditions;
+* its Galerkin multigrid hierarchy and spectral bounds equal the oracle's;
+* malformed input is rejected with an error code and a message.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2310_10430_amd import _lib, workloads as W
+from paper_2310_10430_amd import solver as S
+from oracle import fem, gmg, precond, sequential as seq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "biot_pint.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(biot_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_declared_symbols():
+    lib = _lib.load()
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+    assert b"gfx950" in lib.biot_version()
+
+
+def _to_csr(nbr, vals, comps_r, comps_c):
+    """node-blocked [W][comps_r*comps_c][nn] -> scipy CSR over node-major dofs."""
+    W, nn = nbr.shape
+    rows, cols, data = [], [], []
+    v = vals.reshape(W, comps_r, comps_c, nn)
+    for s in range(W):
+        for a in range(comps_r):
+            for b in range(comps_c):
+                rows.append(np.arange(nn) * comps_r + a)
+                cols.append(nbr[s] * comps_c + b)
+                data.append(v[s, a, b])
+    M = sp.coo_matrix((np.concatenate(data), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(nn * comps_r, nn * comps_c)).tocsr()
+    M.eliminate_zeros()
+    return M
+
+
+def _oracle_fixed_ops(pb):
+    orc = seq.BiotOracle(pb)
+    P = precond.BlockPreconditioner(orc, "P1", "gmg")
+    a = orc.asm
+    nU = orc.nU
+    fu, fp = orc.fixed[:nU], orc.fixed[nU:]
+    ku = sp.diags((~fu).astype(float))
+    kp = sp.diags((~fp).astype(float))
+    return orc, P, dict(A=P.A, S=P.S, B=(ku @ a.B @ kp).tocsr(), Bt=P.Bt,
+                        Cb=(kp @ a.Cb @ kp).tocsr(), F=fem.traction_load(pb) * (~fu))
+
+
+@pytest.mark.parametrize("which", ["terzaghi", "hetero", "3d"])
+def test_host_assembly_matches_oracle(which):
+    if which == "terzaghi":
+        pb = W.terzaghi_problem(8, 4)
+    elif which == "hetero":
+        pb = W.heterogeneous_problem(16, 4)
+    else:
+        pb = W.terzaghi_problem(4, 3, dim=3)
+    lib = _lib.load()
+    h, _ = S.create_handle(pb)
+    try:
+        ex = S.export_level(lib, h, 0)
+    finally:
+        lib.biot_destroy(h)
+    d = pb.dim
+    orc, P, ref = _oracle_fixed_ops(pb)
+    got = dict(A=_to_csr(ex["nbr"], ex["A"], d, d), S=_to_csr(ex["nbr"], ex["S"], 1, 1),
+               B=_to_csr(ex["nbr"], ex["B"], d, 1), Bt=_to_csr(ex["nbr"], ex["Bt"], 1, d),
+               Cb=_to_csr(ex["nbr"], ex["Cb"], 1, 1))
+    for k in got:
+        scale = abs(ref[k]).max()
+        assert abs(got[k] - ref[k]).max() <= 1e-13 * scale, k
+    F = ex["F"]
+    assert np.abs(F[:, :d].ravel() - ref["F"]).max() < 1e-15
+    assert np.all(F[:, d] == 0)
+
+
+def test_host_hierarchy_and_bounds_match_oracle():
+    pb = W.heterogeneous_problem(16, 4)
+    lib = _lib.load()
+    h, _ = S.create_handle(pb)
+    try:
+        info = S.handle_info(lib, h)
+        levels = [S.export_level(lib, h, l) for l in range(info["n_levels"])]
+    finally:
+        lib.biot_destroy(h)
+    orc, P, ref = _oracle_fixed_ops(pb)
+    assert info["level_cells"] == [lev.n for lev in P.HA.levels] == [16, 8, 4, 2]
+    for l, ex in enumerate(levels):
+        A = _to_csr(ex["nbr"], ex["A"], 2, 2)
+        Sm = _to_csr(ex["nbr"], ex["S"], 1, 1)
+        assert abs(A - P.HA.levels[l].K).max() <= 1e-12 * abs(P.HA.levels[l].K).max()
+        assert abs(Sm - P.HS.levels[l].K).max() <= 1e-12 * abs(P.HS.levels[l].K).max()
+    for l in range(info["n_levels"] - 1):
+        assert abs(info["lmax_A"][l] / P.HA.levels[l].lmax - 1) < 1e-12
+        assert abs(info["lmax_S"][l] / P.HS.levels[l].lmax - 1) < 1e-12
+
+
+def test_uneven_grid_coarsens_to_odd_size():
+    pb = W.terzaghi_problem(24, 2)
+    lib = _lib.load()
+    h, _ = S.create_handle(pb)
+    try:
+        assert S.handle_info(lib, h)["level_cells"] == [24, 12, 6, 3]
+    finally:
+        lib.biot_destroy(h)
+
+
+def test_create_rejects_bad_input():
+    pb = W.terzaghi_problem(4, 2)
+    pb.conn = pb.conn[:, [0, 2, 1]].copy()          # inverted triangles
+    with pytest.raises(_lib.BiotError) as e:
+        S.create_handle(pb)
+    assert "inverted" in str(e.value)
+    pb = W.terzaghi_problem(4, 2)
+    pb.young[3] = -1.0
+    with pytest.raises(_lib.BiotError):
+        S.create_handle(pb)
+    pb = W.terzaghi_problem(4, 2)
+    pb.xyz = pb.xyz * 1.5
+    with pytest.raises(_lib.BiotError) as e:
+        S.create_handle(pb)
+    assert "structured" in str(e.value)
+    with pytest.raises(_lib.BiotError):
+        S.create_handle(W.terzaghi_problem(4, 2), omega=-1.0)
+
+
+def test_unbound_handle_refuses_device_calls():
+    lib = _lib.load()
+    h, _ = S.create_handle(W.terzaghi_problem(4, 2))
+    try:
+        assert lib.biot_sweep(h, 1) == -6
+        assert b"not bound" in lib.biot_last_error(h)
+        nbytes = C.c_uint64()
+        assert lib.biot_workspace_size(h, C.byref(nbytes)) == 0 and nbytes.value > 0
+    finally:
+        lib.biot_destroy(h)
