@@ -103,12 +103,13 @@ typedef struct {
   int32_t schedule;     /* BIOT_SCHED_*  (default JACOBI)                          */
   int32_t depth;        /* wavefront: sweeps per pass = iterations in flight (8)   */
   int32_t precond;      /* BIOT_PRECOND_* (default P1)                             */
-  int32_t cheb_degree;  /* Chebyshev smoother degree per smoothing call (2)        */
+  int32_t cheb_degree;  /* Chebyshev smoother degree per smoothing call, 2..8 (2)  */
   double cheb_ratio;    /* smoother interval [lmax/ratio, lmax] (4)                */
   double lmax_safety;   /* factor on the power-iteration estimate of lmax (1.1)    */
   int32_t power_iters;  /* power iterations for lmax per level (20)                */
   int32_t max_batch;    /* Jacobi: columns per launch, <= 0 for all steps (0)      */
   double omega;         /* damping of the outer update (0.6)                       */
+  int32_t col_tile;     /* time-step columns per GPU thread: 1, 2, 4 or 8 (4)      */
 } biot_options;
 
 typedef struct {
@@ -182,6 +183,21 @@ int biot_apply_operator(biot_handle* h, const double* X, double* Y, int32_t ncol
 int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols);
 
 int biot_get_info(const biot_handle* h, biot_info_t* info);
+
+/* Probes: HIP events recorded on the handle's stream around every level-0
+ * launch of the kernels below, with the algorithmic bytes each launch moves
+ * (distinct global inputs and outputs counted once).  Enabling (or disabling)
+ * clears the accumulators; reading synchronizes the stream. */
+#define BIOT_PROBE_RESIDUAL 0     /* fused residual + coupling + norms           */
+#define BIOT_PROBE_CHEB_U 1       /* displacement Chebyshev smoothing steps      */
+#define BIOT_PROBE_CHEB_P 2       /* pressure Chebyshev smoothing steps          */
+#define BIOT_PROBE_LEVRES_U 3     /* displacement residual before restriction    */
+#define BIOT_PROBE_LEVRES_P 4     /* pressure residual before restriction        */
+#define BIOT_PROBE_PSTAGE 5       /* P1 pressure stage t = B' z_u - r_p          */
+#define BIOT_PROBE_COUNT 6
+int biot_profile_enable(biot_handle* h, int32_t enable);
+int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
+                      double* total_bytes, const char** name);
 
 /* Message of the last failed call on h (or of the last failed biot_create when
  * h is NULL).  Valid until the next call on the same handle. */

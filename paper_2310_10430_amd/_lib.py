@@ -11,6 +11,7 @@ BIOT_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDIVERGED", -5: "ENOTCONVERGED", -6: "ESTATE"}
 SCHED = {"jacobi": 0, "wavefront": 1}
 PRECOND = {"P1": 1, "P2": 2}
+PROBES = ["residual", "cheb_u", "cheb_p", "levres_u", "levres_p", "pstage"]
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -35,7 +36,7 @@ class Options(C.Structure):
     _fields_ = [("schedule", C.c_int32), ("depth", C.c_int32), ("precond", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("lmax_safety", C.c_double), ("power_iters", C.c_int32),
-                ("max_batch", C.c_int32), ("omega", C.c_double)]
+                ("max_batch", C.c_int32), ("omega", C.c_double), ("col_tile", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -69,6 +70,10 @@ SIGNATURES = {
     "biot_get_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
     "biot_export_level": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "biot_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
+    "biot_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_uint64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_char_p)]),
     "biot_last_error": (C.c_char_p, [C.c_void_p]),
     "biot_version": (C.c_char_p, []),
     "biot_destroy": (None, [C.c_void_p]),

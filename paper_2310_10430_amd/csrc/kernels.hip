@@ -18,7 +18,6 @@
 namespace biot {
 namespace {
 
-constexpr int CT = 4;  // columns per thread
 
 __constant__ int c_off2[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
                                  {0, -1, 0}, {1, 1, 0}, {-1, -1, 0}};
@@ -62,7 +61,7 @@ __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
 // fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1}, norms, and the
 // first (pointwise) Chebyshev step of the displacement V-cycle
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int CTT>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
                                                      double* __restrict__ ru,
@@ -71,35 +70,40 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      double* __restrict__ d, double inv_theta,
                                                      double* __restrict__ partials, int pstride) {
   constexpr int D1 = DIM + 1;
-  __shared__ double lds[4 * 4 * CT];
+  constexpr int W = DIM == 2 ? 7 : 15;
+  __shared__ double lds[4 * 4 * CTT];
   const int nn = L.nn;
   const int v = blockIdx.y * kBlock + threadIdx.x;
-  const int c0 = blockIdx.x * CT;
+  const int c0 = blockIdx.x * CTT;
   const bool active = v < nn;
-  const double* xc[CT];
-  const double* xp[CT];
-  double coef[CT];
+  const double* xc[CTT];
+  const double* xp[CTT];
+  double coef[CTT];
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
+  for (int t = 0; t < CTT; ++t) {
     const int c = min(c0 + t, nc - 1);
     xc[t] = cols[c].xcur;
     xp[t] = cols[c].xprev;
     coef[t] = cols[c].coef;
   }
-  double au[CT][DIM], ap[CT], bp[CT];
+  double au[CTT][DIM], ap[CTT], bp[CTT];
   double Fu[DIM];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(v) * D1 + a] : 0.0;
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
+  for (int t = 0; t < CTT; ++t) {
 #pragma unroll
     for (int a = 0; a < DIM; ++a) au[t][a] = coef[t] * Fu[a];
     ap[t] = 0.0;
     bp[t] = 0.0;
   }
   if (active) {
-    for (int s = 0; s < L.W; ++s) {
-      const int w = L.nbr[size_t(s) * nn + v];
+    int nb[W];
+#pragma unroll
+    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      const int w = nb[s];
       double Ab[DIM * DIM], Bb[DIM], Btb[DIM];
 #pragma unroll
       for (int e = 0; e < DIM * DIM; ++e) Ab[e] = L.A[(size_t(s) * DIM * DIM + e) * nn + v];
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
       const double Sv = L.S[size_t(s) * nn + v];
       const double Cbv = F.Cb[size_t(s) * nn + v];
 #pragma unroll
-      for (int t = 0; t < CT; ++t) {
+      for (int t = 0; t < CTT; ++t) {
         double xw[D1], xpw[D1];
 #pragma unroll
         for (int k = 0; k < D1; ++k) {
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
       for (int e = 0; e < DIM * DIM; ++e) Di[e] = L.Ainv[size_t(e) * nn + v];
     }
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
+    for (int t = 0; t < CTT; ++t) {
       if (c0 + t >= nc) break;
       const size_t cu = size_t(c0 + t) * nn * DIM;
       if (ru) {
@@ -164,9 +168,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
     }
   }
   if (partials) {
-    double q[4 * CT];
+    double q[4 * CTT];
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
+    for (int t = 0; t < CTT; ++t) {
       double su = 0.0, sb = 0.0;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
@@ -179,10 +183,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
       q[4 * t + 2] = active ? sb : 0.0;
       q[4 * t + 3] = active ? bp[t] * bp[t] : 0.0;
     }
-    block_sum<4 * CT>(q, lds);
+    block_sum<4 * CTT>(q, lds);
     if (threadIdx.x == 0)
 #pragma unroll
-      for (int t = 0; t < CT; ++t) {
+      for (int t = 0; t < CTT; ++t) {
         if (c0 + t >= nc) break;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -192,38 +196,93 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
 }
 
 // ---------------------------------------------------------------------------
-// Chebyshev step on one level:  d <- c1 d + c2 D^{-1}(b - K xin);  xout = xin + d
+// Prolongation weights of fine node f: parents p0, p1 on the coarse grid and the
+// per-component weights (zero where the fine or the coarse dof is prescribed).
 // ---------------------------------------------------------------------------
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, int isA, const double* __restrict__ b,
+template <int DIM, int C>
+__device__ inline void prolong_weights(const LevelDev& Lf, const LevelDev& Lc, int bit0, int f,
+                                       int& p0, int& p1, double (&w0)[C], double (&w1)[C]) {
+  const int mf = Lf.n_cells + 1, mc = Lc.n_cells + 1;
+  int i, j, k;
+  node_coords<DIM>(f, mf, i, j, k);
+  const int ai = i >> 1, aj = j >> 1, ak = k >> 1;
+  const int oi = i & 1, oj = j & 1, ok = k & 1;
+  const bool two = (oi | oj | ok) != 0;
+  p0 = node_id<DIM>(ai, aj, ak, mc);
+  p1 = two ? node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
+  const double wgt = two ? 0.5 : 1.0;
+  const unsigned ff = Lf.fixed[f], f0 = Lc.fixed[p0], f1 = Lc.fixed[p1];
+#pragma unroll
+  for (int a = 0; a < C; ++a) {
+    const bool fm = !((ff >> (bit0 + a)) & 1u);
+    w0[a] = (fm && !((f0 >> (bit0 + a)) & 1u)) ? wgt : 0.0;
+    w1[a] = (two && fm && !((f1 >> (bit0 + a)) & 1u)) ? wgt : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev step on one level, for CTT columns per thread:
+//     x  = xin               (PRO: x = xin + P xc, the coarse correction fused in)
+//     d <- c1 d + c2 D^{-1}(b - K x);   xout = x + d
+// UPD (pressure field, level 0, last step): instead of xout, writes the outer
+// update X^{n,m} = X^{n,m-1} + omega [z_u; x + d] through the column descriptors.
+// ---------------------------------------------------------------------------
+template <int DIM, int C, int CTT, bool PRO, bool UPD, bool FINE>
+__global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int isA,
+                                                 const double* __restrict__ b,
                                                  const double* __restrict__ xin,
+                                                 const double* __restrict__ xc,
                                                  double* __restrict__ xout, double* __restrict__ d,
-                                                 int nc, double c1, double c2) {
+                                                 int nc, double c1, double c2,
+                                                 const ColDesc* __restrict__ cols,
+                                                 const double* __restrict__ zu, double omega) {
+  constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= nn) return;
-  const int c0 = blockIdx.x * CT;
+  const int c0 = blockIdx.x * CTT;
   const double* K = isA ? L.A : L.S;
   const double* Dg = isA ? L.Ainv : L.Sinv;
+  const int bit0 = isA ? 0 : DIM;
   const size_t stride = size_t(nn) * C;
-  double acc[CT][C];
+  const size_t cstride = PRO ? size_t(Lc.nn) * C : 0;
+  size_t cb[CTT], cbc[CTT];
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
-    const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(v) * C;
-#pragma unroll
-    for (int a = 0; a < C; ++a) acc[t][a] = b[base + a];
+  for (int t = 0; t < CTT; ++t) {
+    const int c = min(c0 + t, nc - 1);
+    cb[t] = size_t(c) * stride;
+    cbc[t] = size_t(c) * cstride;
   }
-  for (int s = 0; s < L.W; ++s) {
-    const int w = L.nbr[size_t(s) * nn + v];
+  int nb[W];
+#pragma unroll
+  for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+  double acc[CTT][C];
+#pragma unroll
+  for (int t = 0; t < CTT; ++t)
+#pragma unroll
+    for (int a = 0; a < C; ++a) acc[t][a] = b[cb[t] + size_t(v) * C + a];
+  double xself[CTT][C];
+#pragma unroll
+  for (int s = 0; s < W; ++s) {
+    const int w = nb[s];
     double blk[C * C];
 #pragma unroll
     for (int e = 0; e < C * C; ++e) blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+    int p0 = 0, p1 = 0;
+    double w0[C], w1[C];
+    if (PRO) prolong_weights<DIM, C>(L, Lc, bit0, w, p0, p1, w0, w1);
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
-      const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(w) * C;
+    for (int t = 0; t < CTT; ++t) {
       double xw[C];
 #pragma unroll
-      for (int k = 0; k < C; ++k) xw[k] = xin[base + k];
+      for (int k = 0; k < C; ++k) {
+        xw[k] = xin[cb[t] + size_t(w) * C + k];
+        if (PRO)
+          xw[k] += w0[k] * xc[cbc[t] + size_t(p0) * C + k] + w1[k] * xc[cbc[t] + size_t(p1) * C + k];
+      }
+      if (s == 0)
+#pragma unroll
+        for (int k = 0; k < C; ++k) xself[t][k] = xw[k];
 #pragma unroll
       for (int a = 0; a < C; ++a) {
         double s2 = 0.0;
@@ -237,63 +296,86 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, int isA, const doub
 #pragma unroll
   for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
+  for (int t = 0; t < CTT; ++t) {
     if (c0 + t >= nc) break;
-    const size_t base = size_t(c0 + t) * stride + size_t(v) * C;
+    const size_t base = cb[t] + size_t(v) * C;
+    double xn[C];
 #pragma unroll
     for (int a = 0; a < C; ++a) {
       double z = 0.0;
 #pragma unroll
       for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[t][k];
       const double dn = (c1 != 0.0 ? c1 * d[base + a] : 0.0) + c2 * z;
-      d[base + a] = dn;
-      xout[base + a] = xin[base + a] + dn;
+      if (!UPD) d[base + a] = dn;
+      xn[a] = xself[t][a] + dn;
+    }
+    if (!UPD) {
+#pragma unroll
+      for (int a = 0; a < C; ++a) xout[base + a] = xn[a];
+    } else {
+      // pressure field on level 0 (C == 1): write the updated state column
+      constexpr int D1 = DIM + 1;
+      const ColDesc cd = cols[c0 + t];
+      double out[D1];
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+        out[a] = cd.xcur[size_t(v) * D1 + a] + omega * zu[(size_t(c0 + t) * nn + v) * DIM + a];
+      out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * xn[0];
+#pragma unroll
+      for (int a = 0; a < D1; ++a) cd.xout[size_t(v) * D1 + a] = out[a];
+      if (cd.xout2)
+#pragma unroll
+        for (int a = 0; a < D1; ++a) cd.xout2[size_t(v) * D1 + a] = out[a];
     }
   }
 }
 
 // r = b - K x on one level
-template <int C>
+template <int DIM, int C, int CTT>
 __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
                                                            const double* __restrict__ b,
                                                            const double* __restrict__ x,
                                                            double* __restrict__ r, int nc) {
+  constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= nn) return;
-  const int c0 = blockIdx.x * CT;
+  const int c0 = blockIdx.x * CTT;
   const double* K = isA ? L.A : L.S;
   const size_t stride = size_t(nn) * C;
-  double acc[CT][C];
+  size_t cb[CTT];
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
-    const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(v) * C;
+  for (int t = 0; t < CTT; ++t) cb[t] = size_t(min(c0 + t, nc - 1)) * stride;
+  int nb[W];
 #pragma unroll
-    for (int a = 0; a < C; ++a) acc[t][a] = b[base + a];
-  }
-  for (int s = 0; s < L.W; ++s) {
-    const int w = L.nbr[size_t(s) * nn + v];
+  for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+  double acc[CTT][C];
+#pragma unroll
+  for (int t = 0; t < CTT; ++t)
+#pragma unroll
+    for (int a = 0; a < C; ++a) acc[t][a] = b[cb[t] + size_t(v) * C + a];
+#pragma unroll
+  for (int s = 0; s < W; ++s) {
+    const int w = nb[s];
     double blk[C * C];
 #pragma unroll
     for (int e = 0; e < C * C; ++e) blk[e] = K[(size_t(s) * C * C + e) * nn + v];
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
-      const size_t base = size_t(min(c0 + t, nc - 1)) * stride + size_t(w) * C;
+    for (int t = 0; t < CTT; ++t) {
 #pragma unroll
       for (int a = 0; a < C; ++a) {
         double s2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[base + k];
+        for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[cb[t] + size_t(w) * C + k];
         acc[t][a] -= s2;
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
+  for (int t = 0; t < CTT; ++t) {
     if (c0 + t >= nc) break;
-    const size_t base = size_t(c0 + t) * stride + size_t(v) * C;
 #pragma unroll
-    for (int a = 0; a < C; ++a) r[base + a] = acc[t][a];
+    for (int a = 0; a < C; ++a) r[cb[t] + size_t(v) * C + a] = acc[t][a];
   }
 }
 
@@ -350,39 +432,6 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev Lf, LevelDev Lc, i
   }
 }
 
-// xf_out = xf_in + P xc (P1 interpolation, masked)
-template <int DIM, int C>
-__global__ __launch_bounds__(kBlock) void k_prolong(LevelDev Lf, LevelDev Lc, int isA,
-                                                    const double* __restrict__ xin,
-                                                    const double* __restrict__ xc,
-                                                    double* __restrict__ xout, int nc) {
-  const int f = blockIdx.y * kBlock + threadIdx.x;
-  if (f >= Lf.nn) return;
-  const int c = blockIdx.x;
-  const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
-  int i, j, k;
-  node_coords<DIM>(f, mf, i, j, k);
-  const int ai = i >> 1, aj = j >> 1, ak = k >> 1;
-  const int oi = i & 1, oj = j & 1, ok = k & 1;
-  const int p0 = node_id<DIM>(ai, aj, ak, mc);
-  const bool two = (oi | oj | ok) != 0;
-  const int p1 = two ? node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
-  const double w = two ? 0.5 : 1.0;
-  const int bit0 = isA ? 0 : DIM;
-  const uint8_t ff = Lf.fixed[f], f0 = Lc.fixed[p0], f1 = Lc.fixed[p1];
-  const size_t sf = size_t(Lf.nn) * C, sc = size_t(Lc.nn) * C;
-#pragma unroll
-  for (int a = 0; a < C; ++a) {
-    double add = 0.0;
-    if (!((ff >> (bit0 + a)) & 1)) {
-      if (!((f0 >> (bit0 + a)) & 1)) add += w * xc[size_t(c) * sc + size_t(p0) * C + a];
-      if (two && !((f1 >> (bit0 + a)) & 1)) add += w * xc[size_t(c) * sc + size_t(p1) * C + a];
-    }
-    const size_t idx = size_t(c) * sf + size_t(f) * C + a;
-    xout[idx] = xin[idx] + add;
-  }
-}
-
 // coarsest level: x = M^{-1} b with the dense inverse, one workgroup per column
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ Minv,
                                                          const double* __restrict__ b,
@@ -401,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
 
 // pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), and the first
 // Chebyshev step of the pressure V-cycle
-template <int DIM>
+template <int DIM, int CTT>
 __global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1,
                                                    const double* __restrict__ zu,
                                                    const double* __restrict__ rp,
@@ -412,18 +461,20 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1
   const int nn = L.nn;
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= nn) return;
-  const int c0 = blockIdx.x * CT;
-  double acc[CT];
+  const int c0 = blockIdx.x * CTT;
+  double acc[CTT];
 #pragma unroll
-  for (int t = 0; t < CT; ++t) acc[t] = -rp[size_t(min(c0 + t, nc - 1)) * nn + v];
+  for (int t = 0; t < CTT; ++t) acc[t] = -rp[size_t(min(c0 + t, nc - 1)) * nn + v];
+  constexpr int W = DIM == 2 ? 7 : 15;
   if (p1) {
-    for (int s = 0; s < L.W; ++s) {
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
       const int w = L.nbr[size_t(s) * nn + v];
       double Btb[DIM];
 #pragma unroll
       for (int c = 0; c < DIM; ++c) Btb[c] = F.Bt[(size_t(s) * DIM + c) * nn + v];
 #pragma unroll
-      for (int t = 0; t < CT; ++t) {
+      for (int t = 0; t < CTT; ++t) {
         const size_t base = size_t(min(c0 + t, nc - 1)) * nn * DIM + size_t(w) * DIM;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[t] += Btb[c] * zu[base + c];
@@ -432,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1
   }
   const double si = L.Sinv[v];
 #pragma unroll
-  for (int t = 0; t < CT; ++t) {
+  for (int t = 0; t < CTT; ++t) {
     if (c0 + t >= nc) break;
     const size_t idx = size_t(c0 + t) * nn + v;
     t_out[idx] = acc[t];
@@ -563,39 +614,89 @@ __global__ __launch_bounds__(kBlock) void k_pre1(LevelDev L, int isA, const doub
   }
 }
 
-inline dim3 tiled_grid(int nc, int nn) { return dim3((nc + CT - 1) / CT, num_node_blocks(nn)); }
+inline dim3 tiled_grid(int nc, int nn, int ct) { return dim3((nc + ct - 1) / ct, num_node_blocks(nn)); }
 inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
+
+// runtime column tile -> template instantiation
+#define BIOT_CT_SWITCH(ct, ...)                         \
+  switch (ct) {                                         \
+    case 1: { constexpr int CTT = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int CTT = 2; __VA_ARGS__; } break; \
+    case 8: { constexpr int CTT = 8; __VA_ARGS__; } break; \
+    default: { constexpr int CTT = 4; __VA_ARGS__; } break; \
+  }
 
 }  // namespace
 
+bool valid_col_tile(int ct) { return ct == 1 || ct == 2 || ct == 4 || ct == 8; }
+
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                      double* ru, double* rp, double* xa, double* d, double inv_theta,
-                     double* partials, int pstride, hipStream_t st) {
-  if (dim == 2)
-    hipLaunchKernelGGL(k_residual<2>, tiled_grid(nc, L.nn), dim3(kBlock), 0, st, L, F, cols, nc,
-                       ru, rp, xa, d, inv_theta, partials, pstride);
-  else
-    hipLaunchKernelGGL(k_residual<3>, tiled_grid(nc, L.nn), dim3(kBlock), 0, st, L, F, cols, nc,
-                       ru, rp, xa, d, inv_theta, partials, pstride);
-}
-
-void launch_cheb(int comps, const LevelDev& L, bool is_A, const double* b, const double* xin,
-                 double* xout, double* d, int nc, double c1, double c2, hipStream_t st) {
-  dim3 g = tiled_grid(nc, L.nn);
-  switch (comps) {
-    case 1: hipLaunchKernelGGL(k_cheb<1>, g, dim3(kBlock), 0, st, L, int(is_A), b, xin, xout, d, nc, c1, c2); break;
-    case 2: hipLaunchKernelGGL(k_cheb<2>, g, dim3(kBlock), 0, st, L, int(is_A), b, xin, xout, d, nc, c1, c2); break;
-    default: hipLaunchKernelGGL(k_cheb<3>, g, dim3(kBlock), 0, st, L, int(is_A), b, xin, xout, d, nc, c1, c2); break;
+                     double* partials, int pstride, int ct, hipStream_t st) {
+  const dim3 g = tiled_grid(nc, L.nn, ct);
+  if (dim == 2) {
+    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_residual<2, CTT>), g, dim3(kBlock), 0, st, L, F, cols,
+                                          nc, ru, rp, xa, d, inv_theta, partials, pstride))
+  } else {
+    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_residual<3, CTT>), g, dim3(kBlock), 0, st, L, F, cols,
+                                          nc, ru, rp, xa, d, inv_theta, partials, pstride))
   }
 }
 
-void launch_level_residual(int comps, const LevelDev& L, bool is_A, const double* b,
-                           const double* x, double* r, int nc, hipStream_t st) {
-  dim3 g = tiled_grid(nc, L.nn);
-  switch (comps) {
-    case 1: hipLaunchKernelGGL(k_level_residual<1>, g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc); break;
-    case 2: hipLaunchKernelGGL(k_level_residual<2>, g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc); break;
-    default: hipLaunchKernelGGL(k_level_residual<3>, g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc); break;
+template <int DIM, int C, bool PRO, bool UPD>
+static void cheb_dispatch(const LevelDev& L, const LevelDev& Lc, bool is_A, const double* b,
+                          const double* xin, const double* xc, double* xout, double* d, int nc,
+                          double c1, double c2, const ColDesc* cols, const double* zu,
+                          double omega, int ct, bool fine, hipStream_t st) {
+  const dim3 g = tiled_grid(nc, L.nn, ct);
+  if (fine) {
+    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, CTT, PRO, UPD, true>), g, dim3(kBlock), 0,
+                                          st, L, Lc, int(is_A), b, xin, xc, xout, d, nc, c1, c2,
+                                          cols, zu, omega))
+  } else if (!UPD) {
+    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, CTT, PRO, UPD, false>), g, dim3(kBlock), 0,
+                                          st, L, Lc, int(is_A), b, xin, xc, xout, d, nc, c1, c2,
+                                          cols, zu, omega))
+  }
+}
+
+void launch_cheb(int dim, int comps, const LevelDev& L, const LevelDev* Lc, bool is_A,
+                 const double* b, const double* xin, const double* xc, double* xout, double* d,
+                 int nc, double c1, double c2, const ColDesc* cols, const double* zu,
+                 double omega, int ct, bool fine, hipStream_t st) {
+  const bool pro = xc != nullptr;
+  const bool upd = cols != nullptr;
+  const LevelDev& C2 = Lc ? *Lc : L;
+  if (dim == 2) {
+    if (comps == 1) {
+      if (upd) cheb_dispatch<2, 1, false, true>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      else if (pro) cheb_dispatch<2, 1, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      else cheb_dispatch<2, 1, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+    } else {
+      if (pro) cheb_dispatch<2, 2, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      else cheb_dispatch<2, 2, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+    }
+  } else {
+    if (comps == 1) {
+      if (upd) cheb_dispatch<3, 1, false, true>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      else if (pro) cheb_dispatch<3, 1, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      else cheb_dispatch<3, 1, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+    } else {
+      if (pro) cheb_dispatch<3, 3, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      else cheb_dispatch<3, 3, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+    }
+  }
+}
+
+void launch_level_residual(int dim, int comps, const LevelDev& L, bool is_A, const double* b,
+                           const double* x, double* r, int nc, int ct, hipStream_t st) {
+  const dim3 g = tiled_grid(nc, L.nn, ct);
+  if (dim == 2) {
+    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 1, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 2, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+  } else {
+    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 1, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 3, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
   }
 }
 
@@ -612,17 +713,6 @@ void launch_restrict(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc,
   }
 }
 
-void launch_prolong(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
-                    const double* xf_in, const double* xc, double* xf_out, int nc, hipStream_t st) {
-  dim3 g = col_grid(nc, Lf.nn);
-  if (dim == 2) {
-    if (comps == 1) hipLaunchKernelGGL((k_prolong<2, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
-    else hipLaunchKernelGGL((k_prolong<2, 2>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
-  } else {
-    if (comps == 1) hipLaunchKernelGGL((k_prolong<3, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
-    else hipLaunchKernelGGL((k_prolong<3, 3>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xf_in, xc, xf_out, nc);
-  }
-}
 
 void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, int nc,
                          hipStream_t st) {
@@ -632,12 +722,13 @@ void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, 
 
 void launch_pstage(int dim, const LevelDev& L, const FineDev& F, bool p1, const double* zu,
                    const double* rp, double* t, double* xa, double* d, double inv_theta, int nc,
-                   hipStream_t st) {
-  dim3 g = tiled_grid(nc, L.nn);
-  if (dim == 2)
-    hipLaunchKernelGGL(k_pstage<2>, g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc);
-  else
-    hipLaunchKernelGGL(k_pstage<3>, g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc);
+                   int ct, hipStream_t st) {
+  const dim3 g = tiled_grid(nc, L.nn, ct);
+  if (dim == 2) {
+    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_pstage<2, CTT>), g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc))
+  } else {
+    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_pstage<3, CTT>), g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc))
+  }
 }
 
 void launch_update(int dim, int nn, const ColDesc* cols, const double* zu, const double* zp,

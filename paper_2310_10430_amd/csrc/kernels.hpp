@@ -40,24 +40,29 @@ struct ColDesc {
 };
 
 // Launchers (all asynchronous on `st`).  `nc` = number of columns in the batch;
-// per-column work vectors are contiguous with stride nn*comps.
+// per-column work vectors are contiguous with stride nn*comps.  `ct` = columns
+// per thread in the node-blocked kernels (1, 2, 4 or 8).
+bool valid_col_tile(int ct);
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                      double* ru, double* rp, double* xa, double* d, double inv_theta,
-                     double* partials, int partial_stride, hipStream_t st);
-void launch_cheb(int comps, const LevelDev& L, bool is_A, const double* b, const double* xin,
-                 double* xout, double* d, int nc, double c1, double c2, hipStream_t st);
-void launch_level_residual(int comps, const LevelDev& L, bool is_A, const double* b,
-                           const double* x, double* r, int nc, hipStream_t st);
+                     double* partials, int partial_stride, int ct, hipStream_t st);
+// Chebyshev step; xc != null fuses the coarse-grid correction x += P xc (Lc =
+// the coarse level); cols != null (pressure field, level 0) writes the outer
+// update X^{n,m} = X^{n,m-1} + omega [zu; x_new] instead of xout.
+void launch_cheb(int dim, int comps, const LevelDev& L, const LevelDev* Lc, bool is_A,
+                 const double* b, const double* xin, const double* xc, double* xout, double* d,
+                 int nc, double c1, double c2, const ColDesc* cols, const double* zu,
+                 double omega, int ct, bool fine, hipStream_t st);
+void launch_level_residual(int dim, int comps, const LevelDev& L, bool is_A, const double* b,
+                           const double* x, double* r, int nc, int ct, hipStream_t st);
 void launch_restrict(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
                      const double* rf, double* bc, double* xa_c, double* d_c, double inv_theta_c,
                      int nc, hipStream_t st);
-void launch_prolong(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
-                    const double* xf_in, const double* xc, double* xf_out, int nc, hipStream_t st);
 void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, int nc,
                          hipStream_t st);
 void launch_pstage(int dim, const LevelDev& L, const FineDev& F, bool p1, const double* zu,
                    const double* rp, double* t, double* xa, double* d, double inv_theta, int nc,
-                   hipStream_t st);
+                   int ct, hipStream_t st);
 void launch_update(int dim, int nn, const ColDesc* cols, const double* zu, const double* zp,
                    double omega, int nc, hipStream_t st);
 void launch_reduce_norms(const double* partials, int nblk, int partial_stride, double* norms,

@@ -74,6 +74,15 @@ struct biot_handle {
   std::vector<ChebCoef> chA, chS;
   // host copies of the descriptor tables (uploaded at bind)
   std::vector<ColDesc> h_jac[2], h_k4[2], h_wave[2];
+  // HIP-event probes around level-0 launches (biot_profile_enable)
+  struct Pending { hipEvent_t a, b; int id; double bytes; };
+  struct Acc { uint64_t launches = 0; double ms = 0, bytes = 0; };
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  std::vector<Pending> pending;
+  Acc acc[BIOT_PROBE_COUNT];
+  int cur_copies = 0;  // columns of the current batch that also write a second copy
 };
 
 namespace {
@@ -226,18 +235,109 @@ ChebCoef cheb_of(double lmax, double ratio) {
   return c;
 }
 
+bool level0_smoothed(const biot_handle* h) { return h->nlev > 1; }
+
+const char* kProbeNames[BIOT_PROBE_COUNT] = {
+    "k_residual (fused residual, coupling, norms; level 0)",
+    "k_cheb displacement smoothing (level 0)",
+    "k_cheb pressure smoothing (level 0)",
+    "k_level_residual displacement (level 0)",
+    "k_level_residual pressure (level 0)",
+    "k_pstage (P1 pressure stage; level 0)"};
+
+int harvest(biot_handle* h) {
+  if (h->pending.empty()) {
+    h->ev_next = 0;
+    return BIOT_OK;
+  }
+  HIPCHK(h, hipEventSynchronize(h->pending.back().b));
+  for (const auto& p : h->pending) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, p.a, p.b));
+    h->acc[p.id].launches += 1;
+    h->acc[p.id].ms += ms;
+    h->acc[p.id].bytes += p.bytes;
+  }
+  h->pending.clear();
+  h->ev_next = 0;
+  return BIOT_OK;
+}
+
+// brackets one launch with events when probing; `bytes` = algorithmic bytes
+struct ProbeScope {
+  biot_handle* h;
+  int id;
+  double bytes;
+  hipEvent_t a = nullptr;
+  int rc = BIOT_OK;
+  bool live = true;
+  ProbeScope(biot_handle* h_, int id_, double bytes_) : h(h_), id(id_), bytes(bytes_) {
+    if (!h->prof || id < 0 || bytes <= 0) {
+      live = false;
+      return;
+    }
+    if (h->ev_next + 2 > h->ev_pool.size()) rc = harvest(h);
+    if (rc) return;
+    a = h->ev_pool[h->ev_next++];
+    if (hipEventRecord(a, h->st) != hipSuccess) rc = fail(h, BIOT_EHIP, "hipEventRecord");
+  }
+  int end() {
+    if (!live || rc) return rc;
+    hipEvent_t b = h->ev_pool[h->ev_next++];
+    if (hipEventRecord(b, h->st) != hipSuccess) return fail(h, BIOT_EHIP, "hipEventRecord");
+    h->pending.push_back({a, b, id, bytes});
+    return BIOT_OK;
+  }
+};
+
+// algorithmic bytes of the level-0 launches (distinct inputs and outputs once)
+double bytes_residual(const biot_handle* h, int nc, bool write_r, bool pre) {
+  const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
+  double per_col = 8 * D1 * 2 + (write_r ? 8 * d + 8 : 0) + (pre ? 16 * d : 0);
+  double mat = W * (d * d + 2 * d + 2) * 8 + 4 * W + 8 * D1 + (pre ? 8 * d * d : 0);
+  return nc * nn * per_col + nn * mat;
+}
+double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool pro, bool upd) {
+  const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
+  const double nnc = h->nlev > 1 ? h->P.levels[1].nn : 0;
+  double per_col = 8.0 * C * (2 + (c1 ? 1 : 0) + (upd ? 0 : 2));
+  if (upd) per_col += 8 * D1 * 2 + 8 * d;
+  double total = nc * nn * per_col + (upd ? h->cur_copies * nn * 8 * D1 : 0);
+  if (pro) total += nc * nnc * C * 8 + nn + nnc;
+  total += nn * (W * C * C * 8 + 4 * W + C * C * 8);
+  return total;
+}
+double bytes_levres(const biot_handle* h, int C, int nc) {
+  const double nn = h->nn, W = h->P.levels[0].W;
+  return nc * nn * C * 8 * 3 + nn * (W * C * C * 8 + 4 * W);
+}
+double bytes_pstage(const biot_handle* h, int nc) {
+  const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
+  return nc * nn * (8 * d + 8 + 8 + 16) + nn * (W * d * 8 + 4 * W + 8);
+}
+
 // One V-cycle for field A (is_A) or S on level l for nc columns.  On entry b[l]
 // holds the right-hand side and, unless l is the coarsest level, x0[l]/d[l]
-// hold the first Chebyshev step.  Returns the buffer with the result.
-int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out) {
+// hold the first Chebyshev step.  The result is returned in *out; when `upd`
+// is given (pressure field, level 0) the last smoothing step writes the outer
+// update through those descriptors instead and *out is null.
+int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out, const ColDesc* upd,
+           const double* zu) {
   Field& f = is_A ? h->fa : h->fs;
   const int C = is_A ? h->dim : 1;
   const int last = h->nlev - 1;
+  const int ct = h->opt.col_tile;
   hipStream_t st = h->st;
   if (l == last) {
     launch_coarse_solve(h->P.levels[l].nn * C, is_A ? h->coarseA : h->coarseS, f.b[l], f.x0[l], nc, st);
     LAUNCHCHK(h);
-    *out = f.x0[l];
+    if (upd) {
+      launch_update(h->dim, h->nn, upd, zu, f.x0[l], h->opt.omega, nc, st);
+      LAUNCHCHK(h);
+      *out = nullptr;
+    } else {
+      *out = f.x0[l];
+    }
     return BIOT_OK;
   }
   const ChebCoef& cc = is_A ? h->chA[l] : h->chS[l];
@@ -246,15 +346,24 @@ int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out) {
   double* oth = f.x1[l];
   // pre-smoothing: the first step was done by the producer of b[l]
   double rho = 1.0 / cc.sigma;
+  const bool fine = l == 0;
+  const int pid_cheb = is_A ? BIOT_PROBE_CHEB_U : BIOT_PROBE_CHEB_P;
   for (int j = 2; j <= deg; ++j) {
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
-    launch_cheb(C, h->L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho, 2.0 * rn / cc.delta, st);
+    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, true, false, false) : 0);
+    launch_cheb(h->dim, C, h->L[l], nullptr, is_A, f.b[l], cur, nullptr, oth, f.d[l], nc, rn * rho,
+                2.0 * rn / cc.delta, nullptr, nullptr, 0.0, ct, fine, st);
     LAUNCHCHK(h);
+    if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
     std::swap(cur, oth);
   }
-  launch_level_residual(C, h->L[l], is_A, f.b[l], cur, f.r[l], nc, st);
-  LAUNCHCHK(h);
+  {
+    ProbeScope ps(h, is_A ? BIOT_PROBE_LEVRES_U : BIOT_PROBE_LEVRES_P, fine ? bytes_levres(h, C, nc) : 0);
+    launch_level_residual(h->dim, C, h->L[l], is_A, f.b[l], cur, f.r[l], nc, ct, st);
+    LAUNCHCHK(h);
+    if (fine && ps.end()) return BIOT_EHIP;
+  }
   const bool coarse_last = (l + 1 == last);
   const ChebCoef* cn = coarse_last ? nullptr : (is_A ? &h->chA[l + 1] : &h->chS[l + 1]);
   launch_restrict(h->dim, C, h->L[l], h->L[l + 1], is_A, f.r[l], f.b[l + 1],
@@ -262,52 +371,64 @@ int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out) {
                   coarse_last ? 0.0 : 1.0 / cn->theta, nc, st);
   LAUNCHCHK(h);
   double* xc = nullptr;
-  int rc = vcycle(h, is_A, l + 1, nc, &xc);
+  int rc = vcycle(h, is_A, l + 1, nc, &xc, nullptr, nullptr);
   if (rc) return rc;
-  launch_prolong(h->dim, C, h->L[l], h->L[l + 1], is_A, cur, xc, oth, nc, st);
-  LAUNCHCHK(h);
-  std::swap(cur, oth);
-  // post-smoothing: deg steps, restarting the recurrence
-  launch_cheb(C, h->L[l], is_A, f.b[l], cur, oth, f.d[l], nc, 0.0, 1.0 / cc.theta, st);
-  LAUNCHCHK(h);
-  std::swap(cur, oth);
+  // post-smoothing: deg steps, restarting the recurrence; the first one also
+  // applies the coarse-grid correction x += P xc
   rho = 1.0 / cc.sigma;
-  for (int j = 2; j <= deg; ++j) {
-    const double rn = 1.0 / (2.0 * cc.sigma - rho);
-    launch_cheb(C, h->L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho, 2.0 * rn / cc.delta, st);
+  for (int j = 1; j <= deg; ++j) {
+    double c1 = 0.0, c2 = 1.0 / cc.theta, rn = rho;
+    if (j > 1) {
+      rn = 1.0 / (2.0 * cc.sigma - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / cc.delta;
+    }
+    const bool final_upd = upd && j == deg;
+    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, j == 1, final_upd) : 0);
+    launch_cheb(h->dim, C, h->L[l], j == 1 ? &h->L[l + 1] : nullptr, is_A, f.b[l], cur,
+                j == 1 ? xc : nullptr, oth, f.d[l], nc, c1, c2, final_upd ? upd : nullptr, zu,
+                h->opt.omega, ct, fine, st);
     LAUNCHCHK(h);
+    if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
     std::swap(cur, oth);
   }
-  *out = cur;
+  *out = upd ? nullptr : cur;
   return BIOT_OK;
 }
 
-bool level0_smoothed(const biot_handle* h) { return h->nlev > 1; }
-
 // P^{-1} applied to the batch whose residual is in fa.b[0] (r_u) and rp (r_p);
-// the first Chebyshev step of V_A has been written by the producer.
-int precond_batch(biot_handle* h, int nc, double** zu, double** zp) {
-  int rc = vcycle(h, true, 0, nc, zu);
+// the first Chebyshev step of V_A has been written by the producer.  With
+// `upd`, the outer update is written through those descriptors.
+int precond_batch(biot_handle* h, int nc, double** zu, double** zp, const ColDesc* upd) {
+  int rc = vcycle(h, true, 0, nc, zu, nullptr, nullptr);
   if (rc) return rc;
   const bool sm = level0_smoothed(h);
-  launch_pstage(h->dim, h->L[0], h->F, h->opt.precond == BIOT_PRECOND_P1, *zu, h->rp, h->fs.b[0],
-                h->fs.x0[0], h->fs.d[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc, h->st);
-  LAUNCHCHK(h);
-  return vcycle(h, false, 0, nc, zp);
+  {
+    ProbeScope ps(h, BIOT_PROBE_PSTAGE, bytes_pstage(h, nc));
+    launch_pstage(h->dim, h->L[0], h->F, h->opt.precond == BIOT_PRECOND_P1, *zu, h->rp, h->fs.b[0],
+                  h->fs.x0[0], h->fs.d[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc, h->opt.col_tile,
+                  h->st);
+    LAUNCHCHK(h);
+    if (ps.end()) return BIOT_EHIP;
+  }
+  return vcycle(h, false, 0, nc, zp, upd, *zu);
 }
 
 // one unit for every column of a descriptor batch
 int unit_batch(biot_handle* h, const ColDesc* cols, int nc, double* partials, double* norms_out) {
   const bool sm = level0_smoothed(h);
-  launch_residual(h->dim, h->L[0], h->F, cols, nc, h->fa.b[0], h->rp, sm ? h->fa.x0[0] : nullptr,
-                  h->fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0, partials, h->nblk, h->st);
-  LAUNCHCHK(h);
+  {
+    ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, sm));
+    launch_residual(h->dim, h->L[0], h->F, cols, nc, h->fa.b[0], h->rp, sm ? h->fa.x0[0] : nullptr,
+                    h->fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0, partials, h->nblk,
+                    h->opt.col_tile, h->st);
+    LAUNCHCHK(h);
+    if (ps.end()) return BIOT_EHIP;
+  }
   double *zu = nullptr, *zp = nullptr;
-  int rc = precond_batch(h, nc, &zu, &zp);
+  int rc = precond_batch(h, nc, &zu, &zp, cols);
   if (rc) return rc;
-  launch_update(h->dim, h->nn, cols, zu, zp, h->opt.omega, nc, h->st);
-  LAUNCHCHK(h);
   if (partials && norms_out) {
     launch_reduce_norms(partials, h->nblk, h->nblk, norms_out, nc, h->st);
     LAUNCHCHK(h);
@@ -329,9 +450,12 @@ int jacobi_sweep(biot_handle* h) {
 int wavefront_pass(biot_handle* h) {
   ColDesc* tab = h->desc_wave[h->cur];
   for (size_t w = 0; w < h->wave_off.size(); ++w) {
+    const int wave = int(w) + 1, last_step = wave - h->opt.depth + 1;
+    h->cur_copies = (last_step >= 1 && last_step <= h->N) ? 1 : 0;
     int rc = unit_batch(h, tab + h->wave_off[w], h->wave_cnt[w], nullptr, nullptr);
     if (rc) return rc;
   }
+  h->cur_copies = 0;
   h->cur = 1 - h->cur;
   return BIOT_OK;
 }
@@ -343,7 +467,7 @@ int global_residual(biot_handle* h) {
   for (int n0 = 0; n0 < h->N; n0 += chunk) {
     const int nc = std::min(chunk, h->N - n0);
     launch_residual(h->dim, h->L[0], h->F, tab + n0, nc, nullptr, nullptr, nullptr, nullptr, 0.0,
-                    h->partials, h->nblk, h->st);
+                    h->partials, h->nblk, h->opt.col_tile, h->st);
     LAUNCHCHK(h);
     launch_reduce_norms(h->partials, h->nblk, h->nblk, h->norms + size_t(n0) * 4, nc, h->st);
     LAUNCHCHK(h);
@@ -391,6 +515,7 @@ int biot_default_options(biot_options* o) {
   o->power_iters = 20;
   o->max_batch = 0;
   o->omega = 0.6;
+  o->col_tile = 4;
   return BIOT_OK;
 }
 
@@ -411,6 +536,8 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   if (!(o.omega > 0.0) || !std::isfinite(o.omega)) return fail(nullptr, BIOT_EINVAL, "omega must be > 0");
   if (o.power_iters < 1) return fail(nullptr, BIOT_EINVAL, "power_iters must be >= 1");
   if (!(o.lmax_safety >= 1.0)) return fail(nullptr, BIOT_EINVAL, "lmax_safety must be >= 1");
+  if (o.cheb_degree < 2 || o.cheb_degree > 8) return fail(nullptr, BIOT_EINVAL, "cheb_degree must be in 2..8");
+  if (!valid_col_tile(o.col_tile)) return fail(nullptr, BIOT_EINVAL, "col_tile must be 1, 2, 4 or 8");
   biot_handle* h = new (std::nothrow) biot_handle();
   if (!h) return fail(nullptr, BIOT_ENOMEM, "out of host memory");
   h->opt = o;
@@ -642,10 +769,36 @@ int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols
       LAUNCHCHK(h);
     }
     double *zu = nullptr, *zp = nullptr;
-    if ((rc = precond_batch(h, nc, &zu, &zp))) return rc;
+    if ((rc = precond_batch(h, nc, &zu, &zp, nullptr))) return rc;
     launch_pack(h->dim, h->nn, zu, zp, Z + size_t(c0) * h->col, nc, h->st);
     LAUNCHCHK(h);
   }
+  return BIOT_OK;
+}
+
+int biot_profile_enable(biot_handle* h, int32_t enable) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if ((rc = harvest(h))) return rc;
+  for (auto& a : h->acc) a = biot_handle::Acc{};
+  if (enable && h->ev_pool.empty()) {
+    h->ev_pool.resize(16384);
+    for (auto& e : h->ev_pool) HIPCHK(h, hipEventCreate(&e));
+  }
+  h->prof = enable != 0;
+  return BIOT_OK;
+}
+
+int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
+                      double* total_bytes, const char** name) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (probe < 0 || probe >= BIOT_PROBE_COUNT) return fail(h, BIOT_EINVAL, "unknown probe");
+  if ((rc = harvest(h))) return rc;
+  if (launches) *launches = h->acc[probe].launches;
+  if (total_ms) *total_ms = h->acc[probe].ms;
+  if (total_bytes) *total_bytes = h->acc[probe].bytes;
+  if (name) *name = kProbeNames[probe];
   return BIOT_OK;
 }
 
@@ -689,6 +842,10 @@ const char* biot_last_error(const biot_handle* h) {
 
 const char* biot_version(void) { return "biot_pint 0.1 (gfx950, FP64)"; }
 
-void biot_destroy(biot_handle* h) { delete h; }
+void biot_destroy(biot_handle* h) {
+  if (!h) return;
+  for (auto& e : h->ev_pool) (void)hipEventDestroy(e);
+  delete h;
+}
 
 }  // extern "C"

@@ -16,7 +16,8 @@ from . import _lib
 
 
 def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
-                  cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None):
+                  cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
+                  col_tile=4):
     """biot_create on the host (no device work); returns (handle, options)."""
     lib = _lib.load()
     xyz = np.ascontiguousarray(problem.xyz, dtype=np.float64)
@@ -46,6 +47,7 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     opt.power_iters = power_iters
     opt.max_batch = max_batch
     opt.omega = omega
+    opt.col_tile = col_tile
     h = C.c_void_p()
     _lib.check(lib, lib.biot_create(C.byref(mesh), C.byref(mat), C.byref(load),
                                     float(problem.dt), problem.n_steps, C.byref(opt),
@@ -87,7 +89,7 @@ class BiotSolver:
     def __init__(self, problem, schedule: str = "jacobi", depth: int = 8, precond: str = "P1",
                  omega: float = 0.6, cheb_degree: int = 2, cheb_ratio: float = 4.0,
                  lmax_safety: float = 1.1, power_iters: int = 20, max_batch: int = 0,
-                 device: str = "cuda:0", beta=None):
+                 device: str = "cuda:0", beta=None, col_tile: int = 4):
         if not torch.cuda.is_available():
             raise RuntimeError("BiotSolver needs a ROCm GPU (torch.cuda is not available)")
         self.lib = _lib.load()
@@ -95,7 +97,7 @@ class BiotSolver:
         h, opt = create_handle(problem, schedule=schedule, depth=depth, precond=precond,
                                omega=omega, cheb_degree=cheb_degree, cheb_ratio=cheb_ratio,
                                lmax_safety=lmax_safety, power_iters=power_iters,
-                               max_batch=max_batch, beta=beta)
+                               max_batch=max_batch, beta=beta, col_tile=col_tile)
         self.problem = problem
         self.dim = problem.dim
         self.n_nodes = problem.n_nodes
@@ -178,3 +180,20 @@ class BiotSolver:
 
     def info(self) -> dict:
         return handle_info(self.lib, self.h)
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) the HIP-event probes around level-0 launches."""
+        self._check(self.lib.biot_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for i, key in enumerate(_lib.PROBES):
+            n = C.c_uint64()
+            ms = C.c_double()
+            by = C.c_double()
+            nm = C.c_char_p()
+            self._check(self.lib.biot_profile_read(self.h, i, C.byref(n), C.byref(ms), C.byref(by),
+                                                   C.byref(nm)))
+            out[key] = dict(name=nm.value.decode(), launches=int(n.value), ms=ms.value,
+                            bytes=by.value)
+        return out
