@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--schedule", default="wavefront", choices=["wavefront", "jacobi"])
     ap.add_argument("--depth", type=int, default=64)
     ap.add_argument("--omega", type=float, default=0.6)
-    ap.add_argument("--col-tile", type=int, default=4)
+    ap.add_argument("--col-tile", type=int, default=16)
     ap.add_argument("--rtol", type=float, default=2e-9)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--max-sweeps", type=int, default=600)

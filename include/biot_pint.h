@@ -109,7 +109,7 @@ typedef struct {
   int32_t power_iters;  /* power iterations for lmax per level (20)                */
   int32_t max_batch;    /* Jacobi: columns per launch, <= 0 for all steps (0)      */
   double omega;         /* damping of the outer update (0.6)                       */
-  int32_t col_tile;     /* time-step columns per GPU thread: 1, 2, 4 or 8 (4)      */
+  int32_t col_tile;     /* max time-step columns per GPU thread loop: 1..32 (16)   */
 } biot_options;
 
 typedef struct {

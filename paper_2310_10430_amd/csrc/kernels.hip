@@ -36,6 +36,18 @@ __device__ inline int node_id(int i, int j, int k, int m) {
   return DIM == 2 ? j * m + i : (k * m + j) * m + i;
 }
 
+// XCD-aware workgroup order for the (column tile, node block) grid: workgroups
+// are dealt to the 8 XCDs round-robin, so workgroup i runs on XCD i % 8.  All
+// column tiles of node block b are given ids that land on XCD b % 8 back to
+// back, so the block's operator rows are fetched into that XCD's L2 once and
+// reused by every column tile.
+__device__ inline void tile_coords(int ntiles, int& tile, int& nblk) {
+  const int i = blockIdx.x;
+  const int j = i >> 3;
+  nblk = (j / ntiles) * 8 + (i & 7);
+  tile = j % ntiles;
+}
+
 // Deterministic block sum of Q values per thread (wave64 shuffles, then LDS
 // across the 4 waves in a fixed order).  Result valid in thread 0.
 template <int Q>
@@ -55,13 +67,22 @@ __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
   if (threadIdx.x == 0)
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = ((lds[q] + lds[Q + q]) + lds[2 * Q + q]) + lds[3 * Q + q];
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1}, norms, and the
-// first (pointwise) Chebyshev step of the displacement V-cycle
+// Thread mapping of the node-blocked kernels ("operator-stationary"): a thread
+// owns one node, loads that node's operator row (all slots) into registers
+// once, and then loops over a group of G time-step columns two at a time.  The
+// operator is read once per column group, the column data streams through,
+// and the grid is (column groups) x (node blocks) in XCD-aware order.  Rows too
+// large for registers (3D) are re-read per column pair from L1/L2 instead.
 // ---------------------------------------------------------------------------
-template <int DIM, int CTT>
+
+// fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1}, the coupled
+// right-hand side norms, and the first (pointwise) Chebyshev step of the
+// displacement V-cycle
+template <int DIM, int G>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
                                                      double* __restrict__ ru,
@@ -71,137 +92,166 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      double* __restrict__ partials, int pstride) {
   constexpr int D1 = DIM + 1;
   constexpr int W = DIM == 2 ? 7 : 15;
-  __shared__ double lds[4 * 4 * CTT];
+  constexpr bool STAT = DIM == 2;
+  constexpr int RS = STAT ? W : 1;
+  __shared__ double lds[4 * 8];
   const int nn = L.nn;
-  const int v = blockIdx.y * kBlock + threadIdx.x;
-  const int c0 = blockIdx.x * CTT;
+  int tile, nblk;
+  tile_coords((nc + G - 1) / G, tile, nblk);
+  if (nblk * kBlock >= nn) return;  // padding workgroup (uniform exit)
+  const int v = nblk * kBlock + threadIdx.x;
   const bool active = v < nn;
-  const double* xc[CTT];
-  const double* xp[CTT];
-  double coef[CTT];
+  const int vv = active ? v : nn - 1;
+  int nb[W];
 #pragma unroll
-  for (int t = 0; t < CTT; ++t) {
-    const int c = min(c0 + t, nc - 1);
-    xc[t] = cols[c].xcur;
-    xp[t] = cols[c].xprev;
-    coef[t] = cols[c].coef;
+  for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + vv];
+  double rA[RS][DIM * DIM], rB[RS][DIM], rBt[RS][DIM], rS[RS], rCb[RS];
+  if constexpr (STAT) {
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+#pragma unroll
+      for (int e = 0; e < DIM * DIM; ++e) rA[s][e] = L.A[(size_t(s) * DIM * DIM + e) * nn + vv];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        rB[s][c] = F.B[(size_t(s) * DIM + c) * nn + vv];
+        rBt[s][c] = F.Bt[(size_t(s) * DIM + c) * nn + vv];
+      }
+      rS[s] = L.S[size_t(s) * nn + vv];
+      rCb[s] = F.Cb[size_t(s) * nn + vv];
+    }
   }
-  double au[CTT][DIM], ap[CTT], bp[CTT];
-  double Fu[DIM];
+  double Fu[DIM], Di[DIM * DIM];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(v) * D1 + a] : 0.0;
+  for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(vv) * D1 + a] : 0.0;
 #pragma unroll
-  for (int t = 0; t < CTT; ++t) {
+  for (int e = 0; e < DIM * DIM; ++e) Di[e] = xa ? L.Ainv[size_t(e) * nn + vv] : 0.0;
+  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+#pragma unroll 1
+  for (int c = cbeg; c < cend; c += 2) {
+    const bool two = c + 1 < cend;
+    const int cc[2] = {c, two ? c + 1 : c};
+    const double* xc[2];
+    const double* xp[2];
+    double coef[2], au[2][DIM], ap[2], bp[2];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) au[t][a] = coef[t] * Fu[a];
-    ap[t] = 0.0;
-    bp[t] = 0.0;
-  }
-  if (active) {
-    int nb[W];
+    for (int q = 0; q < 2; ++q) {
+      xc[q] = cols[cc[q]].xcur;
+      xp[q] = cols[cc[q]].xprev;
+      coef[q] = cols[cc[q]].coef;
 #pragma unroll
-    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+      for (int a = 0; a < DIM; ++a) au[q][a] = coef[q] * Fu[a];
+      ap[q] = 0.0;
+      bp[q] = 0.0;
+    }
 #pragma unroll
     for (int s = 0; s < W; ++s) {
       const int w = nb[s];
-      double Ab[DIM * DIM], Bb[DIM], Btb[DIM];
+      double Ab[DIM * DIM], Bb[DIM], Btb[DIM], Sv, Cbv;
+      if constexpr (STAT) {
 #pragma unroll
-      for (int e = 0; e < DIM * DIM; ++e) Ab[e] = L.A[(size_t(s) * DIM * DIM + e) * nn + v];
+        for (int e = 0; e < DIM * DIM; ++e) Ab[e] = rA[s][e];
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        Bb[c] = F.B[(size_t(s) * DIM + c) * nn + v];
-        Btb[c] = F.Bt[(size_t(s) * DIM + c) * nn + v];
+        for (int k = 0; k < DIM; ++k) {
+          Bb[k] = rB[s][k];
+          Btb[k] = rBt[s][k];
+        }
+        Sv = rS[s];
+        Cbv = rCb[s];
+      } else {
+#pragma unroll
+        for (int e = 0; e < DIM * DIM; ++e) Ab[e] = L.A[(size_t(s) * DIM * DIM + e) * nn + vv];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          Bb[k] = F.B[(size_t(s) * DIM + k) * nn + vv];
+          Btb[k] = F.Bt[(size_t(s) * DIM + k) * nn + vv];
+        }
+        Sv = L.S[size_t(s) * nn + vv];
+        Cbv = F.Cb[size_t(s) * nn + vv];
       }
-      const double Sv = L.S[size_t(s) * nn + v];
-      const double Cbv = F.Cb[size_t(s) * nn + v];
 #pragma unroll
-      for (int t = 0; t < CTT; ++t) {
+      for (int q = 0; q < 2; ++q) {
         double xw[D1], xpw[D1];
 #pragma unroll
         for (int k = 0; k < D1; ++k) {
-          xw[k] = xc[t][size_t(w) * D1 + k];
-          xpw[k] = xp[t][size_t(w) * D1 + k];
+          xw[k] = xc[q][size_t(w) * D1 + k];
+          xpw[k] = xp[q][size_t(w) * D1 + k];
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           double acc = Bb[a] * xw[DIM];
 #pragma unroll
-          for (int b = 0; b < DIM; ++b) acc += Ab[a * DIM + b] * xw[b];
-          au[t][a] -= acc;
+          for (int k = 0; k < DIM; ++k) acc += Ab[a * DIM + k] * xw[k];
+          au[q][a] -= acc;
         }
         double btc = 0.0, btp = 0.0;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-          btc += Btb[c] * xw[c];
-          btp += Btb[c] * xpw[c];
+        for (int k = 0; k < DIM; ++k) {
+          btc += Btb[k] * xw[k];
+          btp += Btb[k] * xpw[k];
         }
         const double coup = btp - Cbv * xpw[DIM];
-        bp[t] += coup;
-        ap[t] += coup - btc + Sv * xw[DIM];
+        bp[q] += coup;
+        ap[q] += coup - btc + Sv * xw[DIM];
       }
     }
-    double Di[DIM * DIM];
-    if (xa) {
 #pragma unroll
-      for (int e = 0; e < DIM * DIM; ++e) Di[e] = L.Ainv[size_t(e) * nn + v];
-    }
-#pragma unroll
-    for (int t = 0; t < CTT; ++t) {
-      if (c0 + t >= nc) break;
-      const size_t cu = size_t(c0 + t) * nn * DIM;
+    for (int q = 0; q < 2; ++q) {
+      if (!active || (q == 1 && !two)) break;
+      const size_t cu = size_t(cc[q]) * nn * DIM;
       if (ru) {
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = au[t][a];
-        rp[size_t(c0 + t) * nn + v] = ap[t];
+        for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = au[q][a];
+        rp[size_t(cc[q]) * nn + v] = ap[q];
       }
       if (xa) {
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           double z = 0.0;
 #pragma unroll
-          for (int b = 0; b < DIM; ++b) z += Di[a * DIM + b] * au[t][b];
+          for (int k = 0; k < DIM; ++k) z += Di[a * DIM + k] * au[q][k];
           z *= inv_theta;
           xa[cu + size_t(v) * DIM + a] = z;
           d[cu + size_t(v) * DIM + a] = z;
         }
       }
     }
-  }
-  if (partials) {
-    double q[4 * CTT];
+    if (partials) {
+      double qv[8];
 #pragma unroll
-    for (int t = 0; t < CTT; ++t) {
-      double su = 0.0, sb = 0.0;
+      for (int q = 0; q < 2; ++q) {
+        double su = 0.0, sb = 0.0;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        su += au[t][a] * au[t][a];
-        const double ba = coef[t] * Fu[a];
-        sb += ba * ba;
+        for (int a = 0; a < DIM; ++a) {
+          su += au[q][a] * au[q][a];
+          const double ba = coef[q] * Fu[a];
+          sb += ba * ba;
+        }
+        qv[4 * q + 0] = active ? su : 0.0;
+        qv[4 * q + 1] = active ? ap[q] * ap[q] : 0.0;
+        qv[4 * q + 2] = active ? sb : 0.0;
+        qv[4 * q + 3] = active ? bp[q] * bp[q] : 0.0;
       }
-      q[4 * t + 0] = active ? su : 0.0;
-      q[4 * t + 1] = active ? ap[t] * ap[t] : 0.0;
-      q[4 * t + 2] = active ? sb : 0.0;
-      q[4 * t + 3] = active ? bp[t] * bp[t] : 0.0;
+      block_sum<8>(qv, lds);
+      if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (q == 1 && !two) break;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            partials[(size_t(cc[q]) * pstride + nblk) * 4 + k] = qv[4 * q + k];
+        }
     }
-    block_sum<4 * CTT>(q, lds);
-    if (threadIdx.x == 0)
-#pragma unroll
-      for (int t = 0; t < CTT; ++t) {
-        if (c0 + t >= nc) break;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          partials[(size_t(c0 + t) * pstride + blockIdx.y) * 4 + k] = q[4 * t + k];
-      }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Prolongation weights of fine node f: parents p0, p1 on the coarse grid and the
-// per-component weights (zero where the fine or the coarse dof is prescribed).
+// Prolongation of fine node f: parents p0, p1 on the coarse grid and a bit mask
+// of the components that receive each parent (bit a: p0, bit C+a: p1); the
+// weight is 1 for a coincident node, 1/2 for an edge midpoint.
 // ---------------------------------------------------------------------------
 template <int DIM, int C>
-__device__ inline void prolong_weights(const LevelDev& Lf, const LevelDev& Lc, int bit0, int f,
-                                       int& p0, int& p1, double (&w0)[C], double (&w1)[C]) {
+__device__ inline void prolong_parents(const LevelDev& Lf, const LevelDev& Lc, int bit0, int f,
+                                       int& p0, int& p1, unsigned& mask) {
   const int mf = Lf.n_cells + 1, mc = Lc.n_cells + 1;
   int i, j, k;
   node_coords<DIM>(f, mf, i, j, k);
@@ -210,24 +260,24 @@ __device__ inline void prolong_weights(const LevelDev& Lf, const LevelDev& Lc, i
   const bool two = (oi | oj | ok) != 0;
   p0 = node_id<DIM>(ai, aj, ak, mc);
   p1 = two ? node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
-  const double wgt = two ? 0.5 : 1.0;
   const unsigned ff = Lf.fixed[f], f0 = Lc.fixed[p0], f1 = Lc.fixed[p1];
+  mask = two ? (1u << 2 * C) : 0u;
 #pragma unroll
   for (int a = 0; a < C; ++a) {
     const bool fm = !((ff >> (bit0 + a)) & 1u);
-    w0[a] = (fm && !((f0 >> (bit0 + a)) & 1u)) ? wgt : 0.0;
-    w1[a] = (two && fm && !((f1 >> (bit0 + a)) & 1u)) ? wgt : 0.0;
+    if (fm && !((f0 >> (bit0 + a)) & 1u)) mask |= 1u << a;
+    if (two && fm && !((f1 >> (bit0 + a)) & 1u)) mask |= 1u << (C + a);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Chebyshev step on one level, for CTT columns per thread:
+// Chebyshev step on one level:
 //     x  = xin               (PRO: x = xin + P xc, the coarse correction fused in)
 //     d <- c1 d + c2 D^{-1}(b - K x);   xout = x + d
 // UPD (pressure field, level 0, last step): instead of xout, writes the outer
 // update X^{n,m} = X^{n,m-1} + omega [z_u; x + d] through the column descriptors.
 // ---------------------------------------------------------------------------
-template <int DIM, int C, int CTT, bool PRO, bool UPD, bool FINE>
+template <int DIM, int C, int G, bool PRO, bool UPD, bool FINE>
 __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int isA,
                                                  const double* __restrict__ b,
                                                  const double* __restrict__ xin,
@@ -237,145 +287,209 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
                                                  const ColDesc* __restrict__ cols,
                                                  const double* __restrict__ zu, double omega) {
   constexpr int W = DIM == 2 ? 7 : 15;
+  constexpr bool STAT = W * C * C <= 64;
+  constexpr int RS = STAT ? W : 1;
   const int nn = L.nn;
-  const int v = blockIdx.y * kBlock + threadIdx.x;
+  int tile, nblk;
+  tile_coords((nc + G - 1) / G, tile, nblk);
+  const int v = nblk * kBlock + threadIdx.x;
   if (v >= nn) return;
-  const int c0 = blockIdx.x * CTT;
   const double* K = isA ? L.A : L.S;
   const double* Dg = isA ? L.Ainv : L.Sinv;
   const int bit0 = isA ? 0 : DIM;
   const size_t stride = size_t(nn) * C;
   const size_t cstride = PRO ? size_t(Lc.nn) * C : 0;
-  size_t cb[CTT], cbc[CTT];
-#pragma unroll
-  for (int t = 0; t < CTT; ++t) {
-    const int c = min(c0 + t, nc - 1);
-    cb[t] = size_t(c) * stride;
-    cbc[t] = size_t(c) * cstride;
-  }
   int nb[W];
 #pragma unroll
   for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
-  double acc[CTT][C];
+  double kr[RS][C * C];
+  if constexpr (STAT) {
 #pragma unroll
-  for (int t = 0; t < CTT; ++t)
+    for (int s = 0; s < W; ++s)
 #pragma unroll
-    for (int a = 0; a < C; ++a) acc[t][a] = b[cb[t] + size_t(v) * C + a];
-  double xself[CTT][C];
+      for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
+  }
+  int pp0[PRO ? W : 1], pp1[PRO ? W : 1];
+  unsigned pm[PRO ? W : 1];
+  if constexpr (PRO) {
 #pragma unroll
-  for (int s = 0; s < W; ++s) {
-    const int w = nb[s];
-    double blk[C * C];
-#pragma unroll
-    for (int e = 0; e < C * C; ++e) blk[e] = K[(size_t(s) * C * C + e) * nn + v];
-    int p0 = 0, p1 = 0;
-    double w0[C], w1[C];
-    if (PRO) prolong_weights<DIM, C>(L, Lc, bit0, w, p0, p1, w0, w1);
-#pragma unroll
-    for (int t = 0; t < CTT; ++t) {
-      double xw[C];
-#pragma unroll
-      for (int k = 0; k < C; ++k) {
-        xw[k] = xin[cb[t] + size_t(w) * C + k];
-        if (PRO)
-          xw[k] += w0[k] * xc[cbc[t] + size_t(p0) * C + k] + w1[k] * xc[cbc[t] + size_t(p1) * C + k];
-      }
-      if (s == 0)
-#pragma unroll
-        for (int k = 0; k < C; ++k) xself[t][k] = xw[k];
-#pragma unroll
-      for (int a = 0; a < C; ++a) {
-        double s2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * xw[k];
-        acc[t][a] -= s2;
-      }
-    }
+    for (int s = 0; s < W; ++s) prolong_parents<DIM, C>(L, Lc, bit0, nb[s], pp0[s], pp1[s], pm[s]);
   }
   double Di[C * C];
 #pragma unroll
   for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
+  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+#pragma unroll 1
+  for (int c = cbeg; c < cend; c += 2) {
+    const bool two = c + 1 < cend;
+    const int cc[2] = {c, two ? c + 1 : c};
+    double acc[2][C], xs[2][C];
 #pragma unroll
-  for (int t = 0; t < CTT; ++t) {
-    if (c0 + t >= nc) break;
-    const size_t base = cb[t] + size_t(v) * C;
-    double xn[C];
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + size_t(v) * C + a];
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      const int w = nb[s];
+      double blk[C * C];
+#pragma unroll
+      for (int e = 0; e < C * C; ++e) {
+        if constexpr (STAT) blk[e] = kr[s][e];
+        else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        double xw[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          xw[k] = xin[size_t(cc[q]) * stride + size_t(w) * C + k];
+          if constexpr (PRO) {
+            const double wt = (pm[s] >> (2 * C)) ? 0.5 : 1.0;
+            const size_t cb = size_t(cc[q]) * cstride;
+            if ((pm[s] >> k) & 1u) xw[k] += wt * xc[cb + size_t(pp0[s]) * C + k];
+            if ((pm[s] >> (C + k)) & 1u) xw[k] += wt * xc[cb + size_t(pp1[s]) * C + k];
+          }
+        }
+        if (s == 0)
+#pragma unroll
+          for (int k = 0; k < C; ++k) xs[q][k] = xw[k];
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * xw[k];
+          acc[q][a] -= s2;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q == 1 && !two) break;
+      const size_t base = size_t(cc[q]) * stride + size_t(v) * C;
+      double xn[C];
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        double z = 0.0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
+        const double dn = (c1 != 0.0 ? c1 * d[base + a] : 0.0) + c2 * z;
+        if (!UPD) d[base + a] = dn;
+        xn[a] = xs[q][a] + dn;
+      }
+      if constexpr (!UPD) {
+#pragma unroll
+        for (int a = 0; a < C; ++a) xout[base + a] = xn[a];
+      } else {
+        // pressure field on level 0 (C == 1): write the updated state column
+        constexpr int D1 = DIM + 1;
+        const ColDesc cd = cols[cc[q]];
+        double out[D1];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          out[a] = cd.xcur[size_t(v) * D1 + a] + omega * zu[(size_t(cc[q]) * nn + v) * DIM + a];
+        out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * xn[0];
+#pragma unroll
+        for (int a = 0; a < D1; ++a) cd.xout[size_t(v) * D1 + a] = out[a];
+        if (cd.xout2)
+#pragma unroll
+          for (int a = 0; a < D1; ++a) cd.xout2[size_t(v) * D1 + a] = out[a];
+      }
+    }
+  }
+}
+
+// xout = xin + P xc (P1 interpolation, masked) for a group of columns; the
+// parents of the node are found once and reused for every column
+template <int DIM, int C, int G>
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelDev Lf, LevelDev Lc, int isA,
+                                                    const double* __restrict__ xin,
+                                                    const double* __restrict__ xc,
+                                                    double* __restrict__ xout, int nc) {
+  const int nn = Lf.nn;
+  int tile, nblk;
+  tile_coords((nc + G - 1) / G, tile, nblk);
+  const int v = nblk * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  int p0, p1;
+  unsigned pm;
+  prolong_parents<DIM, C>(Lf, Lc, isA ? 0 : DIM, v, p0, p1, pm);
+  const double wt = (pm >> (2 * C)) ? 0.5 : 1.0;
+  const size_t stride = size_t(nn) * C, cstride = size_t(Lc.nn) * C;
+  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+#pragma unroll 2
+  for (int c = cbeg; c < cend; ++c) {
 #pragma unroll
     for (int a = 0; a < C; ++a) {
-      double z = 0.0;
-#pragma unroll
-      for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[t][k];
-      const double dn = (c1 != 0.0 ? c1 * d[base + a] : 0.0) + c2 * z;
-      if (!UPD) d[base + a] = dn;
-      xn[a] = xself[t][a] + dn;
-    }
-    if (!UPD) {
-#pragma unroll
-      for (int a = 0; a < C; ++a) xout[base + a] = xn[a];
-    } else {
-      // pressure field on level 0 (C == 1): write the updated state column
-      constexpr int D1 = DIM + 1;
-      const ColDesc cd = cols[c0 + t];
-      double out[D1];
-#pragma unroll
-      for (int a = 0; a < DIM; ++a)
-        out[a] = cd.xcur[size_t(v) * D1 + a] + omega * zu[(size_t(c0 + t) * nn + v) * DIM + a];
-      out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * xn[0];
-#pragma unroll
-      for (int a = 0; a < D1; ++a) cd.xout[size_t(v) * D1 + a] = out[a];
-      if (cd.xout2)
-#pragma unroll
-        for (int a = 0; a < D1; ++a) cd.xout2[size_t(v) * D1 + a] = out[a];
+      double x = xin[size_t(c) * stride + size_t(v) * C + a];
+      if ((pm >> a) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p0) * C + a];
+      if ((pm >> (C + a)) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p1) * C + a];
+      xout[size_t(c) * stride + size_t(v) * C + a] = x;
     }
   }
 }
 
 // r = b - K x on one level
-template <int DIM, int C, int CTT>
+template <int DIM, int C, int G>
 __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
                                                            const double* __restrict__ b,
                                                            const double* __restrict__ x,
                                                            double* __restrict__ r, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
+  constexpr bool STAT = W * C * C <= 64;
+  constexpr int RS = STAT ? W : 1;
   const int nn = L.nn;
-  const int v = blockIdx.y * kBlock + threadIdx.x;
+  int tile, nblk;
+  tile_coords((nc + G - 1) / G, tile, nblk);
+  const int v = nblk * kBlock + threadIdx.x;
   if (v >= nn) return;
-  const int c0 = blockIdx.x * CTT;
   const double* K = isA ? L.A : L.S;
   const size_t stride = size_t(nn) * C;
-  size_t cb[CTT];
-#pragma unroll
-  for (int t = 0; t < CTT; ++t) cb[t] = size_t(min(c0 + t, nc - 1)) * stride;
   int nb[W];
 #pragma unroll
   for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
-  double acc[CTT][C];
+  double kr[RS][C * C];
+  if constexpr (STAT) {
 #pragma unroll
-  for (int t = 0; t < CTT; ++t)
+    for (int s = 0; s < W; ++s)
 #pragma unroll
-    for (int a = 0; a < C; ++a) acc[t][a] = b[cb[t] + size_t(v) * C + a];
+      for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
+  }
+  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+#pragma unroll 1
+  for (int c = cbeg; c < cend; c += 2) {
+    const bool two = c + 1 < cend;
+    const int cc[2] = {c, two ? c + 1 : c};
+    double acc[2][C];
 #pragma unroll
-  for (int s = 0; s < W; ++s) {
-    const int w = nb[s];
-    double blk[C * C];
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int e = 0; e < C * C; ++e) blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+      for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + size_t(v) * C + a];
 #pragma unroll
-    for (int t = 0; t < CTT; ++t) {
+    for (int s = 0; s < W; ++s) {
+      const int w = nb[s];
+      double blk[C * C];
 #pragma unroll
-      for (int a = 0; a < C; ++a) {
-        double s2 = 0.0;
+      for (int e = 0; e < C * C; ++e) {
+        if constexpr (STAT) blk[e] = kr[s][e];
+        else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+      }
 #pragma unroll
-        for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[cb[t] + size_t(w) * C + k];
-        acc[t][a] -= s2;
+      for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[size_t(cc[q]) * stride + size_t(w) * C + k];
+          acc[q][a] -= s2;
+        }
       }
     }
-  }
 #pragma unroll
-  for (int t = 0; t < CTT; ++t) {
-    if (c0 + t >= nc) break;
+    for (int q = 0; q < 2; ++q) {
+      if (q == 1 && !two) break;
 #pragma unroll
-    for (int a = 0; a < C; ++a) r[cb[t] + size_t(v) * C + a] = acc[t][a];
+      for (int a = 0; a < C; ++a) r[size_t(cc[q]) * stride + size_t(v) * C + a] = acc[q][a];
+    }
   }
 }
 
@@ -450,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
 
 // pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), and the first
 // Chebyshev step of the pressure V-cycle
-template <int DIM, int CTT>
+template <int DIM, int G>
 __global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1,
                                                    const double* __restrict__ zu,
                                                    const double* __restrict__ rp,
@@ -458,38 +572,50 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1
                                                    double* __restrict__ xa,
                                                    double* __restrict__ d, double inv_theta,
                                                    int nc) {
-  const int nn = L.nn;
-  const int v = blockIdx.y * kBlock + threadIdx.x;
-  if (v >= nn) return;
-  const int c0 = blockIdx.x * CTT;
-  double acc[CTT];
-#pragma unroll
-  for (int t = 0; t < CTT; ++t) acc[t] = -rp[size_t(min(c0 + t, nc - 1)) * nn + v];
   constexpr int W = DIM == 2 ? 7 : 15;
-  if (p1) {
+  const int nn = L.nn;
+  int tile, nblk;
+  tile_coords((nc + G - 1) / G, tile, nblk);
+  const int v = nblk * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  int nb[W];
+  double bt[W][DIM];
 #pragma unroll
-    for (int s = 0; s < W; ++s) {
-      const int w = L.nbr[size_t(s) * nn + v];
-      double Btb[DIM];
+  for (int s = 0; s < W; ++s) {
+    nb[s] = L.nbr[size_t(s) * nn + v];
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) Btb[c] = F.Bt[(size_t(s) * DIM + c) * nn + v];
-#pragma unroll
-      for (int t = 0; t < CTT; ++t) {
-        const size_t base = size_t(min(c0 + t, nc - 1)) * nn * DIM + size_t(w) * DIM;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[t] += Btb[c] * zu[base + c];
-      }
-    }
+    for (int k = 0; k < DIM; ++k) bt[s][k] = p1 ? F.Bt[(size_t(s) * DIM + k) * nn + v] : 0.0;
   }
   const double si = L.Sinv[v];
+  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+#pragma unroll 1
+  for (int c = cbeg; c < cend; c += 2) {
+    const bool two = c + 1 < cend;
+    const int cc[2] = {c, two ? c + 1 : c};
+    double acc[2];
 #pragma unroll
-  for (int t = 0; t < CTT; ++t) {
-    if (c0 + t >= nc) break;
-    const size_t idx = size_t(c0 + t) * nn + v;
-    t_out[idx] = acc[t];
-    const double z = si * acc[t] * inv_theta;
-    xa[idx] = z;
-    d[idx] = z;
+    for (int q = 0; q < 2; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
+    if (p1) {
+#pragma unroll
+      for (int s = 0; s < W; ++s) {
+        const int w = nb[s];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const size_t base = size_t(cc[q]) * nn * DIM + size_t(w) * DIM;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) acc[q] += bt[s][k] * zu[base + k];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q == 1 && !two) break;
+      const size_t idx = size_t(cc[q]) * nn + v;
+      t_out[idx] = acc[q];
+      const double z = si * acc[q] * inv_theta;
+      xa[idx] = z;
+      d[idx] = z;
+    }
   }
 }
 
@@ -614,25 +740,41 @@ __global__ __launch_bounds__(kBlock) void k_pre1(LevelDev L, int isA, const doub
   }
 }
 
-inline dim3 tiled_grid(int nc, int nn, int ct) { return dim3((nc + ct - 1) / ct, num_node_blocks(nn)); }
+inline dim3 tiled_grid(int nc, int nn, int ct) {
+  const int nb8 = (num_node_blocks(nn) + 7) / 8 * 8;
+  return dim3(nb8 * ((nc + ct - 1) / ct));
+}
 inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
 
-// runtime column tile -> template instantiation
-#define BIOT_CT_SWITCH(ct, ...)                         \
-  switch (ct) {                                         \
-    case 1: { constexpr int CTT = 1; __VA_ARGS__; } break; \
-    case 2: { constexpr int CTT = 2; __VA_ARGS__; } break; \
-    case 8: { constexpr int CTT = 8; __VA_ARGS__; } break; \
-    default: { constexpr int CTT = 4; __VA_ARGS__; } break; \
+// runtime column group -> template instantiation
+#define BIOT_CT_SWITCH(ct, ...)                              \
+  switch (ct) {                                              \
+    case 1: { constexpr int CTT = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int CTT = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int CTT = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int CTT = 8; __VA_ARGS__; } break;   \
+    case 32: { constexpr int CTT = 32; __VA_ARGS__; } break; \
+    default: { constexpr int CTT = 16; __VA_ARGS__; } break; \
   }
 
 }  // namespace
 
-bool valid_col_tile(int ct) { return ct == 1 || ct == 2 || ct == 4 || ct == 8; }
+bool valid_col_tile(int ct) {
+  return ct == 1 || ct == 2 || ct == 4 || ct == 8 || ct == 16 || ct == 32;
+}
+
+// largest column group <= gmax that still gives the grid enough workgroups
+int pick_group(int nc, int nn, int gmax) {
+  const long nb8 = (num_node_blocks(nn) + 7) / 8 * 8;
+  int g = gmax;
+  while (g > 1 && nb8 * ((nc + g - 1) / g) < 1024) g >>= 1;
+  return g;
+}
 
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                      double* ru, double* rp, double* xa, double* d, double inv_theta,
                      double* partials, int pstride, int ct, hipStream_t st) {
+  ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
   if (dim == 2) {
     BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_residual<2, CTT>), g, dim3(kBlock), 0, st, L, F, cols,
@@ -648,6 +790,7 @@ static void cheb_dispatch(const LevelDev& L, const LevelDev& Lc, bool is_A, cons
                           const double* xin, const double* xc, double* xout, double* d, int nc,
                           double c1, double c2, const ColDesc* cols, const double* zu,
                           double omega, int ct, bool fine, hipStream_t st) {
+  ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
   if (fine) {
     BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, CTT, PRO, UPD, true>), g, dim3(kBlock), 0,
@@ -690,6 +833,7 @@ void launch_cheb(int dim, int comps, const LevelDev& L, const LevelDev* Lc, bool
 
 void launch_level_residual(int dim, int comps, const LevelDev& L, bool is_A, const double* b,
                            const double* x, double* r, int nc, int ct, hipStream_t st) {
+  ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
   if (dim == 2) {
     if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 1, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
@@ -714,6 +858,20 @@ void launch_restrict(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc,
 }
 
 
+void launch_prolong(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
+                    const double* xin, const double* xc, double* xout, int nc, int ct,
+                    hipStream_t st) {
+  ct = pick_group(nc, Lf.nn, ct);
+  const dim3 g = tiled_grid(nc, Lf.nn, ct);
+  if (dim == 2) {
+    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 1, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 2, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+  } else {
+    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 1, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 3, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+  }
+}
+
 void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, int nc,
                          hipStream_t st) {
   hipLaunchKernelGGL(k_coarse_solve, dim3(nc), dim3(kBlock), size_t(n) * sizeof(double), st, n,
@@ -723,6 +881,7 @@ void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, 
 void launch_pstage(int dim, const LevelDev& L, const FineDev& F, bool p1, const double* zu,
                    const double* rp, double* t, double* xa, double* d, double inv_theta, int nc,
                    int ct, hipStream_t st) {
+  ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
   if (dim == 2) {
     BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_pstage<2, CTT>), g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc))

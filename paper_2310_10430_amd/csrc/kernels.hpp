@@ -58,6 +58,9 @@ void launch_level_residual(int dim, int comps, const LevelDev& L, bool is_A, con
 void launch_restrict(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
                      const double* rf, double* bc, double* xa_c, double* d_c, double inv_theta_c,
                      int nc, hipStream_t st);
+void launch_prolong(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
+                    const double* xin, const double* xc, double* xout, int nc, int ct,
+                    hipStream_t st);
 void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, int nc,
                          hipStream_t st);
 void launch_pstage(int dim, const LevelDev& L, const FineDev& F, bool p1, const double* zu,

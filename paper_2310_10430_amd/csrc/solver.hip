@@ -373,8 +373,10 @@ int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out, const ColDesc
   double* xc = nullptr;
   int rc = vcycle(h, is_A, l + 1, nc, &xc, nullptr, nullptr);
   if (rc) return rc;
-  // post-smoothing: deg steps, restarting the recurrence; the first one also
-  // applies the coarse-grid correction x += P xc
+  // coarse-grid correction x += P xc, then deg post-smoothing steps
+  launch_prolong(h->dim, C, h->L[l], h->L[l + 1], is_A, cur, xc, oth, nc, ct, st);
+  LAUNCHCHK(h);
+  std::swap(cur, oth);
   rho = 1.0 / cc.sigma;
   for (int j = 1; j <= deg; ++j) {
     double c1 = 0.0, c2 = 1.0 / cc.theta, rn = rho;
@@ -384,10 +386,9 @@ int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out, const ColDesc
       c2 = 2.0 * rn / cc.delta;
     }
     const bool final_upd = upd && j == deg;
-    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, j == 1, final_upd) : 0);
-    launch_cheb(h->dim, C, h->L[l], j == 1 ? &h->L[l + 1] : nullptr, is_A, f.b[l], cur,
-                j == 1 ? xc : nullptr, oth, f.d[l], nc, c1, c2, final_upd ? upd : nullptr, zu,
-                h->opt.omega, ct, fine, st);
+    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, false, final_upd) : 0);
+    launch_cheb(h->dim, C, h->L[l], nullptr, is_A, f.b[l], cur, nullptr, oth, f.d[l], nc, c1, c2,
+                final_upd ? upd : nullptr, zu, h->opt.omega, ct, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -515,7 +516,7 @@ int biot_default_options(biot_options* o) {
   o->power_iters = 20;
   o->max_batch = 0;
   o->omega = 0.6;
-  o->col_tile = 4;
+  o->col_tile = 16;
   return BIOT_OK;
 }
 

@@ -17,7 +17,7 @@ from . import _lib
 
 def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
                   cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
-                  col_tile=4):
+                  col_tile=16):
     """biot_create on the host (no device work); returns (handle, options)."""
     lib = _lib.load()
     xyz = np.ascontiguousarray(problem.xyz, dtype=np.float64)
@@ -89,7 +89,7 @@ class BiotSolver:
     def __init__(self, problem, schedule: str = "jacobi", depth: int = 8, precond: str = "P1",
                  omega: float = 0.6, cheb_degree: int = 2, cheb_ratio: float = 4.0,
                  lmax_safety: float = 1.1, power_iters: int = 20, max_batch: int = 0,
-                 device: str = "cuda:0", beta=None, col_tile: int = 4):
+                 device: str = "cuda:0", beta=None, col_tile: int = 16):
         if not torch.cuda.is_available():
             raise RuntimeError("BiotSolver needs a ROCm GPU (torch.cuda is not available)")
         self.lib = _lib.load()
