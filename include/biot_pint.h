@@ -66,6 +66,12 @@ extern "C" {
                                 /* as a pipeline (Alg. 4)                       */
 #define BIOT_PRECOND_P1 1       /* eq. (p1), block lower triangular             */
 #define BIOT_PRECOND_P2 2       /* eq. (p2), block diagonal                     */
+#define BIOT_PRECISION_FP64 0   /* everything in FP64                           */
+#define BIOT_PRECISION_MIXED 1  /* residual, coupling and update in FP64; the   */
+                                /* preconditioner (both V-cycles, the pressure  */
+                                /* stage) in FP32.  Each sweep is one step of   */
+                                /* iterative refinement, so the fixed point is  */
+                                /* the FP64 one                                 */
 
 typedef struct biot_handle biot_handle;
 
@@ -110,6 +116,11 @@ typedef struct {
   int32_t max_batch;    /* Jacobi: columns per launch, <= 0 for all steps (0)      */
   double omega;         /* damping of the outer update (0.6)                       */
   int32_t col_tile;     /* max time-step columns per GPU thread loop: 1..32 (16)   */
+  int32_t coarse_cells; /* multigrid: halve the grid while it is even and the half */
+                        /* still has >= coarse_cells cells per side (2); the last  */
+                        /* level is solved with a dense inverse                    */
+  int32_t use_graph;    /* wavefront: replay each pass as a captured HIP graph (1) */
+  int32_t precision;    /* BIOT_PRECISION_* (default FP64)                          */
 } biot_options;
 
 typedef struct {

@@ -11,6 +11,7 @@ BIOT_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDIVERGED", -5: "ENOTCONVERGED", -6: "ESTATE"}
 SCHED = {"jacobi": 0, "wavefront": 1}
 PRECOND = {"P1": 1, "P2": 2}
+PRECISION = {"fp64": 0, "mixed": 1}
 PROBES = ["residual", "cheb_u", "cheb_p", "levres_u", "levres_p", "pstage"]
 
 _dp = C.POINTER(C.c_double)
@@ -36,7 +37,9 @@ class Options(C.Structure):
     _fields_ = [("schedule", C.c_int32), ("depth", C.c_int32), ("precond", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("lmax_safety", C.c_double), ("power_iters", C.c_int32),
-                ("max_batch", C.c_int32), ("omega", C.c_double), ("col_tile", C.c_int32)]
+                ("max_batch", C.c_int32), ("omega", C.c_double), ("col_tile", C.c_int32),
+                ("coarse_cells", C.c_int32), ("use_graph", C.c_int32),
+                ("precision", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -1,23 +1,26 @@
 // HIP kernels (gfx950) of the preconditioned inverted time-stepping sweep.
 //
 // Every kernel processes a batch of columns (time steps / iterations) at once.
-// A thread owns one node and a tile of CT columns: the node's matrix blocks
-// are loaded once per slot and applied to all CT columns, so the operator is
-// read once per column tile while the column data streams through.  The grid
-// is (column tiles, node blocks) with the column tile fastest, so the
-// workgroups that share a node block -- and its matrix rows -- are dispatched
-// back to back and hit in L2/MALL.
+//
+// Thread mapping of the node-blocked kernels ("operator-stationary"): a thread
+// owns one node, loads that node's operator row (all stencil slots) into
+// registers once, and then loops over a group of G time-step columns two at a
+// time.  The operator is read once per column group while the column data
+// streams through.  The grid is (column groups) x (node blocks), ordered so
+// that all groups of one node block run on the same XCD (see tile_coords).
+// Rows too large for registers (3D displacement blocks) are re-read per column
+// pair, from L1/L2.
 //
 // Layouts (see setup.hpp): operator values [slot][entry][node]; state columns
-// node-major [node][u_x, u_y, (u_z), p]; multigrid work vectors node-major
-// [node][comp], one contiguous vector per column of the batch.
+// node-major [node][u_x, u_y, (u_z), p] in FP64; multigrid work vectors
+// node-major [node][comp], one contiguous vector per column of the batch, of
+// type T (double, or float in the mixed-precision preconditioner).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
 
 namespace biot {
 namespace {
-
 
 __constant__ int c_off2[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0},
                                  {0, -1, 0}, {1, 1, 0}, {-1, -1, 0}};
@@ -36,11 +39,11 @@ __device__ inline int node_id(int i, int j, int k, int m) {
   return DIM == 2 ? j * m + i : (k * m + j) * m + i;
 }
 
-// XCD-aware workgroup order for the (column tile, node block) grid: workgroups
-// are dealt to the 8 XCDs round-robin, so workgroup i runs on XCD i % 8.  All
-// column tiles of node block b are given ids that land on XCD b % 8 back to
-// back, so the block's operator rows are fetched into that XCD's L2 once and
-// reused by every column tile.
+// XCD-aware workgroup order for the (column group, node block) grid: the
+// hardware deals workgroups to the 8 XCDs round-robin (workgroup i on XCD
+// i % 8).  All column groups of node block b get ids that land on XCD b % 8
+// back to back, so the block's operator rows are fetched into that XCD's L2
+// once and reused by every group.
 __device__ inline void tile_coords(int ntiles, int& tile, int& nblk) {
   const int i = blockIdx.x;
   const int j = i >> 3;
@@ -49,7 +52,8 @@ __device__ inline void tile_coords(int ntiles, int& tile, int& nblk) {
 }
 
 // Deterministic block sum of Q values per thread (wave64 shuffles, then LDS
-// across the 4 waves in a fixed order).  Result valid in thread 0.
+// across the 4 waves in a fixed order).  Result valid in thread 0.  Every
+// thread of the block must call it.
 template <int Q>
 __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
 #pragma unroll
@@ -71,24 +75,16 @@ __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
 }
 
 // ---------------------------------------------------------------------------
-// Thread mapping of the node-blocked kernels ("operator-stationary"): a thread
-// owns one node, loads that node's operator row (all slots) into registers
-// once, and then loops over a group of G time-step columns two at a time.  The
-// operator is read once per column group, the column data streams through,
-// and the grid is (column groups) x (node blocks) in XCD-aware order.  Rows too
-// large for registers (3D) are re-read per column pair from L1/L2 instead.
+// fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1} (FP64), the
+// coupled right-hand side norms, and the first (pointwise) Chebyshev step of
+// the displacement V-cycle; r and that step are stored as T
 // ---------------------------------------------------------------------------
-
-// fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1}, the coupled
-// right-hand side norms, and the first (pointwise) Chebyshev step of the
-// displacement V-cycle
-template <int DIM, int G>
+template <int DIM, int G, typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
-                                                     double* __restrict__ ru,
-                                                     double* __restrict__ rp,
-                                                     double* __restrict__ xa,
-                                                     double* __restrict__ d, double inv_theta,
+                                                     T* __restrict__ ru, T* __restrict__ rp,
+                                                     T* __restrict__ xa, T* __restrict__ d,
+                                                     double inv_theta,
                                                      double* __restrict__ partials, int pstride) {
   constexpr int D1 = DIM + 1;
   constexpr int W = DIM == 2 ? 7 : 15;
@@ -200,8 +196,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
       const size_t cu = size_t(cc[q]) * nn * DIM;
       if (ru) {
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = au[q][a];
-        rp[size_t(cc[q]) * nn + v] = ap[q];
+        for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = T(au[q][a]);
+        rp[size_t(cc[q]) * nn + v] = T(ap[q]);
       }
       if (xa) {
 #pragma unroll
@@ -210,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
 #pragma unroll
           for (int k = 0; k < DIM; ++k) z += Di[a * DIM + k] * au[q][k];
           z *= inv_theta;
-          xa[cu + size_t(v) * DIM + a] = z;
-          d[cu + size_t(v) * DIM + a] = z;
+          xa[cu + size_t(v) * DIM + a] = T(z);
+          d[cu + size_t(v) * DIM + a] = T(z);
         }
       }
     }
@@ -246,12 +242,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
 
 // ---------------------------------------------------------------------------
 // Prolongation of fine node f: parents p0, p1 on the coarse grid and a bit mask
-// of the components that receive each parent (bit a: p0, bit C+a: p1); the
-// weight is 1 for a coincident node, 1/2 for an edge midpoint.
+// of the components that receive each parent (bit a: p0, bit C+a: p1, bit 2C:
+// edge midpoint with weight 1/2; otherwise a coincident node with weight 1).
+// A component is masked when the fine or the coarse dof is prescribed.
 // ---------------------------------------------------------------------------
-template <int DIM, int C>
-__device__ inline void prolong_parents(const LevelDev& Lf, const LevelDev& Lc, int bit0, int f,
-                                       int& p0, int& p1, unsigned& mask) {
+template <int DIM, int C, typename T>
+__device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T>& Lc, int bit0,
+                                       int f, int& p0, int& p1, unsigned& mask) {
   const int mf = Lf.n_cells + 1, mc = Lc.n_cells + 1;
   int i, j, k;
   node_coords<DIM>(f, mf, i, j, k);
@@ -271,21 +268,18 @@ __device__ inline void prolong_parents(const LevelDev& Lf, const LevelDev& Lc, i
 }
 
 // ---------------------------------------------------------------------------
-// Chebyshev step on one level:
-//     x  = xin               (PRO: x = xin + P xc, the coarse correction fused in)
-//     d <- c1 d + c2 D^{-1}(b - K x);   xout = x + d
+// Chebyshev step on one level:  d <- c1 d + c2 D^{-1}(b - K xin);  xout = xin + d.
 // UPD (pressure field, level 0, last step): instead of xout, writes the outer
-// update X^{n,m} = X^{n,m-1} + omega [z_u; x + d] through the column descriptors.
+// update X^{n,m} = X^{n,m-1} + omega [z_u; xin + d] (FP64) through the column
+// descriptors.  FINE only makes the level-0 launches a distinct symbol.
 // ---------------------------------------------------------------------------
-template <int DIM, int C, int G, bool PRO, bool UPD, bool FINE>
-__global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int isA,
-                                                 const double* __restrict__ b,
-                                                 const double* __restrict__ xin,
-                                                 const double* __restrict__ xc,
-                                                 double* __restrict__ xout, double* __restrict__ d,
-                                                 int nc, double c1, double c2,
-                                                 const ColDesc* __restrict__ cols,
-                                                 const double* __restrict__ zu, double omega) {
+template <int DIM, int C, int G, bool UPD, bool FINE, typename T>
+__global__ __launch_bounds__(kBlock) void k_cheb(LevelView<T> L, int isA,
+                                                 const T* __restrict__ b,
+                                                 const T* __restrict__ xin,
+                                                 T* __restrict__ xout, T* __restrict__ d, int nc,
+                                                 T c1, T c2, const ColDesc* __restrict__ cols,
+                                                 const T* __restrict__ zu, double omega) {
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = W * C * C <= 64;
   constexpr int RS = STAT ? W : 1;
@@ -294,28 +288,20 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
   tile_coords((nc + G - 1) / G, tile, nblk);
   const int v = nblk * kBlock + threadIdx.x;
   if (v >= nn) return;
-  const double* K = isA ? L.A : L.S;
-  const double* Dg = isA ? L.Ainv : L.Sinv;
-  const int bit0 = isA ? 0 : DIM;
+  const T* K = isA ? L.A : L.S;
+  const T* Dg = isA ? L.Ainv : L.Sinv;
   const size_t stride = size_t(nn) * C;
-  const size_t cstride = PRO ? size_t(Lc.nn) * C : 0;
   int nb[W];
 #pragma unroll
   for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
-  double kr[RS][C * C];
+  T kr[RS][C * C];
   if constexpr (STAT) {
 #pragma unroll
     for (int s = 0; s < W; ++s)
 #pragma unroll
       for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
   }
-  int pp0[PRO ? W : 1], pp1[PRO ? W : 1];
-  unsigned pm[PRO ? W : 1];
-  if constexpr (PRO) {
-#pragma unroll
-    for (int s = 0; s < W; ++s) prolong_parents<DIM, C>(L, Lc, bit0, nb[s], pp0[s], pp1[s], pm[s]);
-  }
-  double Di[C * C];
+  T Di[C * C];
 #pragma unroll
   for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
   const int cbeg = tile * G, cend = min(nc, cbeg + G);
@@ -323,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
   for (int c = cbeg; c < cend; c += 2) {
     const bool two = c + 1 < cend;
     const int cc[2] = {c, two ? c + 1 : c};
-    double acc[2][C], xs[2][C];
+    T acc[2][C], xs[2][C];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -331,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
 #pragma unroll
     for (int s = 0; s < W; ++s) {
       const int w = nb[s];
-      double blk[C * C];
+      T blk[C * C];
 #pragma unroll
       for (int e = 0; e < C * C; ++e) {
         if constexpr (STAT) blk[e] = kr[s][e];
@@ -339,23 +325,15 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
       }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        double xw[C];
+        T xw[C];
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-          xw[k] = xin[size_t(cc[q]) * stride + size_t(w) * C + k];
-          if constexpr (PRO) {
-            const double wt = (pm[s] >> (2 * C)) ? 0.5 : 1.0;
-            const size_t cb = size_t(cc[q]) * cstride;
-            if ((pm[s] >> k) & 1u) xw[k] += wt * xc[cb + size_t(pp0[s]) * C + k];
-            if ((pm[s] >> (C + k)) & 1u) xw[k] += wt * xc[cb + size_t(pp1[s]) * C + k];
-          }
-        }
+        for (int k = 0; k < C; ++k) xw[k] = xin[size_t(cc[q]) * stride + size_t(w) * C + k];
         if (s == 0)
 #pragma unroll
           for (int k = 0; k < C; ++k) xs[q][k] = xw[k];
 #pragma unroll
         for (int a = 0; a < C; ++a) {
-          double s2 = 0.0;
+          T s2 = T(0);
 #pragma unroll
           for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * xw[k];
           acc[q][a] -= s2;
@@ -366,13 +344,13 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
     for (int q = 0; q < 2; ++q) {
       if (q == 1 && !two) break;
       const size_t base = size_t(cc[q]) * stride + size_t(v) * C;
-      double xn[C];
+      T xn[C];
 #pragma unroll
       for (int a = 0; a < C; ++a) {
-        double z = 0.0;
+        T z = T(0);
 #pragma unroll
         for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
-        const double dn = (c1 != 0.0 ? c1 * d[base + a] : 0.0) + c2 * z;
+        const T dn = (c1 != T(0) ? c1 * d[base + a] : T(0)) + c2 * z;
         if (!UPD) d[base + a] = dn;
         xn[a] = xs[q][a] + dn;
       }
@@ -386,8 +364,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
         double out[D1];
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
-          out[a] = cd.xcur[size_t(v) * D1 + a] + omega * zu[(size_t(cc[q]) * nn + v) * DIM + a];
-        out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * xn[0];
+          out[a] = cd.xcur[size_t(v) * D1 + a] +
+                   omega * double(zu[(size_t(cc[q]) * nn + v) * DIM + a]);
+        out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * double(xn[0]);
 #pragma unroll
         for (int a = 0; a < D1; ++a) cd.xout[size_t(v) * D1 + a] = out[a];
         if (cd.xout2)
@@ -400,11 +379,11 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelDev L, LevelDev Lc, int is
 
 // xout = xin + P xc (P1 interpolation, masked) for a group of columns; the
 // parents of the node are found once and reused for every column
-template <int DIM, int C, int G>
-__global__ __launch_bounds__(kBlock) void k_prolong(LevelDev Lf, LevelDev Lc, int isA,
-                                                    const double* __restrict__ xin,
-                                                    const double* __restrict__ xc,
-                                                    double* __restrict__ xout, int nc) {
+template <int DIM, int C, int G, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelView<T> Lf, LevelView<T> Lc, int isA,
+                                                    const T* __restrict__ xin,
+                                                    const T* __restrict__ xc,
+                                                    T* __restrict__ xout, int nc) {
   const int nn = Lf.nn;
   int tile, nblk;
   tile_coords((nc + G - 1) / G, tile, nblk);
@@ -413,14 +392,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelDev Lf, LevelDev Lc, in
   int p0, p1;
   unsigned pm;
   prolong_parents<DIM, C>(Lf, Lc, isA ? 0 : DIM, v, p0, p1, pm);
-  const double wt = (pm >> (2 * C)) ? 0.5 : 1.0;
+  const T wt = (pm >> (2 * C)) ? T(0.5) : T(1);
   const size_t stride = size_t(nn) * C, cstride = size_t(Lc.nn) * C;
   const int cbeg = tile * G, cend = min(nc, cbeg + G);
 #pragma unroll 2
   for (int c = cbeg; c < cend; ++c) {
 #pragma unroll
     for (int a = 0; a < C; ++a) {
-      double x = xin[size_t(c) * stride + size_t(v) * C + a];
+      T x = xin[size_t(c) * stride + size_t(v) * C + a];
       if ((pm >> a) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p0) * C + a];
       if ((pm >> (C + a)) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p1) * C + a];
       xout[size_t(c) * stride + size_t(v) * C + a] = x;
@@ -429,11 +408,11 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelDev Lf, LevelDev Lc, in
 }
 
 // r = b - K x on one level
-template <int DIM, int C, int G>
-__global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
-                                                           const double* __restrict__ b,
-                                                           const double* __restrict__ x,
-                                                           double* __restrict__ r, int nc) {
+template <int DIM, int C, int G, typename T>
+__global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int isA,
+                                                           const T* __restrict__ b,
+                                                           const T* __restrict__ x,
+                                                           T* __restrict__ r, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = W * C * C <= 64;
   constexpr int RS = STAT ? W : 1;
@@ -442,12 +421,12 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
   tile_coords((nc + G - 1) / G, tile, nblk);
   const int v = nblk * kBlock + threadIdx.x;
   if (v >= nn) return;
-  const double* K = isA ? L.A : L.S;
+  const T* K = isA ? L.A : L.S;
   const size_t stride = size_t(nn) * C;
   int nb[W];
 #pragma unroll
   for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
-  double kr[RS][C * C];
+  T kr[RS][C * C];
   if constexpr (STAT) {
 #pragma unroll
     for (int s = 0; s < W; ++s)
@@ -459,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
   for (int c = cbeg; c < cend; c += 2) {
     const bool two = c + 1 < cend;
     const int cc[2] = {c, two ? c + 1 : c};
-    double acc[2][C];
+    T acc[2][C];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -467,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
 #pragma unroll
     for (int s = 0; s < W; ++s) {
       const int w = nb[s];
-      double blk[C * C];
+      T blk[C * C];
 #pragma unroll
       for (int e = 0; e < C * C; ++e) {
         if constexpr (STAT) blk[e] = kr[s][e];
@@ -477,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
       for (int q = 0; q < 2; ++q) {
 #pragma unroll
         for (int a = 0; a < C; ++a) {
-          double s2 = 0.0;
+          T s2 = T(0);
 #pragma unroll
           for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[size_t(cc[q]) * stride + size_t(w) * C + k];
           acc[q][a] -= s2;
@@ -495,13 +474,11 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev L, int isA,
 
 // coarse b = P' r_fine (P1 interpolation transpose, masked), plus the first
 // Chebyshev step of the coarse level when it is not the coarsest
-template <int DIM, int C>
-__global__ __launch_bounds__(kBlock) void k_restrict(LevelDev Lf, LevelDev Lc, int isA,
-                                                     const double* __restrict__ rf,
-                                                     double* __restrict__ bc,
-                                                     double* __restrict__ xa,
-                                                     double* __restrict__ d, double inv_theta,
-                                                     int nc) {
+template <int DIM, int C, typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<T> Lc, int isA,
+                                                     const T* __restrict__ rf,
+                                                     T* __restrict__ bc, T* __restrict__ xa,
+                                                     T* __restrict__ d, T inv_theta, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int I = blockIdx.y * kBlock + threadIdx.x;
   if (I >= Lc.nn) return;
@@ -512,16 +489,16 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev Lf, LevelDev Lc, i
   const uint8_t fc = Lc.fixed[I];
   const int bit0 = isA ? 0 : DIM;
   const size_t sf = size_t(Lf.nn) * C, sc = size_t(Lc.nn) * C;
-  double acc[C];
+  T acc[C];
 #pragma unroll
-  for (int a = 0; a < C; ++a) acc[a] = 0.0;
+  for (int a = 0; a < C; ++a) acc[a] = T(0);
 #pragma unroll
   for (int s = 0; s < W; ++s) {
     const int* o = DIM == 2 ? c_off2[s] : c_off3[s];
     const int fi = 2 * ci + o[0], fj = 2 * cj + o[1], fk = 2 * ck + o[2];
     if (fi < 0 || fi >= mf || fj < 0 || fj >= mf || fk < 0 || fk >= mf) continue;
     const int f = node_id<DIM>(fi, fj, fk, mf);
-    const double wgt = s == 0 ? 1.0 : 0.5;
+    const T wgt = s == 0 ? T(1) : T(0.5);
     const uint8_t ff = Lf.fixed[f];
 #pragma unroll
     for (int a = 0; a < C; ++a)
@@ -529,14 +506,14 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev Lf, LevelDev Lc, i
   }
 #pragma unroll
   for (int a = 0; a < C; ++a) {
-    if ((fc >> (bit0 + a)) & 1) acc[a] = 0.0;
+    if ((fc >> (bit0 + a)) & 1) acc[a] = T(0);
     bc[size_t(c) * sc + size_t(I) * C + a] = acc[a];
   }
   if (xa) {
-    const double* Dg = isA ? Lc.Ainv : Lc.Sinv;
+    const T* Dg = isA ? Lc.Ainv : Lc.Sinv;
 #pragma unroll
     for (int a = 0; a < C; ++a) {
-      double z = 0.0;
+      T z = T(0);
 #pragma unroll
       for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + I] * acc[k];
       z *= inv_theta;
@@ -547,16 +524,18 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev Lf, LevelDev Lc, i
 }
 
 // coarsest level: x = M^{-1} b with the dense inverse, one workgroup per column
-__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ Minv,
-                                                         const double* __restrict__ b,
-                                                         double* __restrict__ x) {
-  extern __shared__ double sb[];
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const T* __restrict__ Minv,
+                                                         const T* __restrict__ b,
+                                                         T* __restrict__ x) {
+  extern __shared__ double sb_raw[];
+  T* sb = reinterpret_cast<T*>(sb_raw);
   const int c = blockIdx.x;
   for (int i = threadIdx.x; i < n; i += kBlock) sb[i] = b[size_t(c) * n + i];
   __syncthreads();
   for (int r = threadIdx.x; r < n; r += kBlock) {
-    double acc = 0.0;
-    const double* row = Minv + size_t(r) * n;
+    T acc = T(0);
+    const T* row = Minv + size_t(r) * n;
     for (int j = 0; j < n; ++j) acc += row[j] * sb[j];
     x[size_t(c) * n + r] = acc;
   }
@@ -564,14 +543,12 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
 
 // pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), and the first
 // Chebyshev step of the pressure V-cycle
-template <int DIM, int G>
-__global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1,
-                                                   const double* __restrict__ zu,
-                                                   const double* __restrict__ rp,
-                                                   double* __restrict__ t_out,
-                                                   double* __restrict__ xa,
-                                                   double* __restrict__ d, double inv_theta,
-                                                   int nc) {
+template <int DIM, int G, typename T>
+__global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __restrict__ Bt,
+                                                   int p1, const T* __restrict__ zu,
+                                                   const T* __restrict__ rp,
+                                                   T* __restrict__ t_out, T* __restrict__ xa,
+                                                   T* __restrict__ d, T inv_theta, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
   int tile, nblk;
@@ -579,20 +556,20 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1
   const int v = nblk * kBlock + threadIdx.x;
   if (v >= nn) return;
   int nb[W];
-  double bt[W][DIM];
+  T bt[W][DIM];
 #pragma unroll
   for (int s = 0; s < W; ++s) {
     nb[s] = L.nbr[size_t(s) * nn + v];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) bt[s][k] = p1 ? F.Bt[(size_t(s) * DIM + k) * nn + v] : 0.0;
+    for (int k = 0; k < DIM; ++k) bt[s][k] = p1 ? Bt[(size_t(s) * DIM + k) * nn + v] : T(0);
   }
-  const double si = L.Sinv[v];
+  const T si = L.Sinv[v];
   const int cbeg = tile * G, cend = min(nc, cbeg + G);
 #pragma unroll 1
   for (int c = cbeg; c < cend; c += 2) {
     const bool two = c + 1 < cend;
     const int cc[2] = {c, two ? c + 1 : c};
-    double acc[2];
+    T acc[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
     if (p1) {
@@ -612,18 +589,18 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelDev L, FineDev F, int p1
       if (q == 1 && !two) break;
       const size_t idx = size_t(cc[q]) * nn + v;
       t_out[idx] = acc[q];
-      const double z = si * acc[q] * inv_theta;
+      const T z = si * acc[q] * inv_theta;
       xa[idx] = z;
       d[idx] = z;
     }
   }
 }
 
-// X^{n,m} = X^{n,m-1} + omega [z_u; z_p]
-template <int DIM>
+// X^{n,m} = X^{n,m-1} + omega [z_u; z_p]   (used when the coarsest level is 0)
+template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_update(int nn, const ColDesc* __restrict__ cols,
-                                                   const double* __restrict__ zu,
-                                                   const double* __restrict__ zp, double omega) {
+                                                   const T* __restrict__ zu,
+                                                   const T* __restrict__ zp, double omega) {
   constexpr int D1 = DIM + 1;
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= nn) return;
@@ -634,8 +611,8 @@ __global__ __launch_bounds__(kBlock) void k_update(int nn, const ColDesc* __rest
   double out[D1];
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
-    out[a] = xc[size_t(v) * D1 + a] + omega * zu[(size_t(c) * nn + v) * DIM + a];
-  out[DIM] = xc[size_t(v) * D1 + DIM] + omega * zp[size_t(c) * nn + v];
+    out[a] = xc[size_t(v) * D1 + a] + omega * double(zu[(size_t(c) * nn + v) * DIM + a]);
+  out[DIM] = xc[size_t(v) * D1 + DIM] + omega * double(zp[size_t(c) * nn + v]);
 #pragma unroll
   for (int a = 0; a < D1; ++a) xo[size_t(v) * D1 + a] = out[a];
   if (xo2)
@@ -659,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_norms(const double* __restric
     for (int k = 0; k < 4; ++k) norms[size_t(c) * 4 + k] = q[k];
 }
 
-// Y = AA X (test/diagnostic path)
+// Y = AA X (diagnostic path)
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_apply_operator(LevelDev L, FineDev F,
                                                            const double* __restrict__ X,
@@ -694,44 +671,43 @@ __global__ __launch_bounds__(kBlock) void k_apply_operator(LevelDev L, FineDev F
   y[size_t(v) * D1 + DIM] = yp;
 }
 
-template <int DIM>
+template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_unpack(int nn, const double* __restrict__ X,
-                                                   double* __restrict__ ru,
-                                                   double* __restrict__ rp) {
+                                                   T* __restrict__ ru, T* __restrict__ rp) {
   constexpr int D1 = DIM + 1;
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= nn) return;
   const size_t c = blockIdx.x;
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) ru[(c * nn + v) * DIM + a] = X[(c * nn + v) * D1 + a];
-  rp[c * nn + v] = X[(c * nn + v) * D1 + DIM];
+  for (int a = 0; a < DIM; ++a) ru[(c * nn + v) * DIM + a] = T(X[(c * nn + v) * D1 + a]);
+  rp[c * nn + v] = T(X[(c * nn + v) * D1 + DIM]);
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_pack(int nn, const double* __restrict__ zu,
-                                                 const double* __restrict__ zp,
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_pack(int nn, const T* __restrict__ zu,
+                                                 const T* __restrict__ zp,
                                                  double* __restrict__ Z) {
   constexpr int D1 = DIM + 1;
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= nn) return;
   const size_t c = blockIdx.x;
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) Z[(c * nn + v) * D1 + a] = zu[(c * nn + v) * DIM + a];
-  Z[(c * nn + v) * D1 + DIM] = zp[c * nn + v];
+  for (int a = 0; a < DIM; ++a) Z[(c * nn + v) * D1 + a] = double(zu[(c * nn + v) * DIM + a]);
+  Z[(c * nn + v) * D1 + DIM] = double(zp[c * nn + v]);
 }
 
 // first Chebyshev step from a zero iterate: xa = d = D^{-1} b / theta
-template <int C>
-__global__ __launch_bounds__(kBlock) void k_pre1(LevelDev L, int isA, const double* __restrict__ b,
-                                                 double* __restrict__ xa, double* __restrict__ d,
-                                                 double inv_theta) {
+template <int C, typename T>
+__global__ __launch_bounds__(kBlock) void k_pre1(LevelView<T> L, int isA, const T* __restrict__ b,
+                                                 T* __restrict__ xa, T* __restrict__ d,
+                                                 T inv_theta) {
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= L.nn) return;
   const size_t base = size_t(blockIdx.x) * L.nn * C + size_t(v) * C;
-  const double* Dg = isA ? L.Ainv : L.Sinv;
+  const T* Dg = isA ? L.Ainv : L.Sinv;
 #pragma unroll
   for (int a = 0; a < C; ++a) {
-    double z = 0.0;
+    T z = T(0);
 #pragma unroll
     for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + v] * b[base + k];
     z *= inv_theta;
@@ -747,14 +723,14 @@ inline dim3 tiled_grid(int nc, int nn, int ct) {
 inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
 
 // runtime column group -> template instantiation
-#define BIOT_CT_SWITCH(ct, ...)                              \
-  switch (ct) {                                              \
-    case 1: { constexpr int CTT = 1; __VA_ARGS__; } break;   \
-    case 2: { constexpr int CTT = 2; __VA_ARGS__; } break;   \
-    case 4: { constexpr int CTT = 4; __VA_ARGS__; } break;   \
-    case 8: { constexpr int CTT = 8; __VA_ARGS__; } break;   \
-    case 32: { constexpr int CTT = 32; __VA_ARGS__; } break; \
-    default: { constexpr int CTT = 16; __VA_ARGS__; } break; \
+#define BIOT_G_SWITCH(g, ...)                              \
+  switch (g) {                                             \
+    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
+    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
+    default: { constexpr int G = 16; __VA_ARGS__; } break; \
   }
 
 }  // namespace
@@ -771,130 +747,153 @@ int pick_group(int nc, int nn, int gmax) {
   return g;
 }
 
+template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                     double* ru, double* rp, double* xa, double* d, double inv_theta,
-                     double* partials, int pstride, int ct, hipStream_t st) {
+                     T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials, int pstride,
+                     int ct, hipStream_t st) {
   ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
   if (dim == 2) {
-    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_residual<2, CTT>), g, dim3(kBlock), 0, st, L, F, cols,
-                                          nc, ru, rp, xa, d, inv_theta, partials, pstride))
+    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_residual<2, G, T>), g, dim3(kBlock), 0, st, L, F, cols,
+                                         nc, ru, rp, xa, d, inv_theta, partials, pstride))
   } else {
-    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_residual<3, CTT>), g, dim3(kBlock), 0, st, L, F, cols,
-                                          nc, ru, rp, xa, d, inv_theta, partials, pstride))
+    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_residual<3, G, T>), g, dim3(kBlock), 0, st, L, F, cols,
+                                         nc, ru, rp, xa, d, inv_theta, partials, pstride))
   }
 }
 
-template <int DIM, int C, bool PRO, bool UPD>
-static void cheb_dispatch(const LevelDev& L, const LevelDev& Lc, bool is_A, const double* b,
-                          const double* xin, const double* xc, double* xout, double* d, int nc,
-                          double c1, double c2, const ColDesc* cols, const double* zu,
+template <int DIM, int C, bool UPD, typename T>
+static void cheb_dispatch(const LevelView<T>& L, bool is_A, const T* b, const T* xin, T* xout,
+                          T* d, int nc, double c1, double c2, const ColDesc* cols, const T* zu,
                           double omega, int ct, bool fine, hipStream_t st) {
   ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
   if (fine) {
-    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, CTT, PRO, UPD, true>), g, dim3(kBlock), 0,
-                                          st, L, Lc, int(is_A), b, xin, xc, xout, d, nc, c1, c2,
-                                          cols, zu, omega))
-  } else if (!UPD) {
-    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, CTT, PRO, UPD, false>), g, dim3(kBlock), 0,
-                                          st, L, Lc, int(is_A), b, xin, xc, xout, d, nc, c1, c2,
-                                          cols, zu, omega))
+    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, G, UPD, true, T>), g, dim3(kBlock), 0, st,
+                                         L, int(is_A), b, xin, xout, d, nc, T(c1), T(c2), cols, zu,
+                                         omega))
+  } else if constexpr (!UPD) {
+    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, G, UPD, false, T>), g, dim3(kBlock), 0,
+                                         st, L, int(is_A), b, xin, xout, d, nc, T(c1), T(c2), cols,
+                                         zu, omega))
   }
 }
 
-void launch_cheb(int dim, int comps, const LevelDev& L, const LevelDev* Lc, bool is_A,
-                 const double* b, const double* xin, const double* xc, double* xout, double* d,
-                 int nc, double c1, double c2, const ColDesc* cols, const double* zu,
+template <typename T>
+void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
+                 T* xout, T* d, int nc, double c1, double c2, const ColDesc* upd, const T* zu,
                  double omega, int ct, bool fine, hipStream_t st) {
-  const bool pro = xc != nullptr;
-  const bool upd = cols != nullptr;
-  const LevelDev& C2 = Lc ? *Lc : L;
   if (dim == 2) {
     if (comps == 1) {
-      if (upd) cheb_dispatch<2, 1, false, true>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
-      else if (pro) cheb_dispatch<2, 1, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
-      else cheb_dispatch<2, 1, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      if (upd) cheb_dispatch<2, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
+      else cheb_dispatch<2, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
     } else {
-      if (pro) cheb_dispatch<2, 2, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
-      else cheb_dispatch<2, 2, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      cheb_dispatch<2, 2, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
     }
   } else {
     if (comps == 1) {
-      if (upd) cheb_dispatch<3, 1, false, true>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
-      else if (pro) cheb_dispatch<3, 1, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
-      else cheb_dispatch<3, 1, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      if (upd) cheb_dispatch<3, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
+      else cheb_dispatch<3, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
     } else {
-      if (pro) cheb_dispatch<3, 3, true, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
-      else cheb_dispatch<3, 3, false, false>(L, C2, is_A, b, xin, xc, xout, d, nc, c1, c2, cols, zu, omega, ct, fine, st);
+      cheb_dispatch<3, 3, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
     }
   }
 }
 
-void launch_level_residual(int dim, int comps, const LevelDev& L, bool is_A, const double* b,
-                           const double* x, double* r, int nc, int ct, hipStream_t st) {
+template <typename T>
+void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
+                           const T* x, T* r, int nc, int ct, hipStream_t st) {
   ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
   if (dim == 2) {
-    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 1, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
-    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 2, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 1, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 2, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
   } else {
-    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 1, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
-    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 3, CTT>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 1, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 3, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
   }
 }
 
-void launch_restrict(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
-                     const double* rf, double* bc, double* xa_c, double* d_c, double inv_theta_c,
-                     int nc, hipStream_t st) {
-  dim3 g = col_grid(nc, Lc.nn);
+template <typename T>
+void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
+                     bool is_A, const T* rf, T* bc, T* xa_c, T* d_c, double inv_theta_c, int nc,
+                     hipStream_t st) {
+  const dim3 g = col_grid(nc, Lc.nn);
+  const T it = T(inv_theta_c);
   if (dim == 2) {
-    if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
-    else hipLaunchKernelGGL((k_restrict<2, 2>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
+    else hipLaunchKernelGGL((k_restrict<2, 2, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
   } else {
-    if (comps == 1) hipLaunchKernelGGL((k_restrict<3, 1>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
-    else hipLaunchKernelGGL((k_restrict<3, 3>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, inv_theta_c, nc);
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<3, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
+    else hipLaunchKernelGGL((k_restrict<3, 3, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
   }
 }
 
-
-void launch_prolong(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
-                    const double* xin, const double* xc, double* xout, int nc, int ct,
-                    hipStream_t st) {
+template <typename T>
+void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
+                    const T* xin, const T* xc, T* xout, int nc, int ct, hipStream_t st) {
   ct = pick_group(nc, Lf.nn, ct);
   const dim3 g = tiled_grid(nc, Lf.nn, ct);
   if (dim == 2) {
-    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 1, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
-    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 2, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 1, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 2, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
   } else {
-    if (comps == 1) { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 1, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
-    else { BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 3, CTT>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 1, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 3, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
   }
 }
 
-void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, int nc,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_coarse_solve, dim3(nc), dim3(kBlock), size_t(n) * sizeof(double), st, n,
+template <typename T>
+void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStream_t st) {
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nc), dim3(kBlock), size_t(n) * sizeof(T), st, n,
                      Minv, b, x);
 }
 
-void launch_pstage(int dim, const LevelDev& L, const FineDev& F, bool p1, const double* zu,
-                   const double* rp, double* t, double* xa, double* d, double inv_theta, int nc,
-                   int ct, hipStream_t st) {
+template <typename T>
+void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
+                   T* t, T* xa, T* d, double inv_theta, int nc, int ct, hipStream_t st) {
   ct = pick_group(nc, L.nn, ct);
   const dim3 g = tiled_grid(nc, L.nn, ct);
+  const T it = T(inv_theta);
   if (dim == 2) {
-    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_pstage<2, CTT>), g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc))
+    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_pstage<2, G, T>), g, dim3(kBlock), 0, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc))
   } else {
-    BIOT_CT_SWITCH(ct, hipLaunchKernelGGL((k_pstage<3, CTT>), g, dim3(kBlock), 0, st, L, F, int(p1), zu, rp, t, xa, d, inv_theta, nc))
+    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_pstage<3, G, T>), g, dim3(kBlock), 0, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc))
   }
 }
 
-void launch_update(int dim, int nn, const ColDesc* cols, const double* zu, const double* zp,
-                   double omega, int nc, hipStream_t st) {
-  dim3 g = col_grid(nc, nn);
-  if (dim == 2) hipLaunchKernelGGL(k_update<2>, g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
-  else hipLaunchKernelGGL(k_update<3>, g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
+template <typename T>
+void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* zp, double omega,
+                   int nc, hipStream_t st) {
+  const dim3 g = col_grid(nc, nn);
+  if (dim == 2) hipLaunchKernelGGL((k_update<2, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
+  else hipLaunchKernelGGL((k_update<3, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
+}
+
+template <typename T>
+void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa, T* d,
+                 double inv_theta, int nc, hipStream_t st) {
+  const dim3 g = col_grid(nc, L.nn);
+  const T it = T(inv_theta);
+  switch (comps) {
+    case 1: hipLaunchKernelGGL((k_pre1<1, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, it); break;
+    case 2: hipLaunchKernelGGL((k_pre1<2, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, it); break;
+    default: hipLaunchKernelGGL((k_pre1<3, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, it); break;
+  }
+}
+
+template <typename T>
+void launch_unpack(int dim, int nn, const double* X, T* ru, T* rp, int nc, hipStream_t st) {
+  const dim3 g = col_grid(nc, nn);
+  if (dim == 2) hipLaunchKernelGGL((k_unpack<2, T>), g, dim3(kBlock), 0, st, nn, X, ru, rp);
+  else hipLaunchKernelGGL((k_unpack<3, T>), g, dim3(kBlock), 0, st, nn, X, ru, rp);
+}
+
+template <typename T>
+void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, hipStream_t st) {
+  const dim3 g = col_grid(nc, nn);
+  if (dim == 2) hipLaunchKernelGGL((k_pack<2, T>), g, dim3(kBlock), 0, st, nn, zu, zp, Z);
+  else hipLaunchKernelGGL((k_pack<3, T>), g, dim3(kBlock), 0, st, nn, zu, zp, Z);
 }
 
 void launch_reduce_norms(const double* partials, int nblk, int pstride, double* norms, int nc,
@@ -904,32 +903,35 @@ void launch_reduce_norms(const double* partials, int nblk, int pstride, double* 
 
 void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const double* X,
                            double* Y, int nc, hipStream_t st) {
-  dim3 g = col_grid(nc, L.nn);
+  const dim3 g = col_grid(nc, L.nn);
   if (dim == 2) hipLaunchKernelGGL(k_apply_operator<2>, g, dim3(kBlock), 0, st, L, F, X, Y);
   else hipLaunchKernelGGL(k_apply_operator<3>, g, dim3(kBlock), 0, st, L, F, X, Y);
 }
 
-void launch_unpack(int dim, int nn, const double* X, double* ru, double* rp, int nc, hipStream_t st) {
-  dim3 g = col_grid(nc, nn);
-  if (dim == 2) hipLaunchKernelGGL(k_unpack<2>, g, dim3(kBlock), 0, st, nn, X, ru, rp);
-  else hipLaunchKernelGGL(k_unpack<3>, g, dim3(kBlock), 0, st, nn, X, ru, rp);
-}
+// explicit instantiations for the two preconditioner precisions
+#define BIOT_INSTANTIATE(T)                                                                      \
+  template void launch_residual<T>(int, const LevelDev&, const FineDev&, const ColDesc*, int, T*, \
+                                   T*, T*, T*, double, double*, int, int, hipStream_t);          \
+  template void launch_cheb<T>(int, int, const LevelView<T>&, bool, const T*, const T*, T*, T*,  \
+                               int, double, double, const ColDesc*, const T*, double, int, bool, \
+                               hipStream_t);                                                      \
+  template void launch_level_residual<T>(int, int, const LevelView<T>&, bool, const T*,          \
+                                         const T*, T*, int, int, hipStream_t);                    \
+  template void launch_restrict<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,     \
+                                   const T*, T*, T*, T*, double, int, hipStream_t);               \
+  template void launch_prolong<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,      \
+                                  const T*, const T*, T*, int, int, hipStream_t);                 \
+  template void launch_coarse_solve<T>(int, const T*, const T*, T*, int, hipStream_t);           \
+  template void launch_pstage<T>(int, const LevelView<T>&, const T*, bool, const T*, const T*,   \
+                                 T*, T*, T*, double, int, int, hipStream_t);                      \
+  template void launch_update<T>(int, int, const ColDesc*, const T*, const T*, double, int,      \
+                                 hipStream_t);                                                    \
+  template void launch_pre1<T>(int, const LevelView<T>&, bool, const T*, T*, T*, double, int,    \
+                               hipStream_t);                                                      \
+  template void launch_unpack<T>(int, int, const double*, T*, T*, int, hipStream_t);             \
+  template void launch_pack<T>(int, int, const T*, const T*, double*, int, hipStream_t);
 
-void launch_pre1(int comps, const LevelDev& L, bool is_A, const double* b, double* xa, double* d,
-                 double inv_theta, int nc, hipStream_t st) {
-  dim3 g = col_grid(nc, L.nn);
-  switch (comps) {
-    case 1: hipLaunchKernelGGL(k_pre1<1>, g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, inv_theta); break;
-    case 2: hipLaunchKernelGGL(k_pre1<2>, g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, inv_theta); break;
-    default: hipLaunchKernelGGL(k_pre1<3>, g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, inv_theta); break;
-  }
-}
-
-void launch_pack(int dim, int nn, const double* zu, const double* zp, double* Z, int nc,
-                 hipStream_t st) {
-  dim3 g = col_grid(nc, nn);
-  if (dim == 2) hipLaunchKernelGGL(k_pack<2>, g, dim3(kBlock), 0, st, nn, zu, zp, Z);
-  else hipLaunchKernelGGL(k_pack<3>, g, dim3(kBlock), 0, st, nn, zu, zp, Z);
-}
+BIOT_INSTANTIATE(double)
+BIOT_INSTANTIATE(float)
 
 }  // namespace biot

@@ -9,18 +9,22 @@ namespace biot {
 
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
 
-// One multigrid level on the device (node-blocked ELL, see setup.hpp).
-struct LevelDev {
+// One multigrid level on the device (node-blocked ELL, see setup.hpp), with
+// operator values of type T (double, or float for the mixed-precision
+// preconditioner).
+template <typename T>
+struct LevelView {
   int nn, W, n_cells;
   const int32_t* nbr;    // [W][nn]
-  const double* A;       // [W][dim*dim][nn]
-  const double* S;       // [W][nn]
-  const double* Ainv;    // [dim*dim][nn]
-  const double* Sinv;    // [nn]
+  const T* A;            // [W][dim*dim][nn]
+  const T* S;            // [W][nn]
+  const T* Ainv;         // [dim*dim][nn]
+  const T* Sinv;         // [nn]
   const uint8_t* fixed;  // [nn]
 };
+using LevelDev = LevelView<double>;
 
-// Fine-level coupling blocks (level 0 only).
+// Fine-level coupling blocks and load (level 0 only, FP64).
 struct FineDev {
   const double* B;   // [W][dim][nn]
   const double* Bt;  // [W][dim][nn]
@@ -40,43 +44,55 @@ struct ColDesc {
 };
 
 // Launchers (all asynchronous on `st`).  `nc` = number of columns in the batch;
-// per-column work vectors are contiguous with stride nn*comps.  `ct` = columns
-// per thread in the node-blocked kernels (1, 2, 4 or 8).
+// per-column work vectors are contiguous with stride nn*comps.  `ct` = the
+// largest group of columns one thread loops over (1..32); smaller groups are
+// chosen on small levels so the grid keeps enough workgroups.  T is the type of
+// the preconditioner's vectors and operators (double or float); the residual
+// and the state update always run in FP64.
 bool valid_col_tile(int ct);
+int pick_group(int nc, int nn, int gmax);
+
+template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                     double* ru, double* rp, double* xa, double* d, double inv_theta,
-                     double* partials, int partial_stride, int ct, hipStream_t st);
-// Chebyshev step; xc != null fuses the coarse-grid correction x += P xc (Lc =
-// the coarse level); cols != null (pressure field, level 0) writes the outer
-// update X^{n,m} = X^{n,m-1} + omega [zu; x_new] instead of xout.
-void launch_cheb(int dim, int comps, const LevelDev& L, const LevelDev* Lc, bool is_A,
-                 const double* b, const double* xin, const double* xc, double* xout, double* d,
-                 int nc, double c1, double c2, const ColDesc* cols, const double* zu,
+                     T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials,
+                     int partial_stride, int ct, hipStream_t st);
+// Chebyshev step d <- c1 d + c2 D^{-1}(b - K xin), xout = xin + d.  With `upd`
+// (pressure field, level 0) the step writes the outer update
+// X^{n,m} = X^{n,m-1} + omega [zu; xin + d] through the descriptors instead.
+template <typename T>
+void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
+                 T* xout, T* d, int nc, double c1, double c2, const ColDesc* upd, const T* zu,
                  double omega, int ct, bool fine, hipStream_t st);
-void launch_level_residual(int dim, int comps, const LevelDev& L, bool is_A, const double* b,
-                           const double* x, double* r, int nc, int ct, hipStream_t st);
-void launch_restrict(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
-                     const double* rf, double* bc, double* xa_c, double* d_c, double inv_theta_c,
-                     int nc, hipStream_t st);
-void launch_prolong(int dim, int comps, const LevelDev& Lf, const LevelDev& Lc, bool is_A,
-                    const double* xin, const double* xc, double* xout, int nc, int ct,
-                    hipStream_t st);
-void launch_coarse_solve(int n, const double* Minv, const double* b, double* x, int nc,
-                         hipStream_t st);
-void launch_pstage(int dim, const LevelDev& L, const FineDev& F, bool p1, const double* zu,
-                   const double* rp, double* t, double* xa, double* d, double inv_theta, int nc,
-                   int ct, hipStream_t st);
-void launch_update(int dim, int nn, const ColDesc* cols, const double* zu, const double* zp,
-                   double omega, int nc, hipStream_t st);
+template <typename T>
+void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
+                           const T* x, T* r, int nc, int ct, hipStream_t st);
+template <typename T>
+void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
+                     bool is_A, const T* rf, T* bc, T* xa_c, T* d_c, double inv_theta_c, int nc,
+                     hipStream_t st);
+template <typename T>
+void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
+                    const T* xin, const T* xc, T* xout, int nc, int ct, hipStream_t st);
+template <typename T>
+void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStream_t st);
+template <typename T>
+void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
+                   T* t, T* xa, T* d, double inv_theta, int nc, int ct, hipStream_t st);
+template <typename T>
+void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* zp, double omega,
+                   int nc, hipStream_t st);
+template <typename T>
+void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa, T* d,
+                 double inv_theta, int nc, hipStream_t st);
+template <typename T>
+void launch_unpack(int dim, int nn, const double* X, T* ru, T* rp, int nc, hipStream_t st);
+template <typename T>
+void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, hipStream_t st);
+
 void launch_reduce_norms(const double* partials, int nblk, int partial_stride, double* norms,
                          int nc, hipStream_t st);
 void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const double* X,
                            double* Y, int nc, hipStream_t st);
-void launch_unpack(int dim, int nn, const double* X, double* ru, double* rp, int nc, hipStream_t st);
-void launch_pre1(int comps, const LevelDev& L, bool is_A, const double* b, double* xa, double* d,
-                 double inv_theta, int nc, hipStream_t st);
-void launch_pack(int dim, int nn, const double* zu, const double* zp, double* Z, int nc,
-                 hipStream_t st);
 
 inline int num_node_blocks(int nn) { return (nn + kBlock - 1) / kBlock; }
 

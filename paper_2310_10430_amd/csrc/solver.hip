@@ -21,6 +21,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/biot_pint.h"
@@ -33,8 +34,23 @@ namespace {
 
 thread_local std::string g_create_error;
 
+template <typename T>
 struct Field {  // work vectors of one V-cycle family per level
-  std::vector<double*> b, x0, x1, d, r;
+  std::vector<T*> b, x0, x1, d, r;
+};
+
+// Preconditioner state in precision T: multigrid levels (operator values of
+// type T; neighbour lists and boundary flags shared with the FP64 levels), the
+// fine-level B' for the P1 pressure stage, dense coarsest inverses and the work
+// vectors of the two V-cycle families.
+template <typename T>
+struct Prec {
+  std::vector<LevelView<T>> L;
+  const T* Bt = nullptr;
+  T* coarseA = nullptr;
+  T* coarseS = nullptr;
+  Field<T> fa, fs;
+  T* rp = nullptr;
 };
 
 struct ChebCoef {
@@ -55,15 +71,13 @@ struct biot_handle {
   hipStream_t st = nullptr;
   char* ws = nullptr;
   uint64_t ws_need = 0;
-  std::vector<LevelDev> L;
+  std::vector<LevelDev> L;       // FP64 levels (level 0 also feeds the residual)
   FineDev F{};
-  double* coarseA = nullptr;
-  double* coarseS = nullptr;
+  Prec<double> pd;               // FP64 preconditioner (precision FP64)
+  Prec<float> pf;                // FP32 preconditioner (precision MIXED)
   double* T[2] = {nullptr, nullptr};
   int cur = 0;
   double* slots = nullptr;
-  Field fa, fs;
-  double* rp = nullptr;
   double* partials = nullptr;
   int nblk = 0;
   double* norms = nullptr;
@@ -83,6 +97,10 @@ struct biot_handle {
   std::vector<Pending> pending;
   Acc acc[BIOT_PROBE_COUNT];
   int cur_copies = 0;  // columns of the current batch that also write a second copy
+  // wavefront passes captured as HIP graphs: [trajectory parity][probes on]
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 namespace {
@@ -120,6 +138,54 @@ struct Bump {
   }
 };
 
+template <typename T>
+void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
+  const int dim = h->dim;
+  p.L.assign(h->nlev, LevelView<T>{});
+  for (int l = 0; l < h->nlev; ++l) {
+    const HostLevel& H = h->P.levels[l];
+    LevelView<T>& D = p.L[l];
+    D.nn = H.nn;
+    D.W = H.W;
+    D.n_cells = H.n_cells;
+    D.nbr = h->L[l].nbr;
+    D.fixed = h->L[l].fixed;
+    if constexpr (std::is_same<T, double>::value) {
+      D.A = h->L[l].A;
+      D.S = h->L[l].S;
+      D.Ainv = h->L[l].Ainv;
+      D.Sinv = h->L[l].Sinv;
+    } else {
+      D.A = b.take<T>(H.A.size());
+      D.S = b.take<T>(H.S.size());
+      D.Ainv = b.take<T>(H.Ainv.size());
+      D.Sinv = b.take<T>(H.Sinv.size());
+    }
+  }
+  if constexpr (std::is_same<T, double>::value) p.Bt = h->F.Bt;
+  else p.Bt = b.take<T>(h->P.levels[0].Bt.size());
+  p.coarseA = b.take<T>(h->P.coarseAinv.size());
+  p.coarseS = b.take<T>(h->P.coarseSinv.size());
+  const int nc = h->ncmax;
+  for (Field<T>* f : {&p.fa, &p.fs}) {
+    const int C = (f == &p.fa) ? dim : 1;
+    f->b.assign(h->nlev, nullptr);
+    f->x0.assign(h->nlev, nullptr);
+    f->x1.assign(h->nlev, nullptr);
+    f->d.assign(h->nlev, nullptr);
+    f->r.assign(h->nlev, nullptr);
+    for (int l = 0; l < h->nlev; ++l) {
+      const size_t n = size_t(nc) * h->P.levels[l].nn * C;
+      f->b[l] = b.take<T>(n);
+      f->x0[l] = b.take<T>(n);
+      f->x1[l] = b.take<T>(n);
+      f->d[l] = b.take<T>(n);
+      f->r[l] = b.take<T>(n);
+    }
+  }
+  p.rp = b.take<T>(size_t(nc) * h->nn);
+}
+
 void plan(biot_handle* h, char* base) {
   Bump b{base};
   const int dim = h->dim;
@@ -142,33 +208,15 @@ void plan(biot_handle* h, char* base) {
   h->F.Bt = b.take<double>(H0.Bt.size());
   h->F.Cb = b.take<double>(H0.Cb.size());
   h->F.F = b.take<double>(h->P.F.size());
-  h->coarseA = b.take<double>(h->P.coarseAinv.size());
-  h->coarseS = b.take<double>(h->P.coarseSinv.size());
   const size_t traj = size_t(h->N + 1) * h->col;
   h->T[0] = b.take<double>(traj);
   h->T[1] = b.take<double>(traj);
   if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
     h->slots = b.take<double>(size_t(2) * h->opt.depth * h->col);
-  const int nc = h->ncmax;
-  for (Field* f : {&h->fa, &h->fs}) {
-    const int C = (f == &h->fa) ? dim : 1;
-    f->b.assign(h->nlev, nullptr);
-    f->x0.assign(h->nlev, nullptr);
-    f->x1.assign(h->nlev, nullptr);
-    f->d.assign(h->nlev, nullptr);
-    f->r.assign(h->nlev, nullptr);
-    for (int l = 0; l < h->nlev; ++l) {
-      const size_t n = size_t(nc) * h->P.levels[l].nn * C;
-      f->b[l] = b.take<double>(n);
-      f->x0[l] = b.take<double>(n);
-      f->x1[l] = b.take<double>(n);
-      f->d[l] = b.take<double>(n);
-      f->r[l] = b.take<double>(n);
-    }
-  }
-  h->rp = b.take<double>(size_t(nc) * h->nn);
+  if (h->opt.precision == BIOT_PRECISION_MIXED) plan_prec<float>(h, b, h->pf);
+  else plan_prec<double>(h, b, h->pd);
   h->nblk = num_node_blocks(h->nn);
-  h->partials = b.take<double>(size_t(std::max(nc, h->N)) * h->nblk * 4);
+  h->partials = b.take<double>(size_t(std::max(h->ncmax, h->N)) * h->nblk * 4);
   h->norms = b.take<double>(size_t(h->N) * 4);
   for (int c = 0; c < 2; ++c) {
     h->desc_jac[c] = b.take<ColDesc>(h->N);
@@ -276,7 +324,13 @@ struct ProbeScope {
       live = false;
       return;
     }
-    if (h->ev_next + 2 > h->ev_pool.size()) rc = harvest(h);
+    if (h->ev_next + 2 > h->ev_pool.size()) {
+      if (h->st == h->cap_stream) {
+        rc = fail(h, BIOT_EHIP, "probe event pool exhausted during graph capture");
+        return;
+      }
+      rc = harvest(h);
+    }
     if (rc) return;
     a = h->ev_pool[h->ev_next++];
     if (hipEventRecord(a, h->st) != hipSuccess) rc = fail(h, BIOT_EHIP, "hipEventRecord");
@@ -290,30 +344,29 @@ struct ProbeScope {
   }
 };
 
-// algorithmic bytes of the level-0 launches (distinct inputs and outputs once)
-double bytes_residual(const biot_handle* h, int nc, bool write_r, bool pre) {
+// algorithmic bytes of the level-0 launches (distinct inputs and outputs once);
+// `t` = bytes per value of the preconditioner precision
+double bytes_residual(const biot_handle* h, int nc, bool write_r, bool pre, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
-  double per_col = 8 * D1 * 2 + (write_r ? 8 * d + 8 : 0) + (pre ? 16 * d : 0);
+  double per_col = 8 * D1 * 2 + (write_r ? t * (d + 1) : 0) + (pre ? 2 * t * d : 0);
   double mat = W * (d * d + 2 * d + 2) * 8 + 4 * W + 8 * D1 + (pre ? 8 * d * d : 0);
   return nc * nn * per_col + nn * mat;
 }
-double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool pro, bool upd) {
+double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool upd, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
-  const double nnc = h->nlev > 1 ? h->P.levels[1].nn : 0;
-  double per_col = 8.0 * C * (2 + (c1 ? 1 : 0) + (upd ? 0 : 2));
-  if (upd) per_col += 8 * D1 * 2 + 8 * d;
+  double per_col = double(t) * C * (2 + (c1 ? 1 : 0) + (upd ? 0 : 2));
+  if (upd) per_col += 8 * D1 * 2 + t * d;
   double total = nc * nn * per_col + (upd ? h->cur_copies * nn * 8 * D1 : 0);
-  if (pro) total += nc * nnc * C * 8 + nn + nnc;
-  total += nn * (W * C * C * 8 + 4 * W + C * C * 8);
+  total += nn * (W * C * C * t + 4 * W + C * C * t);
   return total;
 }
-double bytes_levres(const biot_handle* h, int C, int nc) {
+double bytes_levres(const biot_handle* h, int C, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W;
-  return nc * nn * C * 8 * 3 + nn * (W * C * C * 8 + 4 * W);
+  return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W);
 }
-double bytes_pstage(const biot_handle* h, int nc) {
+double bytes_pstage(const biot_handle* h, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
-  return nc * nn * (8 * d + 8 + 8 + 16) + nn * (W * d * 8 + 4 * W + 8);
+  return nc * nn * t * (d + 4) + nn * (W * d * t + 4 * W + t);
 }
 
 // One V-cycle for field A (is_A) or S on level l for nc columns.  On entry b[l]
@@ -321,18 +374,20 @@ double bytes_pstage(const biot_handle* h, int nc) {
 // hold the first Chebyshev step.  The result is returned in *out; when `upd`
 // is given (pressure field, level 0) the last smoothing step writes the outer
 // update through those descriptors instead and *out is null.
-int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out, const ColDesc* upd,
-           const double* zu) {
-  Field& f = is_A ? h->fa : h->fs;
+template <typename T>
+int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const ColDesc* upd,
+           const T* zu) {
+  Field<T>& f = is_A ? p.fa : p.fs;
   const int C = is_A ? h->dim : 1;
   const int last = h->nlev - 1;
   const int ct = h->opt.col_tile;
+  const int tb = int(sizeof(T));
   hipStream_t st = h->st;
   if (l == last) {
-    launch_coarse_solve(h->P.levels[l].nn * C, is_A ? h->coarseA : h->coarseS, f.b[l], f.x0[l], nc, st);
+    launch_coarse_solve<T>(h->P.levels[l].nn * C, is_A ? p.coarseA : p.coarseS, f.b[l], f.x0[l], nc, st);
     LAUNCHCHK(h);
     if (upd) {
-      launch_update(h->dim, h->nn, upd, zu, f.x0[l], h->opt.omega, nc, st);
+      launch_update<T>(h->dim, h->nn, upd, zu, f.x0[l], h->opt.omega, nc, st);
       LAUNCHCHK(h);
       *out = nullptr;
     } else {
@@ -342,39 +397,40 @@ int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out, const ColDesc
   }
   const ChebCoef& cc = is_A ? h->chA[l] : h->chS[l];
   const int deg = h->opt.cheb_degree;
-  double* cur = f.x0[l];
-  double* oth = f.x1[l];
+  T* cur = f.x0[l];
+  T* oth = f.x1[l];
   // pre-smoothing: the first step was done by the producer of b[l]
   double rho = 1.0 / cc.sigma;
   const bool fine = l == 0;
   const int pid_cheb = is_A ? BIOT_PROBE_CHEB_U : BIOT_PROBE_CHEB_P;
   for (int j = 2; j <= deg; ++j) {
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
-    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, true, false, false) : 0);
-    launch_cheb(h->dim, C, h->L[l], nullptr, is_A, f.b[l], cur, nullptr, oth, f.d[l], nc, rn * rho,
-                2.0 * rn / cc.delta, nullptr, nullptr, 0.0, ct, fine, st);
+    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, true, false, tb) : 0);
+    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho,
+                   2.0 * rn / cc.delta, nullptr, nullptr, 0.0, ct, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
     std::swap(cur, oth);
   }
   {
-    ProbeScope ps(h, is_A ? BIOT_PROBE_LEVRES_U : BIOT_PROBE_LEVRES_P, fine ? bytes_levres(h, C, nc) : 0);
-    launch_level_residual(h->dim, C, h->L[l], is_A, f.b[l], cur, f.r[l], nc, ct, st);
+    ProbeScope ps(h, is_A ? BIOT_PROBE_LEVRES_U : BIOT_PROBE_LEVRES_P,
+                  fine ? bytes_levres(h, C, nc, tb) : 0);
+    launch_level_residual<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, f.r[l], nc, ct, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
   }
   const bool coarse_last = (l + 1 == last);
   const ChebCoef* cn = coarse_last ? nullptr : (is_A ? &h->chA[l + 1] : &h->chS[l + 1]);
-  launch_restrict(h->dim, C, h->L[l], h->L[l + 1], is_A, f.r[l], f.b[l + 1],
-                  coarse_last ? nullptr : f.x0[l + 1], coarse_last ? nullptr : f.d[l + 1],
-                  coarse_last ? 0.0 : 1.0 / cn->theta, nc, st);
+  launch_restrict<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, f.r[l], f.b[l + 1],
+                     coarse_last ? nullptr : f.x0[l + 1], coarse_last ? nullptr : f.d[l + 1],
+                     coarse_last ? 0.0 : 1.0 / cn->theta, nc, st);
   LAUNCHCHK(h);
-  double* xc = nullptr;
-  int rc = vcycle(h, is_A, l + 1, nc, &xc, nullptr, nullptr);
+  T* xc = nullptr;
+  int rc = vcycle<T>(h, p, is_A, l + 1, nc, &xc, nullptr, nullptr);
   if (rc) return rc;
   // coarse-grid correction x += P xc, then deg post-smoothing steps
-  launch_prolong(h->dim, C, h->L[l], h->L[l + 1], is_A, cur, xc, oth, nc, ct, st);
+  launch_prolong<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, cur, xc, oth, nc, ct, st);
   LAUNCHCHK(h);
   std::swap(cur, oth);
   rho = 1.0 / cc.sigma;
@@ -386,9 +442,9 @@ int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out, const ColDesc
       c2 = 2.0 * rn / cc.delta;
     }
     const bool final_upd = upd && j == deg;
-    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, false, final_upd) : 0);
-    launch_cheb(h->dim, C, h->L[l], nullptr, is_A, f.b[l], cur, nullptr, oth, f.d[l], nc, c1, c2,
-                final_upd ? upd : nullptr, zu, h->opt.omega, ct, fine, st);
+    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, tb) : 0);
+    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2,
+                   final_upd ? upd : nullptr, zu, h->opt.omega, ct, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -401,37 +457,61 @@ int vcycle(biot_handle* h, bool is_A, int l, int nc, double** out, const ColDesc
 // P^{-1} applied to the batch whose residual is in fa.b[0] (r_u) and rp (r_p);
 // the first Chebyshev step of V_A has been written by the producer.  With
 // `upd`, the outer update is written through those descriptors.
-int precond_batch(biot_handle* h, int nc, double** zu, double** zp, const ColDesc* upd) {
-  int rc = vcycle(h, true, 0, nc, zu, nullptr, nullptr);
+template <typename T>
+int precond_batch(biot_handle* h, Prec<T>& p, int nc, T** zu, T** zp, const ColDesc* upd) {
+  int rc = vcycle<T>(h, p, true, 0, nc, zu, nullptr, nullptr);
   if (rc) return rc;
   const bool sm = level0_smoothed(h);
   {
-    ProbeScope ps(h, BIOT_PROBE_PSTAGE, bytes_pstage(h, nc));
-    launch_pstage(h->dim, h->L[0], h->F, h->opt.precond == BIOT_PRECOND_P1, *zu, h->rp, h->fs.b[0],
-                  h->fs.x0[0], h->fs.d[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc, h->opt.col_tile,
-                  h->st);
+    ProbeScope ps(h, BIOT_PROBE_PSTAGE, bytes_pstage(h, nc, int(sizeof(T))));
+    launch_pstage<T>(h->dim, p.L[0], p.Bt, h->opt.precond == BIOT_PRECOND_P1, *zu, p.rp,
+                     p.fs.b[0], p.fs.x0[0], p.fs.d[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc,
+                     h->opt.col_tile, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
   }
-  return vcycle(h, false, 0, nc, zp, upd, *zu);
+  return vcycle<T>(h, p, false, 0, nc, zp, upd, *zu);
 }
 
-// one unit for every column of a descriptor batch
-int unit_batch(biot_handle* h, const ColDesc* cols, int nc, double* partials, double* norms_out) {
+// one unit for every column of a descriptor batch: FP64 residual, P^{-1} in
+// precision T, FP64 update
+template <typename T>
+int unit_batch_t(biot_handle* h, Prec<T>& p, const ColDesc* cols, int nc) {
   const bool sm = level0_smoothed(h);
   {
-    ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, sm));
-    launch_residual(h->dim, h->L[0], h->F, cols, nc, h->fa.b[0], h->rp, sm ? h->fa.x0[0] : nullptr,
-                    h->fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0, partials, h->nblk,
-                    h->opt.col_tile, h->st);
+    ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, sm, int(sizeof(T))));
+    launch_residual<T>(h->dim, h->L[0], h->F, cols, nc, p.fa.b[0], p.rp, sm ? p.fa.x0[0] : nullptr,
+                       p.fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0, nullptr, h->nblk,
+                       h->opt.col_tile, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
   }
-  double *zu = nullptr, *zp = nullptr;
-  int rc = precond_batch(h, nc, &zu, &zp, cols);
-  if (rc) return rc;
-  if (partials && norms_out) {
-    launch_reduce_norms(partials, h->nblk, h->nblk, norms_out, nc, h->st);
+  T *zu = nullptr, *zp = nullptr;
+  return precond_batch<T>(h, p, nc, &zu, &zp, cols);
+}
+
+int unit_batch(biot_handle* h, const ColDesc* cols, int nc) {
+  if (h->opt.precision == BIOT_PRECISION_MIXED) return unit_batch_t<float>(h, h->pf, cols, nc);
+  return unit_batch_t<double>(h, h->pd, cols, nc);
+}
+
+// Z = P^{-1} R for caller columns (diagnostic path)
+template <typename T>
+int apply_precond_t(biot_handle* h, Prec<T>& p, const double* R, double* Z, int ncols) {
+  const bool sm = level0_smoothed(h);
+  for (int c0 = 0; c0 < ncols; c0 += h->ncmax) {
+    const int nc = std::min(h->ncmax, ncols - c0);
+    launch_unpack<T>(h->dim, h->nn, R + size_t(c0) * h->col, p.fa.b[0], p.rp, nc, h->st);
+    LAUNCHCHK(h);
+    if (sm) {
+      launch_pre1<T>(h->dim, p.L[0], true, p.fa.b[0], p.fa.x0[0], p.fa.d[0], 1.0 / h->chA[0].theta,
+                     nc, h->st);
+      LAUNCHCHK(h);
+    }
+    T *zu = nullptr, *zp = nullptr;
+    int rc = precond_batch<T>(h, p, nc, &zu, &zp, nullptr);
+    if (rc) return rc;
+    launch_pack<T>(h->dim, h->nn, zu, zp, Z + size_t(c0) * h->col, nc, h->st);
     LAUNCHCHK(h);
   }
   return BIOT_OK;
@@ -441,22 +521,52 @@ int jacobi_sweep(biot_handle* h) {
   ColDesc* tab = h->desc_jac[h->cur];
   for (int n0 = 0; n0 < h->N; n0 += h->ncmax) {
     const int nc = std::min(h->ncmax, h->N - n0);
-    int rc = unit_batch(h, tab + n0, nc, nullptr, nullptr);
+    int rc = unit_batch(h, tab + n0, nc);
     if (rc) return rc;
   }
   h->cur = 1 - h->cur;
   return BIOT_OK;
 }
 
-int wavefront_pass(biot_handle* h) {
+int wavefront_pass_eager(biot_handle* h) {
   ColDesc* tab = h->desc_wave[h->cur];
   for (size_t w = 0; w < h->wave_off.size(); ++w) {
     const int wave = int(w) + 1, last_step = wave - h->opt.depth + 1;
     h->cur_copies = (last_step >= 1 && last_step <= h->N) ? 1 : 0;
-    int rc = unit_batch(h, tab + h->wave_off[w], h->wave_cnt[w], nullptr, nullptr);
+    int rc = unit_batch(h, tab + h->wave_off[w], h->wave_cnt[w]);
     if (rc) return rc;
   }
   h->cur_copies = 0;
+  return BIOT_OK;
+}
+
+// One pass = N + depth - 1 waves.  With use_graph the launch sequence of a
+// pass is captured once per trajectory parity (the descriptor tables fix every
+// pointer) and replayed; probe events become event-record nodes of the graph.
+int wavefront_pass(biot_handle* h) {
+  // probes read HIP events, which cannot be timed inside a replayed graph, so
+  // a probed pass runs its launches eagerly
+  if (!h->opt.use_graph || h->prof) {
+    int rc = wavefront_pass_eager(h);
+    if (rc) return rc;
+    h->cur = 1 - h->cur;
+    return BIOT_OK;
+  }
+  const int c = h->cur;
+  if (!h->gexec[c][0]) {
+    hipStream_t user = h->st;
+    h->st = h->cap_stream;
+    HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    int rc = wavefront_pass_eager(h);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->st, &g);
+    h->st = user;
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(h, BIOT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    h->graph[c][0] = g;
+    HIPCHK(h, hipGraphInstantiate(&h->gexec[c][0], g, nullptr, nullptr, 0));
+  }
+  HIPCHK(h, hipGraphLaunch(h->gexec[c][0], h->st));
   h->cur = 1 - h->cur;
   return BIOT_OK;
 }
@@ -467,8 +577,8 @@ int global_residual(biot_handle* h) {
   const int chunk = std::max(h->ncmax, 1);
   for (int n0 = 0; n0 < h->N; n0 += chunk) {
     const int nc = std::min(chunk, h->N - n0);
-    launch_residual(h->dim, h->L[0], h->F, tab + n0, nc, nullptr, nullptr, nullptr, nullptr, 0.0,
-                    h->partials, h->nblk, h->opt.col_tile, h->st);
+    launch_residual<double>(h->dim, h->L[0], h->F, tab + n0, nc, nullptr, nullptr, nullptr,
+                            nullptr, 0.0, h->partials, h->nblk, h->opt.col_tile, h->st);
     LAUNCHCHK(h);
     launch_reduce_norms(h->partials, h->nblk, h->nblk, h->norms + size_t(n0) * 4, nc, h->st);
     LAUNCHCHK(h);
@@ -517,6 +627,9 @@ int biot_default_options(biot_options* o) {
   o->max_batch = 0;
   o->omega = 0.6;
   o->col_tile = 16;
+  o->coarse_cells = 2;
+  o->use_graph = 1;
+  o->precision = BIOT_PRECISION_FP64;
   return BIOT_OK;
 }
 
@@ -538,7 +651,10 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   if (o.power_iters < 1) return fail(nullptr, BIOT_EINVAL, "power_iters must be >= 1");
   if (!(o.lmax_safety >= 1.0)) return fail(nullptr, BIOT_EINVAL, "lmax_safety must be >= 1");
   if (o.cheb_degree < 2 || o.cheb_degree > 8) return fail(nullptr, BIOT_EINVAL, "cheb_degree must be in 2..8");
-  if (!valid_col_tile(o.col_tile)) return fail(nullptr, BIOT_EINVAL, "col_tile must be 1, 2, 4 or 8");
+  if (!valid_col_tile(o.col_tile)) return fail(nullptr, BIOT_EINVAL, "col_tile must be 1, 2, 4, 8, 16 or 32");
+  if (o.coarse_cells < 1 || o.coarse_cells > 64) return fail(nullptr, BIOT_EINVAL, "coarse_cells must be in 1..64");
+  if (o.precision != BIOT_PRECISION_FP64 && o.precision != BIOT_PRECISION_MIXED)
+    return fail(nullptr, BIOT_EINVAL, "unknown precision");
   biot_handle* h = new (std::nothrow) biot_handle();
   if (!h) return fail(nullptr, BIOT_ENOMEM, "out of host memory");
   h->opt = o;
@@ -550,6 +666,7 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   ho.cheb_ratio = o.cheb_ratio;
   ho.lmax_safety = o.lmax_safety;
   ho.power_iters = o.power_iters;
+  ho.min_cells = o.coarse_cells;
   std::string e;
   try {
     e = build_problem(m, mi, li, dt, n_steps, ho, h->P);
@@ -616,8 +733,28 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
   HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.Bt), H0.Bt.data(), H0.Bt.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.Cb), H0.Cb.data(), H0.Cb.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.F), h->P.F.data(), h->P.F.size() * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(h, hipMemcpyAsync(h->coarseA, h->P.coarseAinv.data(), h->P.coarseAinv.size() * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(h, hipMemcpyAsync(h->coarseS, h->P.coarseSinv.data(), h->P.coarseSinv.size() * 8, hipMemcpyHostToDevice, st));
+  std::vector<std::vector<float>> staging;  // FP32 copies must outlive the async copies
+  auto up32 = [&](const float* dst, const std::vector<double>& src) -> hipError_t {
+    staging.emplace_back(src.begin(), src.end());
+    return hipMemcpyAsync(const_cast<float*>(dst), staging.back().data(), src.size() * 4,
+                          hipMemcpyHostToDevice, st);
+  };
+  if (h->opt.precision == BIOT_PRECISION_MIXED) {
+    for (int l = 0; l < h->nlev; ++l) {
+      const HostLevel& H = h->P.levels[l];
+      const LevelView<float>& D = h->pf.L[l];
+      HIPCHK(h, up32(D.A, H.A));
+      HIPCHK(h, up32(D.S, H.S));
+      HIPCHK(h, up32(D.Ainv, H.Ainv));
+      HIPCHK(h, up32(D.Sinv, H.Sinv));
+    }
+    HIPCHK(h, up32(h->pf.Bt, h->P.levels[0].Bt));
+    HIPCHK(h, up32(h->pf.coarseA, h->P.coarseAinv));
+    HIPCHK(h, up32(h->pf.coarseS, h->P.coarseSinv));
+  } else {
+    HIPCHK(h, hipMemcpyAsync(h->pd.coarseA, h->P.coarseAinv.data(), h->P.coarseAinv.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(h->pd.coarseS, h->P.coarseSinv.data(), h->P.coarseSinv.size() * 8, hipMemcpyHostToDevice, st));
+  }
   for (int c = 0; c < 2; ++c) {
     HIPCHK(h, hipMemcpyAsync(h->desc_jac[c], h->h_jac[c].data(), h->h_jac[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
     HIPCHK(h, hipMemcpyAsync(h->desc_k4[c], h->h_k4[c].data(), h->h_k4[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
@@ -629,6 +766,8 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
   HIPCHK(h, hipMemsetAsync(h->T[1], 0, traj, st));
   if (h->slots) HIPCHK(h, hipMemsetAsync(h->slots, 0, size_t(2) * h->opt.depth * h->col * 8, st));
   HIPCHK(h, hipStreamSynchronize(st));  // host sources must outlive the copies
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT && h->opt.use_graph && !h->cap_stream)
+    HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   h->cur = 0;
   h->bound = true;
   return BIOT_OK;
@@ -760,21 +899,8 @@ int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols
   int rc = check_bound(h);
   if (rc) return rc;
   if (!R || !Z || ncols < 0) return fail(h, BIOT_EINVAL, "bad arguments");
-  const bool sm = level0_smoothed(h);
-  for (int c0 = 0; c0 < ncols; c0 += h->ncmax) {
-    const int nc = std::min(h->ncmax, ncols - c0);
-    launch_unpack(h->dim, h->nn, R + size_t(c0) * h->col, h->fa.b[0], h->rp, nc, h->st);
-    LAUNCHCHK(h);
-    if (sm) {
-      launch_pre1(h->dim, h->L[0], true, h->fa.b[0], h->fa.x0[0], h->fa.d[0], 1.0 / h->chA[0].theta, nc, h->st);
-      LAUNCHCHK(h);
-    }
-    double *zu = nullptr, *zp = nullptr;
-    if ((rc = precond_batch(h, nc, &zu, &zp, nullptr))) return rc;
-    launch_pack(h->dim, h->nn, zu, zp, Z + size_t(c0) * h->col, nc, h->st);
-    LAUNCHCHK(h);
-  }
-  return BIOT_OK;
+  if (h->opt.precision == BIOT_PRECISION_MIXED) return apply_precond_t<float>(h, h->pf, R, Z, ncols);
+  return apply_precond_t<double>(h, h->pd, R, Z, ncols);
 }
 
 int biot_profile_enable(biot_handle* h, int32_t enable) {
@@ -782,12 +908,25 @@ int biot_profile_enable(biot_handle* h, int32_t enable) {
   if (rc) return rc;
   if ((rc = harvest(h))) return rc;
   for (auto& a : h->acc) a = biot_handle::Acc{};
-  if (enable && h->ev_pool.empty()) {
-    h->ev_pool.resize(16384);
-    for (auto& e : h->ev_pool) HIPCHK(h, hipEventCreate(&e));
+  // a captured pass must fit its probe events in the pool (10 probes per wave)
+  const size_t want = std::max<size_t>(16384, 20 * (h->wave_off.size() + 1) + 64);
+  if (enable && h->ev_pool.size() < want) {
+    const size_t old = h->ev_pool.size();
+    h->ev_pool.resize(want);
+    for (size_t i = old; i < want; ++i) HIPCHK(h, hipEventCreate(&h->ev_pool[i]));
   }
   h->prof = enable != 0;
   return BIOT_OK;
+}
+
+static void destroy_graphs(biot_handle* h) {
+  for (int c = 0; c < 2; ++c)
+    for (int p = 0; p < 2; ++p) {
+      if (h->gexec[c][p]) (void)hipGraphExecDestroy(h->gexec[c][p]);
+      if (h->graph[c][p]) (void)hipGraphDestroy(h->graph[c][p]);
+      h->gexec[c][p] = nullptr;
+      h->graph[c][p] = nullptr;
+    }
 }
 
 int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
@@ -841,10 +980,12 @@ const char* biot_last_error(const biot_handle* h) {
   return h ? h->err.c_str() : g_create_error.c_str();
 }
 
-const char* biot_version(void) { return "biot_pint 0.1 (gfx950, FP64)"; }
+const char* biot_version(void) { return "biot_pint 0.2 (gfx950; FP64 and FP32/FP64 mixed)"; }
 
 void biot_destroy(biot_handle* h) {
   if (!h) return;
+  destroy_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto& e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }

@@ -17,7 +17,7 @@ from . import _lib
 
 def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
                   cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
-                  col_tile=16):
+                  col_tile=16, coarse_cells=2, use_graph=True, precision="fp64"):
     """biot_create on the host (no device work); returns (handle, options)."""
     lib = _lib.load()
     xyz = np.ascontiguousarray(problem.xyz, dtype=np.float64)
@@ -48,6 +48,9 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     opt.max_batch = max_batch
     opt.omega = omega
     opt.col_tile = col_tile
+    opt.coarse_cells = coarse_cells
+    opt.use_graph = 1 if use_graph else 0
+    opt.precision = _lib.PRECISION[precision]
     h = C.c_void_p()
     _lib.check(lib, lib.biot_create(C.byref(mesh), C.byref(mat), C.byref(load),
                                     float(problem.dt), problem.n_steps, C.byref(opt),
@@ -89,7 +92,8 @@ class BiotSolver:
     def __init__(self, problem, schedule: str = "jacobi", depth: int = 8, precond: str = "P1",
                  omega: float = 0.6, cheb_degree: int = 2, cheb_ratio: float = 4.0,
                  lmax_safety: float = 1.1, power_iters: int = 20, max_batch: int = 0,
-                 device: str = "cuda:0", beta=None, col_tile: int = 16):
+                 device: str = "cuda:0", beta=None, col_tile: int = 16, coarse_cells: int = 2,
+                 use_graph: bool = True, precision: str = "fp64"):
         if not torch.cuda.is_available():
             raise RuntimeError("BiotSolver needs a ROCm GPU (torch.cuda is not available)")
         self.lib = _lib.load()
@@ -97,7 +101,9 @@ class BiotSolver:
         h, opt = create_handle(problem, schedule=schedule, depth=depth, precond=precond,
                                omega=omega, cheb_degree=cheb_degree, cheb_ratio=cheb_ratio,
                                lmax_safety=lmax_safety, power_iters=power_iters,
-                               max_batch=max_batch, beta=beta, col_tile=col_tile)
+                               max_batch=max_batch, beta=beta, col_tile=col_tile,
+                               coarse_cells=coarse_cells, use_graph=use_graph,
+                               precision=precision)
         self.problem = problem
         self.dim = problem.dim
         self.n_nodes = problem.n_nodes

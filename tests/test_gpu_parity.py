@@ -61,15 +61,15 @@ def test_step_operator(n, dim):
     assert _rel(_fm(Y), Yo) < 1e-13
 
 
-@pytest.mark.parametrize("kind", ["P1", "P2"])
-@pytest.mark.parametrize("n", [16, 24])
-def test_block_preconditioner(kind, n):
+@pytest.mark.parametrize("kind,n,cc", [("P1", 16, 2), ("P2", 16, 2), ("P1", 24, 2), ("P2", 24, 2),
+                                       ("P1", 32, 8)])
+def test_block_preconditioner(kind, n, cc):
     pb = W.heterogeneous_problem(n, 3)
     orc = seq.BiotOracle(pb)
-    P = precond.BlockPreconditioner(orc, kind, "gmg")
+    P = precond.BlockPreconditioner(orc, kind, "gmg", min_cells=cc)
     R = _random_state(orc, 7, 2)
     R[:, orc.nU:] *= 1e-6
-    s = BiotSolver(pb, precond=kind, max_batch=5)     # ragged batches of 5 + 2
+    s = BiotSolver(pb, precond=kind, max_batch=5, coarse_cells=cc)   # ragged batches of 5 + 2
     Z = _fm(s.apply_precond(torch.from_numpy(_nm(R, orc))).cpu().numpy())
     s.close()
     for c in range(R.shape[0]):
@@ -165,3 +165,63 @@ def test_wavefront_rejects_partial_pass():
     with pytest.raises(RuntimeError):
         s.sweep(2)
     s.close()
+
+
+def test_graph_replays_match_eager_passes():
+    """Every replay of a captured wavefront pass (both trajectory parities, with
+    eager work and synchronizations in between) equals the eager pass bit for
+    bit."""
+    pb = W.heterogeneous_problem(16, 9)
+    eager = BiotSolver(pb, schedule="wavefront", depth=3, omega=0.6, use_graph=False)
+    graph = BiotSolver(pb, schedule="wavefront", depth=3, omega=0.6, use_graph=True)
+    for p in range(5):
+        eager.sweep(3)
+        graph.sweep(3)
+        torch.cuda.synchronize()
+        nr = graph.residual_norms()          # eager work between replays
+        assert np.all(np.isfinite(nr))
+        assert torch.equal(eager.trajectory(), graph.trajectory()), p
+    graph.profile(True)                      # probed passes run eagerly
+    eager.sweep(3)
+    graph.sweep(3)
+    assert torch.equal(eager.trajectory(), graph.trajectory())
+    prof = graph.profile_read()
+    assert prof["cheb_u"]["launches"] > 0 and prof["cheb_u"]["ms"] > 0
+    graph.profile(False)
+    eager.sweep(3)
+    graph.sweep(3)
+    assert torch.equal(eager.trajectory(), graph.trajectory())
+    eager.close()
+    graph.close()
+
+
+def test_mixed_precision_preconditioner_is_fp32_rounding_of_oracle():
+    """The FP32 preconditioner equals the oracle's FP64 one to FP32 accuracy."""
+    pb = W.heterogeneous_problem(24, 3)
+    orc = seq.BiotOracle(pb)
+    P = precond.BlockPreconditioner(orc, "P1", "gmg")
+    R = _random_state(orc, 5, 7)
+    R[:, orc.nU:] *= 1e-6
+    s = BiotSolver(pb, precision="mixed")
+    Z = _fm(s.apply_precond(torch.from_numpy(_nm(R, orc))).cpu().numpy())
+    s.close()
+    for c in range(R.shape[0]):
+        Zo = P.apply(R[c])
+        assert _rel(Z[c, : orc.nU], Zo[: orc.nU]) < 2e-5
+        assert _rel(Z[c, orc.nU:], Zo[orc.nU:]) < 2e-5
+
+
+@pytest.mark.parametrize("schedule,depth", [("jacobi", 1), ("wavefront", 8)])
+def test_mixed_precision_solve_reaches_fp64_backward_euler(schedule, depth):
+    """FP64 residual + FP32 preconditioner refines to the FP64 fixed point."""
+    pb = W.heterogeneous_problem(32, 24)
+    pb.dt = 1 / 128
+    orc = seq.BiotOracle(pb)
+    Xs = orc.solve_sequential()
+    s = BiotSolver(pb, schedule=schedule, depth=depth, omega=0.6, precision="mixed")
+    st = s.solve_to_tol(1e-11, max_sweeps=600, check_every=8)
+    Xg = _fm(s.trajectory().cpu().numpy())
+    s.close()
+    assert st["converged"], st
+    err = seq.relative_field_errors(Xg, Xs, orc.n_nodes, orc.dim)
+    assert err["u"] < 1e-9 and err["p"] < 1e-9, (err, st)
