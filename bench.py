@@ -95,6 +95,32 @@ def cpu_baseline(pb, n_sample_steps, X_gpu):
     return info, err
 
 
+def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2):
+    """Solve one workload variant to the same tolerance; time `reps` solves
+    after one warm-up and report throughput and the error at the stored oracle
+    samples."""
+    import torch
+    s = BiotSolver(pb, schedule=args.schedule, depth=args.depth, omega=args.omega,
+                   col_tile=args.col_tile, precision=precision)
+    s.reset()
+    s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.reset()
+        st = s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / reps
+    X = s.trajectory().cpu().numpy()
+    s.close()
+    golden = np.load(os.path.join(ROOT, "tests", "golden", golden_name + ".npz"))
+    acc = accuracy_vs_golden(X, golden)
+    return {"value": pb.n_dof * pb.n_steps / per, "unit": "dof-timestep updates/s",
+            "ms_per_solve": 1e3 * per, "precision": precision, "sweeps": st["sweeps"],
+            "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"]),
+            "max_rel_err_vs_oracle_samples": max(acc.values()), "accuracy": acc}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +135,15 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=600)
     ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="hardware-counter run: 1 GiB reference copy, then exactly two "
+                         "Jacobi-schedule sweeps of the workload (few dispatches), no timing")
+    ap.add_argument("--probe", default="cheb_u",
+                    help="kernel timed with HIP events in the timed region")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mixed-precision and heterogeneous-permeability variants")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
@@ -122,7 +157,21 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("bench: 1 GiB copy done (counter reference: 1 GiB read, 1 GiB written)")
     pb = W.large_terzaghi()
+    if args.pmc_run:
+        s = BiotSolver(pb, schedule="jacobi", omega=args.omega, col_tile=args.col_tile)
+        s.sweep(2)
+        torch.cuda.synchronize()
+        s.close()
+        log("bench: counter run done (2 Jacobi sweeps of 512 columns)")
+        return
     log(f"bench: workload 256x256, {pb.n_steps} steps, {pb.n_dof} unknowns; "
         f"schedule={args.schedule} depth={args.depth} omega={args.omega} rtol={args.rtol}")
     t0 = time.perf_counter()
@@ -139,7 +188,9 @@ def main():
     for i in range(args.warmup):
         st = solve()
         log(f"bench: warmup {i}: {st['sweeps']} sweeps, {st['seconds'] * 1e3:.1f} ms")
-    s.profile(True)
+    # timed region: HIP events bracket every level-0 launch of the dominant
+    # kernel (the displacement smoother) on the solver's stream
+    s.profile(True, probes=[args.probe])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -147,6 +198,10 @@ def main():
         stats.append(solve())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    prof_main = s.profile_read()
+    # breakdown of the other level-0 kernels from one more (untimed) probed solve
+    s.profile(True)
+    st_b = solve()
     prof = s.profile_read()
     s.profile(False)
     ms_per_step = 1e3 * elapsed / args.steps
@@ -154,15 +209,16 @@ def main():
     log(f"bench: {args.steps} solves in {elapsed:.3f} s ({ms_per_step:.1f} ms each, "
         f"{stats[-1]['sweeps']} sweeps)")
 
-    # dominant kernel of the timed region (largest total probe time)
-    key = max(prof, key=lambda k: prof[k]["ms"])
-    p = prof[key]
+    p = prof_main[args.probe]
+    dominant = max(prof, key=lambda k: prof[k]["ms"])
     avg_ms = p["ms"] / max(p["launches"], 1)
     bytes_per_launch = p["bytes"] / max(p["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    solve_ms = st_b["seconds"] * 1e3
     kernels = {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
                    "GBps": (v["bytes"] / max(v["ms"], 1e-30)) / 1e6,
-                   "share_of_step": v["ms"] / (1e3 * elapsed)} for k, v in prof.items()}
+                   "share_of_solve": v["ms"] / solve_ms} for k, v in prof.items()}
+    kernels["dominant"] = dominant
 
     X = s.trajectory().cpu().numpy()
     s.close()
@@ -179,6 +235,17 @@ def main():
         cpu, err = cpu_baseline(pb, args.cpu_steps, X)
         acc.update(err)
     acc["max_rel_err"] = max(v for k, v in acc.items())
+
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        het = W.large_heterogeneous()
+        for name, prob, gname, prec in (
+                ("large_terzaghi_mixed", pb, "large_terzaghi", "mixed"),
+                ("large_heterogeneous_fp64", het, "large_heterogeneous", "fp64"),
+                ("large_heterogeneous_mixed", het, "large_heterogeneous", "mixed")):
+            log(f"bench: variant {name}")
+            variants[name] = run_variant(BiotSolver, prob, gname, prec, args)
 
     out = {
         "metric": METRIC,
@@ -212,6 +279,7 @@ def main():
         },
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

@@ -162,8 +162,9 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* hip_stream
 int biot_reset(biot_handle* h);
 
 /* n_sweeps outer sweeps.  JACOBI: each sweep updates every step from the
- * previous sweep.  WAVEFRONT: n_sweeps must be a multiple of depth; each pass
- * of `depth` Gauss-Seidel-in-time sweeps runs as N+depth-1 pipelined waves. */
+ * previous sweep.  WAVEFRONT: floor(n_sweeps/depth) passes of `depth`
+ * Gauss-Seidel-in-time sweeps, each run as N+depth-1 pipelined waves, then one
+ * shallower pass for the remainder. */
 int biot_sweep(biot_handle* h, int32_t n_sweeps);
 
 /* Space-time residual of the current trajectory: for every step n >= 1 the
@@ -172,8 +173,10 @@ int biot_sweep(biot_handle* h, int32_t n_sweeps);
  * norms[n_steps][4] (host).  Synchronizes the stream. */
 int biot_residual_norms(biot_handle* h, double* norms);
 
-/* Sweeps until max(rel_resid_u, rel_resid_p) <= rtol (checked every
- * `check_every` sweeps) or max_sweeps.  Returns BIOT_ENOTCONVERGED if the
+/* Sweeps until max(rel_resid_u, rel_resid_p) <= rtol or max_sweeps.  JACOBI
+ * checks every `check_every` sweeps; WAVEFRONT checks after each pass, the
+ * first of full depth and later ones sized from the contraction observed so
+ * far.  Returns BIOT_ENOTCONVERGED if the
  * tolerance was not met, BIOT_EDIVERGED on non-finite residuals.  stats may be
  * NULL.  Synchronizes the stream. */
 int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t check_every,
@@ -196,9 +199,11 @@ int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols
 int biot_get_info(const biot_handle* h, biot_info_t* info);
 
 /* Probes: HIP events recorded on the handle's stream around every level-0
- * launch of the kernels below, with the algorithmic bytes each launch moves
- * (distinct global inputs and outputs counted once).  Enabling (or disabling)
- * clears the accumulators; reading synchronizes the stream. */
+ * launch of the selected kernels below, with the algorithmic bytes each launch
+ * moves (distinct global inputs and outputs counted once).  `mask` has bit p
+ * set for probe p (0 disables); enabling or disabling clears the accumulators;
+ * reading synchronizes the stream.  While probes are on, wavefront passes run
+ * their launches eagerly instead of replaying a captured graph. */
 #define BIOT_PROBE_RESIDUAL 0     /* fused residual + coupling + norms           */
 #define BIOT_PROBE_CHEB_U 1       /* displacement Chebyshev smoothing steps      */
 #define BIOT_PROBE_CHEB_P 2       /* pressure Chebyshev smoothing steps          */
@@ -206,7 +211,8 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
 #define BIOT_PROBE_LEVRES_P 4     /* pressure residual before restriction        */
 #define BIOT_PROBE_PSTAGE 5       /* P1 pressure stage t = B' z_u - r_p          */
 #define BIOT_PROBE_COUNT 6
-int biot_profile_enable(biot_handle* h, int32_t enable);
+#define BIOT_PROBE_ALL 0x3F
+int biot_profile_enable(biot_handle* h, int32_t mask);
 int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
                       double* total_bytes, const char** name);
 

@@ -84,7 +84,11 @@ struct biot_handle {
   ColDesc* desc_jac[2] = {nullptr, nullptr};
   ColDesc* desc_k4[2] = {nullptr, nullptr};
   ColDesc* desc_wave[2] = {nullptr, nullptr};
+  ColDesc* desc_part = nullptr;          // table of a partial (shallower) pass
   std::vector<int> wave_off, wave_cnt;
+  std::vector<ColDesc> h_part;
+  std::vector<int> part_off, part_cnt;
+  int part_key = -1;                     // (parity, depth) of the uploaded table
   std::vector<ChebCoef> chA, chS;
   // host copies of the descriptor tables (uploaded at bind)
   std::vector<ColDesc> h_jac[2], h_k4[2], h_wave[2];
@@ -92,6 +96,7 @@ struct biot_handle {
   struct Pending { hipEvent_t a, b; int id; double bytes; };
   struct Acc { uint64_t launches = 0; double ms = 0, bytes = 0; };
   bool prof = false;
+  unsigned prof_mask = 0;  // which probes record events
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
   std::vector<Pending> pending;
@@ -224,7 +229,45 @@ void plan(biot_handle* h, char* base) {
     if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
       h->desc_wave[c] = b.take<ColDesc>(size_t(h->N) * h->opt.depth);
   }
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
+    h->desc_part = b.take<ColDesc>(size_t(h->N) * h->opt.depth);
   h->ws_need = b.off + 256;
+}
+
+// Wavefront table of a pass of depth d (<= the configured depth) reading
+// trajectory T[c] and writing T[1-c]: at wave w, slot s updates step w - s
+// from its iterate of sweep s to sweep s+1.  Slot s reads its input from slot
+// s-1's output of the previous wave (slot 0: the trajectory) and its coupling
+// from its own previous output (step 1: X^0); outputs alternate between two
+// buffers per slot; slot d-1 also writes the trajectory.
+void wave_table(biot_handle* h, int c, int d, std::vector<ColDesc>& tab, std::vector<int>& off,
+                std::vector<int>& cnt) {
+  const size_t col = h->col;
+  const int D = h->opt.depth;
+  double* Tin = h->T[c];
+  double* Tout = h->T[1 - c];
+  auto slot = [&](int s, int parity) { return h->slots + (size_t(parity) * D + s) * col; };
+  tab.clear();
+  off.clear();
+  cnt.clear();
+  for (int w = 1; w <= h->N + d - 1; ++w) {
+    off.push_back(int(tab.size()));
+    int k = 0;
+    for (int s = 0; s < d; ++s) {
+      const int n = w - s;
+      if (n < 1 || n > h->N) continue;
+      ColDesc e{};
+      e.xcur = s == 0 ? Tin + n * col : slot(s - 1, (w - 1) & 1);
+      e.xprev = n == 1 ? Tin : slot(s, (w - 1) & 1);
+      e.xout = slot(s, w & 1);
+      e.xout2 = s == d - 1 ? Tout + n * col : nullptr;
+      e.coef = h->P.coef[n];
+      e.step = n;
+      tab.push_back(e);
+      ++k;
+    }
+    cnt.push_back(k);
+  }
 }
 
 void build_tables(biot_handle* h) {
@@ -246,34 +289,10 @@ void build_tables(biot_handle* h) {
       d.xout = nullptr;
       h->h_k4[c][n - 1] = d;
     }
-    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) {
-      const int D = h->opt.depth;
-      auto slot = [&](int s, int parity) { return h->slots + (size_t(parity) * D + s) * col; };
-      h->h_wave[c].clear();
-      h->wave_off.clear();
-      h->wave_cnt.clear();
-      for (int w = 1; w <= h->N + D - 1; ++w) {
-        h->wave_off.push_back(int(h->h_wave[c].size()));
-        int cnt = 0;
-        for (int s = 0; s < D; ++s) {
-          const int n = w - s;
-          if (n < 1 || n > h->N) continue;
-          ColDesc d{};
-          d.xcur = s == 0 ? Tin + n * col : slot(s - 1, (w - 1) & 1);
-          d.xprev = n == 1 ? Tin : slot(s, (w - 1) & 1);
-          d.xout = slot(s, w & 1);
-          d.xout2 = s == D - 1 ? Tout + n * col : nullptr;
-          d.coef = h->P.coef[n];
-          d.step = n;
-          h->h_wave[c].push_back(d);
-          ++cnt;
-        }
-        h->wave_cnt.push_back(cnt);
-      }
-    }
+    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
+      wave_table(h, c, h->opt.depth, h->h_wave[c], h->wave_off, h->wave_cnt);
   }
 }
-
 ChebCoef cheb_of(double lmax, double ratio) {
   ChebCoef c;
   const double lmin = lmax / ratio;
@@ -320,7 +339,7 @@ struct ProbeScope {
   int rc = BIOT_OK;
   bool live = true;
   ProbeScope(biot_handle* h_, int id_, double bytes_) : h(h_), id(id_), bytes(bytes_) {
-    if (!h->prof || id < 0 || bytes <= 0) {
+    if (!h->prof || id < 0 || bytes <= 0 || !((h->prof_mask >> id) & 1u)) {
       live = false;
       return;
     }
@@ -528,15 +547,35 @@ int jacobi_sweep(biot_handle* h) {
   return BIOT_OK;
 }
 
-int wavefront_pass_eager(biot_handle* h) {
-  ColDesc* tab = h->desc_wave[h->cur];
-  for (size_t w = 0; w < h->wave_off.size(); ++w) {
-    const int wave = int(w) + 1, last_step = wave - h->opt.depth + 1;
+int run_waves(biot_handle* h, const ColDesc* tab, const std::vector<int>& off,
+              const std::vector<int>& cnt, int d) {
+  for (size_t w = 0; w < off.size(); ++w) {
+    const int wave = int(w) + 1, last_step = wave - d + 1;
     h->cur_copies = (last_step >= 1 && last_step <= h->N) ? 1 : 0;
-    int rc = unit_batch(h, tab + h->wave_off[w], h->wave_cnt[w]);
+    int rc = unit_batch(h, tab + off[w], cnt[w]);
     if (rc) return rc;
   }
   h->cur_copies = 0;
+  return BIOT_OK;
+}
+
+int wavefront_pass_eager(biot_handle* h) {
+  return run_waves(h, h->desc_wave[h->cur], h->wave_off, h->wave_cnt, h->opt.depth);
+}
+
+// a pass shallower than the configured depth (eager; table built on demand)
+int wavefront_partial(biot_handle* h, int d) {
+  const int key = h->cur * 65536 + d;
+  if (h->part_key != key) {
+    wave_table(h, h->cur, d, h->h_part, h->part_off, h->part_cnt);
+    HIPCHK(h, hipMemcpyAsync(h->desc_part, h->h_part.data(), h->h_part.size() * sizeof(ColDesc),
+                             hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->part_key = key;
+  }
+  int rc = run_waves(h, h->desc_part, h->part_off, h->part_cnt, d);
+  if (rc) return rc;
+  h->cur = 1 - h->cur;
   return BIOT_OK;
 }
 
@@ -769,6 +808,7 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
   if (h->opt.schedule == BIOT_SCHED_WAVEFRONT && h->opt.use_graph && !h->cap_stream)
     HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   h->cur = 0;
+  h->part_key = -1;
   h->bound = true;
   return BIOT_OK;
 }
@@ -788,9 +828,10 @@ int biot_sweep(biot_handle* h, int32_t n_sweeps) {
   if (rc) return rc;
   if (n_sweeps < 0) return fail(h, BIOT_EINVAL, "n_sweeps < 0");
   if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) {
-    if (n_sweeps % h->opt.depth != 0) return fail(h, BIOT_EINVAL, "wavefront: n_sweeps must be a multiple of depth");
     for (int p = 0; p < n_sweeps / h->opt.depth; ++p)
       if ((rc = wavefront_pass(h))) return rc;
+    if (n_sweeps % h->opt.depth)
+      if ((rc = wavefront_partial(h, n_sweeps % h->opt.depth))) return rc;
   } else {
     for (int s = 0; s < n_sweeps; ++s)
       if ((rc = jacobi_sweep(h))) return rc;
@@ -816,8 +857,7 @@ int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t c
     return fail(h, BIOT_EINVAL, "need rtol > 0, max_sweeps >= 0, check_every >= 1");
   auto t0 = std::chrono::steady_clock::now();
   int step = check_every;
-  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
-    step = ((check_every + h->opt.depth - 1) / h->opt.depth) * h->opt.depth;
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) step = h->opt.depth;  // first pass: full depth
   std::vector<double> nr(size_t(h->N) * 4);
   int done = 0;
   double ru = 0, rp = 0;
@@ -846,8 +886,16 @@ int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t c
       rc = fail(h, BIOT_ENOTCONVERGED, "max_sweeps reached above tolerance");
       break;
     }
-    const int k = std::min(step, max_sweeps - done);
-    const int kk = h->opt.schedule == BIOT_SCHED_WAVEFRONT ? ((k + h->opt.depth - 1) / h->opt.depth) * h->opt.depth : k;
+    int kk = std::min(step, max_sweeps - done);
+    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT && done > 0) {
+      // size the next pass from the observed contraction per sweep, with margin
+      const double rate = std::pow(worst / std::max(first, 1e-300), 1.0 / done);
+      if (rate > 0 && rate < 0.999) {
+        const double need = std::log(rtol / worst) / std::log(rate);
+        const int k = int(std::ceil(1.15 * need)) + 2;
+        kk = std::min({std::max(4, (k + 3) / 4 * 4), h->opt.depth, max_sweeps - done});
+      }
+    }
     int r2 = biot_sweep(h, kk);
     if (r2) return r2;
     done += kk;
@@ -903,7 +951,8 @@ int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols
   return apply_precond_t<double>(h, h->pd, R, Z, ncols);
 }
 
-int biot_profile_enable(biot_handle* h, int32_t enable) {
+int biot_profile_enable(biot_handle* h, int32_t mask) {
+  const int32_t enable = mask;
   int rc = check_bound(h);
   if (rc) return rc;
   if ((rc = harvest(h))) return rc;
@@ -916,6 +965,7 @@ int biot_profile_enable(biot_handle* h, int32_t enable) {
     for (size_t i = old; i < want; ++i) HIPCHK(h, hipEventCreate(&h->ev_pool[i]));
   }
   h->prof = enable != 0;
+  h->prof_mask = unsigned(mask) & ((1u << BIOT_PROBE_COUNT) - 1);
   return BIOT_OK;
 }
 

@@ -187,9 +187,16 @@ class BiotSolver:
     def info(self) -> dict:
         return handle_info(self.lib, self.h)
 
-    def profile(self, enable: bool = True):
-        """Start (or stop) the HIP-event probes around level-0 launches."""
-        self._check(self.lib.biot_profile_enable(self.h, 1 if enable else 0))
+    def profile(self, enable: bool = True, probes=None):
+        """Start (or stop) the HIP-event probes around level-0 launches; `probes`
+        selects a subset by name (see _lib.PROBES), default all."""
+        if not enable:
+            mask = 0
+        elif probes is None:
+            mask = (1 << len(_lib.PROBES)) - 1
+        else:
+            mask = sum(1 << _lib.PROBES.index(p) for p in probes)
+        self._check(self.lib.biot_profile_enable(self.h, mask))
 
     def profile_read(self) -> dict:
         out = {}

@@ -8,7 +8,12 @@ SuperLU solve and one refinement step per step:
                            (numpy default_rng(7), without replacement)
     samples[n, k]          X^n at those dofs
 
-Run:  python tests/golden/make_goldens.py     (about 3 minutes on one core)
+large_heterogeneous.npz -- the same mesh and steps with a log-normal
+permeability field (sigma_log = 1, correlation length 0.1, field seed 2) and
+E ~ U[5e3, 2e4] per element (seed 102); same contents.
+
+Run:  python tests/golden/make_goldens.py [large_terzaghi] [large_heterogeneous]
+      (about 2 minutes each on one core)
 """
 import os
 import sys
@@ -23,8 +28,7 @@ from paper_2310_10430_amd import workloads as W  # noqa: E402
 from oracle import fem, sequential as seq  # noqa: E402
 
 
-def large_terzaghi():
-    pb = W.large_terzaghi()
+def write(name, pb):
     t0 = time.time()
     orc = seq.BiotOracle(pb)
     X = orc.solve_sequential()
@@ -35,12 +39,15 @@ def large_terzaghi():
     free = np.nonzero(~fixed_nm)[0]
     dofs = np.sort(np.random.default_rng(7).choice(free, size=256, replace=False))
     np.savez_compressed(
-        os.path.join(HERE, "large_terzaghi.npz"),
+        os.path.join(HERE, name + ".npz"),
         norm_u=np.linalg.norm(Y[..., :2].reshape(Y.shape[0], -1), axis=1),
         norm_p=np.linalg.norm(Y[..., 2], axis=1),
         dofs=dofs.astype(np.int64), samples=flat[:, dofs])
-    print(f"large_terzaghi.npz written in {time.time() - t0:.1f} s")
+    print(f"{name}.npz written in {time.time() - t0:.1f} s")
 
+
+WORKLOADS = {"large_terzaghi": W.large_terzaghi, "large_heterogeneous": W.large_heterogeneous}
 
 if __name__ == "__main__":
-    large_terzaghi()
+    for name in (sys.argv[1:] or list(WORKLOADS)):
+        write(name, WORKLOADS[name]())

@@ -159,12 +159,22 @@ def test_sweeps_are_deterministic_and_resumable():
     assert torch.equal(A, B)
 
 
-def test_wavefront_rejects_partial_pass():
-    pb = W.terzaghi_problem(8, 5)
-    s = BiotSolver(pb, schedule="wavefront", depth=3)
-    with pytest.raises(RuntimeError):
-        s.sweep(2)
+def test_wavefront_partial_pass_matches_oracle():
+    """sweep(5) with depth 3 = one pass of 3 sweeps then a pass of 2."""
+    pb = W.heterogeneous_problem(16, 7)
+    orc = seq.BiotOracle(pb)
+    P = precond.BlockPreconditioner(orc, "P1", "gmg")
+    X = _random_state(orc, pb.n_steps + 1, 8)
+    X[0] = 0.0
+    s = BiotSolver(pb, schedule="wavefront", depth=3, omega=0.6)
+    s.set_trajectory(torch.from_numpy(_nm(X, orc)))
+    s.sweep(5)
+    Xg = _fm(s.trajectory().cpu().numpy())
     s.close()
+    Xo = inverted.wavefront(orc, X, P, 0.6, 3)
+    Xo = inverted.wavefront(orc, Xo, P, 0.6, 2)
+    assert _rel(Xg[:, : orc.nU], Xo[:, : orc.nU]) < 1e-11
+    assert _rel(Xg[:, orc.nU:], Xo[:, orc.nU:]) < 1e-11
 
 
 def test_graph_replays_match_eager_passes():
