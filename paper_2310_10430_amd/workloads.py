@@ -287,6 +287,24 @@ def large_heterogeneous() -> Problem:
     return heterogeneous_problem(256, 512)
 
 
+def adjoint_problem(n: int = 128, n_steps: int = 256, field_seed: int = 40) -> Problem:
+    """Gradient workload: consolidation column with a log-normal permeability
+    field (the point where the gradient is taken) and homogeneous E, nu."""
+    return terzaghi_problem(n, n_steps, perm=lognormal_perm_2d(n, field_seed))
+
+
+def adjoint_reference_logk(n: int = 128, seed: int = 41) -> np.ndarray:
+    """Log-permeability of the reference field that generates the observations."""
+    return np.log(lognormal_perm_2d(n, seed))
+
+
+def fd_directions(n_elems: int, count: int = 32, seed: int = 43):
+    """Seeded directions (d log K, d lambda / lambda, d mu / mu) per element."""
+    rng = np.random.default_rng(seed)
+    return [(rng.standard_normal(n_elems), rng.standard_normal(n_elems),
+             rng.standard_normal(n_elems)) for _ in range(count)]
+
+
 def batched_samples(count: int = 64, seed: int = 3):
     """(grid n, n_steps, field seed) for independent samples of uneven size."""
     rng = np.random.default_rng(seed)

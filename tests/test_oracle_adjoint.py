@@ -1,0 +1,168 @@
+"""Pins of the oracle's discrete adjoint (CPU only).
+
+* duality: <g, calA^{-1} f> = <calA^{-T} g, f> for the space-time system;
+* dense brute force: calA^T Lam = g solved with numpy.linalg.solve;
+* central finite differences (h = 1e-6, 32 seeded directions) of the objective
+  computed with the direct-solve forward, against <grad J, v>, to 1e-6 of the
+  cancellation-free size sum_i |g_i v_i|;
+* a configuration where the stabilization term dominates the Lame gradients, so
+  that a wrong d beta / d lambda or d beta / d mu would be seen.
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as adj
+from oracle import fem
+from paper_2310_10430_amd import workloads as wl
+
+
+def _params(pb, seed):
+    rng = np.random.default_rng(seed)
+    logk, lam, mu = adj.problem_params(pb)
+    ne = pb.n_elems
+    return (logk + 0.5 * rng.standard_normal(ne), lam * rng.uniform(0.7, 1.3, ne),
+            mu * rng.uniform(0.7, 1.3, ne))
+
+
+def _free_random(orc, N, rng):
+    v = rng.standard_normal((N, orc.n_dof))
+    v[:, orc.fixed] = 0.0
+    return v
+
+
+def test_duality_space_time():
+    pb = wl.terzaghi_problem(4, 6)
+    orc = adj.oracle_for_params(pb, *_params(pb, 1))
+    rng = np.random.default_rng(5)
+    f = _free_random(orc, 6, rng)
+    g = _free_random(orc, 6, rng)
+    X = adj.space_time_solve(orc, f)
+    Lam = adj.adjoint_solve(orc, g)
+    lhs = np.sum(g * X[1:])
+    rhs = np.sum(Lam * f)
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0) * 10
+
+
+def test_adjoint_dense_bruteforce():
+    pb = wl.terzaghi_problem(3, 5)
+    orc = adj.oracle_for_params(pb, *_params(pb, 2))
+    N = 5
+    fr = orc.free
+    m = fr.size
+    AA = orc.AA.toarray()[np.ix_(fr, fr)]
+    Ap = orc.Ap.toarray()[np.ix_(fr, fr)]
+    calA = np.zeros((N * m, N * m))
+    for n in range(N):
+        calA[n * m:(n + 1) * m, n * m:(n + 1) * m] = AA
+        if n > 0:
+            calA[n * m:(n + 1) * m, (n - 1) * m:n * m] = -Ap
+    rng = np.random.default_rng(9)
+    g = _free_random(orc, N, rng)
+    ref = np.linalg.solve(calA.T, g[:, fr].ravel()).reshape(N, m)
+    Lam = adj.adjoint_solve(orc, g)
+    assert np.max(np.abs(Lam[:, fr] - ref)) <= 1e-11 * np.max(np.abs(ref))
+    assert np.all(Lam[:, orc.fixed] == 0.0)
+
+
+def _fd_case(n=8, N=12, stab_h=None, seed=3):
+    pb = wl.terzaghi_problem(n, N)
+    if stab_h is not None:
+        pb.stab_h = stab_h
+    theta = _params(pb, seed)
+    sensors = wl.sensor_nodes(pb, 10, seed=42)
+    ref_logk = theta[0] + 0.8 * np.random.default_rng(seed + 100).standard_normal(pb.n_elems)
+    orc_r, Xr = adj.forward(pb, ref_logk, theta[1], theta[2])
+    p_obs = adj.sensor_pressures(orc_r, Xr, sensors)
+    return pb, theta, sensors, p_obs
+
+
+def _fd_check(pb, theta, sensors, p_obs, dirs, h=1e-6, rel=1e-6):
+    J, (gk, gl, gm), _, _ = adj.objective_and_gradient(pb, *theta, sensors, p_obs)
+    logk, lam, mu = theta
+    worst = 0.0
+    for vk, vl, vm in dirs:
+        # perturb log K additively and lambda, mu relative to their size
+        dk, dl, dm = vk, lam * vl, mu * vm
+        jp = adj.objective_value(pb, logk + h * dk, lam + h * dl, mu + h * dm, sensors, p_obs)
+        jm = adj.objective_value(pb, logk - h * dk, lam - h * dl, mu - h * dm, sensors, p_obs)
+        fd = (jp - jm) / (2 * h)
+        an = gk @ dk + gl @ dl + gm @ dm
+        # relative to the cancellation-free size sum |g_i v_i|: a direction whose
+        # terms cancel has a tiny derivative that FD rounding cannot resolve
+        scale = np.abs(gk * dk).sum() + np.abs(gl * dl).sum() + np.abs(gm * dm).sum()
+        err = abs(fd - an) / max(scale, 1e-300)
+        worst = max(worst, err)
+        assert err <= rel, (fd, an, err)
+    return J, worst
+
+
+def test_gradient_central_fd_32_directions():
+    pb, theta, sensors, p_obs = _fd_case()
+    rng = np.random.default_rng(43)
+    ne = pb.n_elems
+    dirs = [(rng.standard_normal(ne), rng.standard_normal(ne), rng.standard_normal(ne))
+            for _ in range(32)]
+    J, worst = _fd_check(pb, theta, sensors, p_obs, dirs)
+    assert J > 0
+
+
+def test_gradient_fd_each_family():
+    pb, theta, sensors, p_obs = _fd_case(seed=4)
+    rng = np.random.default_rng(44)
+    ne = pb.n_elems
+    z = np.zeros(ne)
+    dirs = []
+    for fam in range(3):
+        for _ in range(3):
+            v = [z, z, z]
+            v[fam] = rng.standard_normal(ne)
+            dirs.append(tuple(v))
+    _fd_check(pb, theta, sensors, p_obs, dirs)
+    # one-element directions on the first, a middle and the last element: their
+    # derivatives are ~1e-3 of J, so a larger step keeps FD rounding below 1e-6
+    single = []
+    for e in (0, ne // 2, ne - 1):
+        for fam in range(3):
+            v = [z.copy(), z.copy(), z.copy()]
+            v[fam][e] = 1.0
+            single.append(tuple(v))
+    _fd_check(pb, theta, sensors, p_obs, single, h=1e-4)
+
+
+def test_gradient_fd_stabilization_dominated():
+    # a large h in beta makes C_beta comparable to tau C_K, so the d beta terms
+    # carry a visible share of the Lame gradients
+    pb, theta, sensors, p_obs = _fd_case(n=6, N=10, stab_h=4.0, seed=5)
+    J, (gk, gl, gm), X, Lam = adj.objective_and_gradient(pb, *theta, sensors, p_obs)
+    orc = adj.oracle_for_params(pb, *theta)
+    # the same contraction with beta frozen: must differ clearly
+    asm = orc.asm
+    frozen = fem.Assembled(asm.dim, asm.n_nodes, asm.A, asm.B, asm.CK, asm.Cb, asm.lam, asm.mu,
+                           np.zeros_like(asm.beta))
+    orc.asm = frozen
+    _, gl0, gm0 = adj.parameter_gradient(orc, X, Lam, np.exp(theta[0]))
+    assert np.linalg.norm(gl - gl0) > 1e-2 * np.linalg.norm(gl)
+    assert np.linalg.norm(gm - gm0) > 1e-2 * np.linalg.norm(gm)
+    rng = np.random.default_rng(45)
+    ne = pb.n_elems
+    z = np.zeros(ne)
+    dirs = [(z, rng.standard_normal(ne), z) for _ in range(4)]
+    dirs += [(z, z, rng.standard_normal(ne)) for _ in range(4)]
+    _fd_check(pb, theta, sensors, p_obs, dirs)
+
+
+def test_global_lame_gradient_is_element_sum():
+    pb, theta, sensors, p_obs = _fd_case(n=6, N=8, seed=6)
+    ne = pb.n_elems
+    one, z = np.ones(ne), np.zeros(ne)
+    # relative perturbation of a global lambda (all elements together)
+    _fd_check(pb, theta, sensors, p_obs, [(z, one, z), (z, z, one)])
+
+
+def test_objective_gradient_state_masks_prescribed():
+    pb, theta, sensors, p_obs = _fd_case(n=4, N=4, seed=7)
+    orc, X = adj.forward(pb, *theta)
+    g = adj.objective_gradient_state(orc, X, sensors, p_obs)
+    assert np.all(g[:, orc.fixed] == 0.0)
+    idx = orc.nU + sensors
+    np.testing.assert_allclose(g[:, idx], 2 * (X[1:, idx] - p_obs), rtol=0, atol=0)
