@@ -12,6 +12,11 @@ E = 1e4, nu = 0.3, alpha = 1, K = 1e-2, 512 backward-Euler steps of dt = 1/512,
 FP64.  value = unknowns x steps / (wall time of one solve), with the accuracy of
 the converged trajectory against the FP64 sequential oracle reported beside it.
 
+Also reported: the seconds for one gradient of a pressure-misfit objective
+(forward + adjoint, 128 x 128 mesh, 256 steps; checkpoints every 16 steps and,
+for comparison, the whole forward trajectory kept), the mixed-precision and
+heterogeneous variants, and the CPU oracle's times on one host core.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
@@ -121,6 +126,96 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2):
             "max_rel_err_vs_oracle_samples": max(acc.values()), "accuracy": acc}
 
 
+def adjoint_errors(grads, golden, pb, lam, mu):
+    """Gradient errors against the stored oracle gradient and central FD."""
+    from paper_2310_10430_amd import workloads as W
+    out = {}
+    for g, key in zip(grads, ("grad_logk", "grad_lambda", "grad_mu")):
+        ref = golden[key]
+        out[key] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    worst = 0.0
+    for (vk, vl, vm), fd, sc in zip(W.fd_directions(pb.n_elems, 32, seed=43), golden["fd"],
+                                    golden["fd_scale"]):
+        an = grads[0] @ vk + grads[1] @ (lam * vl) + grads[2] @ (mu * vm)
+        worst = max(worst, abs(an - fd) / sc)
+    out["fd_32_directions"] = worst
+    return out
+
+
+def run_adjoint(BiotSolver, args, reps=2):
+    """Seconds for one gradient (forward solve + objective + adjoint solve +
+    gradient contraction) of the pressure misfit on the gradient workload, with
+    checkpoints every 16 steps and with the whole forward trajectory kept."""
+    import torch
+    from paper_2310_10430_amd import workloads as W
+    golden = np.load(os.path.join(ROOT, "tests", "golden", "adjoint_c4.npz"))
+    sensors, p_obs = golden["sensors"], golden["p_obs"]
+    pb = W.adjoint_problem()
+    E, nu = pb.young, pb.poisson
+    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
+    mu = E / (2 * (1 + nu))
+    res = {"workload": "adjoint_c4: 128x128 consolidation column, 49923 unknowns, 256 steps "
+                       "dt=1/256, log-normal K (field seed 40), 64 pressure sensors, "
+                       "observations from reference field seed 41; gradient w.r.t. 32768 "
+                       "log K_e and lambda_e, mu_e",
+           "rtol": args.rtol}
+    for stride in (16, 0):
+        s = BiotSolver(pb, schedule=args.schedule, depth=args.depth, omega=args.omega,
+                       col_tile=args.col_tile, adjoint=True, ckpt_stride=stride,
+                       replay_segments=4, max_sensors=64)
+
+        def grad():
+            s.reset()
+            st = s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps,
+                                check_every=args.check_every)
+            out = s.adjoint(sensors, p_obs, rtol=args.rtol, max_sweeps=args.max_sweeps)
+            return st, out
+        grad()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st, out = grad()
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / reps
+        grads = [out[k].cpu().numpy() for k in ("grad_logk", "grad_lambda", "grad_mu")]
+        s.close()
+        key = f"ckpt_{stride}" if stride else "full_trajectory"
+        res[key] = {"seconds": per, "forward_s": st["seconds"],
+                    "adjoint_s": out["seconds_adjoint"], "replay_and_contraction_s":
+                    out["seconds_replay"], "forward_sweeps": st["sweeps"],
+                    "adjoint_sweeps": out["adjoint_sweeps"],
+                    "replay_sweeps": out["replay_sweeps"], "replay_groups": out["replay_groups"],
+                    "J": out["J"], "rel_err_vs_oracle": adjoint_errors(grads, golden, pb, lam, mu)}
+        log(f"bench: adjoint ckpt_stride={stride}: {per:.3f} s per gradient")
+    res["seconds"] = res["ckpt_16"]["seconds"]
+    return res
+
+
+def cpu_adjoint_baseline():
+    """The oracle's gradient (factorization, 256 forward and 256 adjoint direct
+    solves, element contraction) of the gradient workload on one host core."""
+    from oracle import adjoint as adj
+    from paper_2310_10430_amd import workloads as W
+    golden = np.load(os.path.join(ROOT, "tests", "golden", "adjoint_c4.npz"))
+    pb = W.adjoint_problem()
+    try:
+        prev = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(prev)})
+        cores = 1
+    except (AttributeError, OSError):
+        prev = None
+        cores = os.cpu_count()
+    try:
+        t0 = time.perf_counter()
+        adj.objective_and_gradient(pb, *adj.problem_params(pb), golden["sensors"], golden["p_obs"])
+        t = time.perf_counter() - t0
+    finally:
+        if prev is not None:
+            os.sched_setaffinity(0, prev)
+    return {"seconds": t, "cores": cores, "kind": "oracle",
+            "sample": "one whole gradient of the gradient workload (assembly included)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +239,8 @@ def main():
                     help="kernel timed with HIP events in the timed region")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision and heterogeneous-permeability variants")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the gradient (adjoint) measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
@@ -247,6 +344,14 @@ def main():
             log(f"bench: variant {name}")
             variants[name] = run_variant(BiotSolver, prob, gname, prec, args)
 
+    adjoint = None
+    if not args.no_adjoint:
+        log("bench: adjoint gradient workload")
+        adjoint = run_adjoint(BiotSolver, args)
+        if not args.no_cpu_baseline:
+            log("bench: timing the CPU oracle's gradient (about half a minute)")
+            adjoint["cpu_oracle"] = cpu_adjoint_baseline()
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -280,6 +385,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "variants": variants,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
 

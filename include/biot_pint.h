@@ -95,6 +95,9 @@ typedef struct {
                           /* beta_e = alpha^2 stab_h^2 / (4 (lambda_e + 2 mu_e))     */
   double alpha;           /* Biot-Willis coefficient                               */
   double stab_h;          /* mesh size entering the default beta                    */
+  const double* lame_lambda; /* [n_elems] lambda_e, or NULL: both given together   */
+  const double* lame_mu;     /* [n_elems] mu_e > 0; when set, young and poisson     */
+                             /* are ignored (they may be NULL)                      */
 } biot_materials;
 
 /* Surface load: constant traction per boundary facet, scaled per time level. */
@@ -121,7 +124,34 @@ typedef struct {
                         /* level is solved with a dense inverse                    */
   int32_t use_graph;    /* wavefront: replay each pass as a captured HIP graph (1) */
   int32_t precision;    /* BIOT_PRECISION_* (default FP64)                          */
+  /* adjoint (biot_adjoint); its buffers count in the workspace only when on    */
+  int32_t adjoint;         /* 1: reserve the adjoint buffers (0)                   */
+  int32_t ckpt_stride;     /* 0: keep the whole forward trajectory; s > 0: keep    */
+                           /* X^{ks} and X^N only, overwrite the forward           */
+                           /* trajectory with the adjoint one and recompute each   */
+                           /* segment from its checkpoint for the gradient (16)    */
+  int32_t replay_segments; /* segments recomputed together (4)                     */
+  int32_t max_sensors;     /* capacity of the objective's sensor list (256)        */
 } biot_options;
+
+/* Pressure-misfit objective J = sum_{n=1..N} sum_s (p^n(node_s) - p_obs[n-1][s])^2. */
+typedef struct {
+  int32_t n_sensors;        /* 1..max_sensors                                     */
+  const int32_t* nodes;     /* [n_sensors] distinct node ids (host)               */
+  const double* p_obs;      /* [n_steps][n_sensors] observed pressure (host)      */
+} biot_objective;
+
+typedef struct {
+  double J;                 /* objective at the forward trajectory                */
+  int32_t adjoint_sweeps;   /* outer sweeps of the adjoint solve                  */
+  int32_t replay_sweeps;    /* outer sweeps summed over the replayed groups       */
+  int32_t replay_groups;    /* groups of segments recomputed (0 without ckpt)     */
+  double adjoint_rel_resid; /* max over fields of the adjoint's relative residual */
+  double replay_rel_resid;  /* worst over groups of the replays' residuals        */
+  double seconds_adjoint;   /* wall time of the adjoint solve                     */
+  double seconds_replay;    /* wall time of replays and gradient contraction      */
+  double seconds;           /* wall time of the call                              */
+} biot_adjoint_stats;
 
 typedef struct {
   int32_t sweeps;       /* outer sweeps performed                                  */
@@ -216,8 +246,6 @@ int biot_profile_enable(biot_handle* h, int32_t mask);
 int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
                       double* total_bytes, const char** name);
 
-/* Message of the last failed call on h (or of the last failed biot_create when
- * h is NULL).  Valid until the next call on the same handle. */
 /* Host copies of the operators of multigrid level `level` as assembled by
  * biot_create (after the boundary conditions), in the node-blocked layout:
  *   nbr [W][nn]           neighbour node of each slot (slot 0 = the node)
@@ -232,6 +260,40 @@ int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double*
 int biot_export_level(const biot_handle* h, int32_t level, int32_t* nbr, double* A, double* S,
                       double* B, double* Bt, double* Cb, double* F);
 
+/* J of the objective at the current trajectory (host value; synchronizes). */
+int biot_objective_value(biot_handle* h, const biot_objective* obj, double* J);
+
+/* Gradient of the pressure misfit J with respect to the per-element parameters
+ * log K_e, lambda_e and mu_e, by the discrete adjoint of the backward-Euler
+ * trajectory (the fixed point of the inverted iteration, Sec. 3.2).  With the
+ * space-time system calA X = f of eq. (fullysystem) (block row n: AA on the
+ * diagonal, -A' below it), the adjoint states solve calA^T Lam = dJ/dX, i.e.
+ *     AA Lam^n = dJ/dX^n + A'^T Lam^{n+1},   Lam^{N+1} = 0,
+ * which is run through the same inverted iteration, schedule and preconditioner
+ * as the forward problem, backward in time (AA is symmetric).  Then
+ *     dJ/dtheta = -sum_n Lam^n . (dAA/dtheta X^n - dA'/dtheta X^{n-1}),
+ * contracted element by element: log K through S = tau C_K + C_beta, lambda and
+ * mu through A and through the default beta_e (no beta term when the caller
+ * gave beta).  A global lambda or mu has the sum of the entries as gradient.
+ * The trajectory in the handle is taken as the converged forward solution
+ * (call biot_solve_to_tol first) and the call needs options.adjoint = 1.
+ * With ckpt_stride s > 0 the forward trajectory is overwritten (afterwards
+ * biot_sweep, biot_solve_to_tol and biot_get_trajectory return BIOT_ESTATE until
+ * biot_reset); each segment of s steps is recomputed from its checkpoint,
+ * replay_segments at a time, to rtol.  rtol and max_sweeps apply to the adjoint
+ * solve and to every replay.  grad_* are [n_elems] doubles, device pointers if
+ * grads_on_device else host; any may be NULL.  stats may be NULL.
+ * Synchronizes the stream. */
+int biot_adjoint(biot_handle* h, const biot_objective* obj, double rtol, int32_t max_sweeps,
+                 double* grad_logk, double* grad_lambda, double* grad_mu, int32_t grads_on_device,
+                 biot_adjoint_stats* stats);
+
+/* Copies the adjoint states Lam^n, n = n0..n1-1 (1 <= n0 <= n1 <= n_steps+1) of
+ * the last biot_adjoint call to dst ([n1-n0][n_nodes][dim+1], node-major). */
+int biot_get_adjoint(biot_handle* h, int32_t n0, int32_t n1, double* dst, int32_t dst_on_device);
+
+/* Message of the last failed call on h (or of the last failed biot_create when
+ * h is NULL).  Valid until the next call on the same handle. */
 const char* biot_last_error(const biot_handle* h);
 
 const char* biot_version(void);

@@ -26,7 +26,8 @@ class Mesh(C.Structure):
 
 class Materials(C.Structure):
     _fields_ = [("young", _dp), ("poisson", _dp), ("perm", _dp), ("beta", _dp),
-                ("alpha", C.c_double), ("stab_h", C.c_double)]
+                ("alpha", C.c_double), ("stab_h", C.c_double), ("lame_lambda", _dp),
+                ("lame_mu", _dp)]
 
 
 class Load(C.Structure):
@@ -39,7 +40,19 @@ class Options(C.Structure):
                 ("lmax_safety", C.c_double), ("power_iters", C.c_int32),
                 ("max_batch", C.c_int32), ("omega", C.c_double), ("col_tile", C.c_int32),
                 ("coarse_cells", C.c_int32), ("use_graph", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("adjoint", C.c_int32), ("ckpt_stride", C.c_int32),
+                ("replay_segments", C.c_int32), ("max_sensors", C.c_int32)]
+
+
+class Objective(C.Structure):
+    _fields_ = [("n_sensors", C.c_int32), ("nodes", _ip), ("p_obs", _dp)]
+
+
+class AdjointStats(C.Structure):
+    _fields_ = [("J", C.c_double), ("adjoint_sweeps", C.c_int32), ("replay_sweeps", C.c_int32),
+                ("replay_groups", C.c_int32), ("adjoint_rel_resid", C.c_double),
+                ("replay_rel_resid", C.c_double), ("seconds_adjoint", C.c_double),
+                ("seconds_replay", C.c_double), ("seconds", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -77,6 +90,11 @@ SIGNATURES = {
     "biot_profile_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_char_p)]),
+    "biot_objective_value": (C.c_int, [C.c_void_p, C.POINTER(Objective), C.POINTER(C.c_double)]),
+    "biot_adjoint": (C.c_int, [C.c_void_p, C.POINTER(Objective), C.c_double, C.c_int32,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                               C.POINTER(AdjointStats)]),
+    "biot_get_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
     "biot_last_error": (C.c_char_p, [C.c_void_p]),
     "biot_version": (C.c_char_p, []),
     "biot_destroy": (None, [C.c_void_p]),

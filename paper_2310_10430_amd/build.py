@@ -5,15 +5,17 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbiot_pint.so")
-SOURCES = ["setup.cpp", "kernels.hip", "solver.hip"]
+SOURCES = ["setup.cpp", "kernels.hip", "adjoint.hip", "solver.hip"]
+OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "-fPIC",
     "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of every device code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -29,15 +31,26 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found; the HIP toolchain is required to build libbiot_pint.so")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libbiot_pint.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel) and link libbiot_pint.so; always
+    recompiles."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    cc = hipcc()
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    jobs = [[cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for f in [ex.submit(_run, j, verbose) for j in jobs]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([cc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -77,9 +77,13 @@ __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
 // ---------------------------------------------------------------------------
 // fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1} (FP64), the
 // coupled right-hand side norms, and the first (pointwise) Chebyshev step of
-// the displacement V-cycle; r and that step are stored as T
+// the displacement V-cycle; r and that step are stored as T.
+// ADJ: the adjoint recursion run forward in reversed time, whose coupling is
+// A'^T = [0 B; 0 -C_beta] applied to the previous column and whose load is the
+// pressure-row vector gload[step-1] (no traction load):
+//   r = [B p'; -C_beta p' + g] - AA X^{m-1}.
 // ---------------------------------------------------------------------------
-template <int DIM, int G, typename T>
+template <int DIM, int G, typename T, bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
                                                      T* __restrict__ ru, T* __restrict__ rp,
@@ -128,16 +132,24 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
     const int cc[2] = {c, two ? c + 1 : c};
     const double* xc[2];
     const double* xp[2];
-    double coef[2], au[2][DIM], ap[2], bp[2];
+    double coef[2], au[2][DIM], ap[2], bp[2], cu[2][DIM];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       xc[q] = cols[cc[q]].xcur;
       xp[q] = cols[cc[q]].xprev;
       coef[q] = cols[cc[q]].coef;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) au[q][a] = coef[q] * Fu[a];
+      for (int a = 0; a < DIM; ++a) {
+        au[q][a] = coef[q] * Fu[a];
+        cu[q][a] = 0.0;
+      }
       ap[q] = 0.0;
       bp[q] = 0.0;
+      if constexpr (ADJ) {
+        const double g = active ? F.gload[size_t(cols[cc[q]].step - 1) * nn + vv] : 0.0;
+        ap[q] = g;
+        bp[q] = g;
+      }
     }
 #pragma unroll
     for (int s = 0; s < W; ++s) {
@@ -179,13 +191,24 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
           for (int k = 0; k < DIM; ++k) acc += Ab[a * DIM + k] * xw[k];
           au[q][a] -= acc;
         }
-        double btc = 0.0, btp = 0.0;
+        double btc = 0.0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          btc += Btb[k] * xw[k];
-          btp += Btb[k] * xpw[k];
+        for (int k = 0; k < DIM; ++k) btc += Btb[k] * xw[k];
+        double coup;
+        if constexpr (ADJ) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            const double c = Bb[a] * xpw[DIM];
+            cu[q][a] += c;
+            au[q][a] += c;
+          }
+          coup = -Cbv * xpw[DIM];
+        } else {
+          double btp = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) btp += Btb[k] * xpw[k];
+          coup = btp - Cbv * xpw[DIM];
         }
-        const double coup = btp - Cbv * xpw[DIM];
         bp[q] += coup;
         ap[q] += coup - btc + Sv * xw[DIM];
       }
@@ -219,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           su += au[q][a] * au[q][a];
-          const double ba = coef[q] * Fu[a];
+          const double ba = coef[q] * Fu[a] + cu[q][a];
           sb += ba * ba;
         }
         qv[4 * q + 0] = active ? su : 0.0;
@@ -747,18 +770,26 @@ int pick_group(int nc, int nn, int gmax) {
   return g;
 }
 
+template <int DIM, bool ADJ, typename T>
+static void residual_dispatch(const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
+                              T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials,
+                              int pstride, int ct, hipStream_t st) {
+  const dim3 g = tiled_grid(nc, L.nn, ct);
+  BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_residual<DIM, G, T, ADJ>), g, dim3(kBlock), 0, st, L, F,
+                                       cols, nc, ru, rp, xa, d, inv_theta, partials, pstride))
+}
+
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                      T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials, int pstride,
-                     int ct, hipStream_t st) {
+                     int ct, bool adj, hipStream_t st) {
   ct = pick_group(nc, L.nn, ct);
-  const dim3 g = tiled_grid(nc, L.nn, ct);
   if (dim == 2) {
-    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_residual<2, G, T>), g, dim3(kBlock), 0, st, L, F, cols,
-                                         nc, ru, rp, xa, d, inv_theta, partials, pstride))
+    if (adj) residual_dispatch<2, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
+    else residual_dispatch<2, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
   } else {
-    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_residual<3, G, T>), g, dim3(kBlock), 0, st, L, F, cols,
-                                         nc, ru, rp, xa, d, inv_theta, partials, pstride))
+    if (adj) residual_dispatch<3, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
+    else residual_dispatch<3, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
   }
 }
 
@@ -911,7 +942,7 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
 // explicit instantiations for the two preconditioner precisions
 #define BIOT_INSTANTIATE(T)                                                                      \
   template void launch_residual<T>(int, const LevelDev&, const FineDev&, const ColDesc*, int, T*, \
-                                   T*, T*, T*, double, double*, int, int, hipStream_t);          \
+                                   T*, T*, T*, double, double*, int, int, bool, hipStream_t);    \
   template void launch_cheb<T>(int, int, const LevelView<T>&, bool, const T*, const T*, T*, T*,  \
                                int, double, double, const ColDesc*, const T*, double, int, bool, \
                                hipStream_t);                                                      \

@@ -26,10 +26,11 @@ using LevelDev = LevelView<double>;
 
 // Fine-level coupling blocks and load (level 0 only, FP64).
 struct FineDev {
-  const double* B;   // [W][dim][nn]
-  const double* Bt;  // [W][dim][nn]
-  const double* Cb;  // [W][nn]
-  const double* F;   // [nn][dim+1]
+  const double* B;      // [W][dim][nn]
+  const double* Bt;     // [W][dim][nn]
+  const double* Cb;     // [W][nn]
+  const double* F;      // [nn][dim+1]
+  const double* gload;  // adjoint only: pressure-row load [N][nn] per column step
 };
 
 // One (time step, iteration) column of a batch.
@@ -52,10 +53,11 @@ struct ColDesc {
 bool valid_col_tile(int ct);
 int pick_group(int nc, int nn, int gmax);
 
+// `adj`: the adjoint recursion (coupling A'^T, load F.gload; see k_residual)
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                      T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials,
-                     int partial_stride, int ct, hipStream_t st);
+                     int partial_stride, int ct, bool adj, hipStream_t st);
 // Chebyshev step d <- c1 d + c2 D^{-1}(b - K xin), xout = xin + d.  With `upd`
 // (pressure field, level 0) the step writes the outer update
 // X^{n,m} = X^{n,m-1} + omega [zu; xin + d] through the descriptors instead.
@@ -93,6 +95,40 @@ void launch_reduce_norms(const double* partials, int nblk, int partial_stride, d
                          int nc, hipStream_t st);
 void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const double* X,
                            double* Y, int nc, hipStream_t st);
+
+// ---- adjoint (adjoint.hip) ----
+// Element data of the gradient contraction (see HostProblem::geo / conn_t).
+struct ElemDev {
+  int ne;
+  const int32_t* conn;   // [dim+1][ne]
+  const double* geo;     // [(dim+1)*dim + 1][ne]: vertex gradients, then |e|
+  const double* coefK;   // [ne] tau K_e
+  const double* dbl;     // [ne] d beta_e / d lambda_e (0 if beta was given)
+  const double* dbm;     // [ne] d beta_e / d mu_e
+};
+// dJ/dX of the pressure misfit: gload[(m-1)*nn + node_s] = 2 (p^n_s - d^n_s)
+// with n = N+1-m (reversed time) for free pressures, and misfit^2 per entry in
+// jpart[(n-1)*S + s].  gload must be zero elsewhere beforehand.
+void launch_sensor_load(int dim, int nn, int N, int S, const double* X, const int32_t* sens,
+                        const double* pobs, const uint8_t* fixed, double* gload, double* jpart,
+                        hipStream_t st);
+// out[0] = sum of x[0..n) in a fixed order (one workgroup)
+void launch_sum(const double* x, int n, double* out, hipStream_t st);
+// replay start values for steps n0..n0+L of a group: X^{n0} from its checkpoint,
+// the others linearly interpolated between the checkpoints around them
+// (checkpoint k holds X^{k s} for k < K = ceil(N/s), checkpoint K holds X^N)
+void launch_lerp_init(size_t col, const double* ck, int s, int N, int n0, int L, double* out,
+                      hipStream_t st);
+// per-element partial sums over steps [n_beg, n_end) in chunks of `chunk` steps:
+// part[(kbase + y)][4][ne] = sum over chunk y of (grad lp . grad p,
+//   div lu div u, 2 eps(lu):eps(u), grad lp . grad (p - p_prev)) |e|,
+// with X^n at xbase + (n - xstep0) col and Lam^n at lam_top - n col
+void launch_grad_partial(int dim, const ElemDev& E, size_t col, const double* xbase, int xstep0,
+                         const double* lam_top, int n_beg, int n_end, int chunk, int kbase,
+                         double* part, hipStream_t st);
+// gradients from the partials of nchunks chunks (summed in chunk order)
+void launch_grad_finish(const ElemDev& E, const double* part, int nchunks, double* g_logk,
+                        double* g_lam, double* g_mu, hipStream_t st);
 
 inline int num_node_blocks(int nn) { return (nn + kBlock - 1) / kBlock; }
 

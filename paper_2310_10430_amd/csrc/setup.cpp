@@ -346,7 +346,10 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
   const int dim = m.dim;
   if (dim != 2 && dim != 3) return "dim must be 2 or 3";
   if (m.nn <= 0 || m.ne <= 0 || !m.xyz || !m.conn || !m.flags) return "empty or null mesh arrays";
-  if (!mat.young || !mat.poisson || !mat.perm) return "null material arrays";
+  if (!mat.perm) return "null permeability array";
+  if ((mat.lame_lambda == nullptr) != (mat.lame_mu == nullptr))
+    return "lame_lambda and lame_mu must be given together";
+  if (!mat.lame_lambda && (!mat.young || !mat.poisson)) return "null material arrays";
   if (!(dt > 0) || n_steps < 1) return "dt must be > 0 and n_steps >= 1";
   if (m.grid_n < 1) return "only structured meshes (grid_n >= 1) are supported";
   if (!(mat.stab_h >= 0) || !std::isfinite(mat.alpha)) return "bad alpha or stab_h";
@@ -385,6 +388,10 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
   P.lambda_e.resize(m.ne);
   P.mu_e.resize(m.ne);
   P.beta_e.resize(m.ne);
+  P.perm_e.resize(m.ne);
+  P.beta_given = mat.beta != nullptr;
+  P.geo.assign(size_t((dim + 1) * dim + 1) * m.ne, 0.0);
+  P.conn_t.assign(size_t(dim + 1) * m.ne, 0);
   const int nv = dim + 1;
   double xv[12], gr[12];
   int slot[4][4];
@@ -406,15 +413,31 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
         if (slot[a][b] < 0) return "element edge is not on the structured stencil";
       }
     }
-    double E = mat.young[e], nu = mat.poisson[e], K = mat.perm[e];
-    if (!(E > 0) || !(nu > -1 && nu < 0.5) || !(K >= 0)) return "bad material value";
-    double lam = E * nu / ((1 + nu) * (1 - 2 * nu));
-    double mu = E / (2 * (1 + nu));
+    const double K = mat.perm[e];
+    double lam, mu;
+    if (mat.lame_lambda) {
+      lam = mat.lame_lambda[e];
+      mu = mat.lame_mu[e];
+      if (!(mu > 0) || !(lam > -2.0 * mu / dim) || !(K >= 0) || !std::isfinite(lam) ||
+          !std::isfinite(mu))
+        return "bad material value";
+    } else {
+      double E = mat.young[e], nu = mat.poisson[e];
+      if (!(E > 0) || !(nu > -1 && nu < 0.5) || !(K >= 0)) return "bad material value";
+      lam = E * nu / ((1 + nu) * (1 - 2 * nu));
+      mu = E / (2 * (1 + nu));
+    }
     double beta = mat.beta ? mat.beta[e]
                            : mat.alpha * mat.alpha * mat.stab_h * mat.stab_h / (4 * (lam + 2 * mu));
     P.lambda_e[e] = lam;
     P.mu_e[e] = mu;
     P.beta_e[e] = beta;
+    P.perm_e[e] = K;
+    for (int a = 0; a < nv; ++a) {
+      P.conn_t[size_t(a) * m.ne + e] = cv[a];
+      for (int c = 0; c < dim; ++c) P.geo[size_t(a * dim + c) * m.ne + e] = gr[a * dim + c];
+    }
+    P.geo[size_t(nv * dim) * m.ne + e] = vol;
     for (int a = 0; a < nv; ++a) {
       const double* ga = gr + a * dim;
       int va = cv[a];

@@ -48,7 +48,12 @@ struct HostProblem {
   std::vector<double> coef;       // [n_steps+1]
   std::vector<double> coarseAinv; // dense inverse of the coarsest A (node-major dofs)
   std::vector<double> coarseSinv; // dense inverse of the coarsest S
-  std::vector<double> lambda_e, mu_e, beta_e;  // per element (kept for diagnostics)
+  std::vector<double> lambda_e, mu_e, beta_e, perm_e;  // per element
+  bool beta_given = false;        // beta supplied by the caller (no lambda/mu dependence)
+  // element geometry for the adjoint's gradient contraction, element-minor:
+  // geo[(a*dim + c)*ne + e] = d(phi_a)/dx_c, geo[(dim+1)*dim*ne + e] = |e|
+  std::vector<double> geo;
+  std::vector<int32_t> conn_t;    // [dim+1][ne] vertex a of element e at [a*ne + e]
 };
 
 struct MeshIn {
@@ -60,6 +65,7 @@ struct MeshIn {
 struct MaterialsIn {
   const double *young, *poisson, *perm, *beta;  // beta may be null
   double alpha, stab_h;
+  const double *lame_lambda, *lame_mu;          // both null, or both set (override E, nu)
 };
 struct LoadIn {
   int n_facets;

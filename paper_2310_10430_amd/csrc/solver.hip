@@ -57,6 +57,33 @@ struct ChebCoef {
   double theta = 0, delta = 0, sigma = 0;
 };
 
+// One space-time problem that the schedules iterate: the forward problem, the
+// adjoint recursion in reversed time, or a group of checkpointed segments that
+// is recomputed.  Columns 1..N of the trajectory pair T are the unknowns;
+// column 0 is the initial value.  pin[n] (if set) replaces X^{n-1} as the
+// coupling source of step n (a segment that starts from a checkpoint).
+struct Sched {
+  bool adj = false;
+  int N = 0, cap = 0;                 // steps now / table capacity in steps
+  double* T[2] = {nullptr, nullptr};
+  int cur = 0;
+  std::vector<double> coef;           // [N+1] load multiplier per column
+  std::vector<int> gstep;             // [N+1] step number stored in descriptors
+  std::vector<const double*> pin;     // [N+1]
+  ColDesc* desc_jac[2] = {nullptr, nullptr};
+  ColDesc* desc_k4[2] = {nullptr, nullptr};
+  ColDesc* desc_wave[2] = {nullptr, nullptr};
+  ColDesc* desc_part = nullptr;       // table of a partial (shallower) pass
+  std::vector<ColDesc> h_jac[2], h_k4[2], h_wave[2], h_part;
+  std::vector<int> wave_off, wave_cnt, part_off, part_cnt;
+  int part_key = -1;                  // (parity, depth) of the uploaded partial table
+  // wavefront passes captured as HIP graphs, per trajectory parity, valid for
+  // the step count graph_N (the tables' contents may change between replays)
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int graph_N = -1;
+};
+
 }  // namespace
 
 struct biot_handle {
@@ -75,23 +102,28 @@ struct biot_handle {
   FineDev F{};
   Prec<double> pd;               // FP64 preconditioner (precision FP64)
   Prec<float> pf;                // FP32 preconditioner (precision MIXED)
-  double* T[2] = {nullptr, nullptr};
-  int cur = 0;
+  Sched fw;                      // forward problem (the trajectory of the ABI)
+  Sched bw;                      // adjoint recursion, reversed time
+  Sched rp;                      // replay of checkpointed segments
+  bool fw_valid = true;          // false once a checkpointed adjoint overwrote fw.T
+  bool adj_valid = false;        // bw.T holds the states of the last biot_adjoint
   double* slots = nullptr;
   double* partials = nullptr;
   int nblk = 0;
   double* norms = nullptr;
-  ColDesc* desc_jac[2] = {nullptr, nullptr};
-  ColDesc* desc_k4[2] = {nullptr, nullptr};
-  ColDesc* desc_wave[2] = {nullptr, nullptr};
-  ColDesc* desc_part = nullptr;          // table of a partial (shallower) pass
-  std::vector<int> wave_off, wave_cnt;
-  std::vector<ColDesc> h_part;
-  std::vector<int> part_off, part_cnt;
-  int part_key = -1;                     // (parity, depth) of the uploaded table
   std::vector<ChebCoef> chA, chS;
-  // host copies of the descriptor tables (uploaded at bind)
-  std::vector<ColDesc> h_jac[2], h_k4[2], h_wave[2];
+  // adjoint buffers (options.adjoint)
+  int ckK = 0;                   // checkpointed segments ceil(N / ckpt_stride)
+  int n_chunks = 0;              // chunks of the gradient partial sums
+  double* ck = nullptr;          // [ckK+1] checkpoint columns
+  double* gload = nullptr;       // [N][nn] adjoint pressure-row load
+  int32_t* sens = nullptr;       // [max_sensors]
+  double* pobs = nullptr;        // [N][max_sensors]
+  double* jpart = nullptr;       // [N][max_sensors]
+  double* jval = nullptr;        // [1]
+  double* gpart = nullptr;       // [n_chunks][4][ne]
+  double* gout = nullptr;        // [3][ne] staging for host gradients
+  ElemDev E{};
   // HIP-event probes around level-0 launches (biot_profile_enable)
   struct Pending { hipEvent_t a, b; int id; double bytes; };
   struct Acc { uint64_t launches = 0; double ms = 0, bytes = 0; };
@@ -102,13 +134,14 @@ struct biot_handle {
   std::vector<Pending> pending;
   Acc acc[BIOT_PROBE_COUNT];
   int cur_copies = 0;  // columns of the current batch that also write a second copy
-  // wavefront passes captured as HIP graphs: [trajectory parity][probes on]
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipStream_t cap_stream = nullptr;  // stream used for graph capture
 };
 
 namespace {
+
+// steps per chunk of the gradient partial sums when the whole forward
+// trajectory is kept (with checkpoints a chunk is one segment)
+constexpr int kGradChunk = 16;
 
 int fail(biot_handle* h, int code, const std::string& msg) {
   if (h) h->err = msg;
@@ -213,24 +246,63 @@ void plan(biot_handle* h, char* base) {
   h->F.Bt = b.take<double>(H0.Bt.size());
   h->F.Cb = b.take<double>(H0.Cb.size());
   h->F.F = b.take<double>(h->P.F.size());
-  const size_t traj = size_t(h->N + 1) * h->col;
-  h->T[0] = b.take<double>(traj);
-  h->T[1] = b.take<double>(traj);
-  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
-    h->slots = b.take<double>(size_t(2) * h->opt.depth * h->col);
+  h->F.gload = nullptr;
+  const bool wave = h->opt.schedule == BIOT_SCHED_WAVEFRONT;
+  auto traj_pair = [&](Sched& S, int cap) {
+    S.T[0] = b.take<double>(size_t(cap + 1) * h->col);
+    S.T[1] = b.take<double>(size_t(cap + 1) * h->col);
+  };
+  auto tables = [&](Sched& S) {
+    for (int c = 0; c < 2; ++c) {
+      S.desc_jac[c] = b.take<ColDesc>(S.cap);
+      S.desc_k4[c] = b.take<ColDesc>(S.cap);
+      if (wave) S.desc_wave[c] = b.take<ColDesc>(size_t(S.cap) * h->opt.depth);
+    }
+    if (wave) S.desc_part = b.take<ColDesc>(size_t(S.cap) * h->opt.depth);
+  };
+  h->fw.cap = h->N;
+  traj_pair(h->fw, h->N);
+  tables(h->fw);
+  if (h->opt.adjoint) {
+    const int s = h->opt.ckpt_stride;
+    h->bw.cap = h->N;
+    if (s > 0) {
+      // the adjoint reuses the forward trajectory pair; the forward states are
+      // kept at the checkpoints and recomputed segment group by group
+      h->bw.T[0] = h->fw.T[0];
+      h->bw.T[1] = h->fw.T[1];
+      h->ckK = (h->N + s - 1) / s;
+      h->ck = b.take<double>(size_t(h->ckK + 1) * h->col);
+      h->rp.cap = std::min(h->N, h->opt.replay_segments * s);
+      traj_pair(h->rp, h->rp.cap);
+      tables(h->rp);
+      h->n_chunks = h->ckK;
+    } else {
+      traj_pair(h->bw, h->N);
+      h->n_chunks = (h->N + kGradChunk - 1) / kGradChunk;
+    }
+    tables(h->bw);
+    const size_t ne = size_t(h->P.ne), ms = size_t(h->opt.max_sensors);
+    h->gload = b.take<double>(size_t(h->N) * h->nn);
+    h->sens = b.take<int32_t>(ms);
+    h->pobs = b.take<double>(size_t(h->N) * ms);
+    h->jpart = b.take<double>(size_t(h->N) * ms);
+    h->jval = b.take<double>(1);
+    h->E.ne = h->P.ne;
+    h->E.conn = b.take<int32_t>(h->P.conn_t.size());
+    h->E.geo = b.take<double>(h->P.geo.size());
+    h->E.coefK = b.take<double>(ne);
+    h->E.dbl = b.take<double>(ne);
+    h->E.dbm = b.take<double>(ne);
+    h->gpart = b.take<double>(size_t(h->n_chunks) * 4 * ne);
+    h->gout = b.take<double>(3 * ne);
+  }
+  if (wave) h->slots = b.take<double>(size_t(2) * h->opt.depth * h->col);
   if (h->opt.precision == BIOT_PRECISION_MIXED) plan_prec<float>(h, b, h->pf);
   else plan_prec<double>(h, b, h->pd);
   h->nblk = num_node_blocks(h->nn);
   h->partials = b.take<double>(size_t(std::max(h->ncmax, h->N)) * h->nblk * 4);
   h->norms = b.take<double>(size_t(h->N) * 4);
-  for (int c = 0; c < 2; ++c) {
-    h->desc_jac[c] = b.take<ColDesc>(h->N);
-    h->desc_k4[c] = b.take<ColDesc>(h->N);
-    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
-      h->desc_wave[c] = b.take<ColDesc>(size_t(h->N) * h->opt.depth);
-  }
-  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
-    h->desc_part = b.take<ColDesc>(size_t(h->N) * h->opt.depth);
   h->ws_need = b.off + 256;
 }
 
@@ -238,31 +310,32 @@ void plan(biot_handle* h, char* base) {
 // trajectory T[c] and writing T[1-c]: at wave w, slot s updates step w - s
 // from its iterate of sweep s to sweep s+1.  Slot s reads its input from slot
 // s-1's output of the previous wave (slot 0: the trajectory) and its coupling
-// from its own previous output (step 1: X^0); outputs alternate between two
-// buffers per slot; slot d-1 also writes the trajectory.
-void wave_table(biot_handle* h, int c, int d, std::vector<ColDesc>& tab, std::vector<int>& off,
-                std::vector<int>& cnt) {
+// from its own previous output (step 1, or a pinned step: the fixed source);
+// outputs alternate between two buffers per slot; slot d-1 also writes the
+// trajectory.
+void wave_table(biot_handle* h, const Sched& S, int c, int d, std::vector<ColDesc>& tab,
+                std::vector<int>& off, std::vector<int>& cnt) {
   const size_t col = h->col;
   const int D = h->opt.depth;
-  double* Tin = h->T[c];
-  double* Tout = h->T[1 - c];
+  double* Tin = S.T[c];
+  double* Tout = S.T[1 - c];
   auto slot = [&](int s, int parity) { return h->slots + (size_t(parity) * D + s) * col; };
   tab.clear();
   off.clear();
   cnt.clear();
-  for (int w = 1; w <= h->N + d - 1; ++w) {
+  for (int w = 1; w <= S.N + d - 1; ++w) {
     off.push_back(int(tab.size()));
     int k = 0;
     for (int s = 0; s < d; ++s) {
       const int n = w - s;
-      if (n < 1 || n > h->N) continue;
+      if (n < 1 || n > S.N) continue;
       ColDesc e{};
       e.xcur = s == 0 ? Tin + n * col : slot(s - 1, (w - 1) & 1);
-      e.xprev = n == 1 ? Tin : slot(s, (w - 1) & 1);
+      e.xprev = S.pin[n] ? S.pin[n] : (n == 1 ? Tin : slot(s, (w - 1) & 1));
       e.xout = slot(s, w & 1);
       e.xout2 = s == d - 1 ? Tout + n * col : nullptr;
-      e.coef = h->P.coef[n];
-      e.step = n;
+      e.coef = S.coef[n];
+      e.step = S.gstep[n];
       tab.push_back(e);
       ++k;
     }
@@ -270,29 +343,55 @@ void wave_table(biot_handle* h, int c, int d, std::vector<ColDesc>& tab, std::ve
   }
 }
 
-void build_tables(biot_handle* h) {
+// descriptor tables of both parities on the host (Jacobi, residual, wavefront)
+void build_tables(biot_handle* h, Sched& S) {
   const size_t col = h->col;
   for (int c = 0; c < 2; ++c) {
-    double* Tin = h->T[c];
-    double* Tout = h->T[1 - c];
-    h->h_jac[c].resize(h->N);
-    h->h_k4[c].resize(h->N);
-    for (int n = 1; n <= h->N; ++n) {
+    double* Tin = S.T[c];
+    double* Tout = S.T[1 - c];
+    S.h_jac[c].resize(S.N);
+    S.h_k4[c].resize(S.N);
+    for (int n = 1; n <= S.N; ++n) {
       ColDesc d{};
       d.xcur = Tin + n * col;
-      d.xprev = Tin + (n - 1) * col;
+      d.xprev = S.pin[n] ? S.pin[n] : Tin + (n - 1) * col;
       d.xout = Tout + n * col;
       d.xout2 = nullptr;
-      d.coef = h->P.coef[n];
-      d.step = n;
-      h->h_jac[c][n - 1] = d;
+      d.coef = S.coef[n];
+      d.step = S.gstep[n];
+      S.h_jac[c][n - 1] = d;
       d.xout = nullptr;
-      h->h_k4[c][n - 1] = d;
+      S.h_k4[c][n - 1] = d;
     }
     if (h->opt.schedule == BIOT_SCHED_WAVEFRONT)
-      wave_table(h, c, h->opt.depth, h->h_wave[c], h->wave_off, h->wave_cnt);
+      wave_table(h, S, c, h->opt.depth, S.h_wave[c], S.wave_off, S.wave_cnt);
   }
+  S.part_key = -1;
 }
+
+int upload_tables(biot_handle* h, Sched& S) {
+  for (int c = 0; c < 2; ++c) {
+    HIPCHK(h, hipMemcpyAsync(S.desc_jac[c], S.h_jac[c].data(), S.h_jac[c].size() * sizeof(ColDesc),
+                             hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(S.desc_k4[c], S.h_k4[c].data(), S.h_k4[c].size() * sizeof(ColDesc),
+                             hipMemcpyHostToDevice, h->st));
+    if (S.desc_wave[c])
+      HIPCHK(h, hipMemcpyAsync(S.desc_wave[c], S.h_wave[c].data(),
+                               S.h_wave[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, h->st));
+  }
+  return BIOT_OK;
+}
+
+// set the step count and per-column data of a schedule
+void shape_sched(Sched& S, int N, bool adj) {
+  S.adj = adj;
+  S.N = N;
+  S.coef.assign(N + 1, 0.0);
+  S.gstep.resize(N + 1);
+  for (int n = 0; n <= N; ++n) S.gstep[n] = n;
+  S.pin.assign(N + 1, nullptr);
+}
+
 ChebCoef cheb_of(double lmax, double ratio) {
   ChebCoef c;
   const double lmin = lmax / ratio;
@@ -494,14 +593,21 @@ int precond_batch(biot_handle* h, Prec<T>& p, int nc, T** zu, T** zp, const ColD
 
 // one unit for every column of a descriptor batch: FP64 residual, P^{-1} in
 // precision T, FP64 update
+// level-0 coupling data for a schedule (the adjoint adds its pressure load)
+FineDev fine_of(const biot_handle* h, const Sched& S) {
+  FineDev f = h->F;
+  f.gload = S.adj ? h->gload : nullptr;
+  return f;
+}
+
 template <typename T>
-int unit_batch_t(biot_handle* h, Prec<T>& p, const ColDesc* cols, int nc) {
+int unit_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols, int nc) {
   const bool sm = level0_smoothed(h);
   {
     ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, sm, int(sizeof(T))));
-    launch_residual<T>(h->dim, h->L[0], h->F, cols, nc, p.fa.b[0], p.rp, sm ? p.fa.x0[0] : nullptr,
-                       p.fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0, nullptr, h->nblk,
-                       h->opt.col_tile, h->st);
+    launch_residual<T>(h->dim, h->L[0], fine_of(h, S), cols, nc, p.fa.b[0], p.rp,
+                       sm ? p.fa.x0[0] : nullptr, p.fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0,
+                       nullptr, h->nblk, h->opt.col_tile, S.adj, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
   }
@@ -509,9 +615,9 @@ int unit_batch_t(biot_handle* h, Prec<T>& p, const ColDesc* cols, int nc) {
   return precond_batch<T>(h, p, nc, &zu, &zp, cols);
 }
 
-int unit_batch(biot_handle* h, const ColDesc* cols, int nc) {
-  if (h->opt.precision == BIOT_PRECISION_MIXED) return unit_batch_t<float>(h, h->pf, cols, nc);
-  return unit_batch_t<double>(h, h->pd, cols, nc);
+int unit_batch(biot_handle* h, const Sched& S, const ColDesc* cols, int nc) {
+  if (h->opt.precision == BIOT_PRECISION_MIXED) return unit_batch_t<float>(h, S, h->pf, cols, nc);
+  return unit_batch_t<double>(h, S, h->pd, cols, nc);
 }
 
 // Z = P^{-1} R for caller columns (diagnostic path)
@@ -536,91 +642,118 @@ int apply_precond_t(biot_handle* h, Prec<T>& p, const double* R, double* Z, int 
   return BIOT_OK;
 }
 
-int jacobi_sweep(biot_handle* h) {
-  ColDesc* tab = h->desc_jac[h->cur];
-  for (int n0 = 0; n0 < h->N; n0 += h->ncmax) {
-    const int nc = std::min(h->ncmax, h->N - n0);
-    int rc = unit_batch(h, tab + n0, nc);
+int jacobi_sweep(biot_handle* h, Sched& S) {
+  ColDesc* tab = S.desc_jac[S.cur];
+  for (int n0 = 0; n0 < S.N; n0 += h->ncmax) {
+    const int nc = std::min(h->ncmax, S.N - n0);
+    int rc = unit_batch(h, S, tab + n0, nc);
     if (rc) return rc;
   }
-  h->cur = 1 - h->cur;
+  S.cur = 1 - S.cur;
   return BIOT_OK;
 }
 
-int run_waves(biot_handle* h, const ColDesc* tab, const std::vector<int>& off,
+int run_waves(biot_handle* h, const Sched& S, const ColDesc* tab, const std::vector<int>& off,
               const std::vector<int>& cnt, int d) {
   for (size_t w = 0; w < off.size(); ++w) {
     const int wave = int(w) + 1, last_step = wave - d + 1;
-    h->cur_copies = (last_step >= 1 && last_step <= h->N) ? 1 : 0;
-    int rc = unit_batch(h, tab + off[w], cnt[w]);
+    h->cur_copies = (last_step >= 1 && last_step <= S.N) ? 1 : 0;
+    int rc = unit_batch(h, S, tab + off[w], cnt[w]);
     if (rc) return rc;
   }
   h->cur_copies = 0;
   return BIOT_OK;
 }
 
-int wavefront_pass_eager(biot_handle* h) {
-  return run_waves(h, h->desc_wave[h->cur], h->wave_off, h->wave_cnt, h->opt.depth);
+int wavefront_pass_eager(biot_handle* h, Sched& S) {
+  return run_waves(h, S, S.desc_wave[S.cur], S.wave_off, S.wave_cnt, h->opt.depth);
 }
 
 // a pass shallower than the configured depth (eager; table built on demand)
-int wavefront_partial(biot_handle* h, int d) {
-  const int key = h->cur * 65536 + d;
-  if (h->part_key != key) {
-    wave_table(h, h->cur, d, h->h_part, h->part_off, h->part_cnt);
-    HIPCHK(h, hipMemcpyAsync(h->desc_part, h->h_part.data(), h->h_part.size() * sizeof(ColDesc),
+int wavefront_partial(biot_handle* h, Sched& S, int d) {
+  const int key = S.cur * 65536 + d;
+  if (S.part_key != key) {
+    wave_table(h, S, S.cur, d, S.h_part, S.part_off, S.part_cnt);
+    HIPCHK(h, hipMemcpyAsync(S.desc_part, S.h_part.data(), S.h_part.size() * sizeof(ColDesc),
                              hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
-    h->part_key = key;
+    S.part_key = key;
   }
-  int rc = run_waves(h, h->desc_part, h->part_off, h->part_cnt, d);
+  int rc = run_waves(h, S, S.desc_part, S.part_off, S.part_cnt, d);
   if (rc) return rc;
-  h->cur = 1 - h->cur;
+  S.cur = 1 - S.cur;
   return BIOT_OK;
 }
 
+void destroy_graphs(Sched& S) {
+  for (int c = 0; c < 2; ++c) {
+    if (S.gexec[c]) (void)hipGraphExecDestroy(S.gexec[c]);
+    if (S.graph[c]) (void)hipGraphDestroy(S.graph[c]);
+    S.gexec[c] = nullptr;
+    S.graph[c] = nullptr;
+  }
+  S.graph_N = -1;
+}
+
 // One pass = N + depth - 1 waves.  With use_graph the launch sequence of a
-// pass is captured once per trajectory parity (the descriptor tables fix every
-// pointer) and replayed; probe events become event-record nodes of the graph.
-int wavefront_pass(biot_handle* h) {
+// pass is captured once per trajectory parity (the descriptor tables, whose
+// device buffers are fixed, hold every pointer) and replayed.
+int wavefront_pass(biot_handle* h, Sched& S) {
   // probes read HIP events, which cannot be timed inside a replayed graph, so
   // a probed pass runs its launches eagerly
   if (!h->opt.use_graph || h->prof) {
-    int rc = wavefront_pass_eager(h);
+    int rc = wavefront_pass_eager(h, S);
     if (rc) return rc;
-    h->cur = 1 - h->cur;
+    S.cur = 1 - S.cur;
     return BIOT_OK;
   }
-  const int c = h->cur;
-  if (!h->gexec[c][0]) {
+  if (S.graph_N != S.N) destroy_graphs(S);
+  const int c = S.cur;
+  if (!S.gexec[c]) {
     hipStream_t user = h->st;
     h->st = h->cap_stream;
     HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
-    int rc = wavefront_pass_eager(h);
+    int rc = wavefront_pass_eager(h, S);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->st, &g);
     h->st = user;
     if (rc) return rc;
     if (e != hipSuccess) return fail(h, BIOT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    h->graph[c][0] = g;
-    HIPCHK(h, hipGraphInstantiate(&h->gexec[c][0], g, nullptr, nullptr, 0));
+    S.graph[c] = g;
+    HIPCHK(h, hipGraphInstantiate(&S.gexec[c], g, nullptr, nullptr, 0));
+    S.graph_N = S.N;
   }
-  HIPCHK(h, hipGraphLaunch(h->gexec[c][0], h->st));
-  h->cur = 1 - h->cur;
+  HIPCHK(h, hipGraphLaunch(S.gexec[c], h->st));
+  S.cur = 1 - S.cur;
   return BIOT_OK;
 }
 
 // global space-time residual norms of the current trajectory into h->norms
-int global_residual(biot_handle* h) {
-  ColDesc* tab = h->desc_k4[h->cur];
+int global_residual(biot_handle* h, const Sched& S) {
+  ColDesc* tab = S.desc_k4[S.cur];
   const int chunk = std::max(h->ncmax, 1);
-  for (int n0 = 0; n0 < h->N; n0 += chunk) {
-    const int nc = std::min(chunk, h->N - n0);
-    launch_residual<double>(h->dim, h->L[0], h->F, tab + n0, nc, nullptr, nullptr, nullptr,
-                            nullptr, 0.0, h->partials, h->nblk, h->opt.col_tile, h->st);
+  const FineDev f = fine_of(h, S);
+  for (int n0 = 0; n0 < S.N; n0 += chunk) {
+    const int nc = std::min(chunk, S.N - n0);
+    launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, nullptr, nullptr,
+                            0.0, h->partials, h->nblk, h->opt.col_tile, S.adj, h->st);
     LAUNCHCHK(h);
     launch_reduce_norms(h->partials, h->nblk, h->nblk, h->norms + size_t(n0) * 4, nc, h->st);
     LAUNCHCHK(h);
+  }
+  return BIOT_OK;
+}
+
+int sweep_sched(biot_handle* h, Sched& S, int n_sweeps) {
+  int rc = BIOT_OK;
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) {
+    for (int p = 0; p < n_sweeps / h->opt.depth; ++p)
+      if ((rc = wavefront_pass(h, S))) return rc;
+    if (n_sweeps % h->opt.depth)
+      if ((rc = wavefront_partial(h, S, n_sweeps % h->opt.depth))) return rc;
+  } else {
+    for (int s = 0; s < n_sweeps; ++s)
+      if ((rc = jacobi_sweep(h, S))) return rc;
   }
   return BIOT_OK;
 }
@@ -650,6 +783,139 @@ int check_bound(biot_handle* h) {
   return BIOT_OK;
 }
 
+int check_forward(biot_handle* h) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!h->fw_valid)
+    return fail(h, BIOT_ESTATE,
+                "the forward trajectory was overwritten by a checkpointed biot_adjoint; call biot_reset");
+  return BIOT_OK;
+}
+
+struct SolveOut {
+  int sweeps = 0;
+  bool conv = false;
+  double ru = 0, rp = 0;
+};
+
+// Sweeps schedule S until the worst relative residual is <= rtol (see
+// biot_solve_to_tol for the policy).
+int solve_sched(biot_handle* h, Sched& S, double rtol, int max_sweeps, int check_every,
+                SolveOut& out) {
+  int rc = BIOT_OK;
+  int step = check_every;
+  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) step = h->opt.depth;  // first pass: full depth
+  std::vector<double> nr(size_t(S.N) * 4);
+  int done = 0;
+  double first = -1;
+  out = SolveOut{};
+  while (true) {
+    if ((rc = global_residual(h, S))) return rc;
+    HIPCHK(h, hipMemcpyAsync(nr.data(), h->norms, nr.size() * 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    rel_resid(nr, S.N, out.ru, out.rp);
+    if (!std::isfinite(out.ru) || !std::isfinite(out.rp)) {
+      rc = fail(h, BIOT_EDIVERGED, "non-finite residual");
+      break;
+    }
+    const double worst = std::max(out.ru, out.rp);
+    if (first < 0) first = worst;
+    if (worst <= rtol) {
+      out.conv = true;
+      break;
+    }
+    if (done > 0 && worst > 1e6 * std::max(first, 1e-300)) {
+      rc = fail(h, BIOT_EDIVERGED, "residual grew by more than 1e6");
+      break;
+    }
+    if (done >= max_sweeps) {
+      rc = fail(h, BIOT_ENOTCONVERGED, "max_sweeps reached above tolerance");
+      break;
+    }
+    int kk = std::min(step, max_sweeps - done);
+    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT && done > 0) {
+      // size the next pass from the observed contraction per sweep, with margin
+      const double rate = std::pow(worst / std::max(first, 1e-300), 1.0 / done);
+      if (rate > 0 && rate < 0.999) {
+        const double need = std::log(rtol / worst) / std::log(rate);
+        const int k = int(std::ceil(1.15 * need)) + 2;
+        kk = std::min({std::max(4, (k + 3) / 4 * 4), h->opt.depth, max_sweeps - done});
+      }
+    }
+    int r2 = sweep_sched(h, S, kk);
+    if (r2) return r2;
+    done += kk;
+  }
+  out.sweeps = done;
+  return rc;
+}
+
+int zero_traj(biot_handle* h, Sched& S) {
+  const size_t bytes = size_t(S.N + 1) * h->col * 8;
+  HIPCHK(h, hipMemsetAsync(S.T[0], 0, bytes, h->st));
+  HIPCHK(h, hipMemsetAsync(S.T[1], 0, bytes, h->st));
+  S.cur = 0;
+  return BIOT_OK;
+}
+
+// device data of the gradient contraction (element geometry and coefficients)
+int upload_adjoint_data(biot_handle* h, std::vector<std::vector<double>>& keep) {
+  const HostProblem& P = h->P;
+  const size_t ne = size_t(P.ne);
+  std::vector<double> cK(ne), dbl(ne), dbm(ne);
+  for (size_t e = 0; e < ne; ++e) {
+    cK[e] = P.dt * P.perm_e[e];
+    const double den = P.lambda_e[e] + 2.0 * P.mu_e[e];
+    dbl[e] = P.beta_given ? 0.0 : -P.beta_e[e] / den;
+    dbm[e] = P.beta_given ? 0.0 : -2.0 * P.beta_e[e] / den;
+  }
+  keep.push_back(std::move(cK));
+  keep.push_back(std::move(dbl));
+  keep.push_back(std::move(dbm));
+  const size_t n3 = keep.size();
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->E.conn), P.conn_t.data(), P.conn_t.size() * 4,
+                           hipMemcpyHostToDevice, h->st));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->E.geo), P.geo.data(), P.geo.size() * 8,
+                           hipMemcpyHostToDevice, h->st));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->E.coefK), keep[n3 - 3].data(), ne * 8,
+                           hipMemcpyHostToDevice, h->st));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->E.dbl), keep[n3 - 2].data(), ne * 8,
+                           hipMemcpyHostToDevice, h->st));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->E.dbm), keep[n3 - 1].data(), ne * 8,
+                           hipMemcpyHostToDevice, h->st));
+  return BIOT_OK;
+}
+
+// validates the objective and evaluates J and the adjoint load from fw.T
+int objective_load(biot_handle* h, const biot_objective* obj, double* J) {
+  if (!h->opt.adjoint) return fail(h, BIOT_ESTATE, "handle created without options.adjoint");
+  if (!obj || !obj->nodes || !obj->p_obs) return fail(h, BIOT_EINVAL, "NULL objective arrays");
+  const int S = obj->n_sensors;
+  if (S < 1 || S > h->opt.max_sensors)
+    return fail(h, BIOT_EINVAL, "n_sensors must be in 1..max_sensors");
+  std::vector<char> seen(h->nn, 0);
+  for (int i = 0; i < S; ++i) {
+    const int v = obj->nodes[i];
+    if (v < 0 || v >= h->nn) return fail(h, BIOT_EINVAL, "sensor node out of range");
+    if (seen[v]) return fail(h, BIOT_EINVAL, "sensor nodes must be distinct");
+    seen[v] = 1;
+  }
+  const size_t NS = size_t(h->N) * S;
+  for (size_t i = 0; i < NS; ++i)
+    if (!std::isfinite(obj->p_obs[i])) return fail(h, BIOT_EINVAL, "non-finite p_obs");
+  HIPCHK(h, hipMemcpyAsync(h->sens, obj->nodes, size_t(S) * 4, hipMemcpyHostToDevice, h->st));
+  HIPCHK(h, hipMemcpyAsync(h->pobs, obj->p_obs, NS * 8, hipMemcpyHostToDevice, h->st));
+  HIPCHK(h, hipMemsetAsync(h->gload, 0, size_t(h->N) * h->nn * 8, h->st));
+  launch_sensor_load(h->dim, h->nn, h->N, S, h->fw.T[h->fw.cur], h->sens, h->pobs, h->L[0].fixed,
+                     h->gload, h->jpart, h->st);
+  LAUNCHCHK(h);
+  launch_sum(h->jpart, int(NS), h->jval, h->st);
+  LAUNCHCHK(h);
+  HIPCHK(h, hipMemcpyAsync(J, h->jval, 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipStreamSynchronize(h->st));  // host sources must outlive the copies
+  return BIOT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -669,6 +935,10 @@ int biot_default_options(biot_options* o) {
   o->coarse_cells = 2;
   o->use_graph = 1;
   o->precision = BIOT_PRECISION_FP64;
+  o->adjoint = 0;
+  o->ckpt_stride = 16;
+  o->replay_segments = 4;
+  o->max_sensors = 256;
   return BIOT_OK;
 }
 
@@ -694,11 +964,15 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   if (o.coarse_cells < 1 || o.coarse_cells > 64) return fail(nullptr, BIOT_EINVAL, "coarse_cells must be in 1..64");
   if (o.precision != BIOT_PRECISION_FP64 && o.precision != BIOT_PRECISION_MIXED)
     return fail(nullptr, BIOT_EINVAL, "unknown precision");
+  if (o.adjoint != 0 && o.adjoint != 1) return fail(nullptr, BIOT_EINVAL, "adjoint must be 0 or 1");
+  if (o.adjoint && (o.ckpt_stride < 0 || o.replay_segments < 1 || o.max_sensors < 1))
+    return fail(nullptr, BIOT_EINVAL, "need ckpt_stride >= 0, replay_segments >= 1, max_sensors >= 1");
   biot_handle* h = new (std::nothrow) biot_handle();
   if (!h) return fail(nullptr, BIOT_ENOMEM, "out of host memory");
   h->opt = o;
   MeshIn m{mesh->dim, mesh->n_nodes, mesh->n_elems, mesh->grid_n, mesh->xyz, mesh->conn, mesh->dirichlet};
-  MaterialsIn mi{mat->young, mat->poisson, mat->perm, mat->beta, mat->alpha, mat->stab_h};
+  MaterialsIn mi{mat->young,  mat->poisson, mat->perm,        mat->beta,
+                 mat->alpha,  mat->stab_h,  mat->lame_lambda, mat->lame_mu};
   LoadIn li{load->n_facets, load->facet_nodes, load->traction, load->coef};
   HostOptions ho;
   ho.cheb_degree = o.cheb_degree;
@@ -735,6 +1009,9 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
     h->chA[l] = cheb_of(h->P.levels[l].lmaxA, o.cheb_ratio);
     h->chS[l] = cheb_of(h->P.levels[l].lmaxS, o.cheb_ratio);
   }
+  shape_sched(h->fw, n_steps, false);
+  for (int n = 0; n <= n_steps; ++n) h->fw.coef[n] = h->P.coef[n];
+  shape_sched(h->bw, n_steps, true);  // load is gload, no traction
   plan(h, nullptr);
   *out = h;
   return BIOT_OK;
@@ -752,10 +1029,12 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
   if (reinterpret_cast<uintptr_t>(device_ptr) % 256 != 0)
     return fail(h, BIOT_EINVAL, "workspace must be 256-byte aligned");
   if (bytes < h->ws_need) return fail(h, BIOT_ENOMEM, "workspace smaller than biot_workspace_size");
+  for (Sched* S : {&h->fw, &h->bw, &h->rp}) destroy_graphs(*S);
   h->ws = static_cast<char*>(device_ptr);
   h->st = static_cast<hipStream_t>(stream);
   plan(h, h->ws);
-  build_tables(h);
+  build_tables(h, h->fw);
+  if (h->opt.adjoint) build_tables(h, h->bw);
   hipStream_t st = h->st;
   for (int l = 0; l < h->nlev; ++l) {
     const HostLevel& H = h->P.levels[l];
@@ -794,21 +1073,19 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
     HIPCHK(h, hipMemcpyAsync(h->pd.coarseA, h->P.coarseAinv.data(), h->P.coarseAinv.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(h, hipMemcpyAsync(h->pd.coarseS, h->P.coarseSinv.data(), h->P.coarseSinv.size() * 8, hipMemcpyHostToDevice, st));
   }
-  for (int c = 0; c < 2; ++c) {
-    HIPCHK(h, hipMemcpyAsync(h->desc_jac[c], h->h_jac[c].data(), h->h_jac[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
-    HIPCHK(h, hipMemcpyAsync(h->desc_k4[c], h->h_k4[c].data(), h->h_k4[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
-    if (h->desc_wave[c])
-      HIPCHK(h, hipMemcpyAsync(h->desc_wave[c], h->h_wave[c].data(), h->h_wave[c].size() * sizeof(ColDesc), hipMemcpyHostToDevice, st));
-  }
-  const size_t traj = size_t(h->N + 1) * h->col * 8;
-  HIPCHK(h, hipMemsetAsync(h->T[0], 0, traj, st));
-  HIPCHK(h, hipMemsetAsync(h->T[1], 0, traj, st));
+  int rc = upload_tables(h, h->fw);
+  if (!rc && h->opt.adjoint) rc = upload_tables(h, h->bw);
+  std::vector<std::vector<double>> keep;
+  if (!rc && h->opt.adjoint) rc = upload_adjoint_data(h, keep);
+  if (rc) return rc;
+  if ((rc = zero_traj(h, h->fw))) return rc;
+  if (h->opt.adjoint && h->opt.ckpt_stride == 0 && (rc = zero_traj(h, h->bw))) return rc;
   if (h->slots) HIPCHK(h, hipMemsetAsync(h->slots, 0, size_t(2) * h->opt.depth * h->col * 8, st));
   HIPCHK(h, hipStreamSynchronize(st));  // host sources must outlive the copies
   if (h->opt.schedule == BIOT_SCHED_WAVEFRONT && h->opt.use_graph && !h->cap_stream)
     HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-  h->cur = 0;
-  h->part_key = -1;
+  h->fw_valid = true;
+  h->adj_valid = false;
   h->bound = true;
   return BIOT_OK;
 }
@@ -816,34 +1093,25 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
 int biot_reset(biot_handle* h) {
   int rc = check_bound(h);
   if (rc) return rc;
-  const size_t traj = size_t(h->N + 1) * h->col * 8;
-  HIPCHK(h, hipMemsetAsync(h->T[0], 0, traj, h->st));
-  HIPCHK(h, hipMemsetAsync(h->T[1], 0, traj, h->st));
-  h->cur = 0;
+  if ((rc = zero_traj(h, h->fw))) return rc;
+  h->fw_valid = true;
+  if (h->opt.ckpt_stride > 0) h->adj_valid = false;  // shared buffers
   return BIOT_OK;
 }
 
 int biot_sweep(biot_handle* h, int32_t n_sweeps) {
-  int rc = check_bound(h);
+  int rc = check_forward(h);
   if (rc) return rc;
   if (n_sweeps < 0) return fail(h, BIOT_EINVAL, "n_sweeps < 0");
-  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) {
-    for (int p = 0; p < n_sweeps / h->opt.depth; ++p)
-      if ((rc = wavefront_pass(h))) return rc;
-    if (n_sweeps % h->opt.depth)
-      if ((rc = wavefront_partial(h, n_sweeps % h->opt.depth))) return rc;
-  } else {
-    for (int s = 0; s < n_sweeps; ++s)
-      if ((rc = jacobi_sweep(h))) return rc;
-  }
-  return BIOT_OK;
+  if (h->opt.ckpt_stride > 0) h->adj_valid = false;
+  return sweep_sched(h, h->fw, n_sweeps);
 }
 
 int biot_residual_norms(biot_handle* h, double* norms) {
-  int rc = check_bound(h);
+  int rc = check_forward(h);
   if (rc) return rc;
   if (!norms) return fail(h, BIOT_EINVAL, "norms is NULL");
-  if ((rc = global_residual(h))) return rc;
+  if ((rc = global_residual(h, h->fw))) return rc;
   HIPCHK(h, hipMemcpyAsync(norms, h->norms, size_t(h->N) * 4 * 8, hipMemcpyDeviceToHost, h->st));
   HIPCHK(h, hipStreamSynchronize(h->st));
   return BIOT_OK;
@@ -851,71 +1119,30 @@ int biot_residual_norms(biot_handle* h, double* norms) {
 
 int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t check_every,
                       biot_stats* stats) {
-  int rc = check_bound(h);
+  int rc = check_forward(h);
   if (rc) return rc;
   if (!(rtol > 0) || max_sweeps < 0 || check_every < 1)
     return fail(h, BIOT_EINVAL, "need rtol > 0, max_sweeps >= 0, check_every >= 1");
+  if (h->opt.ckpt_stride > 0) h->adj_valid = false;
   auto t0 = std::chrono::steady_clock::now();
-  int step = check_every;
-  if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) step = h->opt.depth;  // first pass: full depth
-  std::vector<double> nr(size_t(h->N) * 4);
-  int done = 0;
-  double ru = 0, rp = 0;
-  bool conv = false;
-  double first = -1;
-  while (true) {
-    if ((rc = global_residual(h))) return rc;
-    HIPCHK(h, hipMemcpyAsync(nr.data(), h->norms, nr.size() * 8, hipMemcpyDeviceToHost, h->st));
-    HIPCHK(h, hipStreamSynchronize(h->st));
-    rel_resid(nr, h->N, ru, rp);
-    if (!std::isfinite(ru) || !std::isfinite(rp)) {
-      rc = fail(h, BIOT_EDIVERGED, "non-finite residual");
-      break;
-    }
-    const double worst = std::max(ru, rp);
-    if (first < 0) first = worst;
-    if (worst <= rtol) {
-      conv = true;
-      break;
-    }
-    if (done > 0 && worst > 1e6 * std::max(first, 1e-300)) {
-      rc = fail(h, BIOT_EDIVERGED, "residual grew by more than 1e6");
-      break;
-    }
-    if (done >= max_sweeps) {
-      rc = fail(h, BIOT_ENOTCONVERGED, "max_sweeps reached above tolerance");
-      break;
-    }
-    int kk = std::min(step, max_sweeps - done);
-    if (h->opt.schedule == BIOT_SCHED_WAVEFRONT && done > 0) {
-      // size the next pass from the observed contraction per sweep, with margin
-      const double rate = std::pow(worst / std::max(first, 1e-300), 1.0 / done);
-      if (rate > 0 && rate < 0.999) {
-        const double need = std::log(rtol / worst) / std::log(rate);
-        const int k = int(std::ceil(1.15 * need)) + 2;
-        kk = std::min({std::max(4, (k + 3) / 4 * 4), h->opt.depth, max_sweeps - done});
-      }
-    }
-    int r2 = biot_sweep(h, kk);
-    if (r2) return r2;
-    done += kk;
-  }
+  SolveOut so;
+  rc = solve_sched(h, h->fw, rtol, max_sweeps, check_every, so);
   if (stats) {
-    stats->sweeps = done;
-    stats->converged = conv ? 1 : 0;
-    stats->rel_resid_u = ru;
-    stats->rel_resid_p = rp;
+    stats->sweeps = so.sweeps;
+    stats->converged = so.conv ? 1 : 0;
+    stats->rel_resid_u = so.ru;
+    stats->rel_resid_p = so.rp;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return rc;
 }
 
 int biot_get_trajectory(biot_handle* h, int32_t n0, int32_t n1, double* dst, int32_t dst_on_device) {
-  int rc = check_bound(h);
+  int rc = check_forward(h);
   if (rc) return rc;
   if (!dst || n0 < 0 || n1 > h->N + 1 || n0 > n1) return fail(h, BIOT_EINVAL, "bad range or NULL dst");
   const size_t bytes = size_t(n1 - n0) * h->col * 8;
-  HIPCHK(h, hipMemcpyAsync(dst, h->T[h->cur] + size_t(n0) * h->col, bytes,
+  HIPCHK(h, hipMemcpyAsync(dst, h->fw.T[h->fw.cur] + size_t(n0) * h->col, bytes,
                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
   if (!dst_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
   return BIOT_OK;
@@ -925,11 +1152,126 @@ int biot_set_trajectory(biot_handle* h, int32_t n0, int32_t n1, const double* sr
   int rc = check_bound(h);
   if (rc) return rc;
   if (!src || n0 < 0 || n1 > h->N + 1 || n0 > n1) return fail(h, BIOT_EINVAL, "bad range or NULL src");
+  if (!h->fw_valid && !(n0 == 0 && n1 == h->N + 1))
+    return fail(h, BIOT_ESTATE, "forward trajectory overwritten: set all steps or call biot_reset");
   const size_t bytes = size_t(n1 - n0) * h->col * 8;
   for (int c = 0; c < 2; ++c)  // both buffers: X^0 must be the same in either
-    HIPCHK(h, hipMemcpyAsync(h->T[c] + size_t(n0) * h->col, src, bytes,
+    HIPCHK(h, hipMemcpyAsync(h->fw.T[c] + size_t(n0) * h->col, src, bytes,
                              src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
   if (!src_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
+  h->fw_valid = true;
+  if (h->opt.ckpt_stride > 0) h->adj_valid = false;
+  return BIOT_OK;
+}
+
+int biot_objective_value(biot_handle* h, const biot_objective* obj, double* J) {
+  int rc = check_forward(h);
+  if (rc) return rc;
+  if (!J) return fail(h, BIOT_EINVAL, "J is NULL");
+  return objective_load(h, obj, J);
+}
+
+int biot_adjoint(biot_handle* h, const biot_objective* obj, double rtol, int32_t max_sweeps,
+                 double* grad_logk, double* grad_lambda, double* grad_mu, int32_t grads_on_device,
+                 biot_adjoint_stats* stats) {
+  int rc = check_forward(h);
+  if (rc) return rc;
+  if (!(rtol > 0) || max_sweeps < 0) return fail(h, BIOT_EINVAL, "need rtol > 0, max_sweeps >= 0");
+  const auto t0 = std::chrono::steady_clock::now();
+  biot_adjoint_stats out{};
+  // J and dJ/dX from the forward trajectory
+  if ((rc = objective_load(h, obj, &out.J))) return rc;
+  const size_t col = h->col;
+  const int N = h->N, s = h->opt.ckpt_stride;
+  const bool ckpt = s > 0;
+  const double* X = h->fw.T[h->fw.cur];
+  if (ckpt) {
+    for (int k = 0; k < h->ckK; ++k)
+      HIPCHK(h, hipMemcpyAsync(h->ck + size_t(k) * col, X + size_t(k) * s * col, col * 8,
+                               hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->ck + size_t(h->ckK) * col, X + size_t(N) * col, col * 8,
+                             hipMemcpyDeviceToDevice, h->st));
+    h->fw_valid = false;  // the adjoint now overwrites the forward pair
+  }
+  // adjoint states: the recursion in reversed time, from zero
+  h->adj_valid = false;
+  if ((rc = zero_traj(h, h->bw))) return rc;
+  SolveOut so;
+  rc = solve_sched(h, h->bw, rtol, max_sweeps, 4, so);
+  out.adjoint_sweeps = so.sweeps;
+  out.adjoint_rel_resid = std::max(so.ru, so.rp);
+  const auto t1 = std::chrono::steady_clock::now();
+  out.seconds_adjoint = std::chrono::duration<double>(t1 - t0).count();
+  if (rc) return rc;
+  h->adj_valid = true;
+  const double* lam_top = h->bw.T[h->bw.cur] + size_t(N + 1) * col;
+  if (!ckpt) {
+    launch_grad_partial(h->dim, h->E, col, X, 0, lam_top, 1, N + 1, kGradChunk, 0, h->gpart, h->st);
+    LAUNCHCHK(h);
+  } else {
+    const int gs = h->opt.replay_segments;
+    double worst = 0.0;
+    for (int k0 = 0; k0 < h->ckK; k0 += gs) {
+      const int n0 = k0 * s;
+      const int L = std::min(gs * s, N - n0);
+      Sched& R = h->rp;
+      HIPCHK(h, hipStreamSynchronize(h->st));  // the previous group's table uploads are done
+      shape_sched(R, L, false);
+      for (int j = 1; j <= L; ++j) {
+        const int n = n0 + j;
+        R.coef[j] = h->P.coef[n];
+        R.gstep[j] = n;
+        if ((n - 1) % s == 0) R.pin[j] = h->ck + size_t((n - 1) / s) * col;
+      }
+      build_tables(h, R);
+      if ((rc = upload_tables(h, R))) return rc;
+      // start values: X^{n0} in both buffers, interpolated checkpoints inside
+      launch_lerp_init(col, h->ck, s, N, n0, L, R.T[0], h->st);
+      LAUNCHCHK(h);
+      HIPCHK(h, hipMemcpyAsync(R.T[1], R.T[0], col * 8, hipMemcpyDeviceToDevice, h->st));
+      R.cur = 0;
+      SolveOut sr;
+      rc = solve_sched(h, R, rtol, max_sweeps, 4, sr);
+      out.replay_sweeps += sr.sweeps;
+      out.replay_groups += 1;
+      worst = std::max(worst, std::max(sr.ru, sr.rp));
+      if (rc) return rc;
+      launch_grad_partial(h->dim, h->E, col, R.T[R.cur], n0, lam_top, n0 + 1, n0 + L + 1, s, k0,
+                          h->gpart, h->st);
+      LAUNCHCHK(h);
+    }
+    out.replay_rel_resid = worst;
+  }
+  double* gk = grads_on_device ? grad_logk : (grad_logk ? h->gout : nullptr);
+  double* gl = grads_on_device ? grad_lambda : (grad_lambda ? h->gout + h->P.ne : nullptr);
+  double* gm = grads_on_device ? grad_mu : (grad_mu ? h->gout + 2 * size_t(h->P.ne) : nullptr);
+  launch_grad_finish(h->E, h->gpart, h->n_chunks, gk, gl, gm, h->st);
+  LAUNCHCHK(h);
+  if (!grads_on_device) {
+    const size_t b = size_t(h->P.ne) * 8;
+    if (grad_logk) HIPCHK(h, hipMemcpyAsync(grad_logk, gk, b, hipMemcpyDeviceToHost, h->st));
+    if (grad_lambda) HIPCHK(h, hipMemcpyAsync(grad_lambda, gl, b, hipMemcpyDeviceToHost, h->st));
+    if (grad_mu) HIPCHK(h, hipMemcpyAsync(grad_mu, gm, b, hipMemcpyDeviceToHost, h->st));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  const auto t2 = std::chrono::steady_clock::now();
+  out.seconds_replay = std::chrono::duration<double>(t2 - t1).count();
+  out.seconds = std::chrono::duration<double>(t2 - t0).count();
+  if (stats) *stats = out;
+  return BIOT_OK;
+}
+
+int biot_get_adjoint(biot_handle* h, int32_t n0, int32_t n1, double* dst, int32_t dst_on_device) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!h->adj_valid) return fail(h, BIOT_ESTATE, "no adjoint states (call biot_adjoint)");
+  if (!dst || n0 < 1 || n1 > h->N + 1 || n0 > n1) return fail(h, BIOT_EINVAL, "bad range or NULL dst");
+  const size_t col = h->col;
+  const double* top = h->bw.T[h->bw.cur] + size_t(h->N + 1) * col;
+  for (int n = n0; n < n1; ++n)  // stored in reversed time: Lam^n at column N+1-n
+    HIPCHK(h, hipMemcpyAsync(dst + size_t(n - n0) * col, top - size_t(n) * col, col * 8,
+                             dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
+  if (!dst_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
   return BIOT_OK;
 }
 
@@ -957,8 +1299,8 @@ int biot_profile_enable(biot_handle* h, int32_t mask) {
   if (rc) return rc;
   if ((rc = harvest(h))) return rc;
   for (auto& a : h->acc) a = biot_handle::Acc{};
-  // a captured pass must fit its probe events in the pool (10 probes per wave)
-  const size_t want = std::max<size_t>(16384, 20 * (h->wave_off.size() + 1) + 64);
+  const size_t waves = std::max(h->fw.wave_off.size(), h->bw.wave_off.size());
+  const size_t want = std::max<size_t>(16384, 20 * (waves + 1) + 64);
   if (enable && h->ev_pool.size() < want) {
     const size_t old = h->ev_pool.size();
     h->ev_pool.resize(want);
@@ -967,16 +1309,6 @@ int biot_profile_enable(biot_handle* h, int32_t mask) {
   h->prof = enable != 0;
   h->prof_mask = unsigned(mask) & ((1u << BIOT_PROBE_COUNT) - 1);
   return BIOT_OK;
-}
-
-static void destroy_graphs(biot_handle* h) {
-  for (int c = 0; c < 2; ++c)
-    for (int p = 0; p < 2; ++p) {
-      if (h->gexec[c][p]) (void)hipGraphExecDestroy(h->gexec[c][p]);
-      if (h->graph[c][p]) (void)hipGraphDestroy(h->graph[c][p]);
-      h->gexec[c][p] = nullptr;
-      h->graph[c][p] = nullptr;
-    }
 }
 
 int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
@@ -1030,11 +1362,13 @@ const char* biot_last_error(const biot_handle* h) {
   return h ? h->err.c_str() : g_create_error.c_str();
 }
 
-const char* biot_version(void) { return "biot_pint 0.2 (gfx950; FP64 and FP32/FP64 mixed)"; }
+const char* biot_version(void) {
+  return "biot_pint 0.3 (gfx950; FP64 and FP32/FP64 mixed; discrete adjoint)";
+}
 
 void biot_destroy(biot_handle* h) {
   if (!h) return;
-  destroy_graphs(h);
+  for (Sched* S : {&h->fw, &h->bw, &h->rp}) destroy_graphs(*S);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto& e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;

@@ -17,8 +17,11 @@ from . import _lib
 
 def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
                   cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
-                  col_tile=16, coarse_cells=2, use_graph=True, precision="fp64"):
-    """biot_create on the host (no device work); returns (handle, options)."""
+                  col_tile=16, coarse_cells=2, use_graph=True, precision="fp64", lame=None,
+                  adjoint=False, ckpt_stride=16, replay_segments=4, max_sensors=256):
+    """biot_create on the host (no device work); returns (handle, options).
+
+    `lame` = (lambda_e, mu_e) per element replaces the problem's E and nu."""
     lib = _lib.load()
     xyz = np.ascontiguousarray(problem.xyz, dtype=np.float64)
     conn = np.ascontiguousarray(problem.conn, dtype=np.int32)
@@ -27,13 +30,20 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     pois = np.ascontiguousarray(problem.poisson, dtype=np.float64)
     perm = np.ascontiguousarray(problem.perm, dtype=np.float64)
     beta_a = None if beta is None else np.ascontiguousarray(beta, dtype=np.float64)
+    lam_a = mu_a = None
+    if lame is not None:
+        lam_a = np.ascontiguousarray(lame[0], dtype=np.float64)
+        mu_a = np.ascontiguousarray(lame[1], dtype=np.float64)
+        if lam_a.shape != (problem.n_elems,) or mu_a.shape != (problem.n_elems,):
+            raise ValueError("lame arrays must have one entry per element")
     facets = np.ascontiguousarray(problem.facets, dtype=np.int32)
     tr = np.ascontiguousarray(problem.traction, dtype=np.float64)
     coef = np.ascontiguousarray(problem.load_coef, dtype=np.float64)
     mesh = _lib.Mesh(problem.dim, problem.n_nodes, problem.n_elems, problem.grid_n,
                      _lib.dptr(xyz), _lib.iptr(conn), _lib.uptr(flags))
     mat = _lib.Materials(_lib.dptr(young), _lib.dptr(pois), _lib.dptr(perm),
-                         _lib.dptr(beta_a), float(problem.alpha), float(problem.stab_h))
+                         _lib.dptr(beta_a), float(problem.alpha), float(problem.stab_h),
+                         _lib.dptr(lam_a), _lib.dptr(mu_a))
     load = _lib.Load(facets.shape[0], _lib.iptr(facets) if facets.size else None,
                      _lib.dptr(tr) if tr.size else None, _lib.dptr(coef))
     opt = _lib.Options()
@@ -51,6 +61,10 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     opt.coarse_cells = coarse_cells
     opt.use_graph = 1 if use_graph else 0
     opt.precision = _lib.PRECISION[precision]
+    opt.adjoint = 1 if adjoint else 0
+    opt.ckpt_stride = ckpt_stride
+    opt.replay_segments = replay_segments
+    opt.max_sensors = max_sensors
     h = C.c_void_p()
     _lib.check(lib, lib.biot_create(C.byref(mesh), C.byref(mat), C.byref(load),
                                     float(problem.dt), problem.n_steps, C.byref(opt),
@@ -93,7 +107,9 @@ class BiotSolver:
                  omega: float = 0.6, cheb_degree: int = 2, cheb_ratio: float = 4.0,
                  lmax_safety: float = 1.1, power_iters: int = 20, max_batch: int = 0,
                  device: str = "cuda:0", beta=None, col_tile: int = 16, coarse_cells: int = 2,
-                 use_graph: bool = True, precision: str = "fp64"):
+                 use_graph: bool = True, precision: str = "fp64", lame=None,
+                 adjoint: bool = False, ckpt_stride: int = 16, replay_segments: int = 4,
+                 max_sensors: int = 256):
         if not torch.cuda.is_available():
             raise RuntimeError("BiotSolver needs a ROCm GPU (torch.cuda is not available)")
         self.lib = _lib.load()
@@ -103,7 +119,9 @@ class BiotSolver:
                                lmax_safety=lmax_safety, power_iters=power_iters,
                                max_batch=max_batch, beta=beta, col_tile=col_tile,
                                coarse_cells=coarse_cells, use_graph=use_graph,
-                               precision=precision)
+                               precision=precision, lame=lame, adjoint=adjoint,
+                               ckpt_stride=ckpt_stride, replay_segments=replay_segments,
+                               max_sensors=max_sensors)
         self.problem = problem
         self.dim = problem.dim
         self.n_nodes = problem.n_nodes
@@ -186,6 +204,46 @@ class BiotSolver:
 
     def info(self) -> dict:
         return handle_info(self.lib, self.h)
+
+    # ------------------------------------------------------------------
+    @staticmethod
+    def _objective(sensors, p_obs):
+        nodes = np.ascontiguousarray(np.asarray(sensors), dtype=np.int32)
+        obs = np.ascontiguousarray(np.asarray(p_obs), dtype=np.float64)
+        if obs.ndim != 2 or obs.shape[1] != nodes.size:
+            raise ValueError("p_obs must be [n_steps, n_sensors]")
+        return _lib.Objective(nodes.size, _lib.iptr(nodes), _lib.dptr(obs)), (nodes, obs)
+
+    def objective(self, sensors, p_obs) -> float:
+        """J = sum_n sum_s (p^n_s - p_obs[n-1, s])^2 at the current trajectory."""
+        obj, keep = self._objective(sensors, p_obs)
+        J = C.c_double()
+        self._check(self.lib.biot_objective_value(self.h, C.byref(obj), C.byref(J)))
+        return J.value
+
+    def adjoint(self, sensors, p_obs, rtol: float = 1e-10, max_sweeps: int = 2000) -> dict:
+        """Gradient of the pressure misfit w.r.t. log K_e, lambda_e, mu_e (device
+        tensors) by biot_adjoint; the trajectory must be the converged forward."""
+        obj, keep = self._objective(sensors, p_obs)
+        ne = self.problem.n_elems
+        g = torch.empty((3, ne), dtype=torch.float64, device=self.device)
+        st = _lib.AdjointStats()
+        ptr = lambda i: C.c_void_p(g[i].data_ptr())
+        self._check(self.lib.biot_adjoint(self.h, C.byref(obj), float(rtol), int(max_sweeps),
+                                          ptr(0), ptr(1), ptr(2), 1, C.byref(st)))
+        return dict(J=st.J, grad_logk=g[0], grad_lambda=g[1], grad_mu=g[2],
+                    adjoint_sweeps=st.adjoint_sweeps, replay_sweeps=st.replay_sweeps,
+                    replay_groups=st.replay_groups, adjoint_rel_resid=st.adjoint_rel_resid,
+                    replay_rel_resid=st.replay_rel_resid, seconds_adjoint=st.seconds_adjoint,
+                    seconds_replay=st.seconds_replay, seconds=st.seconds)
+
+    def adjoint_states(self, n0: int = 1, n1: int | None = None) -> torch.Tensor:
+        """Lam^n for n = n0..n1-1 of the last adjoint call, [n1-n0, nn, dim+1]."""
+        n1 = self.n_steps + 1 if n1 is None else n1
+        out = torch.empty((n1 - n0, self.n_nodes, self.dim + 1), dtype=torch.float64,
+                          device=self.device)
+        self._check(self.lib.biot_get_adjoint(self.h, n0, n1, C.c_void_p(out.data_ptr()), 1))
+        return out
 
     def profile(self, enable: bool = True, probes=None):
         """Start (or stop) the HIP-event probes around level-0 launches; `probes`

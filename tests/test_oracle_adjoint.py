@@ -166,3 +166,16 @@ def test_objective_gradient_state_masks_prescribed():
     assert np.all(g[:, orc.fixed] == 0.0)
     idx = orc.nU + sensors
     np.testing.assert_allclose(g[:, idx], 2 * (X[1:, idx] - p_obs), rtol=0, atol=0)
+
+
+def test_stored_full_size_gradient_matches_stored_fd():
+    # tests/golden/adjoint_c4.npz: oracle gradient and central differences of
+    # the oracle's direct-solve objective, both at 128 x 128 x 256 steps
+    import os
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_c4.npz"))
+    pb = wl.adjoint_problem()
+    _, lam, mu = adj.problem_params(pb)
+    for (vk, vl, vm), fd, sc in zip(wl.fd_directions(pb.n_elems, 32, seed=43), g["fd"],
+                                    g["fd_scale"]):
+        an = g["grad_logk"] @ vk + g["grad_lambda"] @ (lam * vl) + g["grad_mu"] @ (mu * vm)
+        assert abs(an - fd) <= 1e-6 * sc
