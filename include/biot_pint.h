@@ -157,7 +157,9 @@ typedef struct {
   int32_t sweeps;       /* outer sweeps performed                                  */
   int32_t converged;    /* 1 if rel_resid <= rtol                                  */
   double rel_resid_u;   /* max_n ||r_u^n|| / max_n ||b_u^n||                       */
-  double rel_resid_p;   /* max_n ||r_p^n|| / max_n ||b_p^n||                       */
+  double rel_resid_p;   /* max_n ||r_p^n|| / max_n ||b_p^n||; a field whose b is   */
+                        /* zero at every step is divided by max_n ||b_u^n|| and  */
+                        /* max_n ||b_p^n|| combined (root of the sum of squares) */
   double seconds;       /* wall time of the call                                   */
 } biot_stats;
 

@@ -77,9 +77,16 @@ def wavefront(orc, X: np.ndarray, prec, omega: float, depth: int):
 
 
 def relative_residual(nrm: np.ndarray, floor: float = 1e-300) -> float:
-    """max over fields of max_n ||r^n|| / max_n ||b^n|| (per field)."""
+    """max over fields of max_n ||r^n|| / max_n ||b^n|| (per field).
+
+    A field whose right-hand side is zero at every step (e.g. the pressure rows
+    of a single step from a zero initial state) is measured against the whole
+    right-hand side instead."""
     ru = np.sqrt(nrm[:, 0].max())
     rp = np.sqrt(nrm[:, 1].max())
     bu = np.sqrt(nrm[:, 2].max())
     bp = np.sqrt(nrm[:, 3].max())
-    return max(ru / max(bu, floor), rp / max(bp, floor))
+    both = np.sqrt(bu * bu + bp * bp)
+    du = bu if bu > 0 else both
+    dp = bp if bp > 0 else both
+    return max(ru / max(du, floor), rp / max(dp, floor))

@@ -773,8 +773,13 @@ void rel_resid(const std::vector<double>& nr, int N, double& ru, double& rp) {
     ru = rp = NAN;
     return;
   }
-  ru = std::sqrt(mu) / std::max(std::sqrt(bu), 1e-300);
-  rp = std::sqrt(mp) / std::max(std::sqrt(bp), 1e-300);
+  // a field whose right-hand side vanishes at every step (the pressure rows of
+  // a single step from rest, the displacement rows of a one-step adjoint) is
+  // measured against the whole right-hand side
+  const double both = std::sqrt(bu + bp);
+  const double du = bu > 0 ? std::sqrt(bu) : both, dp = bp > 0 ? std::sqrt(bp) : both;
+  ru = std::sqrt(mu) / std::max(du, 1e-300);
+  rp = std::sqrt(mp) / std::max(dp, 1e-300);
 }
 
 int check_bound(biot_handle* h) {
