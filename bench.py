@@ -106,7 +106,7 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2):
     samples."""
     import torch
     s = BiotSolver(pb, schedule=args.schedule, depth=args.depth, omega=args.omega,
-                   col_tile=args.col_tile, precision=precision)
+                   wg_per_cu=args.wg_per_cu, precision=precision)
     s.reset()
     s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
     torch.cuda.synchronize()
@@ -161,7 +161,7 @@ def run_adjoint(BiotSolver, args, reps=2):
            "rtol": args.rtol}
     for stride in (16, 0):
         s = BiotSolver(pb, schedule=args.schedule, depth=args.depth, omega=args.omega,
-                       col_tile=args.col_tile, adjoint=True, ckpt_stride=stride,
+                       wg_per_cu=args.wg_per_cu, adjoint=True, ckpt_stride=stride,
                        replay_segments=4, max_sensors=64)
 
         def grad():
@@ -224,7 +224,8 @@ def main():
     ap.add_argument("--schedule", default="wavefront", choices=["wavefront", "jacobi"])
     ap.add_argument("--depth", type=int, default=64)
     ap.add_argument("--omega", type=float, default=0.6)
-    ap.add_argument("--col-tile", type=int, default=16)
+    ap.add_argument("--wg-per-cu", type=int, default=0,
+                    help="workgroups per CU of the node-blocked kernels (0: occupancy)")
     ap.add_argument("--rtol", type=float, default=2e-9)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--max-sweeps", type=int, default=600)
@@ -263,7 +264,7 @@ def main():
         log("bench: 1 GiB copy done (counter reference: 1 GiB read, 1 GiB written)")
     pb = W.large_terzaghi()
     if args.pmc_run:
-        s = BiotSolver(pb, schedule="jacobi", omega=args.omega, col_tile=args.col_tile)
+        s = BiotSolver(pb, schedule="jacobi", omega=args.omega, wg_per_cu=args.wg_per_cu)
         s.sweep(2)
         torch.cuda.synchronize()
         s.close()
@@ -273,7 +274,7 @@ def main():
         f"schedule={args.schedule} depth={args.depth} omega={args.omega} rtol={args.rtol}")
     t0 = time.perf_counter()
     s = BiotSolver(pb, schedule=args.schedule, depth=args.depth, omega=args.omega,
-                   col_tile=args.col_tile)
+                   wg_per_cu=args.wg_per_cu)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"bench: setup {setup_s:.2f} s, workspace {s.workspace_bytes / 1e9:.2f} GB")
@@ -373,7 +374,7 @@ def main():
             "omega": args.omega, "precond": "P1 with one multigrid V-cycle per inner solve",
             "rtol": args.rtol, "sweeps": stats[-1]["sweeps"],
             "rel_resid": max(stats[-1]["rel_resid_u"], stats[-1]["rel_resid_p"]),
-            "setup_s": setup_s, "col_tile": args.col_tile,
+            "setup_s": setup_s, "wg_per_cu": args.wg_per_cu,
         },
         "accuracy": acc,
         "roofline": {

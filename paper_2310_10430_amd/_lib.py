@@ -38,7 +38,7 @@ class Options(C.Structure):
     _fields_ = [("schedule", C.c_int32), ("depth", C.c_int32), ("precond", C.c_int32),
                 ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("lmax_safety", C.c_double), ("power_iters", C.c_int32),
-                ("max_batch", C.c_int32), ("omega", C.c_double), ("col_tile", C.c_int32),
+                ("max_batch", C.c_int32), ("omega", C.c_double), ("wg_per_cu", C.c_int32),
                 ("coarse_cells", C.c_int32), ("use_graph", C.c_int32),
                 ("precision", C.c_int32), ("adjoint", C.c_int32), ("ckpt_stride", C.c_int32),
                 ("replay_segments", C.c_int32), ("max_sensors", C.c_int32)]

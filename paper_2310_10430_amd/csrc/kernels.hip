@@ -4,10 +4,13 @@
 //
 // Thread mapping of the node-blocked kernels ("operator-stationary"): a thread
 // owns one node, loads that node's operator row (all stencil slots) into
-// registers once, and then loops over a group of G time-step columns two at a
-// time.  The operator is read once per column group while the column data
-// streams through.  The grid is (column groups) x (node blocks), ordered so
-// that all groups of one node block run on the same XCD (see tile_coords).
+// registers once, and then loops over a run of time-step columns two at a
+// time.  The operator is read once per run while the column data streams
+// through.  Work is split evenly over a grid sized to the chip (see
+// for_each_piece): the (node block, column) units of a launch are dealt out as
+// contiguous ranges, so no workgroup is left over for a last partial round, and
+// the ranges of the workgroups on one XCD are contiguous, so the rows above and
+// below a node block (the stencil's other neighbours) sit in the same L2.
 // Rows too large for registers (3D displacement blocks) are re-read per column
 // pair, from L1/L2.
 //
@@ -16,6 +19,11 @@
 // node-major [node][comp], one contiguous vector per column of the batch, of
 // type T (double, or float in the mixed-precision preconditioner).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <functional>
+#include <mutex>
+#include <unordered_map>
 
 #include "kernels.hpp"
 
@@ -39,16 +47,29 @@ __device__ inline int node_id(int i, int j, int k, int m) {
   return DIM == 2 ? j * m + i : (k * m + j) * m + i;
 }
 
-// XCD-aware workgroup order for the (column group, node block) grid: the
-// hardware deals workgroups to the 8 XCDs round-robin (workgroup i on XCD
-// i % 8).  All column groups of node block b get ids that land on XCD b % 8
-// back to back, so the block's operator rows are fetched into that XCD's L2
-// once and reused by every group.
-__device__ inline void tile_coords(int ntiles, int& tile, int& nblk) {
-  const int i = blockIdx.x;
-  const int j = i >> 3;
-  nblk = (j / ntiles) * 8 + (i & 7);
-  tile = j % ntiles;
+// Balanced split of a launch's work over its grid.  The units are the pairs
+// (node block of kBlock nodes, column), ordered block-major; workgroup slot l
+// takes units [U l / P, U (l+1) / P) and calls f(node_block, c_begin, c_end)
+// for each node block its range touches (at most a few), so every workgroup
+// does the same amount of work to within one unit.  The hardware deals
+// workgroups to the 8 XCDs round-robin (workgroup i on XCD i % 8); the slot of
+// workgroup i is chosen so that each XCD holds one contiguous run of slots,
+// i.e. neighbouring node blocks, whose shared stencil rows then hit one L2.
+// The range depends only on blockIdx, so f's control flow is uniform across a
+// workgroup (f may use __syncthreads).
+template <typename F>
+__device__ inline void for_each_piece(int nblocks, int nc, F&& f) {
+  const int P = gridDim.x, i = blockIdx.x;
+  const int l = (P & 7) == 0 ? (i & 7) * (P >> 3) + (i >> 3) : i;
+  const long U = long(nblocks) * nc;
+  long u = U * l / P;
+  const long u1 = U * (l + 1) / P;
+  while (u < u1) {
+    const int nb = int(u / nc), c0 = int(u % nc);
+    const int c1 = int(min(long(nc), c0 + (u1 - u)));
+    u += c1 - c0;
+    f(nb, c0, c1);
+  }
 }
 
 // Deterministic block sum of Q values per thread (wave64 shuffles, then LDS
@@ -83,7 +104,7 @@ __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
 // pressure-row vector gload[step-1] (no traction load):
 //   r = [B p'; -C_beta p' + g] - AA X^{m-1}.
 // ---------------------------------------------------------------------------
-template <int DIM, int G, typename T, bool ADJ>
+template <int DIM, typename T, bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
                                                      T* __restrict__ ru, T* __restrict__ rp,
@@ -96,171 +117,169 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
   constexpr int RS = STAT ? W : 1;
   __shared__ double lds[4 * 8];
   const int nn = L.nn;
-  int tile, nblk;
-  tile_coords((nc + G - 1) / G, tile, nblk);
-  if (nblk * kBlock >= nn) return;  // padding workgroup (uniform exit)
-  const int v = nblk * kBlock + threadIdx.x;
-  const bool active = v < nn;
-  const int vv = active ? v : nn - 1;
-  int nb[W];
+  for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+    const int v = nblk * kBlock + threadIdx.x;
+    const bool active = v < nn;
+    const int vv = active ? v : nn - 1;
+    int nb[W];
 #pragma unroll
-  for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + vv];
-  double rA[RS][DIM * DIM], rB[RS][DIM], rBt[RS][DIM], rS[RS], rCb[RS];
-  if constexpr (STAT) {
+    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + vv];
+    double rA[RS][DIM * DIM], rB[RS][DIM], rBt[RS][DIM], rS[RS], rCb[RS];
+    if constexpr (STAT) {
 #pragma unroll
-    for (int s = 0; s < W; ++s) {
+      for (int s = 0; s < W; ++s) {
 #pragma unroll
-      for (int e = 0; e < DIM * DIM; ++e) rA[s][e] = L.A[(size_t(s) * DIM * DIM + e) * nn + vv];
+        for (int e = 0; e < DIM * DIM; ++e) rA[s][e] = L.A[(size_t(s) * DIM * DIM + e) * nn + vv];
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) {
-        rB[s][c] = F.B[(size_t(s) * DIM + c) * nn + vv];
-        rBt[s][c] = F.Bt[(size_t(s) * DIM + c) * nn + vv];
+        for (int c = 0; c < DIM; ++c) {
+          rB[s][c] = F.B[(size_t(s) * DIM + c) * nn + vv];
+          rBt[s][c] = F.Bt[(size_t(s) * DIM + c) * nn + vv];
+        }
+        rS[s] = L.S[size_t(s) * nn + vv];
+        rCb[s] = F.Cb[size_t(s) * nn + vv];
       }
-      rS[s] = L.S[size_t(s) * nn + vv];
-      rCb[s] = F.Cb[size_t(s) * nn + vv];
     }
-  }
-  double Fu[DIM], Di[DIM * DIM];
+    double Fu[DIM], Di[DIM * DIM];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(vv) * D1 + a] : 0.0;
+    for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(vv) * D1 + a] : 0.0;
 #pragma unroll
-  for (int e = 0; e < DIM * DIM; ++e) Di[e] = xa ? L.Ainv[size_t(e) * nn + vv] : 0.0;
-  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+    for (int e = 0; e < DIM * DIM; ++e) Di[e] = xa ? L.Ainv[size_t(e) * nn + vv] : 0.0;
 #pragma unroll 1
-  for (int c = cbeg; c < cend; c += 2) {
-    const bool two = c + 1 < cend;
-    const int cc[2] = {c, two ? c + 1 : c};
-    const double* xc[2];
-    const double* xp[2];
-    double coef[2], au[2][DIM], ap[2], bp[2], cu[2][DIM];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      xc[q] = cols[cc[q]].xcur;
-      xp[q] = cols[cc[q]].xprev;
-      coef[q] = cols[cc[q]].coef;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        au[q][a] = coef[q] * Fu[a];
-        cu[q][a] = 0.0;
-      }
-      ap[q] = 0.0;
-      bp[q] = 0.0;
-      if constexpr (ADJ) {
-        const double g = active ? F.gload[size_t(cols[cc[q]].step - 1) * nn + vv] : 0.0;
-        ap[q] = g;
-        bp[q] = g;
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < W; ++s) {
-      const int w = nb[s];
-      double Ab[DIM * DIM], Bb[DIM], Btb[DIM], Sv, Cbv;
-      if constexpr (STAT) {
-#pragma unroll
-        for (int e = 0; e < DIM * DIM; ++e) Ab[e] = rA[s][e];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          Bb[k] = rB[s][k];
-          Btb[k] = rBt[s][k];
-        }
-        Sv = rS[s];
-        Cbv = rCb[s];
-      } else {
-#pragma unroll
-        for (int e = 0; e < DIM * DIM; ++e) Ab[e] = L.A[(size_t(s) * DIM * DIM + e) * nn + vv];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          Bb[k] = F.B[(size_t(s) * DIM + k) * nn + vv];
-          Btb[k] = F.Bt[(size_t(s) * DIM + k) * nn + vv];
-        }
-        Sv = L.S[size_t(s) * nn + vv];
-        Cbv = F.Cb[size_t(s) * nn + vv];
-      }
+    for (int c = cbeg; c < cend; c += 2) {
+      const bool two = c + 1 < cend;
+      const int cc[2] = {c, two ? c + 1 : c};
+      const double* xc[2];
+      const double* xp[2];
+      double coef[2], au[2][DIM], ap[2], bp[2], cu[2][DIM];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        double xw[D1], xpw[D1];
-#pragma unroll
-        for (int k = 0; k < D1; ++k) {
-          xw[k] = xc[q][size_t(w) * D1 + k];
-          xpw[k] = xp[q][size_t(w) * D1 + k];
-        }
+        xc[q] = cols[cc[q]].xcur;
+        xp[q] = cols[cc[q]].xprev;
+        coef[q] = cols[cc[q]].coef;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-          double acc = Bb[a] * xw[DIM];
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) acc += Ab[a * DIM + k] * xw[k];
-          au[q][a] -= acc;
+          au[q][a] = coef[q] * Fu[a];
+          cu[q][a] = 0.0;
         }
-        double btc = 0.0;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) btc += Btb[k] * xw[k];
-        double coup;
+        ap[q] = 0.0;
+        bp[q] = 0.0;
         if constexpr (ADJ) {
+          const double g = active ? F.gload[size_t(cols[cc[q]].step - 1) * nn + vv] : 0.0;
+          ap[q] = g;
+          bp[q] = g;
+        }
+      }
 #pragma unroll
-          for (int a = 0; a < DIM; ++a) {
-            const double c = Bb[a] * xpw[DIM];
-            cu[q][a] += c;
-            au[q][a] += c;
+      for (int s = 0; s < W; ++s) {
+        const int w = nb[s];
+        double Ab[DIM * DIM], Bb[DIM], Btb[DIM], Sv, Cbv;
+        if constexpr (STAT) {
+#pragma unroll
+          for (int e = 0; e < DIM * DIM; ++e) Ab[e] = rA[s][e];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            Bb[k] = rB[s][k];
+            Btb[k] = rBt[s][k];
           }
-          coup = -Cbv * xpw[DIM];
+          Sv = rS[s];
+          Cbv = rCb[s];
         } else {
-          double btp = 0.0;
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) btp += Btb[k] * xpw[k];
-          coup = btp - Cbv * xpw[DIM];
+          for (int e = 0; e < DIM * DIM; ++e) Ab[e] = L.A[(size_t(s) * DIM * DIM + e) * nn + vv];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            Bb[k] = F.B[(size_t(s) * DIM + k) * nn + vv];
+            Btb[k] = F.Bt[(size_t(s) * DIM + k) * nn + vv];
+          }
+          Sv = L.S[size_t(s) * nn + vv];
+          Cbv = F.Cb[size_t(s) * nn + vv];
         }
-        bp[q] += coup;
-        ap[q] += coup - btc + Sv * xw[DIM];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (!active || (q == 1 && !two)) break;
-      const size_t cu = size_t(cc[q]) * nn * DIM;
-      if (ru) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = T(au[q][a]);
-        rp[size_t(cc[q]) * nn + v] = T(ap[q]);
-      }
-      if (xa) {
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          double z = 0.0;
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) z += Di[a * DIM + k] * au[q][k];
-          z *= inv_theta;
-          xa[cu + size_t(v) * DIM + a] = T(z);
-          d[cu + size_t(v) * DIM + a] = T(z);
-        }
-      }
-    }
-    if (partials) {
-      double qv[8];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        double su = 0.0, sb = 0.0;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          su += au[q][a] * au[q][a];
-          const double ba = coef[q] * Fu[a] + cu[q][a];
-          sb += ba * ba;
-        }
-        qv[4 * q + 0] = active ? su : 0.0;
-        qv[4 * q + 1] = active ? ap[q] * ap[q] : 0.0;
-        qv[4 * q + 2] = active ? sb : 0.0;
-        qv[4 * q + 3] = active ? bp[q] * bp[q] : 0.0;
-      }
-      block_sum<8>(qv, lds);
-      if (threadIdx.x == 0)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          if (q == 1 && !two) break;
+          double xw[D1], xpw[D1];
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            partials[(size_t(cc[q]) * pstride + nblk) * 4 + k] = qv[4 * q + k];
+          for (int k = 0; k < D1; ++k) {
+            xw[k] = xc[q][size_t(w) * D1 + k];
+            xpw[k] = xp[q][size_t(w) * D1 + k];
+          }
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            double acc = Bb[a] * xw[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) acc += Ab[a * DIM + k] * xw[k];
+            au[q][a] -= acc;
+          }
+          double btc = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) btc += Btb[k] * xw[k];
+          double coup;
+          if constexpr (ADJ) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+              const double c = Bb[a] * xpw[DIM];
+              cu[q][a] += c;
+              au[q][a] += c;
+            }
+            coup = -Cbv * xpw[DIM];
+          } else {
+            double btp = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) btp += Btb[k] * xpw[k];
+            coup = btp - Cbv * xpw[DIM];
+          }
+          bp[q] += coup;
+          ap[q] += coup - btc + Sv * xw[DIM];
         }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (!active || (q == 1 && !two)) break;
+        const size_t cu = size_t(cc[q]) * nn * DIM;
+        if (ru) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = T(au[q][a]);
+          rp[size_t(cc[q]) * nn + v] = T(ap[q]);
+        }
+        if (xa) {
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            double z = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) z += Di[a * DIM + k] * au[q][k];
+            z *= inv_theta;
+            xa[cu + size_t(v) * DIM + a] = T(z);
+            d[cu + size_t(v) * DIM + a] = T(z);
+          }
+        }
+      }
+      if (partials) {
+        double qv[8];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          double su = 0.0, sb = 0.0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            su += au[q][a] * au[q][a];
+            const double ba = coef[q] * Fu[a] + cu[q][a];
+            sb += ba * ba;
+          }
+          qv[4 * q + 0] = active ? su : 0.0;
+          qv[4 * q + 1] = active ? ap[q] * ap[q] : 0.0;
+          qv[4 * q + 2] = active ? sb : 0.0;
+          qv[4 * q + 3] = active ? bp[q] * bp[q] : 0.0;
+        }
+        block_sum<8>(qv, lds);
+        if (threadIdx.x == 0)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            if (q == 1 && !two) break;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              partials[(size_t(cc[q]) * pstride + nblk) * 4 + k] = qv[4 * q + k];
+          }
+      }
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -296,8 +315,8 @@ __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T
 // update X^{n,m} = X^{n,m-1} + omega [z_u; xin + d] (FP64) through the column
 // descriptors.  FINE only makes the level-0 launches a distinct symbol.
 // ---------------------------------------------------------------------------
-template <int DIM, int C, int G, bool UPD, bool FINE, typename T>
-__global__ __launch_bounds__(kBlock) void k_cheb(LevelView<T> L, int isA,
+template <int DIM, int C, bool UPD, bool FINE, typename T>
+__global__ __launch_bounds__(kBlock, DIM == 2 ? 3 : 1) void k_cheb(LevelView<T> L, int isA,
                                                  const T* __restrict__ b,
                                                  const T* __restrict__ xin,
                                                  T* __restrict__ xout, T* __restrict__ d, int nc,
@@ -307,131 +326,132 @@ __global__ __launch_bounds__(kBlock) void k_cheb(LevelView<T> L, int isA,
   constexpr bool STAT = W * C * C <= 64;
   constexpr int RS = STAT ? W : 1;
   const int nn = L.nn;
-  int tile, nblk;
-  tile_coords((nc + G - 1) / G, tile, nblk);
-  const int v = nblk * kBlock + threadIdx.x;
-  if (v >= nn) return;
-  const T* K = isA ? L.A : L.S;
-  const T* Dg = isA ? L.Ainv : L.Sinv;
-  const size_t stride = size_t(nn) * C;
-  int nb[W];
+  for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+    const int v = nblk * kBlock + threadIdx.x;
+    if (v >= nn) return;
+    // C > 1 is the displacement field (A), C == 1 the pressure field (S)
+    const T* K = C > 1 ? L.A : L.S;
+    const T* Dg = C > 1 ? L.Ainv : L.Sinv;
+    const size_t stride = size_t(nn) * C;
+    int nb[W];
 #pragma unroll
-  for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
-  T kr[RS][C * C];
-  if constexpr (STAT) {
+    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+    T kr[RS][C * C];
+    if constexpr (STAT) {
 #pragma unroll
-    for (int s = 0; s < W; ++s)
+      for (int s = 0; s < W; ++s)
 #pragma unroll
-      for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
-  }
-  T Di[C * C];
+        for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
+    }
+    T Di[C * C];
 #pragma unroll
-  for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
-  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+    for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
 #pragma unroll 1
-  for (int c = cbeg; c < cend; c += 2) {
-    const bool two = c + 1 < cend;
-    const int cc[2] = {c, two ? c + 1 : c};
-    T acc[2][C], xs[2][C];
+    for (int c = cbeg; c < cend; c += 2) {
+      const bool two = c + 1 < cend;
+      const int cc[2] = {c, two ? c + 1 : c};
+      // column base pointers; offsets within a column fit in 32 bits
+      const T* xq[2] = {xin + size_t(cc[0]) * stride, xin + size_t(cc[1]) * stride};
+      T acc[2][C], xs[2][C];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + size_t(v) * C + a];
+        for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + v * C + a];
 #pragma unroll
-    for (int s = 0; s < W; ++s) {
-      const int w = nb[s];
-      T blk[C * C];
+      for (int s = 0; s < W; ++s) {
+        const int w = nb[s];
+        T blk[C * C];
 #pragma unroll
-      for (int e = 0; e < C * C; ++e) {
-        if constexpr (STAT) blk[e] = kr[s][e];
-        else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+        for (int e = 0; e < C * C; ++e) {
+          if constexpr (STAT) blk[e] = kr[s][e];
+          else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          T xw[C];
+#pragma unroll
+          for (int k = 0; k < C; ++k) xw[k] = xq[q][w * C + k];
+          if (s == 0)
+#pragma unroll
+            for (int k = 0; k < C; ++k) xs[q][k] = xw[k];
+#pragma unroll
+          for (int a = 0; a < C; ++a) {
+            T s2 = T(0);
+#pragma unroll
+            for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * xw[k];
+            acc[q][a] -= s2;
+          }
+        }
       }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        T xw[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) xw[k] = xin[size_t(cc[q]) * stride + size_t(w) * C + k];
-        if (s == 0)
-#pragma unroll
-          for (int k = 0; k < C; ++k) xs[q][k] = xw[k];
+        if (q == 1 && !two) break;
+        const size_t base = size_t(cc[q]) * stride + size_t(v) * C;
+        T xn[C];
 #pragma unroll
         for (int a = 0; a < C; ++a) {
-          T s2 = T(0);
+          T z = T(0);
 #pragma unroll
-          for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * xw[k];
-          acc[q][a] -= s2;
+          for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
+          const T dn = (c1 != T(0) ? c1 * d[base + a] : T(0)) + c2 * z;
+          if (!UPD) d[base + a] = dn;
+          xn[a] = xs[q][a] + dn;
+        }
+        if constexpr (!UPD) {
+#pragma unroll
+          for (int a = 0; a < C; ++a) xout[base + a] = xn[a];
+        } else {
+          // pressure field on level 0 (C == 1): write the updated state column
+          constexpr int D1 = DIM + 1;
+          const ColDesc cd = cols[cc[q]];
+          double out[D1];
+#pragma unroll
+          for (int a = 0; a < DIM; ++a)
+            out[a] = cd.xcur[size_t(v) * D1 + a] +
+                     omega * double(zu[(size_t(cc[q]) * nn + v) * DIM + a]);
+          out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * double(xn[0]);
+#pragma unroll
+          for (int a = 0; a < D1; ++a) cd.xout[size_t(v) * D1 + a] = out[a];
+          if (cd.xout2)
+#pragma unroll
+            for (int a = 0; a < D1; ++a) cd.xout2[size_t(v) * D1 + a] = out[a];
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (q == 1 && !two) break;
-      const size_t base = size_t(cc[q]) * stride + size_t(v) * C;
-      T xn[C];
-#pragma unroll
-      for (int a = 0; a < C; ++a) {
-        T z = T(0);
-#pragma unroll
-        for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
-        const T dn = (c1 != T(0) ? c1 * d[base + a] : T(0)) + c2 * z;
-        if (!UPD) d[base + a] = dn;
-        xn[a] = xs[q][a] + dn;
-      }
-      if constexpr (!UPD) {
-#pragma unroll
-        for (int a = 0; a < C; ++a) xout[base + a] = xn[a];
-      } else {
-        // pressure field on level 0 (C == 1): write the updated state column
-        constexpr int D1 = DIM + 1;
-        const ColDesc cd = cols[cc[q]];
-        double out[D1];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a)
-          out[a] = cd.xcur[size_t(v) * D1 + a] +
-                   omega * double(zu[(size_t(cc[q]) * nn + v) * DIM + a]);
-        out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * double(xn[0]);
-#pragma unroll
-        for (int a = 0; a < D1; ++a) cd.xout[size_t(v) * D1 + a] = out[a];
-        if (cd.xout2)
-#pragma unroll
-          for (int a = 0; a < D1; ++a) cd.xout2[size_t(v) * D1 + a] = out[a];
-      }
-    }
-  }
+  });
 }
 
 // xout = xin + P xc (P1 interpolation, masked) for a group of columns; the
 // parents of the node are found once and reused for every column
-template <int DIM, int C, int G, typename T>
+template <int DIM, int C, typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(LevelView<T> Lf, LevelView<T> Lc, int isA,
                                                     const T* __restrict__ xin,
                                                     const T* __restrict__ xc,
                                                     T* __restrict__ xout, int nc) {
   const int nn = Lf.nn;
-  int tile, nblk;
-  tile_coords((nc + G - 1) / G, tile, nblk);
-  const int v = nblk * kBlock + threadIdx.x;
-  if (v >= nn) return;
-  int p0, p1;
-  unsigned pm;
-  prolong_parents<DIM, C>(Lf, Lc, isA ? 0 : DIM, v, p0, p1, pm);
-  const T wt = (pm >> (2 * C)) ? T(0.5) : T(1);
-  const size_t stride = size_t(nn) * C, cstride = size_t(Lc.nn) * C;
-  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+  for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+    const int v = nblk * kBlock + threadIdx.x;
+    if (v >= nn) return;
+    int p0, p1;
+    unsigned pm;
+    prolong_parents<DIM, C>(Lf, Lc, isA ? 0 : DIM, v, p0, p1, pm);
+    const T wt = (pm >> (2 * C)) ? T(0.5) : T(1);
+    const size_t stride = size_t(nn) * C, cstride = size_t(Lc.nn) * C;
 #pragma unroll 2
-  for (int c = cbeg; c < cend; ++c) {
+    for (int c = cbeg; c < cend; ++c) {
 #pragma unroll
-    for (int a = 0; a < C; ++a) {
-      T x = xin[size_t(c) * stride + size_t(v) * C + a];
-      if ((pm >> a) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p0) * C + a];
-      if ((pm >> (C + a)) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p1) * C + a];
-      xout[size_t(c) * stride + size_t(v) * C + a] = x;
+      for (int a = 0; a < C; ++a) {
+        T x = xin[size_t(c) * stride + size_t(v) * C + a];
+        if ((pm >> a) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p0) * C + a];
+        if ((pm >> (C + a)) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p1) * C + a];
+        xout[size_t(c) * stride + size_t(v) * C + a] = x;
+      }
     }
-  }
+  });
 }
 
 // r = b - K x on one level
-template <int DIM, int C, int G, typename T>
+template <int DIM, int C, typename T>
 __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int isA,
                                                            const T* __restrict__ b,
                                                            const T* __restrict__ x,
@@ -440,59 +460,58 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
   constexpr bool STAT = W * C * C <= 64;
   constexpr int RS = STAT ? W : 1;
   const int nn = L.nn;
-  int tile, nblk;
-  tile_coords((nc + G - 1) / G, tile, nblk);
-  const int v = nblk * kBlock + threadIdx.x;
-  if (v >= nn) return;
-  const T* K = isA ? L.A : L.S;
-  const size_t stride = size_t(nn) * C;
-  int nb[W];
+  for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+    const int v = nblk * kBlock + threadIdx.x;
+    if (v >= nn) return;
+    const T* K = isA ? L.A : L.S;
+    const size_t stride = size_t(nn) * C;
+    int nb[W];
 #pragma unroll
-  for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
-  T kr[RS][C * C];
-  if constexpr (STAT) {
+    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+    T kr[RS][C * C];
+    if constexpr (STAT) {
 #pragma unroll
-    for (int s = 0; s < W; ++s)
+      for (int s = 0; s < W; ++s)
 #pragma unroll
-      for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
-  }
-  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+        for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
+    }
 #pragma unroll 1
-  for (int c = cbeg; c < cend; c += 2) {
-    const bool two = c + 1 < cend;
-    const int cc[2] = {c, two ? c + 1 : c};
-    T acc[2][C];
+    for (int c = cbeg; c < cend; c += 2) {
+      const bool two = c + 1 < cend;
+      const int cc[2] = {c, two ? c + 1 : c};
+      T acc[2][C];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + size_t(v) * C + a];
+        for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + size_t(v) * C + a];
 #pragma unroll
-    for (int s = 0; s < W; ++s) {
-      const int w = nb[s];
-      T blk[C * C];
+      for (int s = 0; s < W; ++s) {
+        const int w = nb[s];
+        T blk[C * C];
 #pragma unroll
-      for (int e = 0; e < C * C; ++e) {
-        if constexpr (STAT) blk[e] = kr[s][e];
-        else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+        for (int e = 0; e < C * C; ++e) {
+          if constexpr (STAT) blk[e] = kr[s][e];
+          else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+          for (int a = 0; a < C; ++a) {
+            T s2 = T(0);
+#pragma unroll
+            for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[size_t(cc[q]) * stride + size_t(w) * C + k];
+            acc[q][a] -= s2;
+          }
+        }
       }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
+        if (q == 1 && !two) break;
 #pragma unroll
-        for (int a = 0; a < C; ++a) {
-          T s2 = T(0);
-#pragma unroll
-          for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * x[size_t(cc[q]) * stride + size_t(w) * C + k];
-          acc[q][a] -= s2;
-        }
+        for (int a = 0; a < C; ++a) r[size_t(cc[q]) * stride + size_t(v) * C + a] = acc[q][a];
       }
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (q == 1 && !two) break;
-#pragma unroll
-      for (int a = 0; a < C; ++a) r[size_t(cc[q]) * stride + size_t(v) * C + a] = acc[q][a];
-    }
-  }
+  });
 }
 
 // coarse b = P' r_fine (P1 interpolation transpose, masked), plus the first
@@ -566,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const T* __restr
 
 // pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), and the first
 // Chebyshev step of the pressure V-cycle
-template <int DIM, int G, typename T>
+template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __restrict__ Bt,
                                                    int p1, const T* __restrict__ zu,
                                                    const T* __restrict__ rp,
@@ -574,49 +593,48 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
                                                    T* __restrict__ d, T inv_theta, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
-  int tile, nblk;
-  tile_coords((nc + G - 1) / G, tile, nblk);
-  const int v = nblk * kBlock + threadIdx.x;
-  if (v >= nn) return;
-  int nb[W];
-  T bt[W][DIM];
+  for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+    const int v = nblk * kBlock + threadIdx.x;
+    if (v >= nn) return;
+    int nb[W];
+    T bt[W][DIM];
 #pragma unroll
-  for (int s = 0; s < W; ++s) {
-    nb[s] = L.nbr[size_t(s) * nn + v];
+    for (int s = 0; s < W; ++s) {
+      nb[s] = L.nbr[size_t(s) * nn + v];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) bt[s][k] = p1 ? Bt[(size_t(s) * DIM + k) * nn + v] : T(0);
-  }
-  const T si = L.Sinv[v];
-  const int cbeg = tile * G, cend = min(nc, cbeg + G);
+      for (int k = 0; k < DIM; ++k) bt[s][k] = p1 ? Bt[(size_t(s) * DIM + k) * nn + v] : T(0);
+    }
+    const T si = L.Sinv[v];
 #pragma unroll 1
-  for (int c = cbeg; c < cend; c += 2) {
-    const bool two = c + 1 < cend;
-    const int cc[2] = {c, two ? c + 1 : c};
-    T acc[2];
+    for (int c = cbeg; c < cend; c += 2) {
+      const bool two = c + 1 < cend;
+      const int cc[2] = {c, two ? c + 1 : c};
+      T acc[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
-    if (p1) {
+      for (int q = 0; q < 2; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
+      if (p1) {
 #pragma unroll
-      for (int s = 0; s < W; ++s) {
-        const int w = nb[s];
+        for (int s = 0; s < W; ++s) {
+          const int w = nb[s];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const size_t base = size_t(cc[q]) * nn * DIM + size_t(w) * DIM;
+          for (int q = 0; q < 2; ++q) {
+            const size_t base = size_t(cc[q]) * nn * DIM + size_t(w) * DIM;
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) acc[q] += bt[s][k] * zu[base + k];
+            for (int k = 0; k < DIM; ++k) acc[q] += bt[s][k] * zu[base + k];
+          }
         }
       }
-    }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (q == 1 && !two) break;
-      const size_t idx = size_t(cc[q]) * nn + v;
-      t_out[idx] = acc[q];
-      const T z = si * acc[q] * inv_theta;
-      xa[idx] = z;
-      d[idx] = z;
+      for (int q = 0; q < 2; ++q) {
+        if (q == 1 && !two) break;
+        const size_t idx = size_t(cc[q]) * nn + v;
+        t_out[idx] = acc[q];
+        const T z = si * acc[q] * inv_theta;
+        xa[idx] = z;
+        d[idx] = z;
+      }
     }
-  }
+  });
 }
 
 // X^{n,m} = X^{n,m-1} + omega [z_u; z_p]   (used when the coarsest level is 0)
@@ -739,109 +757,123 @@ __global__ __launch_bounds__(kBlock) void k_pre1(LevelView<T> L, int isA, const 
   }
 }
 
-inline dim3 tiled_grid(int nc, int nn, int ct) {
-  const int nb8 = (num_node_blocks(nn) + 7) / 8 * 8;
-  return dim3(nb8 * ((nc + ct - 1) / ct));
-}
 inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
 
-// runtime column group -> template instantiation
-#define BIOT_G_SWITCH(g, ...)                              \
-  switch (g) {                                             \
-    case 1: { constexpr int G = 1; __VA_ARGS__; } break;   \
-    case 2: { constexpr int G = 2; __VA_ARGS__; } break;   \
-    case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
-    case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
-    case 32: { constexpr int G = 32; __VA_ARGS__; } break; \
-    default: { constexpr int G = 16; __VA_ARGS__; } break; \
+// Grid of a balanced launch (for_each_piece): one workgroup per resident
+// workgroup slot of the device (compute units x the kernel's occupancy, or x
+// `wpc` when wpc > 0), and no more than there are (node block, column) units.
+// Occupancies are queried once per kernel and device and cached.
+struct OccKey {
+  const void* fn;
+  int dev;
+  bool operator==(const OccKey& o) const { return fn == o.fn && dev == o.dev; }
+};
+struct OccHash {
+  size_t operator()(const OccKey& k) const {
+    return std::hash<const void*>()(k.fn) ^ (size_t(k.dev) * 0x9E3779B97F4A7C15ull);
   }
+};
+
+dim3 balanced_grid(const void* fn, int nn, int nc, int wpc) {
+  static std::mutex mu;
+  static std::unordered_map<OccKey, int, OccHash> occ;
+  static std::unordered_map<int, int> cus;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int per_cu = wpc, ncu = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto ic = cus.find(dev);
+    if (ic == cus.end()) {
+      int n = 0;
+      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+      ic = cus.emplace(dev, n).first;
+    }
+    ncu = ic->second;
+    if (per_cu <= 0) {
+      auto io = occ.find(OccKey{fn, dev});
+      if (io == occ.end()) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fn, kBlock, 0) != hipSuccess || o < 1) o = 1;
+        io = occ.emplace(OccKey{fn, dev}, o).first;
+      }
+      per_cu = io->second;
+    }
+  }
+  const long units = long(num_node_blocks(nn)) * nc;
+  return dim3(unsigned(std::max(1L, std::min(long(ncu) * per_cu, units))));
+}
+
+#define BIOT_LAUNCH_BALANCED(kern, nn, nc, wpc, st, ...)                                   \
+  hipLaunchKernelGGL(kern, balanced_grid(reinterpret_cast<const void*>(kern), nn, nc, wpc), \
+                     dim3(kBlock), 0, st, __VA_ARGS__)
 
 }  // namespace
-
-bool valid_col_tile(int ct) {
-  return ct == 1 || ct == 2 || ct == 4 || ct == 8 || ct == 16 || ct == 32;
-}
-
-// largest column group <= gmax that still gives the grid enough workgroups
-int pick_group(int nc, int nn, int gmax) {
-  const long nb8 = (num_node_blocks(nn) + 7) / 8 * 8;
-  int g = gmax;
-  while (g > 1 && nb8 * ((nc + g - 1) / g) < 1024) g >>= 1;
-  return g;
-}
 
 template <int DIM, bool ADJ, typename T>
 static void residual_dispatch(const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                               T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials,
-                              int pstride, int ct, hipStream_t st) {
-  const dim3 g = tiled_grid(nc, L.nn, ct);
-  BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_residual<DIM, G, T, ADJ>), g, dim3(kBlock), 0, st, L, F,
-                                       cols, nc, ru, rp, xa, d, inv_theta, partials, pstride))
+                              int pstride, int wpc, hipStream_t st) {
+  BIOT_LAUNCH_BALANCED((k_residual<DIM, T, ADJ>), L.nn, nc, wpc, st, L, F, cols, nc, ru, rp, xa, d,
+                       inv_theta, partials, pstride);
 }
 
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                      T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials, int pstride,
-                     int ct, bool adj, hipStream_t st) {
-  ct = pick_group(nc, L.nn, ct);
+                     int wpc, bool adj, hipStream_t st) {
   if (dim == 2) {
-    if (adj) residual_dispatch<2, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
-    else residual_dispatch<2, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
+    if (adj) residual_dispatch<2, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
+    else residual_dispatch<2, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
   } else {
-    if (adj) residual_dispatch<3, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
-    else residual_dispatch<3, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, ct, st);
+    if (adj) residual_dispatch<3, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
+    else residual_dispatch<3, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
   }
 }
 
 template <int DIM, int C, bool UPD, typename T>
 static void cheb_dispatch(const LevelView<T>& L, bool is_A, const T* b, const T* xin, T* xout,
                           T* d, int nc, double c1, double c2, const ColDesc* cols, const T* zu,
-                          double omega, int ct, bool fine, hipStream_t st) {
-  ct = pick_group(nc, L.nn, ct);
-  const dim3 g = tiled_grid(nc, L.nn, ct);
+                          double omega, int wpc, bool fine, hipStream_t st) {
   if (fine) {
-    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, G, UPD, true, T>), g, dim3(kBlock), 0, st,
-                                         L, int(is_A), b, xin, xout, d, nc, T(c1), T(c2), cols, zu,
-                                         omega))
+    BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, true, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
+                         xout, d, nc, T(c1), T(c2), cols, zu, omega);
   } else if constexpr (!UPD) {
-    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_cheb<DIM, C, G, UPD, false, T>), g, dim3(kBlock), 0,
-                                         st, L, int(is_A), b, xin, xout, d, nc, T(c1), T(c2), cols,
-                                         zu, omega))
+    BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, false, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
+                         xout, d, nc, T(c1), T(c2), cols, zu, omega);
   }
 }
 
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
                  T* xout, T* d, int nc, double c1, double c2, const ColDesc* upd, const T* zu,
-                 double omega, int ct, bool fine, hipStream_t st) {
+                 double omega, int wpc, bool fine, hipStream_t st) {
   if (dim == 2) {
     if (comps == 1) {
-      if (upd) cheb_dispatch<2, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
-      else cheb_dispatch<2, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
+      if (upd) cheb_dispatch<2, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
+      else cheb_dispatch<2, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
     } else {
-      cheb_dispatch<2, 2, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
+      cheb_dispatch<2, 2, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
     }
   } else {
     if (comps == 1) {
-      if (upd) cheb_dispatch<3, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
-      else cheb_dispatch<3, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
+      if (upd) cheb_dispatch<3, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
+      else cheb_dispatch<3, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
     } else {
-      cheb_dispatch<3, 3, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, ct, fine, st);
+      cheb_dispatch<3, 3, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
     }
   }
 }
 
 template <typename T>
 void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
-                           const T* x, T* r, int nc, int ct, hipStream_t st) {
-  ct = pick_group(nc, L.nn, ct);
-  const dim3 g = tiled_grid(nc, L.nn, ct);
+                           const T* x, T* r, int nc, int wpc, hipStream_t st) {
   if (dim == 2) {
-    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 1, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
-    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<2, 2, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_level_residual<2, 1, T>), L.nn, nc, wpc, st, L, int(is_A), b, x, r, nc);
+    else BIOT_LAUNCH_BALANCED((k_level_residual<2, 2, T>), L.nn, nc, wpc, st, L, int(is_A), b, x, r, nc);
   } else {
-    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 1, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
-    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_level_residual<3, 3, G, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, x, r, nc)) }
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_level_residual<3, 1, T>), L.nn, nc, wpc, st, L, int(is_A), b, x, r, nc);
+    else BIOT_LAUNCH_BALANCED((k_level_residual<3, 3, T>), L.nn, nc, wpc, st, L, int(is_A), b, x, r, nc);
   }
 }
 
@@ -862,15 +894,13 @@ void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView
 
 template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
-                    const T* xin, const T* xc, T* xout, int nc, int ct, hipStream_t st) {
-  ct = pick_group(nc, Lf.nn, ct);
-  const dim3 g = tiled_grid(nc, Lf.nn, ct);
+                    const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st) {
   if (dim == 2) {
-    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 1, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
-    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<2, 2, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_prolong<2, 1, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
+    else BIOT_LAUNCH_BALANCED((k_prolong<2, 2, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
   } else {
-    if (comps == 1) { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 1, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
-    else { BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_prolong<3, 3, G, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), xin, xc, xout, nc)) }
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_prolong<3, 1, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
+    else BIOT_LAUNCH_BALANCED((k_prolong<3, 3, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
   }
 }
 
@@ -882,15 +912,10 @@ void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStre
 
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
-                   T* t, T* xa, T* d, double inv_theta, int nc, int ct, hipStream_t st) {
-  ct = pick_group(nc, L.nn, ct);
-  const dim3 g = tiled_grid(nc, L.nn, ct);
+                   T* t, T* xa, T* d, double inv_theta, int nc, int wpc, hipStream_t st) {
   const T it = T(inv_theta);
-  if (dim == 2) {
-    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_pstage<2, G, T>), g, dim3(kBlock), 0, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc))
-  } else {
-    BIOT_G_SWITCH(ct, hipLaunchKernelGGL((k_pstage<3, G, T>), g, dim3(kBlock), 0, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc))
-  }
+  if (dim == 2) BIOT_LAUNCH_BALANCED((k_pstage<2, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc);
+  else BIOT_LAUNCH_BALANCED((k_pstage<3, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc);
 }
 
 template <typename T>

@@ -45,41 +45,40 @@ struct ColDesc {
 };
 
 // Launchers (all asynchronous on `st`).  `nc` = number of columns in the batch;
-// per-column work vectors are contiguous with stride nn*comps.  `ct` = the
-// largest group of columns one thread loops over (1..32); smaller groups are
-// chosen on small levels so the grid keeps enough workgroups.  T is the type of
-// the preconditioner's vectors and operators (double or float); the residual
-// and the state update always run in FP64.
-bool valid_col_tile(int ct);
-int pick_group(int nc, int nn, int gmax);
+// per-column work vectors are contiguous with stride nn*comps.  The node-blocked
+// kernels split their (node block, column) units evenly over a grid of one
+// workgroup per resident slot of the device; `wpc` > 0 fixes the workgroups per
+// compute unit instead of the kernel's occupancy.  T is the type of the
+// preconditioner's vectors and operators (double or float); the residual and
+// the state update always run in FP64.
 
 // `adj`: the adjoint recursion (coupling A'^T, load F.gload; see k_residual)
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                      T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials,
-                     int partial_stride, int ct, bool adj, hipStream_t st);
+                     int partial_stride, int wpc, bool adj, hipStream_t st);
 // Chebyshev step d <- c1 d + c2 D^{-1}(b - K xin), xout = xin + d.  With `upd`
 // (pressure field, level 0) the step writes the outer update
 // X^{n,m} = X^{n,m-1} + omega [zu; xin + d] through the descriptors instead.
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
                  T* xout, T* d, int nc, double c1, double c2, const ColDesc* upd, const T* zu,
-                 double omega, int ct, bool fine, hipStream_t st);
+                 double omega, int wpc, bool fine, hipStream_t st);
 template <typename T>
 void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
-                           const T* x, T* r, int nc, int ct, hipStream_t st);
+                           const T* x, T* r, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
                      bool is_A, const T* rf, T* bc, T* xa_c, T* d_c, double inv_theta_c, int nc,
                      hipStream_t st);
 template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
-                    const T* xin, const T* xc, T* xout, int nc, int ct, hipStream_t st);
+                    const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStream_t st);
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
-                   T* t, T* xa, T* d, double inv_theta, int nc, int ct, hipStream_t st);
+                   T* t, T* xa, T* d, double inv_theta, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* zp, double omega,
                    int nc, hipStream_t st);
@@ -130,6 +129,6 @@ void launch_grad_partial(int dim, const ElemDev& E, size_t col, const double* xb
 void launch_grad_finish(const ElemDev& E, const double* part, int nchunks, double* g_logk,
                         double* g_lam, double* g_mu, hipStream_t st);
 
-inline int num_node_blocks(int nn) { return (nn + kBlock - 1) / kBlock; }
+__host__ __device__ inline int num_node_blocks(int nn) { return (nn + kBlock - 1) / kBlock; }
 
 }  // namespace biot

@@ -498,7 +498,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   Field<T>& f = is_A ? p.fa : p.fs;
   const int C = is_A ? h->dim : 1;
   const int last = h->nlev - 1;
-  const int ct = h->opt.col_tile;
+  const int wpc = h->opt.wg_per_cu;
   const int tb = int(sizeof(T));
   hipStream_t st = h->st;
   if (l == last) {
@@ -525,7 +525,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
     ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, true, false, tb) : 0);
     launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho,
-                   2.0 * rn / cc.delta, nullptr, nullptr, 0.0, ct, fine, st);
+                   2.0 * rn / cc.delta, nullptr, nullptr, 0.0, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -534,7 +534,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   {
     ProbeScope ps(h, is_A ? BIOT_PROBE_LEVRES_U : BIOT_PROBE_LEVRES_P,
                   fine ? bytes_levres(h, C, nc, tb) : 0);
-    launch_level_residual<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, f.r[l], nc, ct, st);
+    launch_level_residual<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, f.r[l], nc, wpc, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
   }
@@ -548,7 +548,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   int rc = vcycle<T>(h, p, is_A, l + 1, nc, &xc, nullptr, nullptr);
   if (rc) return rc;
   // coarse-grid correction x += P xc, then deg post-smoothing steps
-  launch_prolong<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, cur, xc, oth, nc, ct, st);
+  launch_prolong<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, cur, xc, oth, nc, wpc, st);
   LAUNCHCHK(h);
   std::swap(cur, oth);
   rho = 1.0 / cc.sigma;
@@ -562,7 +562,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     const bool final_upd = upd && j == deg;
     ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, tb) : 0);
     launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2,
-                   final_upd ? upd : nullptr, zu, h->opt.omega, ct, fine, st);
+                   final_upd ? upd : nullptr, zu, h->opt.omega, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -584,7 +584,7 @@ int precond_batch(biot_handle* h, Prec<T>& p, int nc, T** zu, T** zp, const ColD
     ProbeScope ps(h, BIOT_PROBE_PSTAGE, bytes_pstage(h, nc, int(sizeof(T))));
     launch_pstage<T>(h->dim, p.L[0], p.Bt, h->opt.precond == BIOT_PRECOND_P1, *zu, p.rp,
                      p.fs.b[0], p.fs.x0[0], p.fs.d[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc,
-                     h->opt.col_tile, h->st);
+                     h->opt.wg_per_cu, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
   }
@@ -607,7 +607,7 @@ int unit_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols
     ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, sm, int(sizeof(T))));
     launch_residual<T>(h->dim, h->L[0], fine_of(h, S), cols, nc, p.fa.b[0], p.rp,
                        sm ? p.fa.x0[0] : nullptr, p.fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0,
-                       nullptr, h->nblk, h->opt.col_tile, S.adj, h->st);
+                       nullptr, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
   }
@@ -736,7 +736,7 @@ int global_residual(biot_handle* h, const Sched& S) {
   for (int n0 = 0; n0 < S.N; n0 += chunk) {
     const int nc = std::min(chunk, S.N - n0);
     launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, nullptr, nullptr,
-                            0.0, h->partials, h->nblk, h->opt.col_tile, S.adj, h->st);
+                            0.0, h->partials, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
     launch_reduce_norms(h->partials, h->nblk, h->nblk, h->norms + size_t(n0) * 4, nc, h->st);
     LAUNCHCHK(h);
@@ -936,7 +936,7 @@ int biot_default_options(biot_options* o) {
   o->power_iters = 20;
   o->max_batch = 0;
   o->omega = 0.6;
-  o->col_tile = 16;
+  o->wg_per_cu = 0;
   o->coarse_cells = 2;
   o->use_graph = 1;
   o->precision = BIOT_PRECISION_FP64;
@@ -965,7 +965,7 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   if (o.power_iters < 1) return fail(nullptr, BIOT_EINVAL, "power_iters must be >= 1");
   if (!(o.lmax_safety >= 1.0)) return fail(nullptr, BIOT_EINVAL, "lmax_safety must be >= 1");
   if (o.cheb_degree < 2 || o.cheb_degree > 8) return fail(nullptr, BIOT_EINVAL, "cheb_degree must be in 2..8");
-  if (!valid_col_tile(o.col_tile)) return fail(nullptr, BIOT_EINVAL, "col_tile must be 1, 2, 4, 8, 16 or 32");
+  if (o.wg_per_cu < 0 || o.wg_per_cu > 32) return fail(nullptr, BIOT_EINVAL, "wg_per_cu must be in 0..32");
   if (o.coarse_cells < 1 || o.coarse_cells > 64) return fail(nullptr, BIOT_EINVAL, "coarse_cells must be in 1..64");
   if (o.precision != BIOT_PRECISION_FP64 && o.precision != BIOT_PRECISION_MIXED)
     return fail(nullptr, BIOT_EINVAL, "unknown precision");

@@ -17,7 +17,7 @@ from . import _lib
 
 def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
                   cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
-                  col_tile=16, coarse_cells=2, use_graph=True, precision="fp64", lame=None,
+                  wg_per_cu=0, coarse_cells=2, use_graph=True, precision="fp64", lame=None,
                   adjoint=False, ckpt_stride=16, replay_segments=4, max_sensors=256):
     """biot_create on the host (no device work); returns (handle, options).
 
@@ -57,7 +57,7 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     opt.power_iters = power_iters
     opt.max_batch = max_batch
     opt.omega = omega
-    opt.col_tile = col_tile
+    opt.wg_per_cu = wg_per_cu
     opt.coarse_cells = coarse_cells
     opt.use_graph = 1 if use_graph else 0
     opt.precision = _lib.PRECISION[precision]
@@ -106,7 +106,7 @@ class BiotSolver:
     def __init__(self, problem, schedule: str = "jacobi", depth: int = 8, precond: str = "P1",
                  omega: float = 0.6, cheb_degree: int = 2, cheb_ratio: float = 4.0,
                  lmax_safety: float = 1.1, power_iters: int = 20, max_batch: int = 0,
-                 device: str = "cuda:0", beta=None, col_tile: int = 16, coarse_cells: int = 2,
+                 device: str = "cuda:0", beta=None, wg_per_cu: int = 0, coarse_cells: int = 2,
                  use_graph: bool = True, precision: str = "fp64", lame=None,
                  adjoint: bool = False, ckpt_stride: int = 16, replay_segments: int = 4,
                  max_sensors: int = 256):
@@ -117,7 +117,7 @@ class BiotSolver:
         h, opt = create_handle(problem, schedule=schedule, depth=depth, precond=precond,
                                omega=omega, cheb_degree=cheb_degree, cheb_ratio=cheb_ratio,
                                lmax_safety=lmax_safety, power_iters=power_iters,
-                               max_batch=max_batch, beta=beta, col_tile=col_tile,
+                               max_batch=max_batch, beta=beta, wg_per_cu=wg_per_cu,
                                coarse_cells=coarse_cells, use_graph=use_graph,
                                precision=precision, lame=lame, adjoint=adjoint,
                                ckpt_stride=ckpt_stride, replay_segments=replay_segments,
