@@ -565,6 +565,249 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
   }
 }
 
+// ---------------------------------------------------------------------------
+// The coarse end of a V-cycle in one launch: levels t..last of the hierarchy
+// for one column per workgroup, every vector in LDS.  The steps are exactly
+// those of the per-level kernels (k_pre1's first Chebyshev step, k_cheb,
+// k_level_residual, k_restrict, k_coarse_solve, k_prolong), in the same order
+// and with the same summation order, so the result is the same as running
+// them one launch at a time; only the launches (each a few microseconds on a
+// level of a few hundred nodes) are saved.
+// ---------------------------------------------------------------------------
+namespace tail {
+
+// x = d = inv_theta D^{-1} b
+template <int C, typename T>
+__device__ inline void first_step(const LevelView<T>& L, const T* b, T* x, T* d, T it) {
+  const T* Dg = C > 1 ? L.Ainv : L.Sinv;
+  for (int v = threadIdx.x; v < L.nn; v += kBlock) {
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      T z = T(0);
+#pragma unroll
+      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + v] * b[v * C + k];
+      z *= it;
+      x[v * C + a] = z;
+      d[v * C + a] = z;
+    }
+  }
+}
+
+// one Chebyshev step xout = xin + d, d <- c1 d + c2 D^{-1}(b - K xin)
+template <int DIM, int C, typename T>
+__device__ inline void cheb(const LevelView<T>& L, const T* b, const T* xin, T* xout, T* d, T c1,
+                            T c2) {
+  constexpr int W = DIM == 2 ? 7 : 15;
+  const T* K = C > 1 ? L.A : L.S;
+  const T* Dg = C > 1 ? L.Ainv : L.Sinv;
+  const int nn = L.nn;
+  for (int v = threadIdx.x; v < nn; v += kBlock) {
+    T acc[C], xs[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) acc[a] = b[v * C + a];
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      const int w = L.nbr[size_t(s) * nn + v];
+      T xw[C];
+#pragma unroll
+      for (int k = 0; k < C; ++k) xw[k] = xin[w * C + k];
+      if (s == 0)
+#pragma unroll
+        for (int k = 0; k < C; ++k) xs[k] = xw[k];
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        T s2 = T(0);
+#pragma unroll
+        for (int k = 0; k < C; ++k) s2 += K[(size_t(s) * C * C + a * C + k) * nn + v] * xw[k];
+        acc[a] -= s2;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      T z = T(0);
+#pragma unroll
+      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * nn + v] * acc[k];
+      const T dn = (c1 != T(0) ? c1 * d[v * C + a] : T(0)) + c2 * z;
+      d[v * C + a] = dn;
+      xout[v * C + a] = xs[a] + dn;
+    }
+  }
+}
+
+template <int DIM, int C, typename T>
+__device__ inline void residual(const LevelView<T>& L, const T* b, const T* x, T* r) {
+  constexpr int W = DIM == 2 ? 7 : 15;
+  const T* K = C > 1 ? L.A : L.S;
+  const int nn = L.nn;
+  for (int v = threadIdx.x; v < nn; v += kBlock) {
+    T acc[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) acc[a] = b[v * C + a];
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      const int w = L.nbr[size_t(s) * nn + v];
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        T s2 = T(0);
+#pragma unroll
+        for (int k = 0; k < C; ++k) s2 += K[(size_t(s) * C * C + a * C + k) * nn + v] * x[w * C + k];
+        acc[a] -= s2;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < C; ++a) r[v * C + a] = acc[a];
+  }
+}
+
+// bc = P' rf (masked); with `first`, also the first Chebyshev step of the
+// coarse level (x = d = it D^{-1} bc)
+template <int DIM, int C, typename T>
+__device__ inline void restrict_to(const LevelView<T>& Lf, const LevelView<T>& Lc, const T* rf,
+                                   T* bc, bool first, T* xa, T* d, T it) {
+  constexpr int W = DIM == 2 ? 7 : 15;
+  const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
+  const int bit0 = C > 1 ? 0 : DIM;
+  for (int I = threadIdx.x; I < Lc.nn; I += kBlock) {
+    int ci, cj, ck;
+    node_coords<DIM>(I, mc, ci, cj, ck);
+    T acc[C];
+#pragma unroll
+    for (int a = 0; a < C; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      const int* o = DIM == 2 ? c_off2[s] : c_off3[s];
+      const int fi = 2 * ci + o[0], fj = 2 * cj + o[1], fk = 2 * ck + o[2];
+      if (fi < 0 || fi >= mf || fj < 0 || fj >= mf || fk < 0 || fk >= mf) continue;
+      const int f = node_id<DIM>(fi, fj, fk, mf);
+      const T wgt = s == 0 ? T(1) : T(0.5);
+      const uint8_t ff = Lf.fixed[f];
+#pragma unroll
+      for (int a = 0; a < C; ++a)
+        if (!((ff >> (bit0 + a)) & 1)) acc[a] += wgt * rf[f * C + a];
+    }
+    const uint8_t fc = Lc.fixed[I];
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      if ((fc >> (bit0 + a)) & 1) acc[a] = T(0);
+      bc[I * C + a] = acc[a];
+    }
+    if (first) {
+      const T* Dg = C > 1 ? Lc.Ainv : Lc.Sinv;
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        T z = T(0);
+#pragma unroll
+        for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + I] * acc[k];
+        z *= it;
+        xa[I * C + a] = z;
+        d[I * C + a] = z;
+      }
+    }
+  }
+}
+
+template <int DIM, int C, typename T>
+__device__ inline void prolong(const LevelView<T>& Lf, const LevelView<T>& Lc, const T* xin,
+                               const T* xc, T* xout) {
+  for (int v = threadIdx.x; v < Lf.nn; v += kBlock) {
+    int p0, p1;
+    unsigned pm;
+    prolong_parents<DIM, C>(Lf, Lc, C > 1 ? 0 : DIM, v, p0, p1, pm);
+    const T wt = (pm >> (2 * C)) ? T(0.5) : T(1);
+#pragma unroll
+    for (int a = 0; a < C; ++a) {
+      T x = xin[v * C + a];
+      if ((pm >> a) & 1u) x += wt * xc[p0 * C + a];
+      if ((pm >> (C + a)) & 1u) x += wt * xc[p1 * C + a];
+      xout[v * C + a] = x;
+    }
+  }
+}
+
+}  // namespace tail
+
+template <int DIM, int C, typename T>
+__global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* __restrict__ b_t,
+                                                        T* __restrict__ x_t) {
+  extern __shared__ double tail_raw[];
+  T* lds = reinterpret_cast<T*>(tail_raw);
+  const int c = blockIdx.x;
+  const int nl = TD.nlev;  // levels t..t+nl-1; the last one is solved densely
+  // level i's LDS block at TD.off[i]: b, x0, x1, d, r (coarsest: b, x0), each
+  // nn_i * C values; bit i of `alt` set when level i's current iterate is x1
+  auto vec = [&](int i, int k) { return lds + TD.off[i] + k * TD.L[i].nn * C; };
+  unsigned alt = 0;
+  const int n0 = TD.L[0].nn * C;
+  for (int i = threadIdx.x; i < n0; i += kBlock) vec(0, 0)[i] = b_t[size_t(c) * n0 + i];
+  __syncthreads();
+  // descend
+  for (int i = 0; i + 1 < nl; ++i) {
+    const LevelView<T>& L = TD.L[i];
+    const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
+    if (i == 0) {
+      tail::first_step<C, T>(L, vec(0, 0), vec(0, 1), vec(0, 3), T(1.0 / theta));
+      __syncthreads();
+    }
+    int xi = 1;  // x0
+    double rho = 1.0 / sigma;
+    for (int j = 2; j <= TD.degree; ++j) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      tail::cheb<DIM, C, T>(L, vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3), T(rn * rho),
+                            T(2.0 * rn / delta));
+      __syncthreads();
+      rho = rn;
+      xi = 3 - xi;
+    }
+    if (xi == 2) alt |= 1u << i;
+    tail::residual<DIM, C, T>(L, vec(i, 0), vec(i, xi), vec(i, 4));
+    __syncthreads();
+    const bool first = i + 2 < nl;
+    tail::restrict_to<DIM, C, T>(L, TD.L[i + 1], vec(i, 4), vec(i + 1, 0), first, vec(i + 1, 1),
+                                 first ? vec(i + 1, 3) : nullptr,
+                                 first ? T(1.0 / TD.theta[i + 1]) : T(0));
+    __syncthreads();
+  }
+  // coarsest level: dense inverse
+  {
+    const int n = TD.L[nl - 1].nn * C;
+    const T* bb = vec(nl - 1, 0);
+    T* xx = vec(nl - 1, 1);
+    for (int r = threadIdx.x; r < n; r += kBlock) {
+      T acc = T(0);
+      const T* row = TD.Minv + size_t(r) * n;
+      for (int j = 0; j < n; ++j) acc += row[j] * bb[j];
+      xx[r] = acc;
+    }
+    __syncthreads();
+  }
+  // ascend: coarse-grid correction, then the post-smoothing steps
+  for (int i = nl - 2; i >= 0; --i) {
+    const LevelView<T>& L = TD.L[i];
+    const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
+    int xi = ((alt >> i) & 1u) ? 2 : 1;
+    const int xci = (i + 2 == nl) ? 1 : (((alt >> (i + 1)) & 1u) ? 2 : 1);
+    tail::prolong<DIM, C, T>(L, TD.L[i + 1], vec(i, xi), vec(i + 1, xci), vec(i, 3 - xi));
+    __syncthreads();
+    xi = 3 - xi;
+    double rho = 1.0 / sigma;
+    for (int j = 1; j <= TD.degree; ++j) {
+      double c1 = 0.0, c2 = 1.0 / theta, rn = rho;
+      if (j > 1) {
+        rn = 1.0 / (2.0 * sigma - rho);
+        c1 = rn * rho;
+        c2 = 2.0 * rn / delta;
+      }
+      tail::cheb<DIM, C, T>(L, vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3), T(c1), T(c2));
+      __syncthreads();
+      rho = rn;
+      xi = 3 - xi;
+    }
+    alt = (alt & ~(1u << i)) | (xi == 2 ? 1u << i : 0u);
+  }
+  const T* res = vec(0, ((alt & 1u) ? 2 : 1));
+  for (int i = threadIdx.x; i < n0; i += kBlock) x_t[size_t(c) * n0 + i] = res[i];
+}
+
 // coarsest level: x = M^{-1} b with the dense inverse, one workgroup per column
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const T* __restrict__ Minv,
@@ -910,6 +1153,28 @@ void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStre
                      Minv, b, x);
 }
 
+size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes) {
+  size_t n = 0;
+  for (int i = 0; i < nlev; ++i) n += size_t(level_nn[i]) * comps * (i + 1 < nlev ? 5 : 2);
+  return n * tbytes;
+}
+
+template <typename T>
+void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T* x, int nc,
+                        hipStream_t st) {
+  int nnl[kTailMaxLevels];
+  for (int i = 0; i < TD.nlev; ++i) nnl[i] = TD.L[i].nn;
+  const size_t lds = tail_lds_bytes(nnl, TD.nlev, comps, int(sizeof(T)));
+  const dim3 g(nc);
+  if (dim == 2) {
+    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T>), g, dim3(kBlock), lds, st, TD, b, x);
+    else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T>), g, dim3(kBlock), lds, st, TD, b, x);
+  } else {
+    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<3, 1, T>), g, dim3(kBlock), lds, st, TD, b, x);
+    else hipLaunchKernelGGL((k_vcycle_tail<3, 3, T>), g, dim3(kBlock), lds, st, TD, b, x);
+  }
+}
+
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
                    T* t, T* xa, T* d, double inv_theta, int nc, int wpc, hipStream_t st) {
@@ -978,6 +1243,7 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
   template void launch_prolong<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,      \
                                   const T*, const T*, T*, int, int, hipStream_t);                 \
   template void launch_coarse_solve<T>(int, const T*, const T*, T*, int, hipStream_t);           \
+  template void launch_vcycle_tail<T>(int, int, const TailDev<T>&, const T*, T*, int, hipStream_t); \
   template void launch_pstage<T>(int, const LevelView<T>&, const T*, bool, const T*, const T*,   \
                                  T*, T*, T*, double, int, int, hipStream_t);                      \
   template void launch_update<T>(int, int, const ColDesc*, const T*, const T*, double, int,      \

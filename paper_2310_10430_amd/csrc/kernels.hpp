@@ -76,6 +76,25 @@ void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<
                     const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStream_t st);
+
+// The coarse end of a V-cycle (levels t..last) in one launch, one workgroup
+// per column with the vectors in LDS (k_vcycle_tail).  L[0] is level t, whose
+// right-hand side b (no first Chebyshev step yet) is read and whose V-cycle
+// result is written to x; L[nlev-1] is the densely solved coarsest level.
+constexpr int kTailMaxLevels = 8;
+constexpr size_t kTailMaxLds = 64 * 1024;
+template <typename T>
+struct TailDev {
+  int nlev, degree;
+  LevelView<T> L[kTailMaxLevels];
+  double theta[kTailMaxLevels], delta[kTailMaxLevels], sigma[kTailMaxLevels];
+  int off[kTailMaxLevels];  // LDS offset (in values) of each level's vectors
+  const T* Minv;
+};
+size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes);
+template <typename T>
+void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T* x, int nc,
+                        hipStream_t st);
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
                    T* t, T* xa, T* d, double inv_theta, int nc, int wpc, hipStream_t st);

@@ -51,6 +51,9 @@ struct Prec {
   T* coarseS = nullptr;
   Field<T> fa, fs;
   T* rp = nullptr;
+  // fused coarse end of the V-cycles (k_vcycle_tail): first level, -1 if none
+  int tailA = -1, tailS = -1;
+  TailDev<T> tdA{}, tdS{};
 };
 
 struct ChebCoef {
@@ -176,6 +179,42 @@ struct Bump {
   }
 };
 
+// The coarsest levels whose V-cycle vectors fit in kTailMaxLds of LDS run as
+// one fused launch; level 0 never does (its steps are fused with the residual
+// and the update).
+template <typename T>
+void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
+  const int last = h->nlev - 1, C = is_A ? h->dim : 1;
+  int& t = is_A ? p.tailA : p.tailS;
+  TailDev<T>& td = is_A ? p.tdA : p.tdS;
+  t = -1;
+  for (int l = 1; l < last; ++l) {
+    const int n = last - l + 1;
+    if (n > kTailMaxLevels) continue;
+    int nnl[kTailMaxLevels];
+    for (int i = 0; i < n; ++i) nnl[i] = h->P.levels[l + i].nn;
+    if (tail_lds_bytes(nnl, n, C, int(sizeof(T))) > kTailMaxLds) continue;
+    t = l;
+    break;
+  }
+  if (t < 0) return;
+  td.nlev = last - t + 1;
+  td.degree = h->opt.cheb_degree;
+  for (int i = 0; i < td.nlev; ++i) {
+    td.L[i] = p.L[t + i];
+    const ChebCoef& cc = is_A ? h->chA[t + i] : h->chS[t + i];
+    td.theta[i] = cc.theta;
+    td.delta[i] = cc.delta;
+    td.sigma[i] = cc.sigma;
+  }
+  td.Minv = is_A ? p.coarseA : p.coarseS;
+  int off = 0;
+  for (int i = 0; i < td.nlev; ++i) {
+    td.off[i] = off;
+    off += h->P.levels[t + i].nn * C * (i + 1 < td.nlev ? 5 : 2);
+  }
+}
+
 template <typename T>
 void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
   const int dim = h->dim;
@@ -222,6 +261,8 @@ void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
     }
   }
   p.rp = b.take<T>(size_t(nc) * h->nn);
+  plan_tail(h, p, true);
+  plan_tail(h, p, false);
 }
 
 void plan(biot_handle* h, char* base) {
@@ -501,6 +542,13 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   const int wpc = h->opt.wg_per_cu;
   const int tb = int(sizeof(T));
   hipStream_t st = h->st;
+  const int tail = is_A ? p.tailA : p.tailS;
+  if (l == tail) {
+    launch_vcycle_tail<T>(h->dim, C, is_A ? p.tdA : p.tdS, f.b[l], f.x0[l], nc, st);
+    LAUNCHCHK(h);
+    *out = f.x0[l];
+    return BIOT_OK;
+  }
   if (l == last) {
     launch_coarse_solve<T>(h->P.levels[l].nn * C, is_A ? p.coarseA : p.coarseS, f.b[l], f.x0[l], nc, st);
     LAUNCHCHK(h);
@@ -538,7 +586,8 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
   }
-  const bool coarse_last = (l + 1 == last);
+  // no first Chebyshev step on the coarsest level or where the fused tail starts
+  const bool coarse_last = (l + 1 == last) || (l + 1 == tail);
   const ChebCoef* cn = coarse_last ? nullptr : (is_A ? &h->chA[l + 1] : &h->chS[l + 1]);
   launch_restrict<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, f.r[l], f.b[l + 1],
                      coarse_last ? nullptr : f.x0[l + 1], coarse_last ? nullptr : f.d[l + 1],
