@@ -27,6 +27,11 @@
 
 #include "kernels.hpp"
 
+// waves per SIMD the 2D Chebyshev kernels are compiled for (register budget)
+#ifndef BIOT_CHEB_MIN_WAVES
+#define BIOT_CHEB_MIN_WAVES 2
+#endif
+
 namespace biot {
 namespace {
 
@@ -111,19 +116,24 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      T* __restrict__ xa, T* __restrict__ d,
                                                      double inv_theta,
                                                      double* __restrict__ partials, int pstride) {
+  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
+  constexpr int NQ = DIM == 2 ? 2 : 1;
   constexpr int D1 = DIM + 1;
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = DIM == 2;
   constexpr int RS = STAT ? W : 1;
+  constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   __shared__ double lds[4 * 8];
   const int nn = L.nn;
   for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
     const int v = nblk * kBlock + threadIdx.x;
     const bool active = v < nn;
     const int vv = active ? v : nn - 1;
-    int nb[W];
+    int nb[RS];
+    if constexpr (STAT) {
 #pragma unroll
-    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + vv];
+      for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + vv];
+    }
     double rA[RS][DIM * DIM], rB[RS][DIM], rBt[RS][DIM], rS[RS], rCb[RS];
     if constexpr (STAT) {
 #pragma unroll
@@ -145,14 +155,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
 #pragma unroll
     for (int e = 0; e < DIM * DIM; ++e) Di[e] = xa ? L.Ainv[size_t(e) * nn + vv] : 0.0;
 #pragma unroll 1
-    for (int c = cbeg; c < cend; c += 2) {
-      const bool two = c + 1 < cend;
-      const int cc[2] = {c, two ? c + 1 : c};
-      const double* xc[2];
-      const double* xp[2];
-      double coef[2], au[2][DIM], ap[2], bp[2], cu[2][DIM];
+    for (int c = cbeg; c < cend; c += NQ) {
+      const bool two = NQ > 1 && c + 1 < cend;
+      int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      const double* xc[NQ];
+      const double* xp[NQ];
+      double coef[NQ], au[NQ][DIM], ap[NQ], bp[NQ], cu[NQ][DIM];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
         xc[q] = cols[cc[q]].xcur;
         xp[q] = cols[cc[q]].xprev;
         coef[q] = cols[cc[q]].coef;
@@ -169,9 +181,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
           bp[q] = g;
         }
       }
-#pragma unroll
+#pragma unroll SU
       for (int s = 0; s < W; ++s) {
-        const int w = nb[s];
+        const int w = STAT ? nb[s] : L.nbr[size_t(s) * nn + vv];
         double Ab[DIM * DIM], Bb[DIM], Btb[DIM], Sv, Cbv;
         if constexpr (STAT) {
 #pragma unroll
@@ -195,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
           Cbv = F.Cb[size_t(s) * nn + vv];
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           double xw[D1], xpw[D1];
 #pragma unroll
           for (int k = 0; k < D1; ++k) {
@@ -232,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         if (!active || (q == 1 && !two)) break;
         const size_t cu = size_t(cc[q]) * nn * DIM;
         if (ru) {
@@ -253,9 +265,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
         }
       }
       if (partials) {
-        double qv[8];
+        double qv[4 * NQ];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           double su = 0.0, sb = 0.0;
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
@@ -268,10 +280,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
           qv[4 * q + 2] = active ? sb : 0.0;
           qv[4 * q + 3] = active ? bp[q] * bp[q] : 0.0;
         }
-        block_sum<8>(qv, lds);
+        block_sum<4 * NQ>(qv, lds);
         if (threadIdx.x == 0)
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
+          for (int q = 0; q < NQ; ++q) {
             if (q == 1 && !two) break;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -316,15 +328,18 @@ __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T
 // descriptors.  FINE only makes the level-0 launches a distinct symbol.
 // ---------------------------------------------------------------------------
 template <int DIM, int C, bool UPD, bool FINE, typename T>
-__global__ __launch_bounds__(kBlock, DIM == 2 ? 3 : 1) void k_cheb(LevelView<T> L, int isA,
+__global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_cheb(LevelView<T> L, int isA,
                                                  const T* __restrict__ b,
                                                  const T* __restrict__ xin,
                                                  T* __restrict__ xout, T* __restrict__ d, int nc,
                                                  T c1, T c2, const ColDesc* __restrict__ cols,
                                                  const T* __restrict__ zu, double omega) {
+  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
+  constexpr int NQ = DIM == 2 ? 2 : 1;
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = W * C * C <= 64;
   constexpr int RS = STAT ? W : 1;
+  constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
   for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
     const int v = nblk * kBlock + threadIdx.x;
@@ -333,9 +348,11 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? 3 : 1) void k_cheb(LevelView<T> 
     const T* K = C > 1 ? L.A : L.S;
     const T* Dg = C > 1 ? L.Ainv : L.Sinv;
     const size_t stride = size_t(nn) * C;
-    int nb[W];
+    int nb[RS];
+    if constexpr (STAT) {
 #pragma unroll
-    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+      for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+    }
     T kr[RS][C * C];
     if constexpr (STAT) {
 #pragma unroll
@@ -347,19 +364,23 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? 3 : 1) void k_cheb(LevelView<T> 
 #pragma unroll
     for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
 #pragma unroll 1
-    for (int c = cbeg; c < cend; c += 2) {
-      const bool two = c + 1 < cend;
-      const int cc[2] = {c, two ? c + 1 : c};
-      // column base pointers; offsets within a column fit in 32 bits
-      const T* xq[2] = {xin + size_t(cc[0]) * stride, xin + size_t(cc[1]) * stride};
-      T acc[2][C], xs[2][C];
+    for (int c = cbeg; c < cend; c += NQ) {
+      const bool two = NQ > 1 && c + 1 < cend;
+      int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      // column base pointers; offsets within a column fit in 32 bits
+      const T* xq[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) xq[q] = xin + size_t(cc[q]) * stride;
+      T acc[NQ][C], xs[NQ][C];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + v * C + a];
-#pragma unroll
+#pragma unroll SU
       for (int s = 0; s < W; ++s) {
-        const int w = nb[s];
+        const int w = STAT ? nb[s] : L.nbr[size_t(s) * nn + v];
         T blk[C * C];
 #pragma unroll
         for (int e = 0; e < C * C; ++e) {
@@ -367,7 +388,7 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? 3 : 1) void k_cheb(LevelView<T> 
           else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NQ; ++q) {
           T xw[C];
 #pragma unroll
           for (int k = 0; k < C; ++k) xw[k] = xq[q][w * C + k];
@@ -384,7 +405,7 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? 3 : 1) void k_cheb(LevelView<T> 
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         if (q == 1 && !two) break;
         const size_t base = size_t(cc[q]) * stride + size_t(v) * C;
         T xn[C];
@@ -456,18 +477,23 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
                                                            const T* __restrict__ b,
                                                            const T* __restrict__ x,
                                                            T* __restrict__ r, int nc) {
+  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
+  constexpr int NQ = DIM == 2 ? 2 : 1;
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = W * C * C <= 64;
   constexpr int RS = STAT ? W : 1;
+  constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
   for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
     const int v = nblk * kBlock + threadIdx.x;
     if (v >= nn) return;
     const T* K = isA ? L.A : L.S;
     const size_t stride = size_t(nn) * C;
-    int nb[W];
+    int nb[RS];
+    if constexpr (STAT) {
 #pragma unroll
-    for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+      for (int s = 0; s < W; ++s) nb[s] = L.nbr[size_t(s) * nn + v];
+    }
     T kr[RS][C * C];
     if constexpr (STAT) {
 #pragma unroll
@@ -476,17 +502,19 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
         for (int e = 0; e < C * C; ++e) kr[s][e] = K[(size_t(s) * C * C + e) * nn + v];
     }
 #pragma unroll 1
-    for (int c = cbeg; c < cend; c += 2) {
-      const bool two = c + 1 < cend;
-      const int cc[2] = {c, two ? c + 1 : c};
-      T acc[2][C];
+    for (int c = cbeg; c < cend; c += NQ) {
+      const bool two = NQ > 1 && c + 1 < cend;
+      int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      T acc[NQ][C];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int a = 0; a < C; ++a) acc[q][a] = b[size_t(cc[q]) * stride + size_t(v) * C + a];
-#pragma unroll
+#pragma unroll SU
       for (int s = 0; s < W; ++s) {
-        const int w = nb[s];
+        const int w = STAT ? nb[s] : L.nbr[size_t(s) * nn + v];
         T blk[C * C];
 #pragma unroll
         for (int e = 0; e < C * C; ++e) {
@@ -494,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
           else blk[e] = K[(size_t(s) * C * C + e) * nn + v];
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < NQ; ++q) {
 #pragma unroll
           for (int a = 0; a < C; ++a) {
             T s2 = T(0);
@@ -505,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         if (q == 1 && !two) break;
 #pragma unroll
         for (int a = 0; a < C; ++a) r[size_t(cc[q]) * stride + size_t(v) * C + a] = acc[q][a];
@@ -834,6 +862,8 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
                                                    const T* __restrict__ rp,
                                                    T* __restrict__ t_out, T* __restrict__ xa,
                                                    T* __restrict__ d, T inv_theta, int nc) {
+  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
+  constexpr int NQ = DIM == 2 ? 2 : 1;
   constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
   for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
@@ -849,18 +879,20 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
     }
     const T si = L.Sinv[v];
 #pragma unroll 1
-    for (int c = cbeg; c < cend; c += 2) {
-      const bool two = c + 1 < cend;
-      const int cc[2] = {c, two ? c + 1 : c};
-      T acc[2];
+    for (int c = cbeg; c < cend; c += NQ) {
+      const bool two = NQ > 1 && c + 1 < cend;
+      int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
+      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      T acc[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
       if (p1) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
           const int w = nb[s];
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
+          for (int q = 0; q < NQ; ++q) {
             const size_t base = size_t(cc[q]) * nn * DIM + size_t(w) * DIM;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) acc[q] += bt[s][k] * zu[base + k];
@@ -868,7 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         if (q == 1 && !two) break;
         const size_t idx = size_t(cc[q]) * nn + v;
         t_out[idx] = acc[q];

@@ -143,6 +143,24 @@ def test_small_terzaghi_solve_reaches_backward_euler(schedule, depth):
     assert err["u"] < 1e-8 and err["p"] < 1e-8, (err, st)
 
 
+@pytest.mark.parametrize("n,steps,schedule,precision", [(6, 8, "wavefront", "fp64"),
+                                                         (8, 6, "jacobi", "fp64"),
+                                                         (8, 6, "wavefront", "mixed")])
+def test_3d_solve_reaches_backward_euler(n, steps, schedule, precision):
+    # Kuhn tetrahedra on the unit cube, heterogeneous K, 15-slot node blocks
+    pb = W.terzaghi_problem(n, steps, dim=3)
+    pb.perm = pb.perm * np.exp(0.5 * np.random.default_rng(5).standard_normal(pb.n_elems))
+    orc = seq.BiotOracle(pb)
+    Xs = orc.solve_sequential()
+    s = BiotSolver(pb, schedule=schedule, depth=4, omega=0.6, precision=precision, max_batch=5)
+    st = s.solve_to_tol(1e-11, max_sweeps=600, check_every=4)
+    Xg = _fm(s.trajectory().cpu().numpy())
+    s.close()
+    assert st["converged"]
+    err = seq.relative_field_errors(Xg, Xs, orc.n_nodes, orc.dim)
+    assert err["u"] < 1e-8 and err["p"] < 1e-8, (err, st)
+
+
 def test_sweeps_are_deterministic_and_resumable():
     pb = W.heterogeneous_problem(16, 8)
     s = BiotSolver(pb, omega=0.6)
