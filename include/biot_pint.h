@@ -172,6 +172,8 @@ typedef struct {
   double lmax_A[16];         /* spectral bounds used by the smoothers (with safety) */
   double lmax_S[16];
   uint64_t workspace_bytes;
+  int32_t n_samples;         /* samples of a batch handle (1 otherwise)             */
+  int32_t nodes_per_sample;  /* node stride of a sample in the trajectory layout    */
 } biot_info_t;
 
 /* Fills *opt with the defaults listed above. */
@@ -182,6 +184,23 @@ int biot_default_options(biot_options* opt);
  * *out is a new handle that must be released with biot_destroy(). */
 int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_load* load,
                 double dt, int32_t n_steps, const biot_options* opt, biot_handle** out);
+
+/* A batch of n_samples independent problems on the same structured mesh, each
+ * with its own materials, load, dt and number of steps, solved together: the
+ * samples are stored as disconnected copies of the grid side by side (each
+ * padded to a multiple of 256 nodes with inert prescribed nodes, so that no
+ * workgroup's node block straddles two samples) and every launch of the sweep
+ * works on all of them.  The handle's step count is the largest n_steps;
+ * shorter samples keep stepping past their end (those steps are computed,
+ * never reported).  Convergence is the worst sample's relative residual over
+ * its own steps.  The load multipliers coef of all samples must agree on their
+ * common steps.  Multigrid spectral bounds are the maximum over the samples.
+ * mats, loads, dts and n_steps have n_samples entries.  Trajectory calls see
+ * [n_steps+1][n_samples * nodes_per_sample][dim+1]; biot_get_sample_trajectory
+ * extracts one sample.  The adjoint needs n_samples = 1. */
+int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_materials* mats,
+                      const biot_load* loads, const double* dts, const int32_t* n_steps,
+                      const biot_options* opt, biot_handle** out);
 
 /* Device bytes the handle needs (operators, two trajectories, work vectors). */
 int biot_workspace_size(const biot_handle* h, uint64_t* bytes);
@@ -203,7 +222,7 @@ int biot_sweep(biot_handle* h, int32_t n_sweeps);
 /* Space-time residual of the current trajectory: for every step n >= 1 the
  * squared norms [||r_u||^2, ||r_p||^2, ||b_u||^2, ||b_p||^2] of
  * r = A' X^{n-1} + f^n - AA X^n and b = A' X^{n-1} + f^n, written to
- * norms[n_steps][4] (host).  Synchronizes the stream. */
+ * norms[n_steps][n_samples][4] (host).  Synchronizes the stream. */
 int biot_residual_norms(biot_handle* h, double* norms);
 
 /* Sweeps until max(rel_resid_u, rel_resid_p) <= rtol or max_sweeps.  JACOBI
@@ -218,6 +237,11 @@ int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t c
 /* Copies steps n0..n1-1 of the trajectory to dst ([n1-n0][n_nodes][dim+1]),
  * a device pointer if dst_on_device else host (host copies synchronize). */
 int biot_get_trajectory(biot_handle* h, int32_t n0, int32_t n1, double* dst, int32_t dst_on_device);
+
+/* Steps n0..n1-1 (n1 <= that sample's n_steps + 1) of one sample's trajectory,
+ * [n1-n0][n_nodes][dim+1] (its grid nodes only), to host or device memory. */
+int biot_get_sample_trajectory(biot_handle* h, int32_t sample, int32_t n0, int32_t n1, double* dst,
+                               int32_t dst_on_device);
 
 /* Overwrites steps n0..n1-1 of the trajectory (warm start / resume). */
 int biot_set_trajectory(biot_handle* h, int32_t n0, int32_t n1, const double* src,

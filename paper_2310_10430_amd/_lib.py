@@ -65,7 +65,8 @@ class Info(C.Structure):
                 ("n_levels", C.c_int32), ("level_cells", C.c_int32 * 16),
                 ("level_nodes", C.c_int32 * 16), ("slots", C.c_int32),
                 ("lmax_A", C.c_double * 16), ("lmax_S", C.c_double * 16),
-                ("workspace_bytes", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("n_samples", C.c_int32),
+                ("nodes_per_sample", C.c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -73,6 +74,9 @@ SIGNATURES = {
     "biot_default_options": (C.c_int, [C.POINTER(Options)]),
     "biot_create": (C.c_int, [C.POINTER(Mesh), C.POINTER(Materials), C.POINTER(Load), C.c_double,
                               C.c_int32, C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "biot_create_batch": (C.c_int, [C.POINTER(Mesh), C.c_int32, C.POINTER(Materials),
+                                    C.POINTER(Load), _dp, _ip, C.POINTER(Options),
+                                    C.POINTER(C.c_void_p)]),
     "biot_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "biot_bind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]),
     "biot_reset": (C.c_int, [C.c_void_p]),
@@ -81,6 +85,8 @@ SIGNATURES = {
     "biot_solve_to_tol": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_int32, C.POINTER(Stats)]),
     "biot_get_trajectory": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
     "biot_set_trajectory": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
+    "biot_get_sample_trajectory": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                             C.c_void_p, C.c_int32]),
     "biot_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "biot_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "biot_get_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),

@@ -304,13 +304,19 @@ template <int DIM, int C, typename T>
 __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T>& Lc, int bit0,
                                        int f, int& p0, int& p1, unsigned& mask) {
   const int mf = Lf.n_cells + 1, mc = Lc.n_cells + 1;
+  const int cp = f / Lf.nn1, lf = f - cp * Lf.nn1;  // copy and node within it
+  if (lf >= Lf.nreal) {  // padding node: no parents
+    p0 = p1 = cp * Lc.nn1;
+    mask = 0u;
+    return;
+  }
   int i, j, k;
-  node_coords<DIM>(f, mf, i, j, k);
+  node_coords<DIM>(lf, mf, i, j, k);
   const int ai = i >> 1, aj = j >> 1, ak = k >> 1;
   const int oi = i & 1, oj = j & 1, ok = k & 1;
   const bool two = (oi | oj | ok) != 0;
-  p0 = node_id<DIM>(ai, aj, ak, mc);
-  p1 = two ? node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
+  p0 = cp * Lc.nn1 + node_id<DIM>(ai, aj, ak, mc);
+  p1 = two ? cp * Lc.nn1 + node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
   const unsigned ff = Lf.fixed[f], f0 = Lc.fixed[p0], f1 = Lc.fixed[p1];
   mask = two ? (1u << 2 * C) : 0u;
 #pragma unroll
@@ -554,8 +560,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
   if (I >= Lc.nn) return;
   const int c = blockIdx.x;
   const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
-  int ci, cj, ck;
-  node_coords<DIM>(I, mc, ci, cj, ck);
+  const int cp = I / Lc.nn1, lI = I - cp * Lc.nn1;  // copy and node within it
+  const bool real = lI < Lc.nreal;
+  int ci = 0, cj = 0, ck = 0;
+  if (real) node_coords<DIM>(lI, mc, ci, cj, ck);
   const uint8_t fc = Lc.fixed[I];
   const int bit0 = isA ? 0 : DIM;
   const size_t sf = size_t(Lf.nn) * C, sc = size_t(Lc.nn) * C;
@@ -566,8 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
   for (int s = 0; s < W; ++s) {
     const int* o = DIM == 2 ? c_off2[s] : c_off3[s];
     const int fi = 2 * ci + o[0], fj = 2 * cj + o[1], fk = 2 * ck + o[2];
-    if (fi < 0 || fi >= mf || fj < 0 || fj >= mf || fk < 0 || fk >= mf) continue;
-    const int f = node_id<DIM>(fi, fj, fk, mf);
+    if (!real || fi < 0 || fi >= mf || fj < 0 || fj >= mf || fk < 0 || fk >= mf) continue;
+    const int f = cp * Lf.nn1 + node_id<DIM>(fi, fj, fk, mf);
     const T wgt = s == 0 ? T(1) : T(0.5);
     const uint8_t ff = Lf.fixed[f];
 #pragma unroll
@@ -604,16 +612,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
 // ---------------------------------------------------------------------------
 namespace tail {
 
+// All routines work on one copy of the grid (one sample of a batch): `base`
+// is the copy's first node in the level's arrays; LDS vectors hold only the
+// copy's grid nodes (local numbering).
+
 // x = d = inv_theta D^{-1} b
 template <int C, typename T>
-__device__ inline void first_step(const LevelView<T>& L, const T* b, T* x, T* d, T it) {
+__device__ inline void first_step(const LevelView<T>& L, int base, const T* b, T* x, T* d, T it) {
   const T* Dg = C > 1 ? L.Ainv : L.Sinv;
-  for (int v = threadIdx.x; v < L.nn; v += kBlock) {
+  for (int v = threadIdx.x; v < L.nreal; v += kBlock) {
+    const int g = base + v;
 #pragma unroll
     for (int a = 0; a < C; ++a) {
       T z = T(0);
 #pragma unroll
-      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + v] * b[v * C + k];
+      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + g] * b[v * C + k];
       z *= it;
       x[v * C + a] = z;
       d[v * C + a] = z;
@@ -623,19 +636,20 @@ __device__ inline void first_step(const LevelView<T>& L, const T* b, T* x, T* d,
 
 // one Chebyshev step xout = xin + d, d <- c1 d + c2 D^{-1}(b - K xin)
 template <int DIM, int C, typename T>
-__device__ inline void cheb(const LevelView<T>& L, const T* b, const T* xin, T* xout, T* d, T c1,
-                            T c2) {
+__device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T* xin, T* xout,
+                            T* d, T c1, T c2) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const T* K = C > 1 ? L.A : L.S;
   const T* Dg = C > 1 ? L.Ainv : L.Sinv;
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < nn; v += kBlock) {
+  for (int v = threadIdx.x; v < L.nreal; v += kBlock) {
+    const int g = base + v;
     T acc[C], xs[C];
 #pragma unroll
     for (int a = 0; a < C; ++a) acc[a] = b[v * C + a];
 #pragma unroll
     for (int s = 0; s < W; ++s) {
-      const int w = L.nbr[size_t(s) * nn + v];
+      const int w = L.nbr[size_t(s) * nn + g] - base;
       T xw[C];
 #pragma unroll
       for (int k = 0; k < C; ++k) xw[k] = xin[w * C + k];
@@ -646,7 +660,7 @@ __device__ inline void cheb(const LevelView<T>& L, const T* b, const T* xin, T* 
       for (int a = 0; a < C; ++a) {
         T s2 = T(0);
 #pragma unroll
-        for (int k = 0; k < C; ++k) s2 += K[(size_t(s) * C * C + a * C + k) * nn + v] * xw[k];
+        for (int k = 0; k < C; ++k) s2 += K[(size_t(s) * C * C + a * C + k) * nn + g] * xw[k];
         acc[a] -= s2;
       }
     }
@@ -654,7 +668,7 @@ __device__ inline void cheb(const LevelView<T>& L, const T* b, const T* xin, T* 
     for (int a = 0; a < C; ++a) {
       T z = T(0);
 #pragma unroll
-      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * nn + v] * acc[k];
+      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * nn + g] * acc[k];
       const T dn = (c1 != T(0) ? c1 * d[v * C + a] : T(0)) + c2 * z;
       d[v * C + a] = dn;
       xout[v * C + a] = xs[a] + dn;
@@ -663,22 +677,23 @@ __device__ inline void cheb(const LevelView<T>& L, const T* b, const T* xin, T* 
 }
 
 template <int DIM, int C, typename T>
-__device__ inline void residual(const LevelView<T>& L, const T* b, const T* x, T* r) {
+__device__ inline void residual(const LevelView<T>& L, int base, const T* b, const T* x, T* r) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const T* K = C > 1 ? L.A : L.S;
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < nn; v += kBlock) {
+  for (int v = threadIdx.x; v < L.nreal; v += kBlock) {
+    const int g = base + v;
     T acc[C];
 #pragma unroll
     for (int a = 0; a < C; ++a) acc[a] = b[v * C + a];
 #pragma unroll
     for (int s = 0; s < W; ++s) {
-      const int w = L.nbr[size_t(s) * nn + v];
+      const int w = L.nbr[size_t(s) * nn + g] - base;
 #pragma unroll
       for (int a = 0; a < C; ++a) {
         T s2 = T(0);
 #pragma unroll
-        for (int k = 0; k < C; ++k) s2 += K[(size_t(s) * C * C + a * C + k) * nn + v] * x[w * C + k];
+        for (int k = 0; k < C; ++k) s2 += K[(size_t(s) * C * C + a * C + k) * nn + g] * x[w * C + k];
         acc[a] -= s2;
       }
     }
@@ -690,12 +705,12 @@ __device__ inline void residual(const LevelView<T>& L, const T* b, const T* x, T
 // bc = P' rf (masked); with `first`, also the first Chebyshev step of the
 // coarse level (x = d = it D^{-1} bc)
 template <int DIM, int C, typename T>
-__device__ inline void restrict_to(const LevelView<T>& Lf, const LevelView<T>& Lc, const T* rf,
-                                   T* bc, bool first, T* xa, T* d, T it) {
+__device__ inline void restrict_to(const LevelView<T>& Lf, int basef, const LevelView<T>& Lc,
+                                   int basec, const T* rf, T* bc, bool first, T* xa, T* d, T it) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
   const int bit0 = C > 1 ? 0 : DIM;
-  for (int I = threadIdx.x; I < Lc.nn; I += kBlock) {
+  for (int I = threadIdx.x; I < Lc.nreal; I += kBlock) {
     int ci, cj, ck;
     node_coords<DIM>(I, mc, ci, cj, ck);
     T acc[C];
@@ -708,12 +723,12 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, const LevelView<T>& L
       if (fi < 0 || fi >= mf || fj < 0 || fj >= mf || fk < 0 || fk >= mf) continue;
       const int f = node_id<DIM>(fi, fj, fk, mf);
       const T wgt = s == 0 ? T(1) : T(0.5);
-      const uint8_t ff = Lf.fixed[f];
+      const uint8_t ff = Lf.fixed[basef + f];
 #pragma unroll
       for (int a = 0; a < C; ++a)
         if (!((ff >> (bit0 + a)) & 1)) acc[a] += wgt * rf[f * C + a];
     }
-    const uint8_t fc = Lc.fixed[I];
+    const uint8_t fc = Lc.fixed[basec + I];
 #pragma unroll
     for (int a = 0; a < C; ++a) {
       if ((fc >> (bit0 + a)) & 1) acc[a] = T(0);
@@ -725,7 +740,7 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, const LevelView<T>& L
       for (int a = 0; a < C; ++a) {
         T z = T(0);
 #pragma unroll
-        for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + I] * acc[k];
+        for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + basec + I] * acc[k];
         z *= it;
         xa[I * C + a] = z;
         d[I * C + a] = z;
@@ -735,12 +750,14 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, const LevelView<T>& L
 }
 
 template <int DIM, int C, typename T>
-__device__ inline void prolong(const LevelView<T>& Lf, const LevelView<T>& Lc, const T* xin,
-                               const T* xc, T* xout) {
-  for (int v = threadIdx.x; v < Lf.nn; v += kBlock) {
+__device__ inline void prolong(const LevelView<T>& Lf, int basef, const LevelView<T>& Lc,
+                               int basec, const T* xin, const T* xc, T* xout) {
+  for (int v = threadIdx.x; v < Lf.nreal; v += kBlock) {
     int p0, p1;
     unsigned pm;
-    prolong_parents<DIM, C>(Lf, Lc, C > 1 ? 0 : DIM, v, p0, p1, pm);
+    prolong_parents<DIM, C>(Lf, Lc, C > 1 ? 0 : DIM, basef + v, p0, p1, pm);
+    p0 -= basec;
+    p1 -= basec;
     const T wt = (pm >> (2 * C)) ? T(0.5) : T(1);
 #pragma unroll
     for (int a = 0; a < C; ++a) {
@@ -754,55 +771,60 @@ __device__ inline void prolong(const LevelView<T>& Lf, const LevelView<T>& Lc, c
 
 }  // namespace tail
 
+// one workgroup per (column, copy)
 template <int DIM, int C, typename T>
 __global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* __restrict__ b_t,
                                                         T* __restrict__ x_t) {
   extern __shared__ double tail_raw[];
   T* lds = reinterpret_cast<T*>(tail_raw);
-  const int c = blockIdx.x;
+  const int copies = TD.L[0].copies;
+  const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
   const int nl = TD.nlev;  // levels t..t+nl-1; the last one is solved densely
   // level i's LDS block at TD.off[i]: b, x0, x1, d, r (coarsest: b, x0), each
-  // nn_i * C values; bit i of `alt` set when level i's current iterate is x1
-  auto vec = [&](int i, int k) { return lds + TD.off[i] + k * TD.L[i].nn * C; };
+  // nreal_i * C values; bit i of `alt` set when level i's current iterate is x1
+  auto vec = [&](int i, int k) { return lds + TD.off[i] + k * TD.L[i].nreal * C; };
+  auto base = [&](int i) { return cp * TD.L[i].nn1; };
   unsigned alt = 0;
-  const int n0 = TD.L[0].nn * C;
-  for (int i = threadIdx.x; i < n0; i += kBlock) vec(0, 0)[i] = b_t[size_t(c) * n0 + i];
+  const int n0 = TD.L[0].nreal * C;
+  const size_t g0 = (size_t(c) * TD.L[0].nn + base(0)) * C;
+  for (int i = threadIdx.x; i < n0; i += kBlock) vec(0, 0)[i] = b_t[g0 + i];
   __syncthreads();
   // descend
   for (int i = 0; i + 1 < nl; ++i) {
     const LevelView<T>& L = TD.L[i];
     const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
     if (i == 0) {
-      tail::first_step<C, T>(L, vec(0, 0), vec(0, 1), vec(0, 3), T(1.0 / theta));
+      tail::first_step<C, T>(L, base(0), vec(0, 0), vec(0, 1), vec(0, 3), T(1.0 / theta));
       __syncthreads();
     }
     int xi = 1;  // x0
     double rho = 1.0 / sigma;
     for (int j = 2; j <= TD.degree; ++j) {
       const double rn = 1.0 / (2.0 * sigma - rho);
-      tail::cheb<DIM, C, T>(L, vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3), T(rn * rho),
-                            T(2.0 * rn / delta));
+      tail::cheb<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3),
+                            T(rn * rho), T(2.0 * rn / delta));
       __syncthreads();
       rho = rn;
       xi = 3 - xi;
     }
     if (xi == 2) alt |= 1u << i;
-    tail::residual<DIM, C, T>(L, vec(i, 0), vec(i, xi), vec(i, 4));
+    tail::residual<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 4));
     __syncthreads();
     const bool first = i + 2 < nl;
-    tail::restrict_to<DIM, C, T>(L, TD.L[i + 1], vec(i, 4), vec(i + 1, 0), first, vec(i + 1, 1),
-                                 first ? vec(i + 1, 3) : nullptr,
+    tail::restrict_to<DIM, C, T>(L, base(i), TD.L[i + 1], base(i + 1), vec(i, 4), vec(i + 1, 0),
+                                 first, vec(i + 1, 1), first ? vec(i + 1, 3) : nullptr,
                                  first ? T(1.0 / TD.theta[i + 1]) : T(0));
     __syncthreads();
   }
-  // coarsest level: dense inverse
+  // coarsest level: dense inverse of this copy
   {
-    const int n = TD.L[nl - 1].nn * C;
+    const int n = TD.L[nl - 1].nreal * C;
     const T* bb = vec(nl - 1, 0);
     T* xx = vec(nl - 1, 1);
+    const T* M = TD.Minv + size_t(cp) * n * n;
     for (int r = threadIdx.x; r < n; r += kBlock) {
       T acc = T(0);
-      const T* row = TD.Minv + size_t(r) * n;
+      const T* row = M + size_t(r) * n;
       for (int j = 0; j < n; ++j) acc += row[j] * bb[j];
       xx[r] = acc;
     }
@@ -814,7 +836,8 @@ __global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* 
     const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
     int xi = ((alt >> i) & 1u) ? 2 : 1;
     const int xci = (i + 2 == nl) ? 1 : (((alt >> (i + 1)) & 1u) ? 2 : 1);
-    tail::prolong<DIM, C, T>(L, TD.L[i + 1], vec(i, xi), vec(i + 1, xci), vec(i, 3 - xi));
+    tail::prolong<DIM, C, T>(L, base(i), TD.L[i + 1], base(i + 1), vec(i, xi), vec(i + 1, xci),
+                             vec(i, 3 - xi));
     __syncthreads();
     xi = 3 - xi;
     double rho = 1.0 / sigma;
@@ -825,7 +848,8 @@ __global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* 
         c1 = rn * rho;
         c2 = 2.0 * rn / delta;
       }
-      tail::cheb<DIM, C, T>(L, vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3), T(c1), T(c2));
+      tail::cheb<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3), T(c1),
+                            T(c2));
       __syncthreads();
       rho = rn;
       xi = 3 - xi;
@@ -833,25 +857,34 @@ __global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* 
     alt = (alt & ~(1u << i)) | (xi == 2 ? 1u << i : 0u);
   }
   const T* res = vec(0, ((alt & 1u) ? 2 : 1));
-  for (int i = threadIdx.x; i < n0; i += kBlock) x_t[size_t(c) * n0 + i] = res[i];
+  for (int i = threadIdx.x; i < n0; i += kBlock) x_t[g0 + i] = res[i];
+  // padding nodes of the copy keep a zero correction
+  const int npad = (TD.L[0].nn1 - TD.L[0].nreal) * C;
+  for (int i = threadIdx.x; i < npad; i += kBlock) x_t[g0 + n0 + i] = T(0);
 }
 
 // coarsest level: x = M^{-1} b with the dense inverse, one workgroup per column
+// (one workgroup per column and copy; n = grid dofs of a copy, stride = dofs of a
+// copy with padding, copies of a column contiguous; padding dofs left as zero)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const T* __restrict__ Minv,
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, int stride, int copies,
+                                                         const T* __restrict__ Minv,
                                                          const T* __restrict__ b,
                                                          T* __restrict__ x) {
   extern __shared__ double sb_raw[];
   T* sb = reinterpret_cast<T*>(sb_raw);
-  const int c = blockIdx.x;
-  for (int i = threadIdx.x; i < n; i += kBlock) sb[i] = b[size_t(c) * n + i];
+  const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
+  const size_t base = (size_t(c) * copies + cp) * stride;
+  const T* M = Minv + size_t(cp) * n * n;
+  for (int i = threadIdx.x; i < n; i += kBlock) sb[i] = b[base + i];
   __syncthreads();
   for (int r = threadIdx.x; r < n; r += kBlock) {
     T acc = T(0);
-    const T* row = Minv + size_t(r) * n;
+    const T* row = M + size_t(r) * n;
     for (int j = 0; j < n; ++j) acc += row[j] * sb[j];
-    x[size_t(c) * n + r] = acc;
+    x[base + r] = acc;
   }
+  for (int r = n + threadIdx.x; r < stride; r += kBlock) x[base + r] = T(0);
 }
 
 // pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), and the first
@@ -938,18 +971,18 @@ __global__ __launch_bounds__(kBlock) void k_update(int nn, const ColDesc* __rest
 
 // per-column sums of the block partials in a fixed order
 __global__ __launch_bounds__(kBlock) void k_reduce_norms(const double* __restrict__ partials,
-                                                         int nblk, int pstride,
+                                                         int bpc, int copies, int pstride,
                                                          double* __restrict__ norms) {
   __shared__ double lds[16];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
   double q[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += kBlock)
+  for (int b = cp * bpc + threadIdx.x; b < (cp + 1) * bpc; b += kBlock)
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] += partials[(size_t(c) * pstride + b) * 4 + k];
   block_sum<4>(q, lds);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) norms[size_t(c) * 4 + k] = q[k];
+    for (int k = 0; k < 4; ++k) norms[(size_t(c) * copies + cp) * 4 + k] = q[k];
 }
 
 // Y = AA X (diagnostic path)
@@ -1180,9 +1213,10 @@ void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<
 }
 
 template <typename T>
-void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStream_t st) {
-  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nc), dim3(kBlock), size_t(n) * sizeof(T), st, n,
-                     Minv, b, x);
+void launch_coarse_solve(int n, int stride, int copies, const T* Minv, const T* b, T* x, int nc,
+                         hipStream_t st) {
+  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nc * copies), dim3(kBlock), size_t(n) * sizeof(T),
+                     st, n, stride, copies, Minv, b, x);
 }
 
 size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes) {
@@ -1195,9 +1229,9 @@ template <typename T>
 void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T* x, int nc,
                         hipStream_t st) {
   int nnl[kTailMaxLevels];
-  for (int i = 0; i < TD.nlev; ++i) nnl[i] = TD.L[i].nn;
+  for (int i = 0; i < TD.nlev; ++i) nnl[i] = TD.L[i].nreal;
   const size_t lds = tail_lds_bytes(nnl, TD.nlev, comps, int(sizeof(T)));
-  const dim3 g(nc);
+  const dim3 g(nc * TD.L[0].copies);
   if (dim == 2) {
     if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T>), g, dim3(kBlock), lds, st, TD, b, x);
     else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T>), g, dim3(kBlock), lds, st, TD, b, x);
@@ -1249,9 +1283,10 @@ void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, h
   else hipLaunchKernelGGL((k_pack<3, T>), g, dim3(kBlock), 0, st, nn, zu, zp, Z);
 }
 
-void launch_reduce_norms(const double* partials, int nblk, int pstride, double* norms, int nc,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_norms, dim3(nc), dim3(kBlock), 0, st, partials, nblk, pstride, norms);
+void launch_reduce_norms(const double* partials, int bpc, int copies, int pstride, double* norms,
+                         int nc, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_norms, dim3(nc * copies), dim3(kBlock), 0, st, partials, bpc, copies,
+                     pstride, norms);
 }
 
 void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const double* X,
@@ -1274,7 +1309,7 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
                                    const T*, T*, T*, T*, double, int, hipStream_t);               \
   template void launch_prolong<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,      \
                                   const T*, const T*, T*, int, int, hipStream_t);                 \
-  template void launch_coarse_solve<T>(int, const T*, const T*, T*, int, hipStream_t);           \
+  template void launch_coarse_solve<T>(int, int, int, const T*, const T*, T*, int, hipStream_t); \
   template void launch_vcycle_tail<T>(int, int, const TailDev<T>&, const T*, T*, int, hipStream_t); \
   template void launch_pstage<T>(int, const LevelView<T>&, const T*, bool, const T*, const T*,   \
                                  T*, T*, T*, double, int, int, hipStream_t);                      \

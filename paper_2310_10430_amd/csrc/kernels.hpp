@@ -15,6 +15,8 @@ constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
 template <typename T>
 struct LevelView {
   int nn, W, n_cells;
+  int copies, nn1, nreal;  // disconnected copies of the grid (samples of a batch),
+                           // nodes per copy with padding, grid nodes per copy
   const int32_t* nbr;    // [W][nn]
   const T* A;            // [W][dim*dim][nn]
   const T* S;            // [W][nn]
@@ -74,8 +76,11 @@ void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView
 template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
                     const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st);
+// dense coarsest solve per column and copy: n grid dofs per copy, `stride` dofs
+// per copy with padding, Minv = copies dense inverses
 template <typename T>
-void launch_coarse_solve(int n, const T* Minv, const T* b, T* x, int nc, hipStream_t st);
+void launch_coarse_solve(int n, int stride, int copies, const T* Minv, const T* b, T* x, int nc,
+                         hipStream_t st);
 
 // The coarse end of a V-cycle (levels t..last) in one launch, one workgroup
 // per column with the vectors in LDS (k_vcycle_tail).  L[0] is level t, whose
@@ -109,8 +114,10 @@ void launch_unpack(int dim, int nn, const double* X, T* ru, T* rp, int nc, hipSt
 template <typename T>
 void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, hipStream_t st);
 
-void launch_reduce_norms(const double* partials, int nblk, int partial_stride, double* norms,
-                         int nc, hipStream_t st);
+// norms[c][copy][4] = sums of the block partials of each copy (blocks of a copy
+// are contiguous: bpc = blocks per copy)
+void launch_reduce_norms(const double* partials, int bpc, int copies, int partial_stride,
+                         double* norms, int nc, hipStream_t st);
 void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const double* X,
                            double* Y, int nc, hipStream_t st);
 

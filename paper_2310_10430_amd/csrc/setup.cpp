@@ -49,6 +49,9 @@ struct Grid {
 void init_level(HostLevel& L, const Grid& g, int dim) {
   L.n_cells = g.n;
   L.nn = g.nn();
+  L.copies = 1;
+  L.nn1 = L.nn;
+  L.nreal = L.nn;
   L.W = g.W();
   L.nbr.assign(size_t(L.W) * L.nn, 0);
   for (int v = 0; v < L.nn; ++v) {
@@ -553,6 +556,96 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
       }
     if (!invert(Ms, ns)) return "coarsest pressure operator is singular";
     P.coarseSinv.swap(Ms);
+  }
+  return "";
+}
+
+std::string concat_problems(const std::vector<HostProblem>& parts, int pad, HostProblem& P) {
+  if (parts.empty()) return "no samples";
+  const HostProblem& p0 = parts[0];
+  const int S = int(parts.size()), dim = p0.dim, D1 = dim + 1;
+  for (const HostProblem& q : parts) {
+    if (q.dim != dim || q.nn != p0.nn || q.levels.size() != p0.levels.size())
+      return "samples of a batch must share the mesh";
+    const size_t nmin = std::min(q.coef.size(), p0.coef.size());
+    for (size_t n = 0; n < nmin; ++n)
+      if (q.coef[n] != p0.coef[n]) return "load multipliers of a batch must agree step by step";
+  }
+  P = HostProblem{};
+  P.dim = dim;
+  P.alpha = p0.alpha;
+  P.dt = p0.dt;
+  int nmax = 0;
+  for (const HostProblem& q : parts) {
+    nmax = std::max(nmax, q.n_steps);
+    if (q.coef.size() > P.coef.size()) P.coef = q.coef;
+  }
+  P.n_steps = nmax;
+  const size_t dd = size_t(dim) * dim;
+  for (size_t l = 0; l < p0.levels.size(); ++l) {
+    const HostLevel& a = p0.levels[l];
+    HostLevel L;
+    L.n_cells = a.n_cells;
+    L.W = a.W;
+    L.copies = S;
+    L.nreal = a.nn;
+    L.nn1 = (a.nn + pad - 1) / pad * pad;
+    L.nn = S * L.nn1;
+    const int W = L.W, nn = L.nn, n1 = a.nn;
+    L.nbr.assign(size_t(W) * nn, 0);
+    L.A.assign(size_t(W) * dd * nn, 0.0);
+    L.S.assign(size_t(W) * nn, 0.0);
+    L.Ainv.assign(dd * nn, 0.0);
+    L.Sinv.assign(size_t(nn), 0.0);
+    L.fixed.assign(size_t(nn), uint8_t((1u << D1) - 1));
+    const bool fine = l == 0;
+    if (fine) {
+      L.B.assign(size_t(W) * dim * nn, 0.0);
+      L.Bt.assign(size_t(W) * dim * nn, 0.0);
+      L.Cb.assign(size_t(W) * nn, 0.0);
+    }
+    for (int c = 0; c < S; ++c) {
+      const HostLevel& q = parts[c].levels[l];
+      const int base = c * L.nn1;
+      for (int v = 0; v < L.nn1; ++v) {
+        const int g = base + v;
+        const bool real = v < n1;
+        for (int s2 = 0; s2 < W; ++s2) {
+          L.nbr[size_t(s2) * nn + g] = real ? base + q.nbr[size_t(s2) * n1 + v] : g;
+          for (size_t e = 0; e < dd; ++e)
+            L.A[(s2 * dd + e) * nn + g] = real ? q.A[(s2 * dd + e) * n1 + v] : 0.0;
+          L.S[size_t(s2) * nn + g] = real ? q.S[size_t(s2) * n1 + v] : 0.0;
+          if (fine)
+            for (int k = 0; k < dim; ++k) {
+              L.B[(size_t(s2) * dim + k) * nn + g] = real ? q.B[(size_t(s2) * dim + k) * n1 + v] : 0.0;
+              L.Bt[(size_t(s2) * dim + k) * nn + g] = real ? q.Bt[(size_t(s2) * dim + k) * n1 + v] : 0.0;
+            }
+          if (fine) L.Cb[size_t(s2) * nn + g] = real ? q.Cb[size_t(s2) * n1 + v] : 0.0;
+        }
+        for (size_t e = 0; e < dd; ++e)
+          L.Ainv[e * nn + g] = real ? q.Ainv[e * n1 + v] : (e % (dim + 1) == 0 ? 1.0 : 0.0);
+        L.Sinv[g] = real ? q.Sinv[v] : 1.0;
+        if (real) {
+          L.fixed[g] = q.fixed[v];
+        } else {
+          for (int k = 0; k < dim; ++k) L.A[(k * dim + k) * size_t(nn) + g] = 1.0;  // slot 0
+          L.S[g] = 1.0;
+        }
+      }
+      L.lmaxA = std::max(L.lmaxA, q.lmaxA);
+      L.lmaxS = std::max(L.lmaxS, q.lmaxS);
+    }
+    P.levels.push_back(std::move(L));
+  }
+  const HostLevel& L0 = P.levels[0];
+  P.nn = L0.nn;
+  P.ne = 0;
+  P.F.assign(size_t(L0.nn) * D1, 0.0);
+  for (int c = 0; c < S; ++c)
+    std::copy(parts[c].F.begin(), parts[c].F.end(), P.F.begin() + size_t(c) * L0.nn1 * D1);
+  for (const HostProblem& q : parts) {
+    P.coarseAinv.insert(P.coarseAinv.end(), q.coarseAinv.begin(), q.coarseAinv.end());
+    P.coarseSinv.insert(P.coarseSinv.end(), q.coarseSinv.begin(), q.coarseSinv.end());
   }
   return "";
 }

@@ -15,7 +15,11 @@ namespace biot {
 // read consecutive addresses.
 struct HostLevel {
   int n_cells = 0;           // cells per side
-  int nn = 0;                // nodes
+  int nn = 0;                // nodes (all copies, padding included)
+  int copies = 1;            // samples stored as disconnected copies of the grid
+  int nn1 = 0;               // nodes per copy, padding included (nn = copies * nn1)
+  int nreal = 0;             // grid nodes per copy ((n_cells+1)^dim); the rest of a
+                             // copy's nn1 are inert prescribed padding nodes
   int W = 0;                 // slots per node
   std::vector<int32_t> nbr;  // [W][nn]
   std::vector<double> A;     // [W][dim*dim][nn]  displacement block, entry a*dim+b
@@ -46,8 +50,8 @@ struct HostProblem {
   std::vector<HostLevel> levels;
   std::vector<double> F;          // [nn][dim+1] load for a unit multiplier (p part zero)
   std::vector<double> coef;       // [n_steps+1]
-  std::vector<double> coarseAinv; // dense inverse of the coarsest A (node-major dofs)
-  std::vector<double> coarseSinv; // dense inverse of the coarsest S
+  std::vector<double> coarseAinv; // dense inverse of the coarsest A (node-major dofs), per copy
+  std::vector<double> coarseSinv; // dense inverse of the coarsest S, per copy
   std::vector<double> lambda_e, mu_e, beta_e, perm_e;  // per element
   bool beta_given = false;        // beta supplied by the caller (no lambda/mu dependence)
   // element geometry for the adjoint's gradient contraction, element-minor:
@@ -77,6 +81,14 @@ struct LoadIn {
 // Returns an empty string on success, an error message otherwise.
 std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn& ld,
                           double dt, int n_steps, const HostOptions& opt, HostProblem& out);
+
+// Joins single-sample problems on the same structured mesh into one problem of
+// parts.size() disconnected copies.  Each copy's nodes are padded to a multiple
+// of `pad` with inert nodes (prescribed in every component, identity diagonal,
+// no neighbours, no load), so that blocks of `pad` nodes never straddle copies.
+// Spectral bounds become the maximum over the copies.  The load multipliers of
+// all parts must agree on their common steps (the result keeps the longest).
+std::string concat_problems(const std::vector<HostProblem>& parts, int pad, HostProblem& out);
 
 // SplitMix64-based start vector in [0.5, 1.5) shared by the spectral bounds.
 double splitmix_unit(uint64_t index);

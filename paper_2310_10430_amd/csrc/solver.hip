@@ -95,6 +95,8 @@ struct biot_handle {
   biot_options opt{};
   int dim = 2, D1 = 3, nn = 0, N = 0, nlev = 0;
   int ncmax = 0;  // batch capacity (columns)
+  int S = 1;                     // samples (copies of the grid) in the handle
+  std::vector<int> steps;        // steps of each sample (<= N; later ones are padding)
   size_t col = 0; // doubles per state column
   // device state
   bool bound = false;
@@ -192,7 +194,7 @@ void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
     const int n = last - l + 1;
     if (n > kTailMaxLevels) continue;
     int nnl[kTailMaxLevels];
-    for (int i = 0; i < n; ++i) nnl[i] = h->P.levels[l + i].nn;
+    for (int i = 0; i < n; ++i) nnl[i] = h->P.levels[l + i].nreal;
     if (tail_lds_bytes(nnl, n, C, int(sizeof(T))) > kTailMaxLds) continue;
     t = l;
     break;
@@ -211,7 +213,7 @@ void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
   int off = 0;
   for (int i = 0; i < td.nlev; ++i) {
     td.off[i] = off;
-    off += h->P.levels[t + i].nn * C * (i + 1 < td.nlev ? 5 : 2);
+    off += h->P.levels[t + i].nreal * C * (i + 1 < td.nlev ? 5 : 2);
   }
 }
 
@@ -225,6 +227,9 @@ void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
     D.nn = H.nn;
     D.W = H.W;
     D.n_cells = H.n_cells;
+    D.copies = H.copies;
+    D.nn1 = H.nn1;
+    D.nreal = H.nreal;
     D.nbr = h->L[l].nbr;
     D.fixed = h->L[l].fixed;
     if constexpr (std::is_same<T, double>::value) {
@@ -275,6 +280,9 @@ void plan(biot_handle* h, char* base) {
     D.nn = H.nn;
     D.W = H.W;
     D.n_cells = H.n_cells;
+    D.copies = H.copies;
+    D.nn1 = H.nn1;
+    D.nreal = H.nreal;
     D.nbr = b.take<int32_t>(H.nbr.size());
     D.A = b.take<double>(H.A.size());
     D.S = b.take<double>(H.S.size());
@@ -343,7 +351,7 @@ void plan(biot_handle* h, char* base) {
   else plan_prec<double>(h, b, h->pd);
   h->nblk = num_node_blocks(h->nn);
   h->partials = b.take<double>(size_t(std::max(h->ncmax, h->N)) * h->nblk * 4);
-  h->norms = b.take<double>(size_t(h->N) * 4);
+  h->norms = b.take<double>(size_t(h->N) * h->S * 4);
   h->ws_need = b.off + 256;
 }
 
@@ -550,7 +558,9 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     return BIOT_OK;
   }
   if (l == last) {
-    launch_coarse_solve<T>(h->P.levels[l].nn * C, is_A ? p.coarseA : p.coarseS, f.b[l], f.x0[l], nc, st);
+    const HostLevel& H = h->P.levels[l];
+    launch_coarse_solve<T>(H.nreal * C, H.nn1 * C, H.copies, is_A ? p.coarseA : p.coarseS, f.b[l],
+                           f.x0[l], nc, st);
     LAUNCHCHK(h);
     if (upd) {
       launch_update<T>(h->dim, h->nn, upd, zu, f.x0[l], h->opt.omega, nc, st);
@@ -787,7 +797,8 @@ int global_residual(biot_handle* h, const Sched& S) {
     launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, nullptr, nullptr,
                             0.0, h->partials, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
-    launch_reduce_norms(h->partials, h->nblk, h->nblk, h->norms + size_t(n0) * 4, nc, h->st);
+    launch_reduce_norms(h->partials, num_node_blocks(h->P.levels[0].nn1), h->S, h->nblk,
+                        h->norms + size_t(n0) * h->S * 4, nc, h->st);
     LAUNCHCHK(h);
   }
   return BIOT_OK;
@@ -807,28 +818,34 @@ int sweep_sched(biot_handle* h, Sched& S, int n_sweeps) {
   return BIOT_OK;
 }
 
-void rel_resid(const std::vector<double>& nr, int N, double& ru, double& rp) {
-  double mu = 0, mp = 0, bu = 0, bp = 0;
-  bool bad = false;
-  for (int n = 0; n < N; ++n) {
-    for (int k = 0; k < 4; ++k)
-      if (!std::isfinite(nr[size_t(n) * 4 + k])) bad = true;
-    mu = std::max(mu, nr[size_t(n) * 4 + 0]);
-    mp = std::max(mp, nr[size_t(n) * 4 + 1]);
-    bu = std::max(bu, nr[size_t(n) * 4 + 2]);
-    bp = std::max(bp, nr[size_t(n) * 4 + 3]);
+// Relative residual per field: max_n ||r^n|| / max_n ||b^n|| of each sample over
+// its own steps (nr is [N][S][4]); the worst sample is returned.  A field
+// whose right-hand side vanishes at every step (the pressure rows of a single
+// step from rest, the displacement rows of a one-step adjoint) is measured
+// against the whole right-hand side.
+void rel_resid(const std::vector<double>& nr, int N, int S, const std::vector<int>& steps,
+               double& ru, double& rp) {
+  ru = rp = 0.0;
+  for (int sm = 0; sm < S; ++sm) {
+    const int Ns = S == 1 ? N : std::min(N, steps[sm]);
+    double mu = 0, mp = 0, bu = 0, bp = 0;
+    for (int n = 0; n < Ns; ++n) {
+      const double* q = &nr[(size_t(n) * S + sm) * 4];
+      for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(q[k])) {
+          ru = rp = NAN;
+          return;
+        }
+      mu = std::max(mu, q[0]);
+      mp = std::max(mp, q[1]);
+      bu = std::max(bu, q[2]);
+      bp = std::max(bp, q[3]);
+    }
+    const double both = std::sqrt(bu + bp);
+    const double du = bu > 0 ? std::sqrt(bu) : both, dp = bp > 0 ? std::sqrt(bp) : both;
+    ru = std::max(ru, std::sqrt(mu) / std::max(du, 1e-300));
+    rp = std::max(rp, std::sqrt(mp) / std::max(dp, 1e-300));
   }
-  if (bad) {
-    ru = rp = NAN;
-    return;
-  }
-  // a field whose right-hand side vanishes at every step (the pressure rows of
-  // a single step from rest, the displacement rows of a one-step adjoint) is
-  // measured against the whole right-hand side
-  const double both = std::sqrt(bu + bp);
-  const double du = bu > 0 ? std::sqrt(bu) : both, dp = bp > 0 ? std::sqrt(bp) : both;
-  ru = std::sqrt(mu) / std::max(du, 1e-300);
-  rp = std::sqrt(mp) / std::max(dp, 1e-300);
 }
 
 int check_bound(biot_handle* h) {
@@ -859,7 +876,7 @@ int solve_sched(biot_handle* h, Sched& S, double rtol, int max_sweeps, int check
   int rc = BIOT_OK;
   int step = check_every;
   if (h->opt.schedule == BIOT_SCHED_WAVEFRONT) step = h->opt.depth;  // first pass: full depth
-  std::vector<double> nr(size_t(S.N) * 4);
+  std::vector<double> nr(size_t(S.N) * h->S * 4);
   int done = 0;
   double first = -1;
   out = SolveOut{};
@@ -867,7 +884,7 @@ int solve_sched(biot_handle* h, Sched& S, double rtol, int max_sweeps, int check
     if ((rc = global_residual(h, S))) return rc;
     HIPCHK(h, hipMemcpyAsync(nr.data(), h->norms, nr.size() * 8, hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
-    rel_resid(nr, S.N, out.ru, out.rp);
+    rel_resid(nr, S.N, h->S, h->steps, out.ru, out.rp);
     if (!std::isfinite(out.ru) || !std::isfinite(out.rp)) {
       rc = fail(h, BIOT_EDIVERGED, "non-finite residual");
       break;
@@ -998,9 +1015,17 @@ int biot_default_options(biot_options* o) {
 
 int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_load* load,
                 double dt, int32_t n_steps, const biot_options* opt, biot_handle** out) {
+  return biot_create_batch(mesh, 1, mat, load, &dt, &n_steps, opt, out);
+}
+
+int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_materials* mats,
+                      const biot_load* loads, const double* dts, const int32_t* n_steps,
+                      const biot_options* opt, biot_handle** out) {
   if (!out) return fail(nullptr, BIOT_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!mesh || !mat || !load) return fail(nullptr, BIOT_EINVAL, "NULL mesh, materials or load");
+  if (!mesh || !mats || !loads || !dts || !n_steps)
+    return fail(nullptr, BIOT_EINVAL, "NULL mesh, materials, load, dt or n_steps");
+  if (n_samples < 1 || n_samples > 4096) return fail(nullptr, BIOT_EINVAL, "n_samples must be in 1..4096");
   biot_options o;
   biot_default_options(&o);
   if (opt) o = *opt;
@@ -1021,13 +1046,11 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   if (o.adjoint != 0 && o.adjoint != 1) return fail(nullptr, BIOT_EINVAL, "adjoint must be 0 or 1");
   if (o.adjoint && (o.ckpt_stride < 0 || o.replay_segments < 1 || o.max_sensors < 1))
     return fail(nullptr, BIOT_EINVAL, "need ckpt_stride >= 0, replay_segments >= 1, max_sensors >= 1");
+  if (o.adjoint && n_samples > 1) return fail(nullptr, BIOT_EINVAL, "the adjoint takes one sample per handle");
   biot_handle* h = new (std::nothrow) biot_handle();
   if (!h) return fail(nullptr, BIOT_ENOMEM, "out of host memory");
   h->opt = o;
   MeshIn m{mesh->dim, mesh->n_nodes, mesh->n_elems, mesh->grid_n, mesh->xyz, mesh->conn, mesh->dirichlet};
-  MaterialsIn mi{mat->young,  mat->poisson, mat->perm,        mat->beta,
-                 mat->alpha,  mat->stab_h,  mat->lame_lambda, mat->lame_mu};
-  LoadIn li{load->n_facets, load->facet_nodes, load->traction, load->coef};
   HostOptions ho;
   ho.cheb_degree = o.cheb_degree;
   ho.cheb_ratio = o.cheb_ratio;
@@ -1035,8 +1058,28 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   ho.power_iters = o.power_iters;
   ho.min_cells = o.coarse_cells;
   std::string e;
+  int nmax = 0;
   try {
-    e = build_problem(m, mi, li, dt, n_steps, ho, h->P);
+    if (n_samples == 1) {
+      MaterialsIn mi{mats->young,  mats->poisson, mats->perm,        mats->beta,
+                     mats->alpha,  mats->stab_h,  mats->lame_lambda, mats->lame_mu};
+      LoadIn li{loads->n_facets, loads->facet_nodes, loads->traction, loads->coef};
+      e = build_problem(m, mi, li, dts[0], n_steps[0], ho, h->P);
+      nmax = n_steps[0];
+    } else {
+      std::vector<HostProblem> parts(n_samples);
+      for (int sm = 0; sm < n_samples && e.empty(); ++sm) {
+        const biot_materials& mt = mats[sm];
+        const biot_load& ld = loads[sm];
+        MaterialsIn mi{mt.young, mt.poisson, mt.perm, mt.beta, mt.alpha, mt.stab_h,
+                       mt.lame_lambda, mt.lame_mu};
+        LoadIn li{ld.n_facets, ld.facet_nodes, ld.traction, ld.coef};
+        e = build_problem(m, mi, li, dts[sm], n_steps[sm], ho, parts[sm]);
+        if (!e.empty()) e = "sample " + std::to_string(sm) + ": " + e;
+        nmax = std::max(nmax, n_steps[sm]);
+      }
+      if (e.empty()) e = concat_problems(parts, kBlock, h->P);
+    }
   } catch (const std::exception& ex) {
     e = std::string("set-up failed: ") + ex.what();
   }
@@ -1044,10 +1087,12 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
     delete h;
     return fail(nullptr, BIOT_EINVAL, e);
   }
+  h->S = n_samples;
+  h->steps.assign(n_steps, n_steps + n_samples);
   h->dim = h->P.dim;
   h->D1 = h->dim + 1;
   h->nn = h->P.nn;
-  h->N = n_steps;
+  h->N = nmax;
   h->nlev = int(h->P.levels.size());
   if (h->nlev > 16) {
     delete h;
@@ -1056,16 +1101,16 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   h->col = size_t(h->nn) * h->D1;
   h->ncmax = o.schedule == BIOT_SCHED_WAVEFRONT
                  ? std::max(o.depth, 1)
-                 : (o.max_batch > 0 ? std::min<int>(o.max_batch, n_steps) : n_steps);
+                 : (o.max_batch > 0 ? std::min<int>(o.max_batch, nmax) : nmax);
   h->chA.resize(h->nlev);
   h->chS.resize(h->nlev);
   for (int l = 0; l + 1 < h->nlev; ++l) {
     h->chA[l] = cheb_of(h->P.levels[l].lmaxA, o.cheb_ratio);
     h->chS[l] = cheb_of(h->P.levels[l].lmaxS, o.cheb_ratio);
   }
-  shape_sched(h->fw, n_steps, false);
-  for (int n = 0; n <= n_steps; ++n) h->fw.coef[n] = h->P.coef[n];
-  shape_sched(h->bw, n_steps, true);  // load is gload, no traction
+  shape_sched(h->fw, nmax, false);
+  for (int n = 0; n <= nmax; ++n) h->fw.coef[n] = h->P.coef[n];
+  shape_sched(h->bw, nmax, true);  // load is gload, no traction
   plan(h, nullptr);
   *out = h;
   return BIOT_OK;
@@ -1166,7 +1211,7 @@ int biot_residual_norms(biot_handle* h, double* norms) {
   if (rc) return rc;
   if (!norms) return fail(h, BIOT_EINVAL, "norms is NULL");
   if ((rc = global_residual(h, h->fw))) return rc;
-  HIPCHK(h, hipMemcpyAsync(norms, h->norms, size_t(h->N) * 4 * 8, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipMemcpyAsync(norms, h->norms, size_t(h->N) * h->S * 4 * 8, hipMemcpyDeviceToHost, h->st));
   HIPCHK(h, hipStreamSynchronize(h->st));
   return BIOT_OK;
 }
@@ -1198,6 +1243,23 @@ int biot_get_trajectory(biot_handle* h, int32_t n0, int32_t n1, double* dst, int
   const size_t bytes = size_t(n1 - n0) * h->col * 8;
   HIPCHK(h, hipMemcpyAsync(dst, h->fw.T[h->fw.cur] + size_t(n0) * h->col, bytes,
                            dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
+  if (!dst_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
+  return BIOT_OK;
+}
+
+int biot_get_sample_trajectory(biot_handle* h, int32_t sample, int32_t n0, int32_t n1, double* dst,
+                               int32_t dst_on_device) {
+  int rc = check_forward(h);
+  if (rc) return rc;
+  if (sample < 0 || sample >= h->S) return fail(h, BIOT_EINVAL, "sample out of range");
+  if (!dst || n0 < 0 || n1 > h->steps[sample] + 1 || n0 > n1)
+    return fail(h, BIOT_EINVAL, "bad range or NULL dst");
+  if (n1 == n0) return BIOT_OK;
+  const HostLevel& L0 = h->P.levels[0];
+  const size_t width = size_t(L0.nreal) * h->D1 * 8;
+  const double* src = h->fw.T[h->fw.cur] + size_t(n0) * h->col + size_t(sample) * L0.nn1 * h->D1;
+  HIPCHK(h, hipMemcpy2DAsync(dst, width, src, h->col * 8, width, size_t(n1 - n0),
+                             dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
   if (!dst_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
   return BIOT_OK;
 }
@@ -1393,6 +1455,8 @@ int biot_get_info(const biot_handle* h, biot_info_t* info) {
   }
   info->slots = h->P.levels[0].W;
   info->workspace_bytes = h->ws_need;
+  info->n_samples = h->S;
+  info->nodes_per_sample = h->P.levels[0].nn1;
   return BIOT_OK;
 }
 

@@ -15,17 +15,17 @@ import torch
 from . import _lib
 
 
-def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
-                  cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
-                  wg_per_cu=0, coarse_cells=2, use_graph=True, precision="fp64", lame=None,
-                  adjoint=False, ckpt_stride=16, replay_segments=4, max_sensors=256):
-    """biot_create on the host (no device work); returns (handle, options).
-
-    `lame` = (lambda_e, mu_e) per element replaces the problem's E and nu."""
-    lib = _lib.load()
+def _mesh_struct(problem, keep):
     xyz = np.ascontiguousarray(problem.xyz, dtype=np.float64)
     conn = np.ascontiguousarray(problem.conn, dtype=np.int32)
     flags = np.ascontiguousarray(problem.flags, dtype=np.uint8)
+    keep += [xyz, conn, flags]
+    return _lib.Mesh(problem.dim, problem.n_nodes, problem.n_elems, problem.grid_n,
+                     _lib.dptr(xyz), _lib.iptr(conn), _lib.uptr(flags))
+
+
+def _sample_structs(problem, beta, lame, keep):
+    """biot_materials and biot_load of one problem (arrays kept alive in `keep`)."""
     young = np.ascontiguousarray(problem.young, dtype=np.float64)
     pois = np.ascontiguousarray(problem.poisson, dtype=np.float64)
     perm = np.ascontiguousarray(problem.perm, dtype=np.float64)
@@ -39,13 +39,25 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     facets = np.ascontiguousarray(problem.facets, dtype=np.int32)
     tr = np.ascontiguousarray(problem.traction, dtype=np.float64)
     coef = np.ascontiguousarray(problem.load_coef, dtype=np.float64)
-    mesh = _lib.Mesh(problem.dim, problem.n_nodes, problem.n_elems, problem.grid_n,
-                     _lib.dptr(xyz), _lib.iptr(conn), _lib.uptr(flags))
+    keep += [young, pois, perm, beta_a, lam_a, mu_a, facets, tr, coef]
     mat = _lib.Materials(_lib.dptr(young), _lib.dptr(pois), _lib.dptr(perm),
                          _lib.dptr(beta_a), float(problem.alpha), float(problem.stab_h),
                          _lib.dptr(lam_a), _lib.dptr(mu_a))
     load = _lib.Load(facets.shape[0], _lib.iptr(facets) if facets.size else None,
                      _lib.dptr(tr) if tr.size else None, _lib.dptr(coef))
+    return mat, load
+
+
+def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, cheb_degree=2,
+                  cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
+                  wg_per_cu=0, coarse_cells=2, use_graph=True, precision="fp64", lame=None,
+                  adjoint=False, ckpt_stride=16, replay_segments=4, max_sensors=256):
+    """biot_create (one problem) or biot_create_batch (a list of problems on the
+    same mesh) on the host, no device work; returns (handle, options).
+
+    `lame` = (lambda_e, mu_e) per element replaces the problem's E and nu (one
+    problem only)."""
+    lib = _lib.load()
     opt = _lib.Options()
     lib.biot_default_options(C.byref(opt))
     opt.schedule = _lib.SCHED[schedule]
@@ -65,10 +77,27 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     opt.ckpt_stride = ckpt_stride
     opt.replay_segments = replay_segments
     opt.max_sensors = max_sensors
+    keep = []
     h = C.c_void_p()
-    _lib.check(lib, lib.biot_create(C.byref(mesh), C.byref(mat), C.byref(load),
-                                    float(problem.dt), problem.n_steps, C.byref(opt),
-                                    C.byref(h)), None)
+    if isinstance(problem, (list, tuple)):
+        if beta is not None or lame is not None:
+            raise ValueError("beta and lame are per problem; not supported for batches")
+        mesh = _mesh_struct(problem[0], keep)
+        S = len(problem)
+        mats = (_lib.Materials * S)()
+        loads = (_lib.Load * S)()
+        for i, pb in enumerate(problem):
+            mats[i], loads[i] = _sample_structs(pb, None, None, keep)
+        dts = np.ascontiguousarray([float(pb.dt) for pb in problem], dtype=np.float64)
+        steps = np.ascontiguousarray([int(pb.n_steps) for pb in problem], dtype=np.int32)
+        _lib.check(lib, lib.biot_create_batch(C.byref(mesh), S, mats, loads, _lib.dptr(dts),
+                                              _lib.iptr(steps), C.byref(opt), C.byref(h)), None)
+    else:
+        mesh = _mesh_struct(problem, keep)
+        mat, load = _sample_structs(problem, beta, lame, keep)
+        _lib.check(lib, lib.biot_create(C.byref(mesh), C.byref(mat), C.byref(load),
+                                        float(problem.dt), problem.n_steps, C.byref(opt),
+                                        C.byref(h)), None)
     return h, opt
 
 
@@ -79,7 +108,8 @@ def handle_info(lib, h) -> dict:
     return dict(dim=inf.dim, n_nodes=inf.n_nodes, n_steps=inf.n_steps, n_levels=L,
                 level_cells=list(inf.level_cells[:L]), level_nodes=list(inf.level_nodes[:L]),
                 slots=inf.slots, lmax_A=list(inf.lmax_A[:L]), lmax_S=list(inf.lmax_S[:L]),
-                workspace_bytes=int(inf.workspace_bytes))
+                workspace_bytes=int(inf.workspace_bytes), n_samples=inf.n_samples,
+                nodes_per_sample=inf.nodes_per_sample)
 
 
 def export_level(lib, h, level: int) -> dict:
@@ -123,9 +153,12 @@ class BiotSolver:
                                ckpt_stride=ckpt_stride, replay_segments=replay_segments,
                                max_sensors=max_sensors)
         self.problem = problem
-        self.dim = problem.dim
-        self.n_nodes = problem.n_nodes
-        self.n_steps = problem.n_steps
+        self.batch = isinstance(problem, (list, tuple))
+        first = problem[0] if self.batch else problem
+        self.dim = first.dim
+        self.n_samples = len(problem) if self.batch else 1
+        self.sample_steps = [pb.n_steps for pb in problem] if self.batch else [problem.n_steps]
+        self.n_steps = max(self.sample_steps)
         self.options = opt
         lib = self.lib
         self.h = h
@@ -136,6 +169,9 @@ class BiotSolver:
         self.stream = torch.cuda.current_stream(self.device)
         self._check(lib.biot_bind(h, C.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
                                   C.c_void_p(self.stream.cuda_stream)))
+        inf = handle_info(lib, h)
+        self.grid_nodes = first.n_nodes              # nodes of one sample's grid
+        self.n_nodes = inf["n_samples"] * inf["nodes_per_sample"] if self.batch else first.n_nodes
 
     # ------------------------------------------------------------------
     def _check(self, rc):
@@ -162,8 +198,18 @@ class BiotSolver:
         self._check(self.lib.biot_sweep(self.h, int(n)))
 
     def residual_norms(self) -> np.ndarray:
-        out = np.zeros((self.n_steps, 4))
+        """[n_steps, 4] (one problem) or [n_steps, n_samples, 4] (batch)."""
+        out = np.zeros((self.n_steps, self.n_samples, 4))
         self._check(self.lib.biot_residual_norms(self.h, _lib.dptr(out)))
+        return out if self.batch else out[:, 0, :]
+
+    def sample_trajectory(self, sample: int, n0: int = 0, n1: int | None = None) -> torch.Tensor:
+        """Steps n0..n1-1 of one sample of a batch, [n1-n0, grid nodes, dim+1]."""
+        n1 = self.sample_steps[sample] + 1 if n1 is None else n1
+        out = torch.empty((n1 - n0, self.grid_nodes, self.dim + 1), dtype=torch.float64,
+                          device=self.device)
+        self._check(self.lib.biot_get_sample_trajectory(self.h, int(sample), n0, n1,
+                                                        C.c_void_p(out.data_ptr()), 1))
         return out
 
     def solve_to_tol(self, rtol: float, max_sweeps: int = 1000, check_every: int = 4,

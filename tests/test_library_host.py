@@ -153,3 +153,56 @@ def test_unbound_handle_refuses_device_calls():
         assert lib.biot_workspace_size(h, C.byref(nbytes)) == 0 and nbytes.value > 0
     finally:
         lib.biot_destroy(h)
+
+
+def _batch_samples():
+    # same 8 x 8 mesh, different fields, moduli, steps and dt
+    return [W.heterogeneous_problem(8, N, field_seed=3000 + i, young_seed=4000 + i)
+            for i, N in enumerate((5, 9, 7))]
+
+
+def test_batch_concatenates_samples_with_inert_padding():
+    lib = _lib.load()
+    pbs = _batch_samples()
+    hb, _ = S.create_handle(pbs)
+    singles = [S.create_handle(pb)[0] for pb in pbs]
+    try:
+        info = S.handle_info(lib, hb)
+        assert info["n_samples"] == 3 and info["n_steps"] == 9
+        stride = info["nodes_per_sample"]
+        assert stride % 256 == 0 and stride >= pbs[0].n_nodes
+        for lev in range(info["n_levels"]):
+            eb = S.export_level(lib, hb, lev)
+            n1 = S.handle_info(lib, singles[0])["level_nodes"][lev]
+            st = info["level_nodes"][lev] // 3
+            assert st % 256 == 0
+            for i, hs in enumerate(singles):
+                es = S.export_level(lib, hs, lev)
+                sl = slice(i * st, i * st + n1)
+                np.testing.assert_array_equal(eb["nbr"][:, sl], es["nbr"] + i * st)
+                for k in ("A", "S") + (("B", "Bt", "Cb") if lev == 0 else ()):
+                    np.testing.assert_array_equal(eb[k][..., sl], es[k])
+                if lev == 0:
+                    np.testing.assert_array_equal(eb["F"][sl], es["F"])
+                pad = slice(i * st + n1, (i + 1) * st)
+                assert np.all(eb["nbr"][:, pad] == np.arange(i * st + n1, (i + 1) * st))
+                d = pbs[0].dim
+                A0 = eb["A"][0, :, pad].reshape(d, d, -1)
+                assert np.all(A0 == np.eye(d)[:, :, None]) and np.all(eb["A"][1:, :, pad] == 0)
+                assert np.all(eb["S"][0, pad] == 1) and np.all(eb["S"][1:, pad] == 0)
+            lmax = [S.handle_info(lib, hs)["lmax_A"][lev] for hs in singles]
+            if lev + 1 < info["n_levels"]:
+                assert info["lmax_A"][lev] == max(lmax)
+    finally:
+        for h in [hb] + singles:
+            lib.biot_destroy(h)
+
+
+def test_batch_rejects_inconsistent_samples():
+    pbs = _batch_samples()
+    pbs[1].load_coef = pbs[1].load_coef * 2.0
+    with pytest.raises(_lib.BiotError, match="load multipliers"):
+        S.create_handle(pbs)
+    other = W.heterogeneous_problem(16, 5)
+    with pytest.raises(_lib.BiotError):
+        S.create_handle([_batch_samples()[0], other])
