@@ -191,6 +191,96 @@ def run_adjoint(BiotSolver, args, reps=2):
     return res
 
 
+def _max_rel_diff(a, b):
+    """per field max_n |a - b| / max_n |b| over a node-major trajectory pair"""
+    d = a.shape[-1] - 1
+    return max(float(((a[..., sl] - b[..., sl]).abs().max() / b[..., sl].abs().max()).item())
+               for sl in (slice(0, d), slice(d, d + 1)))
+
+
+def run_batched(args):
+    """64 independent samples on uneven meshes (sizes from {32,48,64,96,128},
+    128..512 steps, own permeability field and moduli each), solved to the same
+    tolerance three ways: one handle per sample in FP64 (the plain GPU method),
+    and tuned batch handles (one per mesh size, split by the autotuner) in FP64
+    and with the mixed-precision preconditioner."""
+    from paper_2310_10430_amd import autotune
+    from paper_2310_10430_amd import workloads as W
+    specs = W.batched_samples(64, seed=3)
+    probs = [W.heterogeneous_problem(n, N, field_seed=seed, young_seed=seed + 1000)
+             for n, N, seed in specs]
+    real = float(sum(pb.n_dof * pb.n_steps for pb in probs))
+    sizes = sorted({pb.grid_n for pb in probs})
+    buckets = [[(i, pb) for i, pb in enumerate(probs) if pb.grid_n == n] for n in sizes]
+    res = {"workload": "64 samples: grid n from {32,48,64,96,128} and steps from 128..512 "
+                       "(seeded), log-normal K and E~U[5e3,2e4] per sample (seeds 3000+i, "
+                       "4000+i), dt = 1/steps",
+           "samples_per_size": {str(n): len(b) for n, b in zip(sizes, buckets)},
+           "dof_steps": real, "rtol": args.rtol}
+    log("bench: batched: one handle per sample, FP64")
+    wall, st, ref = autotune.solve_groups([[it] for b in buckets for it in b], args.rtol, "fp64",
+                                          max_sweeps=args.max_sweeps, keep=True)
+    res["per_sample_fp64"] = {"seconds": wall, "value": real / wall,
+                              "sweeps_max": max(x["sweeps"] for x in st)}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        choices = [autotune.tune([pb for _, pb in b], precision=prec) for b in buckets]
+        tune_s = time.perf_counter() - t0
+        groups, wpcs = [], []
+        for b, ch in zip(buckets, choices):
+            for g in autotune.tuned_groups(b, ch):
+                groups.append(g)
+                wpcs.append(ch["wg_per_cu"])
+        log(f"bench: batched {prec}: {len(groups)} handles")
+        wall, st, tr = autotune.solve_groups(groups, args.rtol, prec, wpcs=wpcs,
+                                             max_sweeps=args.max_sweeps, keep=True)
+        diff = max(_max_rel_diff(tr[i], ref[i]) for i in ref)
+        res[f"batched_{prec}"] = {
+            "seconds": wall, "value": real / wall, "handles": len(groups),
+            "sweeps_max": max(x["sweeps"] for x in st),
+            "max_rel_diff_vs_per_sample_fp64": diff, "tuning_s": tune_s,
+            "choices": {str(n): {"split": ch["split"], "wg_per_cu": ch["wg_per_cu"],
+                                 "cached": ch["cached"]} for n, ch in zip(sizes, choices)}}
+        del tr
+    del ref
+    res["unit"] = "dof-timestep updates/s"
+    return res
+
+
+def run_cube(args):
+    """3D unit cube, 40^3 Kuhn tetrahedra (68,921 nodes, 275,684 unknowns),
+    256 steps of dt = 1/256, homogeneous materials, FP64 and mixed."""
+    import torch
+    from paper_2310_10430_amd import workloads as W
+    from paper_2310_10430_amd.solver import BiotSolver
+    pb = W.terzaghi_problem(40, 256, dim=3)
+    res = {"workload": "cube40: 40^3 unit cube, Kuhn tetrahedra, 275684 unknowns, 256 steps "
+                       "dt=1/256, E=1e4 nu=0.3 K=1e-2", "rtol": args.rtol}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        s = BiotSolver(pb, schedule="wavefront", depth=args.depth, omega=args.omega,
+                       precision=prec)
+        setup = time.perf_counter() - t0
+        s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.reset()
+        st = s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
+        torch.cuda.synchronize()
+        per = time.perf_counter() - t0
+        X = s.trajectory()
+        s.close()
+        res[prec] = {"seconds": per, "value": pb.n_dof * pb.n_steps / per, "setup_s": setup,
+                     "sweeps": st["sweeps"], "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"])}
+        if prec == "fp64":
+            Xf = X
+        else:
+            res[prec]["max_rel_diff_vs_fp64"] = _max_rel_diff(X, Xf)
+        log(f"bench: cube40 {prec}: {per:.3f} s per solve")
+    res["unit"] = "dof-timestep updates/s"
+    return res
+
+
 def cpu_adjoint_baseline():
     """The oracle's gradient (factorization, 256 forward and 256 adjoint direct
     solves, element contraction) of the gradient workload on one host core."""
@@ -242,6 +332,10 @@ def main():
                     help="skip the mixed-precision and heterogeneous-permeability variants")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the gradient (adjoint) measurement")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-sample batched measurement")
+    ap.add_argument("--no-cube", action="store_true",
+                    help="skip the 3D 40^3 measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
@@ -353,6 +447,9 @@ def main():
             log("bench: timing the CPU oracle's gradient (about half a minute)")
             adjoint["cpu_oracle"] = cpu_adjoint_baseline()
 
+    batched = None if args.no_batched else run_batched(args)
+    cube = None if args.no_cube else run_cube(args)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -387,6 +484,8 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "adjoint": adjoint,
+        "batched": batched,
+        "cube40": cube,
     }
     print(json.dumps(out), flush=True)
 
