@@ -72,6 +72,11 @@ extern "C" {
                                 /* stage) in FP32.  Each sweep is one step of   */
                                 /* iterative refinement, so the fixed point is  */
                                 /* the FP64 one                                 */
+#define BIOT_INNER_RICHARDSON 0  /* unit = one damped preconditioned update     */
+#define BIOT_INNER_GMRES 1       /* unit = GMRES(k) on AA x = b^{n,m} from      */
+                                 /* X^{n,m-1}, left-preconditioned by P (the    */
+                                 /* Krylov solver K of Alg. 3; PETSc's default  */
+                                 /* side), minimizing ||P^{-1}(b - AA x)||      */
 
 typedef struct biot_handle biot_handle;
 
@@ -133,6 +138,8 @@ typedef struct {
                            /* segment from its checkpoint for the gradient (16)    */
   int32_t replay_segments; /* segments recomputed together (4)                     */
   int32_t max_sensors;     /* capacity of the objective's sensor list (256)        */
+  int32_t inner;           /* BIOT_INNER_* : what one unit does (RICHARDSON)       */
+  int32_t gmres_k;         /* GMRES iterations per unit, 1..8 (4); omega unused    */
 } biot_options;
 
 /* Pressure-misfit objective J = sum_{n=1..N} sum_s (p^n(node_s) - p_obs[n-1][s])^2. */
@@ -309,7 +316,8 @@ int biot_objective_value(biot_handle* h, const biot_objective* obj, double* J);
  * biot_reset); each segment of s steps is recomputed from its checkpoint,
  * replay_segments at a time, to rtol.  rtol and max_sweeps apply to the adjoint
  * solve and to every replay.  grad_* are [n_elems] doubles, device pointers if
- * grads_on_device else host; any may be NULL.  stats may be NULL.
+ * grads_on_device else host; any may be NULL.  stats may be NULL; when the
+ * adjoint solve or a replay fails, stats still reports how far it got.
  * Synchronizes the stream. */
 int biot_adjoint(biot_handle* h, const biot_objective* obj, double rtol, int32_t max_sweeps,
                  double* grad_logk, double* grad_lambda, double* grad_mu, int32_t grads_on_device,

@@ -5,11 +5,14 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 Alg. 3 writes one unit of the inverted iteration as
     X^{n,m} = K(P, AA, X^{n,m-1}, b^{n,m}, n_iter),
 K being a Krylov method (the paper uses PETSc's GMRES) preconditioned by P.
-Here K is restarted GMRES with right preconditioning, k iterations from the
-previous iterate (Saad, Iterative Methods for Sparse Linear Systems, the
-right-preconditioned GMRES algorithm): r0 = b - A x0, v_1 = r0/||r0||, Arnoldi
-on A P^{-1} with modified Gram-Schmidt, y minimizing ||beta e_1 - H_k y|| (here
-by numpy's least squares on the small Hessenberg matrix), x = x0 + P^{-1} V_k y.
+Here K is restarted GMRES with left preconditioning (PETSc's default side for
+GMRES), k iterations from the previous iterate (Saad, Iterative Methods for
+Sparse Linear Systems, the left-preconditioned GMRES algorithm):
+r0 = P^{-1}(b - A x0), v_1 = r0/||r0||, Arnoldi on P^{-1} A with modified
+Gram-Schmidt, y minimizing ||beta e_1 - H_k y|| (here by numpy's least squares
+on the small Hessenberg matrix), x = x0 + V_k y.  It minimizes the
+preconditioned residual ||P^{-1}(b - A x)||, which weighs the displacement and
+pressure rows (of very different scales) by the preconditioner.
 
 All vectors live on the free (not prescribed) dofs: the operator and the
 preconditioner outputs are zeroed on prescribed dofs.
@@ -21,20 +24,17 @@ import numpy as np
 from .inverted import norms, step_residual
 
 
-def gmres_right(apply_A, apply_P, b: np.ndarray, x0: np.ndarray, k: int) -> np.ndarray:
-    """k iterations of right-preconditioned GMRES for A x = b from x0."""
-    r0 = b - apply_A(x0)
+def gmres_left(apply_A, apply_P, b: np.ndarray, x0: np.ndarray, k: int) -> np.ndarray:
+    """k iterations of left-preconditioned GMRES for A x = b from x0."""
+    r0 = apply_P(b - apply_A(x0))
     beta = np.linalg.norm(r0)
     if beta == 0.0:
         return x0.copy()
     V = [r0 / beta]
     H = np.zeros((k + 1, k))
-    Z = []
     m = k
     for j in range(k):
-        z = apply_P(V[j])
-        Z.append(z)
-        w = apply_A(z)
+        w = apply_P(apply_A(V[j]))
         for i in range(j + 1):
             H[i, j] = w @ V[i]
             w = w - H[i, j] * V[i]
@@ -46,7 +46,7 @@ def gmres_right(apply_A, apply_P, b: np.ndarray, x0: np.ndarray, k: int) -> np.n
     e1 = np.zeros(m + 1)
     e1[0] = beta
     y = np.linalg.lstsq(H[: m + 1, :m], e1, rcond=None)[0]
-    return x0 + sum(y[j] * Z[j] for j in range(m))
+    return x0 + sum(y[j] * V[j] for j in range(m))
 
 
 class GmresUnit:
@@ -68,7 +68,7 @@ class GmresUnit:
     def update(self, n: int, X_prev: np.ndarray, X_cur: np.ndarray):
         """(X^{n,m}, norms of the unit's residual before the update)."""
         b, r = step_residual(self.orc, n, X_prev, X_cur)
-        return gmres_right(self._A, self._P, b, X_cur, self.k), norms(self.orc, b, r)
+        return gmres_left(self._A, self._P, b, X_cur, self.k), norms(self.orc, b, r)
 
 
 def sweep(orc, X: np.ndarray, unit, order: str = "gauss_seidel"):

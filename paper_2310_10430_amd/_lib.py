@@ -12,6 +12,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDIVERGED", -5: "ENOTCONV
 SCHED = {"jacobi": 0, "wavefront": 1}
 PRECOND = {"P1": 1, "P2": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
+INNER = {"richardson": 0, "gmres": 1}
 PROBES = ["residual", "cheb_u", "cheb_p", "levres_u", "levres_p", "pstage"]
 
 _dp = C.POINTER(C.c_double)
@@ -41,7 +42,8 @@ class Options(C.Structure):
                 ("max_batch", C.c_int32), ("omega", C.c_double), ("wg_per_cu", C.c_int32),
                 ("coarse_cells", C.c_int32), ("use_graph", C.c_int32),
                 ("precision", C.c_int32), ("adjoint", C.c_int32), ("ckpt_stride", C.c_int32),
-                ("replay_segments", C.c_int32), ("max_sensors", C.c_int32)]
+                ("replay_segments", C.c_int32), ("max_sensors", C.c_int32),
+                ("inner", C.c_int32), ("gmres_k", C.c_int32)]
 
 
 class Objective(C.Structure):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbiot_pint.so")
-SOURCES = ["setup.cpp", "kernels.hip", "adjoint.hip", "solver.hip"]
+SOURCES = ["setup.cpp", "kernels.hip", "adjoint.hip", "gmres.hip", "solver.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [

@@ -155,6 +155,36 @@ void launch_grad_partial(int dim, const ElemDev& E, size_t col, const double* xb
 void launch_grad_finish(const ElemDev& E, const double* part, int nchunks, double* g_logk,
                         double* g_lam, double* g_mu, hipStream_t st);
 
+// ---- GMRES(k) per unit (gmres.hip) ----
+// Per batch column c: basis vectors V_i at base + i*stride_v + c*col (node-major
+// FP64 columns of `col` values); Hessenberg H[c][i][j] at ((c*(K+1)+i)*K + j),
+// g[c][i] at c*(K+1)+i, rotations and y at c*K + j, with K = kGmresMaxK.
+constexpr int kGmresMaxK = 8;
+struct GmresVecs {
+  const double* base;
+  size_t stride_v;
+  size_t col;
+};
+// <V_i[c], W[c]> for i < nvec into out[c*ocs + i*ois]: mode 0 store, 1 add,
+// 2 store the square root (a norm); out2 (optional) += the same values.
+// `part` holds [nc][120][K+1] partial sums.
+void gmres_dot(const GmresVecs& V, int nvec, const double* W, double* part, double* out,
+               size_t ocs, size_t ois, int mode, double* out2, size_t ocs2, size_t ois2, int nc,
+               hipStream_t st);
+// W[c] -= sum_{i < nvec} coef[c*ccs + i*cis] V_i[c]
+void gmres_axpy(const GmresVecs& V, int nvec, const double* coef, size_t ccs, size_t cis, double* W,
+                int nc, hipStream_t st);
+// X[c] /= s[c*s_stride] (times zero when s is zero)
+void gmres_scale(double* X, size_t col, const double* s, size_t s_stride, int nc, hipStream_t st);
+// g[c] = (beta[c*beta_stride], 0, ...)
+void gmres_start(const double* beta, size_t beta_stride, double* g, int nc, hipStream_t st);
+// Givens rotation j on every column's Hessenberg column j and g
+void gmres_givens(double* H, double* g, double* cs, double* sn, int j, int nc, hipStream_t st);
+// y = R^{-1} g and X^{n,m} = X^{n,m-1} + V y through the descriptors
+void gmres_finish(int dim, int nn, const ColDesc* cols, const GmresVecs& Z, int k, const double* H,
+                  const double* g, double* y, int nc, hipStream_t st);
+constexpr int kGmresDotBlocks = 120;
+
 __host__ __device__ inline int num_node_blocks(int nn) { return (nn + kBlock - 1) / kBlock; }
 
 }  // namespace biot

@@ -129,6 +129,19 @@ struct biot_handle {
   double* gpart = nullptr;       // [n_chunks][4][ne]
   double* gout = nullptr;        // [3][ne] staging for host gradients
   ElemDev E{};
+  // GMRES(k) per unit (options.inner = GMRES), per batch column
+  double* gV = nullptr;          // basis V_0..V_k        [k+1][ncmax][col]
+  double* gT = nullptr;          // operator products     [ncmax][col]
+  double* gru = nullptr;         // r0 in field layout    [ncmax][nn][dim]
+  double* grp = nullptr;         //                       [ncmax][nn]
+  double* kpart = nullptr;       // dot partials
+  double* gH = nullptr;          // Hessenberg            [ncmax][K+1][K]
+  double* gg = nullptr;          // rotated rhs           [ncmax][K+1]
+  double* gcs = nullptr;         // rotations, y          [ncmax][K]
+  double* gsn = nullptr;
+  double* gy = nullptr;
+  double* gbeta = nullptr;       // ||r0||                [ncmax]
+  double* gcorr = nullptr;       // second Gram-Schmidt pass [ncmax][K+1]
   // HIP-event probes around level-0 launches (biot_profile_enable)
   struct Pending { hipEvent_t a, b; int id; double bytes; };
   struct Acc { uint64_t launches = 0; double ms = 0, bytes = 0; };
@@ -347,6 +360,21 @@ void plan(biot_handle* h, char* base) {
     h->gout = b.take<double>(3 * ne);
   }
   if (wave) h->slots = b.take<double>(size_t(2) * h->opt.depth * h->col);
+  if (h->opt.inner == BIOT_INNER_GMRES) {
+    const size_t nc = size_t(h->ncmax), K = kGmresMaxK, k = size_t(h->opt.gmres_k);
+    h->gV = b.take<double>((k + 1) * nc * h->col);
+    h->gT = b.take<double>(nc * h->col);
+    h->gru = b.take<double>(nc * h->nn * h->dim);
+    h->grp = b.take<double>(nc * h->nn);
+    h->kpart = b.take<double>(nc * kGmresDotBlocks * (K + 1));
+    h->gH = b.take<double>(nc * (K + 1) * K);
+    h->gg = b.take<double>(nc * (K + 1));
+    h->gcs = b.take<double>(nc * K);
+    h->gsn = b.take<double>(nc * K);
+    h->gy = b.take<double>(nc * K);
+    h->gbeta = b.take<double>(nc);
+    h->gcorr = b.take<double>(nc * (K + 1));
+  }
   if (h->opt.precision == BIOT_PRECISION_MIXED) plan_prec<float>(h, b, h->pf);
   else plan_prec<double>(h, b, h->pd);
   h->nblk = num_node_blocks(h->nn);
@@ -674,10 +702,6 @@ int unit_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols
   return precond_batch<T>(h, p, nc, &zu, &zp, cols);
 }
 
-int unit_batch(biot_handle* h, const Sched& S, const ColDesc* cols, int nc) {
-  if (h->opt.precision == BIOT_PRECISION_MIXED) return unit_batch_t<float>(h, S, h->pf, cols, nc);
-  return unit_batch_t<double>(h, S, h->pd, cols, nc);
-}
 
 // Z = P^{-1} R for caller columns (diagnostic path)
 template <typename T>
@@ -699,6 +723,61 @@ int apply_precond_t(biot_handle* h, Prec<T>& p, const double* R, double* Z, int 
     LAUNCHCHK(h);
   }
   return BIOT_OK;
+}
+
+// One unit as GMRES(k) on AA x = b (b = coupling + load of each column),
+// left-preconditioned by P (PETSc's default side for GMRES, the Krylov solver
+// K of Alg. 3) and started from X^{n,m-1}: v_0 = P^{-1}(b - AA x0)/beta; for
+// j < k: w = P^{-1} AA v_j orthogonalized against v_0..v_j (classical
+// Gram-Schmidt applied twice), v_{j+1} = w/||w||, Givens rotation of the
+// Hessenberg column; then X^{n,m} = x0 + V y with y minimizing
+// ||beta e_1 - H y||, i.e. the preconditioned residual ||P^{-1}(b - AA x)||,
+// which weighs the displacement and pressure rows by the preconditioner.
+template <typename T>
+int gmres_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols, int nc) {
+  const size_t K = kGmresMaxK, col = h->col, sv = size_t(h->ncmax) * col;
+  const int k = h->opt.gmres_k;
+  hipStream_t st = h->st;
+  const GmresVecs Vv{h->gV, sv, col};
+  launch_residual<double>(h->dim, h->L[0], fine_of(h, S), cols, nc, h->gru, h->grp, nullptr,
+                          nullptr, 0.0, nullptr, h->nblk, h->opt.wg_per_cu, S.adj, st);
+  LAUNCHCHK(h);
+  launch_pack<double>(h->dim, h->nn, h->gru, h->grp, h->gT, nc, st);
+  LAUNCHCHK(h);
+  int rc = apply_precond_t<T>(h, p, h->gT, h->gV, nc);
+  if (rc) return rc;
+  gmres_dot(GmresVecs{h->gV, 0, col}, 1, h->gV, h->kpart, h->gbeta, 1, 0, 2, nullptr, 0, 0, nc, st);
+  gmres_scale(h->gV, col, h->gbeta, 1, nc, st);
+  gmres_start(h->gbeta, 1, h->gg, nc, st);
+  LAUNCHCHK(h);
+  const size_t hcs = (K + 1) * K;
+  for (int j = 0; j < k; ++j) {
+    double* Vj = h->gV + j * sv;
+    double* W = h->gV + (j + 1) * sv;
+    launch_apply_operator(h->dim, h->L[0], h->F, Vj, h->gT, nc, st);
+    LAUNCHCHK(h);
+    if ((rc = apply_precond_t<T>(h, p, h->gT, W, nc))) return rc;
+    gmres_dot(Vv, j + 1, W, h->kpart, h->gH + j, hcs, K, 0, nullptr, 0, 0, nc, st);
+    gmres_axpy(Vv, j + 1, h->gH + j, hcs, K, W, nc, st);
+    gmres_dot(Vv, j + 1, W, h->kpart, h->gcorr, K + 1, 1, 0, h->gH + j, hcs, K, nc, st);
+    gmres_axpy(Vv, j + 1, h->gcorr, K + 1, 1, W, nc, st);
+    double* hn = h->gH + (j + 1) * K + j;
+    gmres_dot(GmresVecs{W, 0, col}, 1, W, h->kpart, hn, hcs, 0, 2, nullptr, 0, 0, nc, st);
+    gmres_scale(W, col, hn, hcs, nc, st);
+    gmres_givens(h->gH, h->gg, h->gcs, h->gsn, j, nc, st);
+    LAUNCHCHK(h);
+  }
+  gmres_finish(h->dim, h->nn, cols, Vv, k, h->gH, h->gg, h->gy, nc, st);
+  LAUNCHCHK(h);
+  return BIOT_OK;
+}
+
+int unit_batch(biot_handle* h, const Sched& S, const ColDesc* cols, int nc) {
+  const bool mixed = h->opt.precision == BIOT_PRECISION_MIXED;
+  if (h->opt.inner == BIOT_INNER_GMRES)
+    return mixed ? gmres_batch_t<float>(h, S, h->pf, cols, nc)
+                 : gmres_batch_t<double>(h, S, h->pd, cols, nc);
+  return mixed ? unit_batch_t<float>(h, S, h->pf, cols, nc) : unit_batch_t<double>(h, S, h->pd, cols, nc);
 }
 
 int jacobi_sweep(biot_handle* h, Sched& S) {
@@ -1010,6 +1089,8 @@ int biot_default_options(biot_options* o) {
   o->ckpt_stride = 16;
   o->replay_segments = 4;
   o->max_sensors = 256;
+  o->inner = BIOT_INNER_RICHARDSON;
+  o->gmres_k = 4;
   return BIOT_OK;
 }
 
@@ -1047,6 +1128,10 @@ int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_mater
   if (o.adjoint && (o.ckpt_stride < 0 || o.replay_segments < 1 || o.max_sensors < 1))
     return fail(nullptr, BIOT_EINVAL, "need ckpt_stride >= 0, replay_segments >= 1, max_sensors >= 1");
   if (o.adjoint && n_samples > 1) return fail(nullptr, BIOT_EINVAL, "the adjoint takes one sample per handle");
+  if (o.inner != BIOT_INNER_RICHARDSON && o.inner != BIOT_INNER_GMRES)
+    return fail(nullptr, BIOT_EINVAL, "unknown inner solver");
+  if (o.inner == BIOT_INNER_GMRES && (o.gmres_k < 1 || o.gmres_k > kGmresMaxK))
+    return fail(nullptr, BIOT_EINVAL, "gmres_k must be in 1..8");
   biot_handle* h = new (std::nothrow) biot_handle();
   if (!h) return fail(nullptr, BIOT_ENOMEM, "out of host memory");
   h->opt = o;
@@ -1318,7 +1403,10 @@ int biot_adjoint(biot_handle* h, const biot_objective* obj, double rtol, int32_t
   out.adjoint_rel_resid = std::max(so.ru, so.rp);
   const auto t1 = std::chrono::steady_clock::now();
   out.seconds_adjoint = std::chrono::duration<double>(t1 - t0).count();
-  if (rc) return rc;
+  if (rc) {
+    if (stats) *stats = out;  // how far the adjoint solve got
+    return rc;
+  }
   h->adj_valid = true;
   const double* lam_top = h->bw.T[h->bw.cur] + size_t(N + 1) * col;
   if (!ckpt) {
@@ -1351,7 +1439,11 @@ int biot_adjoint(biot_handle* h, const biot_objective* obj, double rtol, int32_t
       out.replay_sweeps += sr.sweeps;
       out.replay_groups += 1;
       worst = std::max(worst, std::max(sr.ru, sr.rp));
-      if (rc) return rc;
+      if (rc) {
+        out.replay_rel_resid = worst;
+        if (stats) *stats = out;
+        return rc;
+      }
       launch_grad_partial(h->dim, h->E, col, R.T[R.cur], n0, lam_top, n0 + 1, n0 + L + 1, s, k0,
                           h->gpart, h->st);
       LAUNCHCHK(h);

@@ -1,9 +1,9 @@
 """Pins of the oracle's GMRES(k) unit (CPU only).
 
 * with k equal to the system size, GMRES returns the solution of the system;
-* for k below it, the result is the minimizer of ||b - A x|| over
-  x0 + span{P^{-1} r0, P^{-1}(A P^{-1}) r0, ...}, computed independently from
-  the explicit Krylov matrix with numpy's least squares;
+* for k below it, the result is the minimizer of ||P^{-1}(b - A x)|| over
+  x0 + span{s0, (P^{-1}A) s0, ...} with s0 = P^{-1} r0, computed independently
+  from the explicit Krylov matrix with numpy's least squares;
 * GMRES units in the inverted iteration converge to backward Euler, in fewer
   sweeps than the damped Richardson units.
 """
@@ -25,7 +25,7 @@ def _system(n=12, seed=0):
 def test_full_dimension_gmres_solves_exactly():
     A, M, b, x0 = _system()
     Minv = np.linalg.inv(M)
-    x = krylov.gmres_right(lambda v: A @ v, lambda v: Minv @ v, b, x0, k=12)
+    x = krylov.gmres_left(lambda v: A @ v, lambda v: Minv @ v, b, x0, k=12)
     np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-10, atol=1e-12)
 
 
@@ -39,18 +39,17 @@ def test_gmres_is_the_krylov_least_squares_minimizer():
     x0 = rng.standard_normal(n)
     Minv = np.linalg.inv(M)
     k = 5
-    x = krylov.gmres_right(lambda v: A @ v, lambda v: Minv @ v, b, x0, k)
-    r0 = b - A @ x0
-    cols, v = [], r0.copy()
+    x = krylov.gmres_left(lambda v: A @ v, lambda v: Minv @ v, b, x0, k)
+    s0 = Minv @ (b - A @ x0)
+    cols, v = [], s0.copy()
     for _ in range(k):
-        z = Minv @ v
-        cols.append(z)
-        v = A @ z
-    Kmat = np.stack(cols, axis=1)               # P^{-1} [r0, A P^{-1} r0, ...]
-    c = np.linalg.lstsq(A @ Kmat, r0, rcond=None)[0]
+        cols.append(v)
+        v = Minv @ (A @ v)
+    Kmat = np.stack(cols, axis=1)               # [s0, P^{-1}A s0, ...]
+    c = np.linalg.lstsq(Minv @ A @ Kmat, s0, rcond=None)[0]
     x_ref = x0 + Kmat @ c
     np.testing.assert_allclose(x, x_ref, rtol=1e-9, atol=1e-12)
-    assert np.linalg.norm(b - A @ x) <= np.linalg.norm(r0)
+    assert np.linalg.norm(Minv @ (b - A @ x)) <= np.linalg.norm(s0)
 
 
 def test_gmres_units_converge_to_backward_euler():
