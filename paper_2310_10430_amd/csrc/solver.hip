@@ -80,10 +80,11 @@ struct Sched {
   std::vector<ColDesc> h_jac[2], h_k4[2], h_wave[2], h_part;
   std::vector<int> wave_off, wave_cnt, part_off, part_cnt;
   int part_key = -1;                  // (parity, depth) of the uploaded partial table
-  // wavefront passes captured as HIP graphs, per trajectory parity, valid for
-  // the step count graph_N (the tables' contents may change between replays)
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // wavefront passes captured as HIP graphs, per trajectory parity, each pass
+  // as a few graphs of consecutive waves; valid for the step count graph_N
+  // (the tables' contents may change between replays)
+  std::vector<hipGraph_t> graph[2];
+  std::vector<hipGraphExec_t> gexec[2];
   int graph_N = -1;
 };
 
@@ -792,8 +793,9 @@ int jacobi_sweep(biot_handle* h, Sched& S) {
 }
 
 int run_waves(biot_handle* h, const Sched& S, const ColDesc* tab, const std::vector<int>& off,
-              const std::vector<int>& cnt, int d) {
-  for (size_t w = 0; w < off.size(); ++w) {
+              const std::vector<int>& cnt, int d, size_t w0 = 0, size_t w1 = size_t(-1)) {
+  w1 = std::min(w1, off.size());
+  for (size_t w = w0; w < w1; ++w) {
     const int wave = int(w) + 1, last_step = wave - d + 1;
     h->cur_copies = (last_step >= 1 && last_step <= S.N) ? 1 : 0;
     int rc = unit_batch(h, S, tab + off[w], cnt[w]);
@@ -825,17 +827,46 @@ int wavefront_partial(biot_handle* h, Sched& S, int d) {
 
 void destroy_graphs(Sched& S) {
   for (int c = 0; c < 2; ++c) {
-    if (S.gexec[c]) (void)hipGraphExecDestroy(S.gexec[c]);
-    if (S.graph[c]) (void)hipGraphDestroy(S.graph[c]);
-    S.gexec[c] = nullptr;
-    S.graph[c] = nullptr;
+    for (auto e : S.gexec[c]) (void)hipGraphExecDestroy(e);
+    for (auto g : S.graph[c]) (void)hipGraphDestroy(g);
+    S.gexec[c].clear();
+    S.graph[c].clear();
   }
   S.graph_N = -1;
 }
 
+// kernel nodes per captured graph: a pass of several hundred waves, each of up
+// to a few hundred launches (GMRES units), is split into graphs of consecutive
+// waves of about this size
+constexpr size_t kGraphNodeBudget = 8192;
+
+// captures waves [w0, w1) of the pass of parity c into one graph
+int capture_waves(biot_handle* h, Sched& S, int c, size_t w0, size_t w1, size_t* nodes) {
+  hipStream_t user = h->st;
+  h->st = h->cap_stream;
+  HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+  int rc = run_waves(h, S, S.desc_wave[c], S.wave_off, S.wave_cnt, h->opt.depth, w0, w1);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->st, &g);
+  h->st = user;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(h, BIOT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  S.graph[c].push_back(g);
+  if (nodes) HIPCHK(h, hipGraphGetNodes(g, nullptr, nodes));
+  hipGraphExec_t x = nullptr;
+  HIPCHK(h, hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
+  S.gexec[c].push_back(x);
+  return BIOT_OK;
+}
+
 // One pass = N + depth - 1 waves.  With use_graph the launch sequence of a
 // pass is captured once per trajectory parity (the descriptor tables, whose
-// device buffers are fixed, hold every pointer) and replayed.
+// device buffers are fixed, hold every pointer) and replayed: the first wave
+// alone, which measures the launches per wave, then chunks of waves of about
+// kGraphNodeBudget launches.
 int wavefront_pass(biot_handle* h, Sched& S) {
   // probes read HIP events, which cannot be timed inside a replayed graph, so
   // a probed pass runs its launches eagerly
@@ -847,21 +878,20 @@ int wavefront_pass(biot_handle* h, Sched& S) {
   }
   if (S.graph_N != S.N) destroy_graphs(S);
   const int c = S.cur;
-  if (!S.gexec[c]) {
-    hipStream_t user = h->st;
-    h->st = h->cap_stream;
-    HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
-    int rc = wavefront_pass_eager(h, S);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(h->st, &g);
-    h->st = user;
-    if (rc) return rc;
-    if (e != hipSuccess) return fail(h, BIOT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    S.graph[c] = g;
-    HIPCHK(h, hipGraphInstantiate(&S.gexec[c], g, nullptr, nullptr, 0));
+  if (S.gexec[c].empty()) {
+    const size_t waves = S.wave_off.size();
+    size_t per_wave = 0;
+    int rc = capture_waves(h, S, c, 0, 1, &per_wave);
+    const size_t chunk = std::max<size_t>(1, kGraphNodeBudget / std::max<size_t>(per_wave, 1));
+    for (size_t w0 = 1; !rc && w0 < waves; w0 += chunk)
+      rc = capture_waves(h, S, c, w0, std::min(waves, w0 + chunk), nullptr);
+    if (rc) {
+      destroy_graphs(S);
+      return rc;
+    }
     S.graph_N = S.N;
   }
-  HIPCHK(h, hipGraphLaunch(S.gexec[c], h->st));
+  for (auto x : S.gexec[c]) HIPCHK(h, hipGraphLaunch(x, h->st));
   S.cur = 1 - S.cur;
   return BIOT_OK;
 }
