@@ -100,13 +100,16 @@ def cpu_baseline(pb, n_sample_steps, X_gpu):
     return info, err
 
 
-def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2):
+def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2, **kw):
     """Solve one workload variant to the same tolerance; time `reps` solves
     after one warm-up and report throughput and the error at the stored oracle
-    samples."""
+    samples.  `kw` overrides solver options (inner solver, preconditioner,
+    depth)."""
     import torch
-    s = BiotSolver(pb, schedule=args.schedule, depth=args.depth, omega=args.omega,
-                   wg_per_cu=args.wg_per_cu, precision=precision)
+    opts = dict(schedule=args.schedule, depth=args.depth, omega=args.omega,
+                wg_per_cu=args.wg_per_cu, precision=precision)
+    opts.update(kw)
+    s = BiotSolver(pb, **opts)
     s.reset()
     s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
     torch.cuda.synchronize()
@@ -121,7 +124,8 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2):
     golden = np.load(os.path.join(ROOT, "tests", "golden", golden_name + ".npz"))
     acc = accuracy_vs_golden(X, golden)
     return {"value": pb.n_dof * pb.n_steps / per, "unit": "dof-timestep updates/s",
-            "ms_per_solve": 1e3 * per, "precision": precision, "sweeps": st["sweeps"],
+            "ms_per_solve": 1e3 * per, "precision": precision, "options": kw,
+            "sweeps": st["sweeps"],
             "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"]),
             "max_rel_err_vs_oracle_samples": max(acc.values()), "accuracy": acc}
 
@@ -432,12 +436,18 @@ def main():
     if not args.no_variants:
         variants = {}
         het = W.large_heterogeneous()
-        for name, prob, gname, prec in (
-                ("large_terzaghi_mixed", pb, "large_terzaghi", "mixed"),
-                ("large_heterogeneous_fp64", het, "large_heterogeneous", "fp64"),
-                ("large_heterogeneous_mixed", het, "large_heterogeneous", "mixed")):
+        gm = dict(inner="gmres", gmres_k=4, depth=8)
+        for name, prob, gname, prec, kw in (
+                ("large_terzaghi_mixed", pb, "large_terzaghi", "mixed", {}),
+                ("large_heterogeneous_fp64", het, "large_heterogeneous", "fp64", {}),
+                ("large_heterogeneous_mixed", het, "large_heterogeneous", "mixed", {}),
+                ("large_terzaghi_gmres4_P1", pb, "large_terzaghi", "fp64", gm),
+                ("large_terzaghi_gmres4_P2", pb, "large_terzaghi", "fp64", dict(gm, precond="P2"))):
             log(f"bench: variant {name}")
-            variants[name] = run_variant(BiotSolver, prob, gname, prec, args)
+            try:
+                variants[name] = run_variant(BiotSolver, prob, gname, prec, args, **kw)
+            except RuntimeError as e:      # a variant that does not converge is reported
+                variants[name] = {"error": str(e), "options": kw, "precision": prec}
 
     adjoint = None
     if not args.no_adjoint:

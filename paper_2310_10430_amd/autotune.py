@@ -47,12 +47,18 @@ def split_groups(problems, split: int):
     split = max(1, min(split, len(order)))
     total = sum(problems[i].n_steps for i in order)
     groups, cur, acc = [], [], 0
-    for i in order:
+    for pos, i in enumerate(order):
+        left = len(order) - pos                 # samples not yet placed, i included
+        need = split - 1 - len(groups)          # cuts still to make
+        if cur and need > 0:
+            target = total * (len(groups) + 1) / split
+            # cut before sample i when that lands closer to the group's share,
+            # or when every remaining sample must start a group of its own
+            if abs(acc + problems[i].n_steps - target) > abs(acc - target) or left <= need:
+                groups.append(cur)
+                cur = []
         cur.append(i)
         acc += problems[i].n_steps
-        if len(groups) < split - 1 and acc >= total * (len(groups) + 1) / split:
-            groups.append(cur)
-            cur = []
     if cur:
         groups.append(cur)
     return groups
