@@ -33,11 +33,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# HBM traffic of the dominant kernel (level-0 displacement Chebyshev step) from
+# two rocprofv3 counter passes (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the
+# factors of a plain 1 GiB copy) over 64-column launches, and the kernel
+# source they were taken with; see profiles/level0_kernels_large_terzaghi_hbm_counters.md
+CHEB_U_TRAFFIC = {"kernels_sha256_prefix": "e39edcf30470788f",
+                  "bytes_per_launch": 383.8e6, "launch_columns": 64,
+                  "algorithmic_bytes_per_launch": 334.4e6}
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def traffic_fields(probe, algo_bytes_avg):
+    """`traffic`: counter-measured HBM bytes per 64-column launch of the dominant
+    kernel (None when the kernel source changed since the counters were taken
+    or another kernel is probed), with the launch shape it was measured on and
+    the same measured/algorithmic ratio applied to the bench's average launch."""
+    import hashlib
+    out = {"traffic": None}
+    if probe != "cheb_u":
+        return out
+    src = os.path.join(ROOT, "paper_2310_10430_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    if not h.startswith(CHEB_U_TRAFFIC["kernels_sha256_prefix"]):
+        return out
+    ratio = CHEB_U_TRAFFIC["bytes_per_launch"] / CHEB_U_TRAFFIC["algorithmic_bytes_per_launch"]
+    out.update(traffic=CHEB_U_TRAFFIC["bytes_per_launch"],
+               traffic_launch_columns=CHEB_U_TRAFFIC["launch_columns"],
+               traffic_over_algorithmic=ratio,
+               traffic_per_average_launch=ratio * algo_bytes_avg)
+    return out
 
 
 def accuracy_vs_golden(X, golden):
@@ -328,8 +358,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--pmc-run", action="store_true",
-                    help="hardware-counter run: 1 GiB reference copy, then exactly two "
-                         "Jacobi-schedule sweeps of the workload (few dispatches), no timing")
+                    help="hardware-counter run: one Jacobi-schedule sweep of the workload in "
+                         "batches of --depth columns (the bench's full-wave launch shape, few "
+                         "dispatches), no timing")
     ap.add_argument("--probe", default="cheb_u",
                     help="kernel timed with HIP events in the timed region")
     ap.add_argument("--no-variants", action="store_true",
@@ -362,11 +393,14 @@ def main():
         log("bench: 1 GiB copy done (counter reference: 1 GiB read, 1 GiB written)")
     pb = W.large_terzaghi()
     if args.pmc_run:
-        s = BiotSolver(pb, schedule="jacobi", omega=args.omega, wg_per_cu=args.wg_per_cu)
-        s.sweep(2)
+        # the wavefront's full-wave launch shape (64 columns) in few dispatches:
+        # one Jacobi sweep in batches of 64 time-step columns
+        s = BiotSolver(pb, schedule="jacobi", omega=args.omega, wg_per_cu=args.wg_per_cu,
+                       max_batch=args.depth)
+        s.sweep(1)
         torch.cuda.synchronize()
         s.close()
-        log("bench: counter run done (2 Jacobi sweeps of 512 columns)")
+        log(f"bench: counter run done (1 Jacobi sweep in batches of {args.depth} columns)")
         return
     log(f"bench: workload 256x256, {pb.n_steps} steps, {pb.n_dof} unknowns; "
         f"schedule={args.schedule} depth={args.depth} omega={args.omega} rtol={args.rtol}")
@@ -486,7 +520,8 @@ def main():
         "accuracy": acc,
         "roofline": {
             "bound": "hbm", "kernel": p["name"], "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, **traffic_fields(args.probe,
+                                                                             bytes_per_launch),
             "avg_launch_us": 1e3 * avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches": p["launches"],
         },
