@@ -97,6 +97,17 @@ def test_divergence_theorem_for_coupling():
     assert abs((asm.B.T @ u2).sum() + 0.7 * 1.5) < 1e-13
 
 
+def test_divergence_theorem_for_coupling_3d():
+    pb = W.terzaghi_problem(4, 2, dim=3, alpha=0.7)
+    asm = fem.assemble(pb)
+    x = pb.xyz
+    u = np.stack([0 * x[:, 0], x[:, 1], 0 * x[:, 2]], axis=1).ravel()      # div u = 1
+    assert abs((asm.B.T @ u).sum() + 0.7) < 1e-13
+    # u = (x z, 0, y): div u = z, int_cube z = 1/2
+    u2 = np.stack([x[:, 0] * x[:, 2], 0 * x[:, 1], x[:, 1]], axis=1).ravel()
+    assert abs((asm.B.T @ u2).sum() + 0.7 * 0.5) < 1e-13
+
+
 def test_elasticity_matches_voigt_form():
     """Element matrix equals vol * Bv' D Bv with the plane-strain Voigt matrices."""
     rng = np.random.default_rng(3)

@@ -13,10 +13,21 @@ from paper_2310_10430_amd import workloads as W
 from oracle import analytic, fem, sequential as seq
 
 
-def test_dense_space_time_brute_force():
+def _tiny_problem(dim):
+    if dim == 2:
+        pb = W.heterogeneous_problem(3, 5, field_seed=7, young_seed=8)
+        pb.dt = 0.05
+        return pb
+    rng = np.random.default_rng(9)
+    ne = 6 * 2 ** 3
+    return W.terzaghi_problem(2, 4, dim=3, dt=0.05, young=rng.uniform(5e3, 2e4, ne),
+                              perm=np.exp(rng.normal(np.log(1e-2), 1.0, ne)))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dense_space_time_brute_force(dim):
     """Assemble [AA; -A' AA; ...] densely and solve it with LAPACK."""
-    pb = W.heterogeneous_problem(3, 5, field_seed=7, young_seed=8)
-    pb.dt = 0.05
+    pb = _tiny_problem(dim)
     orc = seq.BiotOracle(pb)
     X = orc.solve_sequential()
     fr = orc.free
@@ -48,6 +59,22 @@ def test_small_terzaghi_reaches_exact_steady_state():
     assert np.abs(Y[-1, :, 1] - uy).max() < 1e-12 * np.abs(uy).max()
     assert np.abs(Y[-1, :, 0]).max() < 1e-12 * np.abs(uy).max()
     assert np.abs(Y[-1, :, 2]).max() < 1e-12
+
+
+def test_cube_terzaghi_reaches_exact_steady_state():
+    """3D column on Kuhn tetrahedra: u_z = -z/(lambda+2mu), u_x = u_y = 0,
+    p = 0 is linear, hence in the P1 space, and is the steady state under
+    roller sides, fixed base and a unit top load."""
+    pb = W.terzaghi_problem(4, 32, dim=3)
+    orc = seq.BiotOracle(pb)
+    Y = orc.trajectory_node_major(orc.solve_sequential())
+    lam, mu = fem.lame(1e4, 0.3)
+    uz = -pb.xyz[:, 2] / (lam + 2 * mu)
+    assert np.abs(Y[-1, :, 2] - uz).max() < 1e-12 * np.abs(uz).max()
+    assert np.abs(Y[-1, :, :2]).max() < 1e-12 * np.abs(uz).max()
+    assert np.abs(Y[-1, :, 3]).max() < 1e-12
+    # and the transient is not trivially at rest: the first step is far from it
+    assert np.abs(Y[1, :, 2] - uz).max() > 1e-3 * np.abs(uz).max()
 
 
 def test_backward_error_per_step():
