@@ -70,22 +70,43 @@ def traffic_fields(probe, algo_bytes_avg):
     return out
 
 
-def accuracy_vs_golden(X, golden):
-    """Errors of the GPU trajectory X [N+1, nn, 3] at the stored oracle samples."""
+def sampled_errors(X, dofs, samp, norm_u, norm_p):
+    """Errors of the GPU trajectory X [N+1, nn, dim+1] at stored oracle samples
+    (unknowns `dofs` of the node-major layout, values samp[n, k]) and in the
+    per-step field norms; each relative to the largest oracle value."""
+    d1 = X.shape[2]
     flat = X.reshape(X.shape[0], -1)
-    dofs = golden["dofs"]
-    samp = golden["samples"]
     got = flat[:, dofs]
-    is_p = (dofs % 3) == 2
+    is_p = (dofs % d1) == d1 - 1
     out = {}
     for name, m in (("u", ~is_p), ("p", is_p)):
-        ref = samp[:, m]
-        out[f"sampled_{name}"] = float(np.abs(got[:, m] - ref).max() / np.abs(ref).max())
-    nu = np.linalg.norm(X[..., :2].reshape(X.shape[0], -1), axis=1)
-    npn = np.linalg.norm(X[..., 2], axis=1)
-    out["norms_u"] = float(np.abs(nu - golden["norm_u"]).max() / golden["norm_u"].max())
-    out["norms_p"] = float(np.abs(npn - golden["norm_p"]).max() / golden["norm_p"].max())
+        if m.any():
+            ref = samp[:, m]
+            out[f"sampled_{name}"] = float(np.abs(got[:, m] - ref).max() / np.abs(ref).max())
+    nu = np.linalg.norm(X[..., : d1 - 1].reshape(X.shape[0], -1), axis=1)
+    npn = np.linalg.norm(X[..., d1 - 1], axis=1)
+    out["norms_u"] = float(np.abs(nu - norm_u).max() / norm_u.max())
+    out["norms_p"] = float(np.abs(npn - norm_p).max() / norm_p.max())
     return out
+
+
+def accuracy_vs_golden(X, golden):
+    """Errors of the GPU trajectory at the stored oracle samples of a workload."""
+    return sampled_errors(X, golden["dofs"], golden["samples"], golden["norm_u"],
+                          golden["norm_p"])
+
+
+def steady_state_error(X, pb):
+    """The consolidation column's final state against its closed form: the
+    vertical displacement -x_up / (lambda + 2 mu), zero lateral displacement and
+    zero pressure (homogeneous materials, E = 1e4, nu = 0.3)."""
+    lam = 1e4 * 0.3 / (1.3 * 0.4)
+    mu = 1e4 / 2.6
+    up = pb.dim - 1
+    ref = -pb.xyz[:, up] / (lam + 2 * mu)
+    err = np.abs(X[-1, :, up] - ref).max()
+    err = max(err, np.abs(X[-1, :, :up]).max())
+    return float(max(err / np.abs(ref).max(), np.abs(X[-1, :, pb.dim]).max()))
 
 
 def cpu_baseline(pb, n_sample_steps, X_gpu):
@@ -232,6 +253,24 @@ def _max_rel_diff(a, b):
                for sl in (slice(0, d), slice(d, d + 1)))
 
 
+def batched_oracle_errors(trajs):
+    """Worst error over the 64 samples at their stored oracle samples and step
+    norms (None when the stored values are absent)."""
+    gpath = os.path.join(ROOT, "tests", "golden", "batched64.npz")
+    if not os.path.exists(gpath):
+        return None
+    g = np.load(gpath)
+    worst = {}
+    for i, X in trajs.items():
+        a, b = int(g["offsets"][i]), int(g["offsets"][i + 1])
+        e = sampled_errors(X.cpu().numpy(), g["dofs"][i], g["samples"][a:b], g["norm_u"][a:b],
+                           g["norm_p"][a:b])
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    worst["max"] = max(worst.values())
+    return worst
+
+
 def run_batched(args):
     """64 independent samples on uneven meshes (sizes from {32,48,64,96,128},
     128..512 steps, own permeability field and moduli each), solved to the same
@@ -255,7 +294,8 @@ def run_batched(args):
     wall, st, ref = autotune.solve_groups([[it] for b in buckets for it in b], args.rtol, "fp64",
                                           max_sweeps=args.max_sweeps, keep=True)
     res["per_sample_fp64"] = {"seconds": wall, "value": real / wall,
-                              "sweeps_max": max(x["sweeps"] for x in st)}
+                              "sweeps_max": max(x["sweeps"] for x in st),
+                              "max_rel_err_vs_oracle": batched_oracle_errors(ref)}
     for prec in ("fp64", "mixed"):
         t0 = time.perf_counter()
         choices = [autotune.tune([pb for _, pb in b], precision=prec) for b in buckets]
@@ -269,10 +309,12 @@ def run_batched(args):
         wall, st, tr = autotune.solve_groups(groups, args.rtol, prec, wpcs=wpcs,
                                              max_sweeps=args.max_sweeps, keep=True)
         diff = max(_max_rel_diff(tr[i], ref[i]) for i in ref)
+        err = batched_oracle_errors(tr)
         res[f"batched_{prec}"] = {
             "seconds": wall, "value": real / wall, "handles": len(groups),
             "sweeps_max": max(x["sweeps"] for x in st),
             "max_rel_diff_vs_per_sample_fp64": diff, "tuning_s": tune_s,
+            "max_rel_err_vs_oracle": err,
             "choices": {str(n): {"split": ch["split"], "wg_per_cu": ch["wg_per_cu"],
                                  "cached": ch["cached"]} for n, ch in zip(sizes, choices)}}
         del tr
@@ -290,6 +332,9 @@ def run_cube(args):
     pb = W.terzaghi_problem(40, 256, dim=3)
     res = {"workload": "cube40: 40^3 unit cube, Kuhn tetrahedra, 275684 unknowns, 256 steps "
                        "dt=1/256, E=1e4 nu=0.3 K=1e-2", "rtol": args.rtol}
+    gpath = os.path.join(ROOT, "tests", "golden", "cube40.npz")
+    golden = np.load(gpath) if os.path.exists(gpath) else None
+    res["oracle_golden"] = golden is not None
     for prec in ("fp64", "mixed"):
         t0 = time.perf_counter()
         s = BiotSolver(pb, schedule="wavefront", depth=args.depth, omega=args.omega,
@@ -306,6 +351,13 @@ def run_cube(args):
         s.close()
         res[prec] = {"seconds": per, "value": pb.n_dof * pb.n_steps / per, "setup_s": setup,
                      "sweeps": st["sweeps"], "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"])}
+        Xn = X.cpu().numpy()
+        acc = {"final_step_vs_steady_state": steady_state_error(Xn, pb)}
+        if golden is not None:
+            acc.update(accuracy_vs_golden(Xn, golden))
+        res[prec]["accuracy"] = acc
+        res[prec]["max_rel_err_vs_oracle"] = max(acc.values())
+        del Xn
         if prec == "fp64":
             Xf = X
         else:
@@ -454,10 +506,7 @@ def main():
     s.close()
     golden = np.load(os.path.join(ROOT, "tests", "golden", "large_terzaghi.npz"))
     acc = accuracy_vs_golden(X, golden)
-    lam = 1e4 * 0.3 / (1.3 * 0.4)
-    mu = 1e4 / 2.6
-    uy = -pb.xyz[:, 1] / (lam + 2 * mu)
-    acc["final_step_vs_steady_state"] = float(np.abs(X[-1, :, 1] - uy).max() / np.abs(uy).max())
+    acc["final_step_vs_steady_state"] = steady_state_error(X, pb)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -103,7 +103,10 @@ __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
 // ---------------------------------------------------------------------------
 // fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1} (FP64), the
 // coupled right-hand side norms, and the first (pointwise) Chebyshev step of
-// the displacement V-cycle; r and that step are stored as T.
+// the displacement V-cycle; r and that step are stored as T.  A first step
+// from zero equals its own increment, so only x is stored (the next step
+// reads x as the previous increment; the same holds for k_restrict, k_pstage
+// and k_pre1).
 // ADJ: the adjoint recursion run forward in reversed time, whose coupling is
 // A'^T = [0 B; 0 -C_beta] applied to the previous column and whose load is the
 // pressure-row vector gload[step-1] (no traction load):
@@ -113,8 +116,7 @@ template <int DIM, typename T, bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
                                                      T* __restrict__ ru, T* __restrict__ rp,
-                                                     T* __restrict__ xa, T* __restrict__ d,
-                                                     double inv_theta,
+                                                     T* __restrict__ xa, double inv_theta,
                                                      double* __restrict__ partials, int pstride) {
   // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
   constexpr int NQ = DIM == 2 ? 2 : 1;
@@ -260,7 +262,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
             for (int k = 0; k < DIM; ++k) z += Di[a * DIM + k] * au[q][k];
             z *= inv_theta;
             xa[cu + size_t(v) * DIM + a] = T(z);
-            d[cu + size_t(v) * DIM + a] = T(z);
           }
         }
       }
@@ -329,6 +330,10 @@ __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T
 
 // ---------------------------------------------------------------------------
 // Chebyshev step on one level:  d <- c1 d + c2 D^{-1}(b - K xin);  xout = xin + d.
+// wd = 0 leaves d unwritten (the last step before a residual or at the end of
+// the smoothing, after which d is dead); dx = 1 takes the previous increment
+// to be xin itself (the step after a first step from zero, whose producer
+// stores only x).
 // UPD (pressure field, level 0, last step): instead of xout, writes the outer
 // update X^{n,m} = X^{n,m-1} + omega [z_u; xin + d] (FP64) through the column
 // descriptors.  FINE only makes the level-0 launches a distinct symbol.
@@ -338,7 +343,8 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
                                                  const T* __restrict__ b,
                                                  const T* __restrict__ xin,
                                                  T* __restrict__ xout, T* __restrict__ d, int nc,
-                                                 T c1, T c2, const ColDesc* __restrict__ cols,
+                                                 T c1, T c2, int wd, int dx,
+                                                 const ColDesc* __restrict__ cols,
                                                  const T* __restrict__ zu, double omega) {
   // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
   constexpr int NQ = DIM == 2 ? 2 : 1;
@@ -420,8 +426,9 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
           T z = T(0);
 #pragma unroll
           for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
-          const T dn = (c1 != T(0) ? c1 * d[base + a] : T(0)) + c2 * z;
-          if (!UPD) d[base + a] = dn;
+          const T dp = c1 == T(0) ? T(0) : (dx ? xs[q][a] : d[base + a]);
+          const T dn = c1 * dp + c2 * z;
+          if (!UPD && wd) d[base + a] = dn;
           xn[a] = xs[q][a] + dn;
         }
         if constexpr (!UPD) {
@@ -554,7 +561,7 @@ template <int DIM, int C, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<T> Lc, int isA,
                                                      const T* __restrict__ rf,
                                                      T* __restrict__ bc, T* __restrict__ xa,
-                                                     T* __restrict__ d, T inv_theta, int nc) {
+                                                     T inv_theta, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int I = blockIdx.y * kBlock + threadIdx.x;
   if (I >= Lc.nn) return;
@@ -596,7 +603,6 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
       for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + I] * acc[k];
       z *= inv_theta;
       xa[size_t(c) * sc + size_t(I) * C + a] = z;
-      d[size_t(c) * sc + size_t(I) * C + a] = z;
     }
   }
 }
@@ -612,15 +618,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
 // ---------------------------------------------------------------------------
 namespace tail {
 
+// workgroup size of the fused tail: the levels are small, so a phase is one or
+// two nodes per thread and its cost is the latency of the operator loads;
+// more threads keep more of them in flight (3D rows need the registers of 256)
+template <int DIM>
+constexpr int block() { return DIM == 2 ? 1024 : 256; }
+
 // All routines work on one copy of the grid (one sample of a batch): `base`
 // is the copy's first node in the level's arrays; LDS vectors hold only the
 // copy's grid nodes (local numbering).
 
 // x = d = inv_theta D^{-1} b
-template <int C, typename T>
+template <int DIM, int C, typename T>
 __device__ inline void first_step(const LevelView<T>& L, int base, const T* b, T* x, T* d, T it) {
   const T* Dg = C > 1 ? L.Ainv : L.Sinv;
-  for (int v = threadIdx.x; v < L.nreal; v += kBlock) {
+  for (int v = threadIdx.x; v < L.nreal; v += block<DIM>()) {
     const int g = base + v;
 #pragma unroll
     for (int a = 0; a < C; ++a) {
@@ -642,7 +654,7 @@ __device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T
   const T* K = C > 1 ? L.A : L.S;
   const T* Dg = C > 1 ? L.Ainv : L.Sinv;
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < L.nreal; v += kBlock) {
+  for (int v = threadIdx.x; v < L.nreal; v += block<DIM>()) {
     const int g = base + v;
     T acc[C], xs[C];
 #pragma unroll
@@ -681,7 +693,7 @@ __device__ inline void residual(const LevelView<T>& L, int base, const T* b, con
   constexpr int W = DIM == 2 ? 7 : 15;
   const T* K = C > 1 ? L.A : L.S;
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < L.nreal; v += kBlock) {
+  for (int v = threadIdx.x; v < L.nreal; v += block<DIM>()) {
     const int g = base + v;
     T acc[C];
 #pragma unroll
@@ -710,7 +722,7 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, const Leve
   constexpr int W = DIM == 2 ? 7 : 15;
   const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
   const int bit0 = C > 1 ? 0 : DIM;
-  for (int I = threadIdx.x; I < Lc.nreal; I += kBlock) {
+  for (int I = threadIdx.x; I < Lc.nreal; I += block<DIM>()) {
     int ci, cj, ck;
     node_coords<DIM>(I, mc, ci, cj, ck);
     T acc[C];
@@ -752,7 +764,7 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, const Leve
 template <int DIM, int C, typename T>
 __device__ inline void prolong(const LevelView<T>& Lf, int basef, const LevelView<T>& Lc,
                                int basec, const T* xin, const T* xc, T* xout) {
-  for (int v = threadIdx.x; v < Lf.nreal; v += kBlock) {
+  for (int v = threadIdx.x; v < Lf.nreal; v += block<DIM>()) {
     int p0, p1;
     unsigned pm;
     prolong_parents<DIM, C>(Lf, Lc, C > 1 ? 0 : DIM, basef + v, p0, p1, pm);
@@ -773,7 +785,7 @@ __device__ inline void prolong(const LevelView<T>& Lf, int basef, const LevelVie
 
 // one workgroup per (column, copy)
 template <int DIM, int C, typename T>
-__global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* __restrict__ b_t,
+__global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> TD, const T* __restrict__ b_t,
                                                         T* __restrict__ x_t) {
   extern __shared__ double tail_raw[];
   T* lds = reinterpret_cast<T*>(tail_raw);
@@ -787,14 +799,14 @@ __global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* 
   unsigned alt = 0;
   const int n0 = TD.L[0].nreal * C;
   const size_t g0 = (size_t(c) * TD.L[0].nn + base(0)) * C;
-  for (int i = threadIdx.x; i < n0; i += kBlock) vec(0, 0)[i] = b_t[g0 + i];
+  for (int i = threadIdx.x; i < n0; i += tail::block<DIM>()) vec(0, 0)[i] = b_t[g0 + i];
   __syncthreads();
   // descend
   for (int i = 0; i + 1 < nl; ++i) {
     const LevelView<T>& L = TD.L[i];
     const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
     if (i == 0) {
-      tail::first_step<C, T>(L, base(0), vec(0, 0), vec(0, 1), vec(0, 3), T(1.0 / theta));
+      tail::first_step<DIM, C, T>(L, base(0), vec(0, 0), vec(0, 1), vec(0, 3), T(1.0 / theta));
       __syncthreads();
     }
     int xi = 1;  // x0
@@ -822,7 +834,7 @@ __global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* 
     const T* bb = vec(nl - 1, 0);
     T* xx = vec(nl - 1, 1);
     const T* M = TD.Minv + size_t(cp) * n * n;
-    for (int r = threadIdx.x; r < n; r += kBlock) {
+    for (int r = threadIdx.x; r < n; r += tail::block<DIM>()) {
       T acc = T(0);
       const T* row = M + size_t(r) * n;
       for (int j = 0; j < n; ++j) acc += row[j] * bb[j];
@@ -857,10 +869,10 @@ __global__ __launch_bounds__(kBlock) void k_vcycle_tail(TailDev<T> TD, const T* 
     alt = (alt & ~(1u << i)) | (xi == 2 ? 1u << i : 0u);
   }
   const T* res = vec(0, ((alt & 1u) ? 2 : 1));
-  for (int i = threadIdx.x; i < n0; i += kBlock) x_t[g0 + i] = res[i];
+  for (int i = threadIdx.x; i < n0; i += tail::block<DIM>()) x_t[g0 + i] = res[i];
   // padding nodes of the copy keep a zero correction
   const int npad = (TD.L[0].nn1 - TD.L[0].nreal) * C;
-  for (int i = threadIdx.x; i < npad; i += kBlock) x_t[g0 + n0 + i] = T(0);
+  for (int i = threadIdx.x; i < npad; i += tail::block<DIM>()) x_t[g0 + n0 + i] = T(0);
 }
 
 // coarsest level: x = M^{-1} b with the dense inverse, one workgroup per column
@@ -894,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
                                                    int p1, const T* __restrict__ zu,
                                                    const T* __restrict__ rp,
                                                    T* __restrict__ t_out, T* __restrict__ xa,
-                                                   T* __restrict__ d, T inv_theta, int nc) {
+                                                   T inv_theta, int nc) {
   // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
   constexpr int NQ = DIM == 2 ? 2 : 1;
   constexpr int W = DIM == 2 ? 7 : 15;
@@ -939,7 +951,6 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
         t_out[idx] = acc[q];
         const T z = si * acc[q] * inv_theta;
         xa[idx] = z;
-        d[idx] = z;
       }
     }
   });
@@ -1045,11 +1056,11 @@ __global__ __launch_bounds__(kBlock) void k_pack(int nn, const T* __restrict__ z
   Z[(c * nn + v) * D1 + DIM] = double(zp[c * nn + v]);
 }
 
-// first Chebyshev step from a zero iterate: xa = d = D^{-1} b / theta
+// first Chebyshev step from a zero iterate: xa = D^{-1} b / theta (also the
+// step's increment)
 template <int C, typename T>
 __global__ __launch_bounds__(kBlock) void k_pre1(LevelView<T> L, int isA, const T* __restrict__ b,
-                                                 T* __restrict__ xa, T* __restrict__ d,
-                                                 T inv_theta) {
+                                                 T* __restrict__ xa, T inv_theta) {
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= L.nn) return;
   const size_t base = size_t(blockIdx.x) * L.nn * C + size_t(v) * C;
@@ -1061,7 +1072,6 @@ __global__ __launch_bounds__(kBlock) void k_pre1(LevelView<T> L, int isA, const 
     for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + v] * b[base + k];
     z *= inv_theta;
     xa[base + a] = z;
-    d[base + a] = z;
   }
 }
 
@@ -1120,55 +1130,57 @@ dim3 balanced_grid(const void* fn, int nn, int nc, int wpc) {
 
 template <int DIM, bool ADJ, typename T>
 static void residual_dispatch(const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                              T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials,
+                              T* ru, T* rp, T* xa, double inv_theta, double* partials,
                               int pstride, int wpc, hipStream_t st) {
-  BIOT_LAUNCH_BALANCED((k_residual<DIM, T, ADJ>), L.nn, nc, wpc, st, L, F, cols, nc, ru, rp, xa, d,
+  BIOT_LAUNCH_BALANCED((k_residual<DIM, T, ADJ>), L.nn, nc, wpc, st, L, F, cols, nc, ru, rp, xa,
                        inv_theta, partials, pstride);
 }
 
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                     T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials, int pstride,
+                     T* ru, T* rp, T* xa, double inv_theta, double* partials, int pstride,
                      int wpc, bool adj, hipStream_t st) {
   if (dim == 2) {
-    if (adj) residual_dispatch<2, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
-    else residual_dispatch<2, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
+    if (adj) residual_dispatch<2, true, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
+    else residual_dispatch<2, false, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
   } else {
-    if (adj) residual_dispatch<3, true, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
-    else residual_dispatch<3, false, T>(L, F, cols, nc, ru, rp, xa, d, inv_theta, partials, pstride, wpc, st);
+    if (adj) residual_dispatch<3, true, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
+    else residual_dispatch<3, false, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
   }
 }
 
 template <int DIM, int C, bool UPD, typename T>
 static void cheb_dispatch(const LevelView<T>& L, bool is_A, const T* b, const T* xin, T* xout,
-                          T* d, int nc, double c1, double c2, const ColDesc* cols, const T* zu,
-                          double omega, int wpc, bool fine, hipStream_t st) {
+                          T* d, int nc, double c1, double c2, bool wd, bool dx,
+                          const ColDesc* cols, const T* zu, double omega, int wpc, bool fine,
+                          hipStream_t st) {
   if (fine) {
     BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, true, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
-                         xout, d, nc, T(c1), T(c2), cols, zu, omega);
+                         xout, d, nc, T(c1), T(c2), int(wd), int(dx), cols, zu, omega);
   } else if constexpr (!UPD) {
     BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, false, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
-                         xout, d, nc, T(c1), T(c2), cols, zu, omega);
+                         xout, d, nc, T(c1), T(c2), int(wd), int(dx), cols, zu, omega);
   }
 }
 
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
-                 T* xout, T* d, int nc, double c1, double c2, const ColDesc* upd, const T* zu,
-                 double omega, int wpc, bool fine, hipStream_t st) {
+                 T* xout, T* d, int nc, double c1, double c2, bool wd, bool dx,
+                 const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
+                 hipStream_t st) {
   if (dim == 2) {
     if (comps == 1) {
-      if (upd) cheb_dispatch<2, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
-      else cheb_dispatch<2, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
+      if (upd) cheb_dispatch<2, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
+      else cheb_dispatch<2, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
     } else {
-      cheb_dispatch<2, 2, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
+      cheb_dispatch<2, 2, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
     }
   } else {
     if (comps == 1) {
-      if (upd) cheb_dispatch<3, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
-      else cheb_dispatch<3, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
+      if (upd) cheb_dispatch<3, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
+      else cheb_dispatch<3, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
     } else {
-      cheb_dispatch<3, 3, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, upd, zu, omega, wpc, fine, st);
+      cheb_dispatch<3, 3, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
     }
   }
 }
@@ -1187,16 +1199,16 @@ void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A,
 
 template <typename T>
 void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
-                     bool is_A, const T* rf, T* bc, T* xa_c, T* d_c, double inv_theta_c, int nc,
+                     bool is_A, const T* rf, T* bc, T* xa_c, double inv_theta_c, int nc,
                      hipStream_t st) {
   const dim3 g = col_grid(nc, Lc.nn);
   const T it = T(inv_theta_c);
   if (dim == 2) {
-    if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
-    else hipLaunchKernelGGL((k_restrict<2, 2, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
+    else hipLaunchKernelGGL((k_restrict<2, 2, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
   } else {
-    if (comps == 1) hipLaunchKernelGGL((k_restrict<3, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
-    else hipLaunchKernelGGL((k_restrict<3, 3, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, d_c, it, nc);
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<3, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
+    else hipLaunchKernelGGL((k_restrict<3, 3, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
   }
 }
 
@@ -1233,20 +1245,22 @@ void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T*
   const size_t lds = tail_lds_bytes(nnl, TD.nlev, comps, int(sizeof(T)));
   const dim3 g(nc * TD.L[0].copies);
   if (dim == 2) {
-    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T>), g, dim3(kBlock), lds, st, TD, b, x);
-    else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T>), g, dim3(kBlock), lds, st, TD, b, x);
+    const dim3 tb(tail::block<2>());
+    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T>), g, tb, lds, st, TD, b, x);
+    else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T>), g, tb, lds, st, TD, b, x);
   } else {
-    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<3, 1, T>), g, dim3(kBlock), lds, st, TD, b, x);
-    else hipLaunchKernelGGL((k_vcycle_tail<3, 3, T>), g, dim3(kBlock), lds, st, TD, b, x);
+    const dim3 tb(tail::block<3>());
+    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<3, 1, T>), g, tb, lds, st, TD, b, x);
+    else hipLaunchKernelGGL((k_vcycle_tail<3, 3, T>), g, tb, lds, st, TD, b, x);
   }
 }
 
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
-                   T* t, T* xa, T* d, double inv_theta, int nc, int wpc, hipStream_t st) {
+                   T* t, T* xa, double inv_theta, int nc, int wpc, hipStream_t st) {
   const T it = T(inv_theta);
-  if (dim == 2) BIOT_LAUNCH_BALANCED((k_pstage<2, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc);
-  else BIOT_LAUNCH_BALANCED((k_pstage<3, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, d, it, nc);
+  if (dim == 2) BIOT_LAUNCH_BALANCED((k_pstage<2, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, it, nc);
+  else BIOT_LAUNCH_BALANCED((k_pstage<3, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, it, nc);
 }
 
 template <typename T>
@@ -1258,14 +1272,14 @@ void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* z
 }
 
 template <typename T>
-void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa, T* d,
+void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa,
                  double inv_theta, int nc, hipStream_t st) {
   const dim3 g = col_grid(nc, L.nn);
   const T it = T(inv_theta);
   switch (comps) {
-    case 1: hipLaunchKernelGGL((k_pre1<1, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, it); break;
-    case 2: hipLaunchKernelGGL((k_pre1<2, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, it); break;
-    default: hipLaunchKernelGGL((k_pre1<3, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, d, it); break;
+    case 1: hipLaunchKernelGGL((k_pre1<1, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, it); break;
+    case 2: hipLaunchKernelGGL((k_pre1<2, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, it); break;
+    default: hipLaunchKernelGGL((k_pre1<3, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, it); break;
   }
 }
 
@@ -1299,23 +1313,23 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
 // explicit instantiations for the two preconditioner precisions
 #define BIOT_INSTANTIATE(T)                                                                      \
   template void launch_residual<T>(int, const LevelDev&, const FineDev&, const ColDesc*, int, T*, \
-                                   T*, T*, T*, double, double*, int, int, bool, hipStream_t);    \
+                                   T*, T*, double, double*, int, int, bool, hipStream_t);        \
   template void launch_cheb<T>(int, int, const LevelView<T>&, bool, const T*, const T*, T*, T*,  \
-                               int, double, double, const ColDesc*, const T*, double, int, bool, \
-                               hipStream_t);                                                      \
+                               int, double, double, bool, bool, const ColDesc*, const T*, double, \
+                               int, bool, hipStream_t);                                           \
   template void launch_level_residual<T>(int, int, const LevelView<T>&, bool, const T*,          \
                                          const T*, T*, int, int, hipStream_t);                    \
   template void launch_restrict<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,     \
-                                   const T*, T*, T*, T*, double, int, hipStream_t);               \
+                                   const T*, T*, T*, double, int, hipStream_t);                   \
   template void launch_prolong<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,      \
                                   const T*, const T*, T*, int, int, hipStream_t);                 \
   template void launch_coarse_solve<T>(int, int, int, const T*, const T*, T*, int, hipStream_t); \
   template void launch_vcycle_tail<T>(int, int, const TailDev<T>&, const T*, T*, int, hipStream_t); \
   template void launch_pstage<T>(int, const LevelView<T>&, const T*, bool, const T*, const T*,   \
-                                 T*, T*, T*, double, int, int, hipStream_t);                      \
+                                 T*, T*, double, int, int, hipStream_t);                          \
   template void launch_update<T>(int, int, const ColDesc*, const T*, const T*, double, int,      \
                                  hipStream_t);                                                    \
-  template void launch_pre1<T>(int, const LevelView<T>&, bool, const T*, T*, T*, double, int,    \
+  template void launch_pre1<T>(int, const LevelView<T>&, bool, const T*, T*, double, int,        \
                                hipStream_t);                                                      \
   template void launch_unpack<T>(int, int, const double*, T*, T*, int, hipStream_t);             \
   template void launch_pack<T>(int, int, const T*, const T*, double*, int, hipStream_t);

@@ -57,21 +57,25 @@ struct ColDesc {
 // `adj`: the adjoint recursion (coupling A'^T, load F.gload; see k_residual)
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                     T* ru, T* rp, T* xa, T* d, double inv_theta, double* partials,
+                     T* ru, T* rp, T* xa, double inv_theta, double* partials,
                      int partial_stride, int wpc, bool adj, hipStream_t st);
 // Chebyshev step d <- c1 d + c2 D^{-1}(b - K xin), xout = xin + d.  With `upd`
 // (pressure field, level 0) the step writes the outer update
 // X^{n,m} = X^{n,m-1} + omega [zu; xin + d] through the descriptors instead.
+// wd = false skips storing d (dead after the step); dx = true takes the
+// previous d to be xin (the step after a first step from zero: the producers
+// of a first step store only x).
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
-                 T* xout, T* d, int nc, double c1, double c2, const ColDesc* upd, const T* zu,
-                 double omega, int wpc, bool fine, hipStream_t st);
+                 T* xout, T* d, int nc, double c1, double c2, bool wd, bool dx,
+                 const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
+                 hipStream_t st);
 template <typename T>
 void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
                            const T* x, T* r, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
-                     bool is_A, const T* rf, T* bc, T* xa_c, T* d_c, double inv_theta_c, int nc,
+                     bool is_A, const T* rf, T* bc, T* xa_c, double inv_theta_c, int nc,
                      hipStream_t st);
 template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
@@ -87,7 +91,9 @@ void launch_coarse_solve(int n, int stride, int copies, const T* Minv, const T* 
 // right-hand side b (no first Chebyshev step yet) is read and whose V-cycle
 // result is written to x; L[nlev-1] is the densely solved coarsest level.
 constexpr int kTailMaxLevels = 8;
-constexpr size_t kTailMaxLds = 64 * 1024;
+// LDS budget of the fused V-cycle tail: gfx950's 160 KB per workgroup (capped
+// at bind by what the device reports)
+constexpr size_t kTailMaxLds = 160 * 1024;
 template <typename T>
 struct TailDev {
   int nlev, degree;
@@ -102,12 +108,12 @@ void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T*
                         hipStream_t st);
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
-                   T* t, T* xa, T* d, double inv_theta, int nc, int wpc, hipStream_t st);
+                   T* t, T* xa, double inv_theta, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* zp, double omega,
                    int nc, hipStream_t st);
 template <typename T>
-void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa, T* d,
+void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa,
                  double inv_theta, int nc, hipStream_t st);
 template <typename T>
 void launch_unpack(int dim, int nn, const double* X, T* ru, T* rp, int nc, hipStream_t st);

@@ -148,6 +148,7 @@ struct biot_handle {
   struct Acc { uint64_t launches = 0; double ms = 0, bytes = 0; };
   bool prof = false;
   unsigned prof_mask = 0;  // which probes record events
+  size_t tail_lds = kTailMaxLds;  // LDS a fused tail may use (device limit, at bind)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
   std::vector<Pending> pending;
@@ -195,9 +196,9 @@ struct Bump {
   }
 };
 
-// The coarsest levels whose V-cycle vectors fit in kTailMaxLds of LDS run as
-// one fused launch; level 0 never does (its steps are fused with the residual
-// and the update).
+// The coarsest levels whose V-cycle vectors fit in the LDS of one workgroup
+// (kTailMaxLds, or less if the device allows less) run as one fused launch;
+// level 0 never does (its steps are fused with the residual and the update).
 template <typename T>
 void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
   const int last = h->nlev - 1, C = is_A ? h->dim : 1;
@@ -209,7 +210,7 @@ void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
     if (n > kTailMaxLevels) continue;
     int nnl[kTailMaxLevels];
     for (int i = 0; i < n; ++i) nnl[i] = h->P.levels[l + i].nreal;
-    if (tail_lds_bytes(nnl, n, C, int(sizeof(T))) > kTailMaxLds) continue;
+    if (tail_lds_bytes(nnl, n, C, int(sizeof(T))) > std::min(kTailMaxLds, h->tail_lds)) continue;
     t = l;
     break;
   }
@@ -544,13 +545,13 @@ struct ProbeScope {
 // `t` = bytes per value of the preconditioner precision
 double bytes_residual(const biot_handle* h, int nc, bool write_r, bool pre, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
-  double per_col = 8 * D1 * 2 + (write_r ? t * (d + 1) : 0) + (pre ? 2 * t * d : 0);
+  double per_col = 8 * D1 * 2 + (write_r ? t * (d + 1) : 0) + (pre ? t * d : 0);
   double mat = W * (d * d + 2 * d + 2) * 8 + 4 * W + 8 * D1 + (pre ? 8 * d * d : 0);
   return nc * nn * per_col + nn * mat;
 }
-double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool upd, int t) {
+double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool upd, bool wd, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
-  double per_col = double(t) * C * (2 + (c1 ? 1 : 0) + (upd ? 0 : 2));
+  double per_col = double(t) * C * (2 + (c1 ? 1 : 0) + (upd ? 0 : 1 + (wd ? 1 : 0)));
   if (upd) per_col += 8 * D1 * 2 + t * d;
   double total = nc * nn * per_col + (upd ? h->cur_copies * nn * 8 * D1 : 0);
   total += nn * (W * C * C * t + 4 * W + C * C * t);
@@ -562,7 +563,7 @@ double bytes_levres(const biot_handle* h, int C, int nc, int t) {
 }
 double bytes_pstage(const biot_handle* h, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
-  return nc * nn * t * (d + 4) + nn * (W * d * t + 4 * W + t);
+  return nc * nn * t * (d + 3) + nn * (W * d * t + 4 * W + t);
 }
 
 // One V-cycle for field A (is_A) or S on level l for nc columns.  On entry b[l]
@@ -610,9 +611,12 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   const int pid_cheb = is_A ? BIOT_PROBE_CHEB_U : BIOT_PROBE_CHEB_P;
   for (int j = 2; j <= deg; ++j) {
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
-    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, true, false, tb) : 0);
+    // d after the last pre-smoothing step is dead: the first post-smoothing
+    // step does not read it
+    const bool wd = j < deg;
+    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, j > 2, false, wd, tb) : 0);
     launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho,
-                   2.0 * rn / cc.delta, nullptr, nullptr, 0.0, wpc, fine, st);
+                   2.0 * rn / cc.delta, wd, j == 2, nullptr, nullptr, 0.0, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -629,8 +633,8 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   const bool coarse_last = (l + 1 == last) || (l + 1 == tail);
   const ChebCoef* cn = coarse_last ? nullptr : (is_A ? &h->chA[l + 1] : &h->chS[l + 1]);
   launch_restrict<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, f.r[l], f.b[l + 1],
-                     coarse_last ? nullptr : f.x0[l + 1], coarse_last ? nullptr : f.d[l + 1],
-                     coarse_last ? 0.0 : 1.0 / cn->theta, nc, st);
+                     coarse_last ? nullptr : f.x0[l + 1], coarse_last ? 0.0 : 1.0 / cn->theta, nc,
+                     st);
   LAUNCHCHK(h);
   T* xc = nullptr;
   int rc = vcycle<T>(h, p, is_A, l + 1, nc, &xc, nullptr, nullptr);
@@ -648,8 +652,9 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
       c2 = 2.0 * rn / cc.delta;
     }
     const bool final_upd = upd && j == deg;
-    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, tb) : 0);
-    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2,
+    const bool wd = j < deg;  // d after the last step is dead
+    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, wd, tb) : 0);
+    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2, wd, false,
                    final_upd ? upd : nullptr, zu, h->opt.omega, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
@@ -671,7 +676,7 @@ int precond_batch(biot_handle* h, Prec<T>& p, int nc, T** zu, T** zp, const ColD
   {
     ProbeScope ps(h, BIOT_PROBE_PSTAGE, bytes_pstage(h, nc, int(sizeof(T))));
     launch_pstage<T>(h->dim, p.L[0], p.Bt, h->opt.precond == BIOT_PRECOND_P1, *zu, p.rp,
-                     p.fs.b[0], p.fs.x0[0], p.fs.d[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc,
+                     p.fs.b[0], p.fs.x0[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc,
                      h->opt.wg_per_cu, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
@@ -694,7 +699,7 @@ int unit_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols
   {
     ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, sm, int(sizeof(T))));
     launch_residual<T>(h->dim, h->L[0], fine_of(h, S), cols, nc, p.fa.b[0], p.rp,
-                       sm ? p.fa.x0[0] : nullptr, p.fa.d[0], sm ? 1.0 / h->chA[0].theta : 0.0,
+                       sm ? p.fa.x0[0] : nullptr, sm ? 1.0 / h->chA[0].theta : 0.0,
                        nullptr, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
@@ -713,7 +718,7 @@ int apply_precond_t(biot_handle* h, Prec<T>& p, const double* R, double* Z, int 
     launch_unpack<T>(h->dim, h->nn, R + size_t(c0) * h->col, p.fa.b[0], p.rp, nc, h->st);
     LAUNCHCHK(h);
     if (sm) {
-      launch_pre1<T>(h->dim, p.L[0], true, p.fa.b[0], p.fa.x0[0], p.fa.d[0], 1.0 / h->chA[0].theta,
+      launch_pre1<T>(h->dim, p.L[0], true, p.fa.b[0], p.fa.x0[0], 1.0 / h->chA[0].theta,
                      nc, h->st);
       LAUNCHCHK(h);
     }
@@ -741,7 +746,7 @@ int gmres_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* col
   hipStream_t st = h->st;
   const GmresVecs Vv{h->gV, sv, col};
   launch_residual<double>(h->dim, h->L[0], fine_of(h, S), cols, nc, h->gru, h->grp, nullptr,
-                          nullptr, 0.0, nullptr, h->nblk, h->opt.wg_per_cu, S.adj, st);
+                          0.0, nullptr, h->nblk, h->opt.wg_per_cu, S.adj, st);
   LAUNCHCHK(h);
   launch_pack<double>(h->dim, h->nn, h->gru, h->grp, h->gT, nc, st);
   LAUNCHCHK(h);
@@ -903,8 +908,8 @@ int global_residual(biot_handle* h, const Sched& S) {
   const FineDev f = fine_of(h, S);
   for (int n0 = 0; n0 < S.N; n0 += chunk) {
     const int nc = std::min(chunk, S.N - n0);
-    launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, nullptr, nullptr,
-                            0.0, h->partials, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
+    launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, nullptr, 0.0,
+                            h->partials, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
     launch_reduce_norms(h->partials, num_node_blocks(h->P.levels[0].nn1), h->S, h->nblk,
                         h->norms + size_t(n0) * h->S * 4, nc, h->st);
@@ -1244,6 +1249,12 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
     return fail(h, BIOT_EINVAL, "workspace must be 256-byte aligned");
   if (bytes < h->ws_need) return fail(h, BIOT_ENOMEM, "workspace smaller than biot_workspace_size");
   for (Sched* S : {&h->fw, &h->bw, &h->rp}) destroy_graphs(*S);
+  {
+    int dev = 0, lds = 0;
+    HIPCHK(h, hipGetDevice(&dev));
+    HIPCHK(h, hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    h->tail_lds = std::min(kTailMaxLds, size_t(lds));
+  }
   h->ws = static_cast<char*>(device_ptr);
   h->st = static_cast<hipStream_t>(stream);
   plan(h, h->ws);

@@ -8,9 +8,24 @@ SuperLU solve and one refinement step per step:
                            (numpy default_rng(7), without replacement)
     samples[n, k]          X^n at those dofs
 
+cube40.npz -- 40^3 unit cube on Kuhn tetrahedra (68,921 nodes, 275,684
+unknowns), 256 steps of dt = 1/256, homogeneous materials, the 3D column;
+same contents (dofs index the node-major [nn][4] layout).
+
 large_heterogeneous.npz -- the same mesh and steps with a log-normal
 permeability field (sigma_log = 1, correlation length 0.1, field seed 2) and
 E ~ U[5e3, 2e4] per element (seed 102); same contents.
+
+batched64.npz -- the 64 samples of the batched workload (grid n, steps and
+field seed from workloads.batched_samples(64, seed=3); log-normal permeability
+with field seed 3000+i and E ~ U[5e3, 2e4] with seed 4000+i), each solved by
+the sequential oracle:
+    grid_n[64], n_steps[64], offsets[65]   sample i's rows are
+                                           offsets[i] .. offsets[i+1]-1 (steps 0..N_i)
+    norm_u, norm_p                         ||U^n||_2, ||P^n||_2 per sample and step
+    dofs[64, 8]                            sampled free unknowns of each sample
+                                           (numpy default_rng(100 + i))
+    samples[rows, 8]                       X^n at those unknowns
 
 adjoint_c4.npz -- gradient workload: 128 x 128 consolidation column, 256 steps
 of dt = 1/256, log-normal permeability (field seed 40) where the gradient is
@@ -24,8 +39,9 @@ taken, homogeneous E = 1e4, nu = 0.3; 64 sensor nodes with free pressure
                                   d lambda = lambda v_l, d mu = mu v_m
     fd_scale[32]                  sum_i |g_i v_i| of each direction
 
-Run:  python tests/golden/make_goldens.py [large_terzaghi] [large_heterogeneous] [adjoint_c4]
-      (about 2 minutes each on one core; adjoint_c4 uses a process pool)
+Run:  python tests/golden/make_goldens.py [large_terzaghi] [large_heterogeneous] [cube40] [batched64] [adjoint_c4]
+      (about 2 minutes each on one core; cube40's 3D factorization takes far longer;
+      batched64 and adjoint_c4 use a process pool)
 """
 import os
 import sys
@@ -44,16 +60,16 @@ def write(name, pb):
     t0 = time.time()
     orc = seq.BiotOracle(pb)
     X = orc.solve_sequential()
-    Y = orc.trajectory_node_major(X)           # [513, nn, 3]
-    nn, d1 = Y.shape[1], Y.shape[2]
+    Y = orc.trajectory_node_major(X)           # [N+1, nn, dim+1]
+    nn, dim = Y.shape[1], Y.shape[2] - 1
     flat = Y.reshape(Y.shape[0], -1)
-    fixed_nm = fem.field_to_node_major(orc.fixed.astype(float), nn, 2).reshape(-1) > 0.5
+    fixed_nm = fem.field_to_node_major(orc.fixed.astype(float), nn, dim).reshape(-1) > 0.5
     free = np.nonzero(~fixed_nm)[0]
     dofs = np.sort(np.random.default_rng(7).choice(free, size=256, replace=False))
     np.savez_compressed(
         os.path.join(HERE, name + ".npz"),
-        norm_u=np.linalg.norm(Y[..., :2].reshape(Y.shape[0], -1), axis=1),
-        norm_p=np.linalg.norm(Y[..., 2], axis=1),
+        norm_u=np.linalg.norm(Y[..., :dim].reshape(Y.shape[0], -1), axis=1),
+        norm_p=np.linalg.norm(Y[..., dim], axis=1),
         dofs=dofs.astype(np.int64), samples=flat[:, dofs])
     print(f"{name}.npz written in {time.time() - t0:.1f} s")
 
@@ -87,11 +103,44 @@ def write_adjoint(name="adjoint_c4", workers=6):
     print(f"{name}.npz written in {time.time() - t0:.1f} s")
 
 
-WORKLOADS = {"large_terzaghi": W.large_terzaghi, "large_heterogeneous": W.large_heterogeneous}
+def _batched_one(args):
+    i, n, steps, seed = args
+    pb = W.heterogeneous_problem(n, steps, field_seed=seed, young_seed=seed + 1000)
+    orc = seq.BiotOracle(pb)
+    Y = orc.trajectory_node_major(orc.solve_sequential())
+    nn = Y.shape[1]
+    fixed_nm = fem.field_to_node_major(orc.fixed.astype(float), nn, 2).reshape(-1) > 0.5
+    free = np.nonzero(~fixed_nm)[0]
+    dofs = np.sort(np.random.default_rng(100 + i).choice(free, size=8, replace=False))
+    flat = Y.reshape(Y.shape[0], -1)
+    return (np.linalg.norm(Y[..., :2].reshape(Y.shape[0], -1), axis=1),
+            np.linalg.norm(Y[..., 2], axis=1), dofs, flat[:, dofs])
+
+
+def write_batched(name="batched64", workers=6):
+    from multiprocessing import Pool
+    t0 = time.time()
+    specs = W.batched_samples(64, seed=3)
+    with Pool(workers) as pool:
+        out = pool.map(_batched_one, [(i, n, N, sd) for i, (n, N, sd) in enumerate(specs)])
+    steps = np.array([N for _, N, _ in specs], dtype=np.int64)
+    np.savez_compressed(
+        os.path.join(HERE, name + ".npz"), grid_n=np.array([n for n, _, _ in specs]),
+        n_steps=steps, offsets=np.concatenate([[0], np.cumsum(steps + 1)]).astype(np.int64),
+        norm_u=np.concatenate([o[0] for o in out]), norm_p=np.concatenate([o[1] for o in out]),
+        dofs=np.stack([o[2] for o in out]).astype(np.int64),
+        samples=np.concatenate([o[3] for o in out]))
+    print(f"{name}.npz written in {time.time() - t0:.1f} s")
+
+
+WORKLOADS = {"large_terzaghi": W.large_terzaghi, "large_heterogeneous": W.large_heterogeneous,
+             "cube40": lambda: W.terzaghi_problem(40, 256, dim=3)}
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(WORKLOADS) + ["adjoint_c4"]):
         if name == "adjoint_c4":
             write_adjoint()
+        elif name == "batched64":
+            write_batched()
         else:
             write(name, WORKLOADS[name]())

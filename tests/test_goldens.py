@@ -1,0 +1,75 @@
+"""Checks of the stored oracle values under tests/golden/ (CPU only).
+
+The full-size goldens are written by tests/golden/make_goldens.py from the
+oracle; these tests tie them to something other than that script:
+* the consolidation columns reach their closed-form steady state (vertical
+  displacement -x_up/(lambda+2mu), no lateral displacement, no pressure), so
+  the stored final-step samples and norms of large_terzaghi (and of cube40 when
+  present) must equal it;
+* two of the 64 batched samples (the smallest meshes) are recomputed with the
+  oracle and must match the stored values, and the stored layout (offsets,
+  step counts, sizes) must follow the seeded sample recipe.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fem, sequential as seq
+from paper_2310_10430_amd import workloads as W
+
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+LAM, MU = fem.lame(1e4, 0.3)
+
+
+def _steady_check(g, pb):
+    d1 = pb.dim + 1
+    dofs, last = g["dofs"], g["samples"][-1]
+    node, comp = dofs // d1, dofs % d1
+    up = pb.dim - 1
+    ref = np.where(comp == up, -pb.xyz[node, up] / (LAM + 2 * MU), 0.0)
+    # the slowest mode has decayed to a few 1e-10 of the load response by t = 1
+    scale = 1.0 / (LAM + 2 * MU)
+    assert np.abs(last - ref).max() < 1e-9 * scale
+    # ||U^N|| of the closed form over all nodes
+    nu = np.linalg.norm(pb.xyz[:, up] / (LAM + 2 * MU))
+    assert abs(g["norm_u"][-1] - nu) < 1e-9 * nu
+    assert g["norm_p"][-1] < 1e-9
+
+
+def test_large_terzaghi_golden_final_step_is_the_steady_state():
+    g = np.load(os.path.join(HERE, "large_terzaghi.npz"))
+    pb = W.large_terzaghi()
+    assert g["samples"].shape[0] == pb.n_steps + 1
+    _steady_check(g, pb)
+
+
+def test_cube40_golden_final_step_is_the_steady_state():
+    path = os.path.join(HERE, "cube40.npz")
+    if not os.path.exists(path):
+        pytest.skip("cube40.npz not written")
+    g = np.load(path)
+    pb = W.terzaghi_problem(40, 256, dim=3)
+    assert g["samples"].shape[0] == pb.n_steps + 1
+    _steady_check(g, pb)
+
+
+def test_batched_golden_layout_and_recomputed_samples():
+    g = np.load(os.path.join(HERE, "batched64.npz"))
+    specs = W.batched_samples(64, seed=3)
+    assert list(g["grid_n"]) == [n for n, _, _ in specs]
+    assert list(g["n_steps"]) == [N for _, N, _ in specs]
+    assert np.array_equal(np.diff(g["offsets"]), g["n_steps"] + 1)
+    small = [i for i, (n, _, _) in enumerate(specs) if n == 32][:2]
+    assert small
+    for i in small:
+        n, N, seed = specs[i]
+        pb = W.heterogeneous_problem(n, N, field_seed=seed, young_seed=seed + 1000)
+        orc = seq.BiotOracle(pb)
+        Y = orc.trajectory_node_major(orc.solve_sequential())
+        a, b = g["offsets"][i], g["offsets"][i + 1]
+        flat = Y.reshape(Y.shape[0], -1)
+        ref = g["samples"][a:b]
+        assert np.abs(flat[:, g["dofs"][i]] - ref).max() <= 1e-12 * np.abs(ref).max()
+        nu = np.linalg.norm(Y[..., :2].reshape(Y.shape[0], -1), axis=1)
+        assert np.abs(nu - g["norm_u"][a:b]).max() <= 1e-12 * nu.max()
