@@ -331,9 +331,14 @@ __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T
 // ---------------------------------------------------------------------------
 // Chebyshev step on one level:  d <- c1 d + c2 D^{-1}(b - K xin);  xout = xin + d.
 // wd = 0 leaves d unwritten (the last step before a residual or at the end of
-// the smoothing, after which d is dead); dx = 1 takes the previous increment
-// to be xin itself (the step after a first step from zero, whose producer
-// stores only x).
+// the smoothing, after which d is dead, and the first step after a coarse-grid
+// correction).  dx selects where the previous increment comes from:
+//   0: d;
+//   1: xin itself (the step after a first step from zero, whose producer
+//      stores only x);
+//   2: xin - xout, xout still holding the previous step's input (the step
+//      after the first post-smoothing step, which stores no d); the node's
+//      own xout value is read before it is overwritten.
 // UPD (pressure field, level 0, last step): instead of xout, writes the outer
 // update X^{n,m} = X^{n,m-1} + omega [z_u; xin + d] (FP64) through the column
 // descriptors.  FINE only makes the level-0 launches a distinct symbol.
@@ -342,7 +347,7 @@ template <int DIM, int C, bool UPD, bool FINE, typename T>
 __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_cheb(LevelView<T> L, int isA,
                                                  const T* __restrict__ b,
                                                  const T* __restrict__ xin,
-                                                 T* __restrict__ xout, T* __restrict__ d, int nc,
+                                                 T* xout, T* __restrict__ d, int nc,
                                                  T c1, T c2, int wd, int dx,
                                                  const ColDesc* __restrict__ cols,
                                                  const T* __restrict__ zu, double omega) {
@@ -426,7 +431,10 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
           T z = T(0);
 #pragma unroll
           for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
-          const T dp = c1 == T(0) ? T(0) : (dx ? xs[q][a] : d[base + a]);
+          const T dp = c1 == T(0) ? T(0)
+                       : dx == 1 ? xs[q][a]
+                       : dx == 2 ? xs[q][a] - xout[base + a]
+                                 : d[base + a];
           const T dn = c1 * dp + c2 * z;
           if (!UPD && wd) d[base + a] = dn;
           xn[a] = xs[q][a] + dn;
@@ -473,11 +481,20 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelView<T> Lf, LevelView<T
     const size_t stride = size_t(nn) * C, cstride = size_t(Lc.nn) * C;
 #pragma unroll 2
     for (int c = cbeg; c < cend; ++c) {
+      // all loads first (p0, p1 are valid nodes even when masked), then the
+      // masked sums
+      T xv[C], c0[C], c1[C];
 #pragma unroll
       for (int a = 0; a < C; ++a) {
-        T x = xin[size_t(c) * stride + size_t(v) * C + a];
-        if ((pm >> a) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p0) * C + a];
-        if ((pm >> (C + a)) & 1u) x += wt * xc[size_t(c) * cstride + size_t(p1) * C + a];
+        xv[a] = xin[size_t(c) * stride + size_t(v) * C + a];
+        c0[a] = xc[size_t(c) * cstride + size_t(p0) * C + a];
+        c1[a] = xc[size_t(c) * cstride + size_t(p1) * C + a];
+      }
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        T x = xv[a];
+        if ((pm >> a) & 1u) x += wt * c0[a];
+        if ((pm >> (C + a)) & 1u) x += wt * c1[a];
         xout[size_t(c) * stride + size_t(v) * C + a] = x;
       }
     }
@@ -574,20 +591,36 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
   const uint8_t fc = Lc.fixed[I];
   const int bit0 = isA ? 0 : DIM;
   const size_t sf = size_t(Lf.nn) * C, sc = size_t(Lc.nn) * C;
+  // fine node under each slot (a missing one is replaced by the copy's first
+  // node and masked out); every load is issued before the masked sums
+  int fs[W];
+  unsigned ok = 0u;
+#pragma unroll
+  for (int s = 0; s < W; ++s) {
+    const int* o = DIM == 2 ? c_off2[s] : c_off3[s];
+    const int fi = 2 * ci + o[0], fj = 2 * cj + o[1], fk = 2 * ck + o[2];
+    const bool in = real && fi >= 0 && fi < mf && fj >= 0 && fj < mf && fk >= 0 && fk < mf;
+    fs[s] = cp * Lf.nn1 + (in ? node_id<DIM>(fi, fj, fk, mf) : 0);
+    ok |= unsigned(in) << s;
+  }
+  unsigned ff[W];
+  T rv[W][C];
+#pragma unroll
+  for (int s = 0; s < W; ++s) {
+    ff[s] = Lf.fixed[fs[s]];
+#pragma unroll
+    for (int a = 0; a < C; ++a) rv[s][a] = rf[size_t(c) * sf + size_t(fs[s]) * C + a];
+  }
   T acc[C];
 #pragma unroll
   for (int a = 0; a < C; ++a) acc[a] = T(0);
 #pragma unroll
   for (int s = 0; s < W; ++s) {
-    const int* o = DIM == 2 ? c_off2[s] : c_off3[s];
-    const int fi = 2 * ci + o[0], fj = 2 * cj + o[1], fk = 2 * ck + o[2];
-    if (!real || fi < 0 || fi >= mf || fj < 0 || fj >= mf || fk < 0 || fk >= mf) continue;
-    const int f = cp * Lf.nn1 + node_id<DIM>(fi, fj, fk, mf);
+    if (!((ok >> s) & 1u)) continue;
     const T wgt = s == 0 ? T(1) : T(0.5);
-    const uint8_t ff = Lf.fixed[f];
 #pragma unroll
     for (int a = 0; a < C; ++a)
-      if (!((ff >> (bit0 + a)) & 1)) acc[a] += wgt * rf[size_t(c) * sf + size_t(f) * C + a];
+      if (!((ff[s] >> (bit0 + a)) & 1u)) acc[a] += wgt * rv[s][a];
   }
 #pragma unroll
   for (int a = 0; a < C; ++a) {
@@ -1151,21 +1184,21 @@ void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc
 
 template <int DIM, int C, bool UPD, typename T>
 static void cheb_dispatch(const LevelView<T>& L, bool is_A, const T* b, const T* xin, T* xout,
-                          T* d, int nc, double c1, double c2, bool wd, bool dx,
+                          T* d, int nc, double c1, double c2, bool wd, int dx,
                           const ColDesc* cols, const T* zu, double omega, int wpc, bool fine,
                           hipStream_t st) {
   if (fine) {
     BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, true, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
-                         xout, d, nc, T(c1), T(c2), int(wd), int(dx), cols, zu, omega);
+                         xout, d, nc, T(c1), T(c2), int(wd), dx, cols, zu, omega);
   } else if constexpr (!UPD) {
     BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, false, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
-                         xout, d, nc, T(c1), T(c2), int(wd), int(dx), cols, zu, omega);
+                         xout, d, nc, T(c1), T(c2), int(wd), dx, cols, zu, omega);
   }
 }
 
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
-                 T* xout, T* d, int nc, double c1, double c2, bool wd, bool dx,
+                 T* xout, T* d, int nc, double c1, double c2, bool wd, int dx,
                  const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
                  hipStream_t st) {
   if (dim == 2) {
@@ -1315,7 +1348,7 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
   template void launch_residual<T>(int, const LevelDev&, const FineDev&, const ColDesc*, int, T*, \
                                    T*, T*, double, double*, int, int, bool, hipStream_t);        \
   template void launch_cheb<T>(int, int, const LevelView<T>&, bool, const T*, const T*, T*, T*,  \
-                               int, double, double, bool, bool, const ColDesc*, const T*, double, \
+                               int, double, double, bool, int, const ColDesc*, const T*, double, \
                                int, bool, hipStream_t);                                           \
   template void launch_level_residual<T>(int, int, const LevelView<T>&, bool, const T*,          \
                                          const T*, T*, int, int, hipStream_t);                    \

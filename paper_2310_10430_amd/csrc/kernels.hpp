@@ -62,12 +62,13 @@ void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc
 // Chebyshev step d <- c1 d + c2 D^{-1}(b - K xin), xout = xin + d.  With `upd`
 // (pressure field, level 0) the step writes the outer update
 // X^{n,m} = X^{n,m-1} + omega [zu; xin + d] through the descriptors instead.
-// wd = false skips storing d (dead after the step); dx = true takes the
-// previous d to be xin (the step after a first step from zero: the producers
-// of a first step store only x).
+// wd = false skips storing d; dx: where the previous d comes from (0: d;
+// 1: xin, after a first step from zero, whose producers store only x;
+// 2: xin - xout, after the first post-smoothing step, xout still holding that
+// step's input).
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
-                 T* xout, T* d, int nc, double c1, double c2, bool wd, bool dx,
+                 T* xout, T* d, int nc, double c1, double c2, bool wd, int dx,
                  const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
                  hipStream_t st);
 template <typename T>

@@ -616,7 +616,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     const bool wd = j < deg;
     ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, j > 2, false, wd, tb) : 0);
     launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho,
-                   2.0 * rn / cc.delta, wd, j == 2, nullptr, nullptr, 0.0, wpc, fine, st);
+                   2.0 * rn / cc.delta, wd, j == 2 ? 1 : 0, nullptr, nullptr, 0.0, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -652,9 +652,13 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
       c2 = 2.0 * rn / cc.delta;
     }
     const bool final_upd = upd && j == deg;
-    const bool wd = j < deg;  // d after the last step is dead
+    // d after the last step is dead, and the step after the first one (c1 = 0)
+    // recovers it as its input minus the buffer it overwrites, which still
+    // holds the first step's input
+    const bool wd = j > 1 && j < deg;
+    const int dx = j == 2 ? 2 : 0;
     ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, wd, tb) : 0);
-    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2, wd, false,
+    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2, wd, dx,
                    final_upd ? upd : nullptr, zu, h->opt.omega, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
