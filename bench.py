@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # two rocprofv3 counter passes (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the
 # factors of a plain 1 GiB copy) over 64-column launches, and the kernel
 # source they were taken with; see profiles/level0_kernels_large_terzaghi_hbm_counters.md
-CHEB_U_TRAFFIC = {"kernels_sha256_prefix": "e39edcf30470788f",
-                  "bytes_per_launch": 383.8e6, "launch_columns": 64,
-                  "algorithmic_bytes_per_launch": 334.4e6}
+CHEB_U_TRAFFIC = {"kernels_sha256_prefix": "ab4df60c918eadd6",
+                  "bytes_per_launch": 281.7e6, "launch_columns": 64,
+                  "algorithmic_bytes_per_launch": 244.2e6}
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"
 
 
@@ -70,19 +70,21 @@ def traffic_fields(probe, algo_bytes_avg):
     return out
 
 
-def sampled_errors(X, dofs, samp, norm_u, norm_p):
+def sampled_errors(X, dofs, samp, norm_u, norm_p, scale=None):
     """Errors of the GPU trajectory X [N+1, nn, dim+1] at stored oracle samples
     (unknowns `dofs` of the node-major layout, values samp[n, k]) and in the
-    per-step field norms; each relative to the largest oracle value."""
+    per-step field norms; each relative to the largest oracle value (of the
+    samples, or scale = (largest |u|, largest |p|) of the whole trajectory)."""
     d1 = X.shape[2]
     flat = X.reshape(X.shape[0], -1)
     got = flat[:, dofs]
     is_p = (dofs % d1) == d1 - 1
     out = {}
-    for name, m in (("u", ~is_p), ("p", is_p)):
+    for f, (name, m) in enumerate((("u", ~is_p), ("p", is_p))):
         if m.any():
             ref = samp[:, m]
-            out[f"sampled_{name}"] = float(np.abs(got[:, m] - ref).max() / np.abs(ref).max())
+            den = np.abs(ref).max() if scale is None else scale[f]
+            out[f"sampled_{name}"] = float(np.abs(got[:, m] - ref).max() / den)
     nu = np.linalg.norm(X[..., : d1 - 1].reshape(X.shape[0], -1), axis=1)
     npn = np.linalg.norm(X[..., d1 - 1], axis=1)
     out["norms_u"] = float(np.abs(nu - norm_u).max() / norm_u.max())
@@ -264,7 +266,7 @@ def batched_oracle_errors(trajs):
     for i, X in trajs.items():
         a, b = int(g["offsets"][i]), int(g["offsets"][i + 1])
         e = sampled_errors(X.cpu().numpy(), g["dofs"][i], g["samples"][a:b], g["norm_u"][a:b],
-                           g["norm_p"][a:b])
+                           g["norm_p"][a:b], scale=(g["amax_u"][i], g["amax_p"][i]))
         for k, v in e.items():
             worst[k] = max(worst.get(k, 0.0), v)
     worst["max"] = max(worst.values())

@@ -26,6 +26,8 @@ the sequential oracle:
     dofs[64, 8]                            sampled free unknowns of each sample
                                            (numpy default_rng(100 + i))
     samples[rows, 8]                       X^n at those unknowns
+    amax_u[64], amax_p[64]                 largest |u| and |p| of each sample's trajectory
+                                           (the scale of its relative errors)
 
 adjoint_c4.npz -- gradient workload: 128 x 128 consolidation column, 256 steps
 of dt = 1/256, log-normal permeability (field seed 40) where the gradient is
@@ -114,7 +116,8 @@ def _batched_one(args):
     dofs = np.sort(np.random.default_rng(100 + i).choice(free, size=8, replace=False))
     flat = Y.reshape(Y.shape[0], -1)
     return (np.linalg.norm(Y[..., :2].reshape(Y.shape[0], -1), axis=1),
-            np.linalg.norm(Y[..., 2], axis=1), dofs, flat[:, dofs])
+            np.linalg.norm(Y[..., 2], axis=1), dofs, flat[:, dofs],
+            np.abs(Y[..., :2]).max(), np.abs(Y[..., 2]).max())
 
 
 def write_batched(name="batched64", workers=6):
@@ -129,7 +132,8 @@ def write_batched(name="batched64", workers=6):
         n_steps=steps, offsets=np.concatenate([[0], np.cumsum(steps + 1)]).astype(np.int64),
         norm_u=np.concatenate([o[0] for o in out]), norm_p=np.concatenate([o[1] for o in out]),
         dofs=np.stack([o[2] for o in out]).astype(np.int64),
-        samples=np.concatenate([o[3] for o in out]))
+        samples=np.concatenate([o[3] for o in out]),
+        amax_u=np.array([o[4] for o in out]), amax_p=np.array([o[5] for o in out]))
     print(f"{name}.npz written in {time.time() - t0:.1f} s")
 
 

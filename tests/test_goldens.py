@@ -73,3 +73,5 @@ def test_batched_golden_layout_and_recomputed_samples():
         assert np.abs(flat[:, g["dofs"][i]] - ref).max() <= 1e-12 * np.abs(ref).max()
         nu = np.linalg.norm(Y[..., :2].reshape(Y.shape[0], -1), axis=1)
         assert np.abs(nu - g["norm_u"][a:b]).max() <= 1e-12 * nu.max()
+        assert abs(np.abs(Y[..., :2]).max() - g["amax_u"][i]) <= 1e-12 * g["amax_u"][i]
+        assert abs(np.abs(Y[..., 2]).max() - g["amax_p"][i]) <= 1e-12 * g["amax_p"][i]
