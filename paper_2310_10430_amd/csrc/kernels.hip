@@ -102,11 +102,9 @@ __device__ inline void block_sum(double (&v)[Q], double* lds /* [4][Q] */) {
 
 // ---------------------------------------------------------------------------
 // fine-level residual r = c(n) F + A' X^{n-1} - AA X^{n,m-1} (FP64), the
-// coupled right-hand side norms, and the first (pointwise) Chebyshev step of
-// the displacement V-cycle; r and that step are stored as T.  A first step
-// from zero equals its own increment, so only x is stored (the next step
-// reads x as the previous increment; the same holds for k_restrict, k_pstage
-// and k_pre1).
+// coupled right-hand side norms; r is stored as T.  The displacement V-cycle's
+// first Chebyshev step from zero (x = D^{-1} r / theta, pointwise) is not
+// stored: the next step forms it on the fly (see k_cheb's `first`).
 // ADJ: the adjoint recursion run forward in reversed time, whose coupling is
 // A'^T = [0 B; 0 -C_beta] applied to the previous column and whose load is the
 // pressure-row vector gload[step-1] (no traction load):
@@ -116,7 +114,6 @@ template <int DIM, typename T, bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
                                                      T* __restrict__ ru, T* __restrict__ rp,
-                                                     T* __restrict__ xa, double inv_theta,
                                                      double* __restrict__ partials, int pstride) {
   // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
   constexpr int NQ = DIM == 2 ? 2 : 1;
@@ -151,11 +148,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
         rCb[s] = F.Cb[size_t(s) * nn + vv];
       }
     }
-    double Fu[DIM], Di[DIM * DIM];
+    double Fu[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(vv) * D1 + a] : 0.0;
-#pragma unroll
-    for (int e = 0; e < DIM * DIM; ++e) Di[e] = xa ? L.Ainv[size_t(e) * nn + vv] : 0.0;
 #pragma unroll 1
     for (int c = cbeg; c < cend; c += NQ) {
       const bool two = NQ > 1 && c + 1 < cend;
@@ -254,16 +249,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
           for (int a = 0; a < DIM; ++a) ru[cu + size_t(v) * DIM + a] = T(au[q][a]);
           rp[size_t(cc[q]) * nn + v] = T(ap[q]);
         }
-        if (xa) {
-#pragma unroll
-          for (int a = 0; a < DIM; ++a) {
-            double z = 0.0;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) z += Di[a * DIM + k] * au[q][k];
-            z *= inv_theta;
-            xa[cu + size_t(v) * DIM + a] = T(z);
-          }
-        }
       }
       if (partials) {
         double qv[4 * NQ];
@@ -334,11 +319,13 @@ __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T
 // the smoothing, after which d is dead, and the first step after a coarse-grid
 // correction).  dx selects where the previous increment comes from:
 //   0: d;
-//   1: xin itself (the step after a first step from zero, whose producer
-//      stores only x);
+//   1: xin itself (the step after a first step from zero);
 //   2: xin - xout, xout still holding the previous step's input (the step
 //      after the first post-smoothing step, which stores no d); the node's
 //      own xout value is read before it is overwritten.
+// first = 1: this is the step after the first step from zero, which is not
+// stored: xin = it D^{-1} b is formed on the fly, K xin as it * KD b with the
+// folded operator KD_k = K_k D^{-1}(nbr_k) (L.AD / L.SD); use with dx = 1.
 // UPD (pressure field, level 0, last step): instead of xout, writes the outer
 // update X^{n,m} = X^{n,m-1} + omega [z_u; xin + d] (FP64) through the column
 // descriptors.  FINE only makes the level-0 launches a distinct symbol.
@@ -348,7 +335,7 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
                                                  const T* __restrict__ b,
                                                  const T* __restrict__ xin,
                                                  T* xout, T* __restrict__ d, int nc,
-                                                 T c1, T c2, int wd, int dx,
+                                                 T c1, T c2, int wd, int dx, int first, T it,
                                                  const ColDesc* __restrict__ cols,
                                                  const T* __restrict__ zu, double omega) {
   // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
@@ -362,8 +349,10 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
     const int v = nblk * kBlock + threadIdx.x;
     if (v >= nn) return;
     // C > 1 is the displacement field (A), C == 1 the pressure field (S)
-    const T* K = C > 1 ? L.A : L.S;
+    const T* K = first ? (C > 1 ? L.AD : L.SD) : (C > 1 ? L.A : L.S);
     const T* Dg = C > 1 ? L.Ainv : L.Sinv;
+    const T* src = first ? b : xin;       // the gathered vector
+    const T sc = first ? it : T(1);       // its scale in K xin
     const size_t stride = size_t(nn) * C;
     int nb[RS];
     if constexpr (STAT) {
@@ -389,7 +378,7 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
       // column base pointers; offsets within a column fit in 32 bits
       const T* xq[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) xq[q] = xin + size_t(cc[q]) * stride;
+      for (int q = 0; q < NQ; ++q) xq[q] = src + size_t(cc[q]) * stride;
       T acc[NQ][C], xs[NQ][C];
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
@@ -409,15 +398,26 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
           T xw[C];
 #pragma unroll
           for (int k = 0; k < C; ++k) xw[k] = xq[q][w * C + k];
-          if (s == 0)
+          if (s == 0) {
+            if (first) {
 #pragma unroll
-            for (int k = 0; k < C; ++k) xs[q][k] = xw[k];
+              for (int a = 0; a < C; ++a) {
+                T z = T(0);
+#pragma unroll
+                for (int k = 0; k < C; ++k) z += Di[a * C + k] * xw[k];
+                xs[q][a] = z * it;
+              }
+            } else {
+#pragma unroll
+              for (int k = 0; k < C; ++k) xs[q][k] = xw[k];
+            }
+          }
 #pragma unroll
           for (int a = 0; a < C; ++a) {
             T s2 = T(0);
 #pragma unroll
             for (int k = 0; k < C; ++k) s2 += blk[a * C + k] * xw[k];
-            acc[q][a] -= s2;
+            acc[q][a] -= sc * s2;
           }
         }
       }
@@ -572,13 +572,11 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
   });
 }
 
-// coarse b = P' r_fine (P1 interpolation transpose, masked), plus the first
-// Chebyshev step of the coarse level when it is not the coarsest
+// coarse b = P' r_fine (P1 interpolation transpose, masked)
 template <int DIM, int C, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<T> Lc, int isA,
                                                      const T* __restrict__ rf,
-                                                     T* __restrict__ bc, T* __restrict__ xa,
-                                                     T inv_theta, int nc) {
+                                                     T* __restrict__ bc, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int I = blockIdx.y * kBlock + threadIdx.x;
   if (I >= Lc.nn) return;
@@ -626,17 +624,6 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
   for (int a = 0; a < C; ++a) {
     if ((fc >> (bit0 + a)) & 1) acc[a] = T(0);
     bc[size_t(c) * sc + size_t(I) * C + a] = acc[a];
-  }
-  if (xa) {
-    const T* Dg = isA ? Lc.Ainv : Lc.Sinv;
-#pragma unroll
-    for (int a = 0; a < C; ++a) {
-      T z = T(0);
-#pragma unroll
-      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + I] * acc[k];
-      z *= inv_theta;
-      xa[size_t(c) * sc + size_t(I) * C + a] = z;
-    }
   }
 }
 
@@ -932,14 +919,13 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, int stride, int 
   for (int r = n + threadIdx.x; r < stride; r += kBlock) x[base + r] = T(0);
 }
 
-// pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), and the first
-// Chebyshev step of the pressure V-cycle
+// pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), the right-hand side
+// of the pressure V-cycle
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __restrict__ Bt,
                                                    int p1, const T* __restrict__ zu,
                                                    const T* __restrict__ rp,
-                                                   T* __restrict__ t_out, T* __restrict__ xa,
-                                                   T inv_theta, int nc) {
+                                                   T* __restrict__ t_out, int nc) {
   // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
   constexpr int NQ = DIM == 2 ? 2 : 1;
   constexpr int W = DIM == 2 ? 7 : 15;
@@ -955,7 +941,6 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
 #pragma unroll
       for (int k = 0; k < DIM; ++k) bt[s][k] = p1 ? Bt[(size_t(s) * DIM + k) * nn + v] : T(0);
     }
-    const T si = L.Sinv[v];
 #pragma unroll 1
     for (int c = cbeg; c < cend; c += NQ) {
       const bool two = NQ > 1 && c + 1 < cend;
@@ -980,10 +965,7 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (q == 1 && !two) break;
-        const size_t idx = size_t(cc[q]) * nn + v;
-        t_out[idx] = acc[q];
-        const T z = si * acc[q] * inv_theta;
-        xa[idx] = z;
+        t_out[size_t(cc[q]) * nn + v] = acc[q];
       }
     }
   });
@@ -1089,25 +1071,6 @@ __global__ __launch_bounds__(kBlock) void k_pack(int nn, const T* __restrict__ z
   Z[(c * nn + v) * D1 + DIM] = double(zp[c * nn + v]);
 }
 
-// first Chebyshev step from a zero iterate: xa = D^{-1} b / theta (also the
-// step's increment)
-template <int C, typename T>
-__global__ __launch_bounds__(kBlock) void k_pre1(LevelView<T> L, int isA, const T* __restrict__ b,
-                                                 T* __restrict__ xa, T inv_theta) {
-  const int v = blockIdx.y * kBlock + threadIdx.x;
-  if (v >= L.nn) return;
-  const size_t base = size_t(blockIdx.x) * L.nn * C + size_t(v) * C;
-  const T* Dg = isA ? L.Ainv : L.Sinv;
-#pragma unroll
-  for (int a = 0; a < C; ++a) {
-    T z = T(0);
-#pragma unroll
-    for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + v] * b[base + k];
-    z *= inv_theta;
-    xa[base + a] = z;
-  }
-}
-
 inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
 
 // Grid of a balanced launch (for_each_piece): one workgroup per resident
@@ -1163,57 +1126,57 @@ dim3 balanced_grid(const void* fn, int nn, int nc, int wpc) {
 
 template <int DIM, bool ADJ, typename T>
 static void residual_dispatch(const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                              T* ru, T* rp, T* xa, double inv_theta, double* partials,
-                              int pstride, int wpc, hipStream_t st) {
-  BIOT_LAUNCH_BALANCED((k_residual<DIM, T, ADJ>), L.nn, nc, wpc, st, L, F, cols, nc, ru, rp, xa,
-                       inv_theta, partials, pstride);
+                              T* ru, T* rp, double* partials, int pstride, int wpc,
+                              hipStream_t st) {
+  BIOT_LAUNCH_BALANCED((k_residual<DIM, T, ADJ>), L.nn, nc, wpc, st, L, F, cols, nc, ru, rp,
+                       partials, pstride);
 }
 
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                     T* ru, T* rp, T* xa, double inv_theta, double* partials, int pstride,
-                     int wpc, bool adj, hipStream_t st) {
+                     T* ru, T* rp, double* partials, int pstride, int wpc, bool adj,
+                     hipStream_t st) {
   if (dim == 2) {
-    if (adj) residual_dispatch<2, true, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
-    else residual_dispatch<2, false, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
+    if (adj) residual_dispatch<2, true, T>(L, F, cols, nc, ru, rp, partials, pstride, wpc, st);
+    else residual_dispatch<2, false, T>(L, F, cols, nc, ru, rp, partials, pstride, wpc, st);
   } else {
-    if (adj) residual_dispatch<3, true, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
-    else residual_dispatch<3, false, T>(L, F, cols, nc, ru, rp, xa, inv_theta, partials, pstride, wpc, st);
+    if (adj) residual_dispatch<3, true, T>(L, F, cols, nc, ru, rp, partials, pstride, wpc, st);
+    else residual_dispatch<3, false, T>(L, F, cols, nc, ru, rp, partials, pstride, wpc, st);
   }
 }
 
 template <int DIM, int C, bool UPD, typename T>
 static void cheb_dispatch(const LevelView<T>& L, bool is_A, const T* b, const T* xin, T* xout,
-                          T* d, int nc, double c1, double c2, bool wd, int dx,
-                          const ColDesc* cols, const T* zu, double omega, int wpc, bool fine,
-                          hipStream_t st) {
+                          T* d, int nc, double c1, double c2, bool wd, int dx, bool first,
+                          double it, const ColDesc* cols, const T* zu, double omega, int wpc,
+                          bool fine, hipStream_t st) {
   if (fine) {
     BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, true, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
-                         xout, d, nc, T(c1), T(c2), int(wd), dx, cols, zu, omega);
+                         xout, d, nc, T(c1), T(c2), int(wd), dx, int(first), T(it), cols, zu, omega);
   } else if constexpr (!UPD) {
     BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, false, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
-                         xout, d, nc, T(c1), T(c2), int(wd), dx, cols, zu, omega);
+                         xout, d, nc, T(c1), T(c2), int(wd), dx, int(first), T(it), cols, zu, omega);
   }
 }
 
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
-                 T* xout, T* d, int nc, double c1, double c2, bool wd, int dx,
-                 const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
+                 T* xout, T* d, int nc, double c1, double c2, bool wd, int dx, bool first,
+                 double it, const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
                  hipStream_t st) {
   if (dim == 2) {
     if (comps == 1) {
-      if (upd) cheb_dispatch<2, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
-      else cheb_dispatch<2, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
+      if (upd) cheb_dispatch<2, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, first, it, upd, zu, omega, wpc, fine, st);
+      else cheb_dispatch<2, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, first, it, upd, zu, omega, wpc, fine, st);
     } else {
-      cheb_dispatch<2, 2, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
+      cheb_dispatch<2, 2, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, first, it, upd, zu, omega, wpc, fine, st);
     }
   } else {
     if (comps == 1) {
-      if (upd) cheb_dispatch<3, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
-      else cheb_dispatch<3, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
+      if (upd) cheb_dispatch<3, 1, true, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, first, it, upd, zu, omega, wpc, fine, st);
+      else cheb_dispatch<3, 1, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, first, it, upd, zu, omega, wpc, fine, st);
     } else {
-      cheb_dispatch<3, 3, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, upd, zu, omega, wpc, fine, st);
+      cheb_dispatch<3, 3, false, T>(L, is_A, b, xin, xout, d, nc, c1, c2, wd, dx, first, it, upd, zu, omega, wpc, fine, st);
     }
   }
 }
@@ -1232,16 +1195,14 @@ void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A,
 
 template <typename T>
 void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
-                     bool is_A, const T* rf, T* bc, T* xa_c, double inv_theta_c, int nc,
-                     hipStream_t st) {
+                     bool is_A, const T* rf, T* bc, int nc, hipStream_t st) {
   const dim3 g = col_grid(nc, Lc.nn);
-  const T it = T(inv_theta_c);
   if (dim == 2) {
-    if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
-    else hipLaunchKernelGGL((k_restrict<2, 2, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, nc);
+    else hipLaunchKernelGGL((k_restrict<2, 2, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, nc);
   } else {
-    if (comps == 1) hipLaunchKernelGGL((k_restrict<3, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
-    else hipLaunchKernelGGL((k_restrict<3, 3, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, xa_c, it, nc);
+    if (comps == 1) hipLaunchKernelGGL((k_restrict<3, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, nc);
+    else hipLaunchKernelGGL((k_restrict<3, 3, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, nc);
   }
 }
 
@@ -1290,10 +1251,9 @@ void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T*
 
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
-                   T* t, T* xa, double inv_theta, int nc, int wpc, hipStream_t st) {
-  const T it = T(inv_theta);
-  if (dim == 2) BIOT_LAUNCH_BALANCED((k_pstage<2, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, it, nc);
-  else BIOT_LAUNCH_BALANCED((k_pstage<3, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, xa, it, nc);
+                   T* t, int nc, int wpc, hipStream_t st) {
+  if (dim == 2) BIOT_LAUNCH_BALANCED((k_pstage<2, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, nc);
+  else BIOT_LAUNCH_BALANCED((k_pstage<3, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, nc);
 }
 
 template <typename T>
@@ -1302,18 +1262,6 @@ void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* z
   const dim3 g = col_grid(nc, nn);
   if (dim == 2) hipLaunchKernelGGL((k_update<2, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
   else hipLaunchKernelGGL((k_update<3, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
-}
-
-template <typename T>
-void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa,
-                 double inv_theta, int nc, hipStream_t st) {
-  const dim3 g = col_grid(nc, L.nn);
-  const T it = T(inv_theta);
-  switch (comps) {
-    case 1: hipLaunchKernelGGL((k_pre1<1, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, it); break;
-    case 2: hipLaunchKernelGGL((k_pre1<2, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, it); break;
-    default: hipLaunchKernelGGL((k_pre1<3, T>), g, dim3(kBlock), 0, st, L, int(is_A), b, xa, it); break;
-  }
 }
 
 template <typename T>
@@ -1346,24 +1294,22 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
 // explicit instantiations for the two preconditioner precisions
 #define BIOT_INSTANTIATE(T)                                                                      \
   template void launch_residual<T>(int, const LevelDev&, const FineDev&, const ColDesc*, int, T*, \
-                                   T*, T*, double, double*, int, int, bool, hipStream_t);        \
+                                   T*, double*, int, int, bool, hipStream_t);                    \
   template void launch_cheb<T>(int, int, const LevelView<T>&, bool, const T*, const T*, T*, T*,  \
-                               int, double, double, bool, int, const ColDesc*, const T*, double, \
-                               int, bool, hipStream_t);                                           \
+                               int, double, double, bool, int, bool, double, const ColDesc*,     \
+                               const T*, double, int, bool, hipStream_t);                         \
   template void launch_level_residual<T>(int, int, const LevelView<T>&, bool, const T*,          \
                                          const T*, T*, int, int, hipStream_t);                    \
   template void launch_restrict<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,     \
-                                   const T*, T*, T*, double, int, hipStream_t);                   \
+                                   const T*, T*, int, hipStream_t);                               \
   template void launch_prolong<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,      \
                                   const T*, const T*, T*, int, int, hipStream_t);                 \
   template void launch_coarse_solve<T>(int, int, int, const T*, const T*, T*, int, hipStream_t); \
   template void launch_vcycle_tail<T>(int, int, const TailDev<T>&, const T*, T*, int, hipStream_t); \
   template void launch_pstage<T>(int, const LevelView<T>&, const T*, bool, const T*, const T*,   \
-                                 T*, T*, double, int, int, hipStream_t);                          \
+                                 T*, int, int, hipStream_t);                                      \
   template void launch_update<T>(int, int, const ColDesc*, const T*, const T*, double, int,      \
                                  hipStream_t);                                                    \
-  template void launch_pre1<T>(int, const LevelView<T>&, bool, const T*, T*, double, int,        \
-                               hipStream_t);                                                      \
   template void launch_unpack<T>(int, int, const double*, T*, T*, int, hipStream_t);             \
   template void launch_pack<T>(int, int, const T*, const T*, double*, int, hipStream_t);
 

@@ -23,6 +23,8 @@ struct LevelView {
   const T* Ainv;         // [dim*dim][nn]
   const T* Sinv;         // [nn]
   const uint8_t* fixed;  // [nn]
+  const T* AD;           // [W][dim*dim][nn]  A_k(i) Ainv(nbr_k(i))
+  const T* SD;           // [W][nn]           S_k(i) Sinv(nbr_k(i))
 };
 using LevelDev = LevelView<double>;
 
@@ -57,27 +59,28 @@ struct ColDesc {
 // `adj`: the adjoint recursion (coupling A'^T, load F.gload; see k_residual)
 template <typename T>
 void launch_residual(int dim, const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
-                     T* ru, T* rp, T* xa, double inv_theta, double* partials,
-                     int partial_stride, int wpc, bool adj, hipStream_t st);
+                     T* ru, T* rp, double* partials, int partial_stride, int wpc, bool adj,
+                     hipStream_t st);
 // Chebyshev step d <- c1 d + c2 D^{-1}(b - K xin), xout = xin + d.  With `upd`
 // (pressure field, level 0) the step writes the outer update
 // X^{n,m} = X^{n,m-1} + omega [zu; xin + d] through the descriptors instead.
 // wd = false skips storing d; dx: where the previous d comes from (0: d;
-// 1: xin, after a first step from zero, whose producers store only x;
-// 2: xin - xout, after the first post-smoothing step, xout still holding that
-// step's input).
+// 1: xin, after a first step from zero; 2: xin - xout, after the first
+// post-smoothing step, xout still holding that step's input).  first = true:
+// the step after the first step from zero, which is never stored: xin =
+// it D^{-1} b is formed on the fly through the folded operators (L.AD, L.SD);
+// xin is then unused.
 template <typename T>
 void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b, const T* xin,
-                 T* xout, T* d, int nc, double c1, double c2, bool wd, int dx,
-                 const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
+                 T* xout, T* d, int nc, double c1, double c2, bool wd, int dx, bool first,
+                 double it, const ColDesc* upd, const T* zu, double omega, int wpc, bool fine,
                  hipStream_t st);
 template <typename T>
 void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
                            const T* x, T* r, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
-                     bool is_A, const T* rf, T* bc, T* xa_c, double inv_theta_c, int nc,
-                     hipStream_t st);
+                     bool is_A, const T* rf, T* bc, int nc, hipStream_t st);
 template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
                     const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st);
@@ -109,13 +112,10 @@ void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T*
                         hipStream_t st);
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
-                   T* t, T* xa, double inv_theta, int nc, int wpc, hipStream_t st);
+                   T* t, int nc, int wpc, hipStream_t st);
 template <typename T>
 void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* zp, double omega,
                    int nc, hipStream_t st);
-template <typename T>
-void launch_pre1(int comps, const LevelView<T>& L, bool is_A, const T* b, T* xa,
-                 double inv_theta, int nc, hipStream_t st);
 template <typename T>
 void launch_unpack(int dim, int nn, const double* X, T* ru, T* rp, int nc, hipStream_t st);
 template <typename T>

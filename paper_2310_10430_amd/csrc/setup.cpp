@@ -650,4 +650,25 @@ std::string concat_problems(const std::vector<HostProblem>& parts, int pad, Host
   return "";
 }
 
+void fold_first_step(HostProblem& p) {
+  const int dim = p.dim, dd = dim * dim;
+  for (HostLevel& L : p.levels) {
+    const size_t nn = size_t(L.nn);
+    L.AD.assign(size_t(L.W) * dd * nn, 0.0);
+    L.SD.assign(size_t(L.W) * nn, 0.0);
+    for (int k = 0; k < L.W; ++k)
+      for (size_t i = 0; i < nn; ++i) {
+        const size_t w = size_t(L.nbr[k * nn + i]);
+        for (int a = 0; a < dim; ++a)
+          for (int c = 0; c < dim; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < dim; ++j)
+              acc += L.A[(size_t(k) * dd + a * dim + j) * nn + i] * L.Ainv[size_t(j * dim + c) * nn + w];
+            L.AD[(size_t(k) * dd + a * dim + c) * nn + i] = acc;
+          }
+        L.SD[k * nn + i] = L.S[k * nn + i] * L.Sinv[w];
+      }
+  }
+}
+
 }  // namespace biot

@@ -27,6 +27,11 @@ struct HostLevel {
   std::vector<double> Ainv;  // [dim*dim][nn]     inverse of the node's A block
   std::vector<double> Sinv;  // [nn]
   std::vector<uint8_t> fixed;// [nn] bit c (<dim): u_c prescribed, bit dim: p prescribed
+  // the operators with the neighbour's block-Jacobi inverse folded in, for the
+  // smoothing step that follows a first step from zero (x = D^{-1} b / theta at
+  // every node): AD_k(i) = A_k(i) Ainv(nbr_k(i)), SD_k(i) = S_k(i) Sinv(nbr_k(i))
+  std::vector<double> AD;    // [W][dim*dim][nn]
+  std::vector<double> SD;    // [W][nn]
   double lmaxA = 0, lmaxS = 0;  // spectral bounds of D^{-1}A and D^{-1}S (with safety)
   // fine level only
   std::vector<double> B;     // [W][dim][nn]  u-row / p-column coupling (matrix of -b)
@@ -89,6 +94,9 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
 // Spectral bounds become the maximum over the copies.  The load multipliers of
 // all parts must agree on their common steps (the result keeps the longest).
 std::string concat_problems(const std::vector<HostProblem>& parts, int pad, HostProblem& out);
+
+// Fills AD and SD of every level from A, S, their block inverses and nbr.
+void fold_first_step(HostProblem& p);
 
 // SplitMix64-based start vector in [0.5, 1.5) shared by the spectral bounds.
 double splitmix_unit(uint64_t index);

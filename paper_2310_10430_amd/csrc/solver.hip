@@ -252,11 +252,15 @@ void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
       D.S = h->L[l].S;
       D.Ainv = h->L[l].Ainv;
       D.Sinv = h->L[l].Sinv;
+      D.AD = h->L[l].AD;
+      D.SD = h->L[l].SD;
     } else {
       D.A = b.take<T>(H.A.size());
       D.S = b.take<T>(H.S.size());
       D.Ainv = b.take<T>(H.Ainv.size());
       D.Sinv = b.take<T>(H.Sinv.size());
+      D.AD = b.take<T>(H.AD.size());
+      D.SD = b.take<T>(H.SD.size());
     }
   }
   if constexpr (std::is_same<T, double>::value) p.Bt = h->F.Bt;
@@ -304,6 +308,8 @@ void plan(biot_handle* h, char* base) {
     D.Ainv = b.take<double>(H.Ainv.size());
     D.Sinv = b.take<double>(H.Sinv.size());
     D.fixed = b.take<uint8_t>(H.fixed.size());
+    D.AD = b.take<double>(H.AD.size());
+    D.SD = b.take<double>(H.SD.size());
   }
   const HostLevel& H0 = h->P.levels[0];
   h->F.B = b.take<double>(H0.B.size());
@@ -480,7 +486,6 @@ ChebCoef cheb_of(double lmax, double ratio) {
   return c;
 }
 
-bool level0_smoothed(const biot_handle* h) { return h->nlev > 1; }
 
 const char* kProbeNames[BIOT_PROBE_COUNT] = {
     "k_residual (fused residual, coupling, norms; level 0)",
@@ -543,15 +548,19 @@ struct ProbeScope {
 
 // algorithmic bytes of the level-0 launches (distinct inputs and outputs once);
 // `t` = bytes per value of the preconditioner precision
-double bytes_residual(const biot_handle* h, int nc, bool write_r, bool pre, int t) {
+double bytes_residual(const biot_handle* h, int nc, bool write_r, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
-  double per_col = 8 * D1 * 2 + (write_r ? t * (d + 1) : 0) + (pre ? t * d : 0);
-  double mat = W * (d * d + 2 * d + 2) * 8 + 4 * W + 8 * D1 + (pre ? 8 * d * d : 0);
+  double per_col = 8 * D1 * 2 + (write_r ? t * (d + 1) : 0);
+  double mat = W * (d * d + 2 * d + 2) * 8 + 4 * W + 8 * D1;
   return nc * nn * per_col + nn * mat;
 }
-double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool upd, bool wd, int t) {
+// `first`: the step after the unstored first step reads only b (the gathered
+// vector) and no separate iterate
+double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool upd, bool wd, bool first,
+                  int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
-  double per_col = double(t) * C * (2 + (c1 ? 1 : 0) + (upd ? 0 : 1 + (wd ? 1 : 0)));
+  double per_col =
+      double(t) * C * ((first ? 1 : 2) + (c1 ? 1 : 0) + (upd ? 0 : 1 + (wd ? 1 : 0)));
   if (upd) per_col += 8 * D1 * 2 + t * d;
   double total = nc * nn * per_col + (upd ? h->cur_copies * nn * 8 * D1 : 0);
   total += nn * (W * C * C * t + 4 * W + C * C * t);
@@ -563,12 +572,13 @@ double bytes_levres(const biot_handle* h, int C, int nc, int t) {
 }
 double bytes_pstage(const biot_handle* h, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
-  return nc * nn * t * (d + 3) + nn * (W * d * t + 4 * W + t);
+  return nc * nn * t * (d + 2) + nn * (W * d * t + 4 * W);
 }
 
 // One V-cycle for field A (is_A) or S on level l for nc columns.  On entry b[l]
-// holds the right-hand side and, unless l is the coarsest level, x0[l]/d[l]
-// hold the first Chebyshev step.  The result is returned in *out; when `upd`
+// holds the right-hand side; the first Chebyshev step from zero is pointwise
+// and never stored (the second step forms it from b).  The result is returned
+// in *out; when `upd`
 // is given (pressure field, level 0) the last smoothing step writes the outer
 // update through those descriptors instead and *out is null.
 template <typename T>
@@ -612,11 +622,15 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   for (int j = 2; j <= deg; ++j) {
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
     // d after the last pre-smoothing step is dead: the first post-smoothing
-    // step does not read it
+    // step does not read it.  The first step from zero (x = D^{-1} b / theta)
+    // is never stored: step 2 forms it from b.
     const bool wd = j < deg;
-    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? bytes_cheb(h, C, nc, j > 2, false, wd, tb) : 0);
-    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, rn * rho,
-                   2.0 * rn / cc.delta, wd, j == 2 ? 1 : 0, nullptr, nullptr, 0.0, wpc, fine, st);
+    const bool first = j == 2;
+    ProbeScope ps(h, fine ? pid_cheb : -1,
+                  fine ? bytes_cheb(h, C, nc, j > 2, false, wd, first, tb) : 0);
+    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], first ? f.b[l] : cur, oth, f.d[l], nc,
+                   rn * rho, 2.0 * rn / cc.delta, wd, first ? 1 : 0, first, 1.0 / cc.theta,
+                   nullptr, nullptr, 0.0, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -629,12 +643,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
   }
-  // no first Chebyshev step on the coarsest level or where the fused tail starts
-  const bool coarse_last = (l + 1 == last) || (l + 1 == tail);
-  const ChebCoef* cn = coarse_last ? nullptr : (is_A ? &h->chA[l + 1] : &h->chS[l + 1]);
-  launch_restrict<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, f.r[l], f.b[l + 1],
-                     coarse_last ? nullptr : f.x0[l + 1], coarse_last ? 0.0 : 1.0 / cn->theta, nc,
-                     st);
+  launch_restrict<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, f.r[l], f.b[l + 1], nc, st);
   LAUNCHCHK(h);
   T* xc = nullptr;
   int rc = vcycle<T>(h, p, is_A, l + 1, nc, &xc, nullptr, nullptr);
@@ -657,9 +666,9 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     // holds the first step's input
     const bool wd = j > 1 && j < deg;
     const int dx = j == 2 ? 2 : 0;
-    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, wd, tb) : 0);
-    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2, wd, dx,
-                   final_upd ? upd : nullptr, zu, h->opt.omega, wpc, fine, st);
+    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, wd, false, tb) : 0);
+    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2, wd, dx, false,
+                   0.0, final_upd ? upd : nullptr, zu, h->opt.omega, wpc, fine, st);
     LAUNCHCHK(h);
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
@@ -669,19 +678,16 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   return BIOT_OK;
 }
 
-// P^{-1} applied to the batch whose residual is in fa.b[0] (r_u) and rp (r_p);
-// the first Chebyshev step of V_A has been written by the producer.  With
-// `upd`, the outer update is written through those descriptors.
+// P^{-1} applied to the batch whose residual is in fa.b[0] (r_u) and rp (r_p).
+// With `upd`, the outer update is written through those descriptors.
 template <typename T>
 int precond_batch(biot_handle* h, Prec<T>& p, int nc, T** zu, T** zp, const ColDesc* upd) {
   int rc = vcycle<T>(h, p, true, 0, nc, zu, nullptr, nullptr);
   if (rc) return rc;
-  const bool sm = level0_smoothed(h);
   {
     ProbeScope ps(h, BIOT_PROBE_PSTAGE, bytes_pstage(h, nc, int(sizeof(T))));
     launch_pstage<T>(h->dim, p.L[0], p.Bt, h->opt.precond == BIOT_PRECOND_P1, *zu, p.rp,
-                     p.fs.b[0], p.fs.x0[0], sm ? 1.0 / h->chS[0].theta : 0.0, nc,
-                     h->opt.wg_per_cu, h->st);
+                     p.fs.b[0], nc, h->opt.wg_per_cu, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
   }
@@ -699,12 +705,10 @@ FineDev fine_of(const biot_handle* h, const Sched& S) {
 
 template <typename T>
 int unit_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols, int nc) {
-  const bool sm = level0_smoothed(h);
   {
-    ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, sm, int(sizeof(T))));
-    launch_residual<T>(h->dim, h->L[0], fine_of(h, S), cols, nc, p.fa.b[0], p.rp,
-                       sm ? p.fa.x0[0] : nullptr, sm ? 1.0 / h->chA[0].theta : 0.0,
-                       nullptr, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
+    ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, int(sizeof(T))));
+    launch_residual<T>(h->dim, h->L[0], fine_of(h, S), cols, nc, p.fa.b[0], p.rp, nullptr,
+                       h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
     if (ps.end()) return BIOT_EHIP;
   }
@@ -716,16 +720,10 @@ int unit_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols
 // Z = P^{-1} R for caller columns (diagnostic path)
 template <typename T>
 int apply_precond_t(biot_handle* h, Prec<T>& p, const double* R, double* Z, int ncols) {
-  const bool sm = level0_smoothed(h);
   for (int c0 = 0; c0 < ncols; c0 += h->ncmax) {
     const int nc = std::min(h->ncmax, ncols - c0);
     launch_unpack<T>(h->dim, h->nn, R + size_t(c0) * h->col, p.fa.b[0], p.rp, nc, h->st);
     LAUNCHCHK(h);
-    if (sm) {
-      launch_pre1<T>(h->dim, p.L[0], true, p.fa.b[0], p.fa.x0[0], 1.0 / h->chA[0].theta,
-                     nc, h->st);
-      LAUNCHCHK(h);
-    }
     T *zu = nullptr, *zp = nullptr;
     int rc = precond_batch<T>(h, p, nc, &zu, &zp, nullptr);
     if (rc) return rc;
@@ -750,7 +748,7 @@ int gmres_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* col
   hipStream_t st = h->st;
   const GmresVecs Vv{h->gV, sv, col};
   launch_residual<double>(h->dim, h->L[0], fine_of(h, S), cols, nc, h->gru, h->grp, nullptr,
-                          0.0, nullptr, h->nblk, h->opt.wg_per_cu, S.adj, st);
+                          h->nblk, h->opt.wg_per_cu, S.adj, st);
   LAUNCHCHK(h);
   launch_pack<double>(h->dim, h->nn, h->gru, h->grp, h->gT, nc, st);
   LAUNCHCHK(h);
@@ -912,8 +910,8 @@ int global_residual(biot_handle* h, const Sched& S) {
   const FineDev f = fine_of(h, S);
   for (int n0 = 0; n0 < S.N; n0 += chunk) {
     const int nc = std::min(chunk, S.N - n0);
-    launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, nullptr, 0.0,
-                            h->partials, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
+    launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, h->partials,
+                            h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
     launch_reduce_norms(h->partials, num_node_blocks(h->P.levels[0].nn1), h->S, h->nblk,
                         h->norms + size_t(n0) * h->S * 4, nc, h->st);
@@ -1204,6 +1202,7 @@ int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_mater
       }
       if (e.empty()) e = concat_problems(parts, kBlock, h->P);
     }
+    if (e.empty()) fold_first_step(h->P);
   } catch (const std::exception& ex) {
     e = std::string("set-up failed: ") + ex.what();
   }
@@ -1274,6 +1273,8 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
     HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.Ainv), H.Ainv.data(), H.Ainv.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.Sinv), H.Sinv.data(), H.Sinv.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(h, hipMemcpyAsync(const_cast<uint8_t*>(D.fixed), H.fixed.data(), H.fixed.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.AD), H.AD.data(), H.AD.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.SD), H.SD.data(), H.SD.size() * 8, hipMemcpyHostToDevice, st));
   }
   const HostLevel& H0 = h->P.levels[0];
   HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.B), H0.B.data(), H0.B.size() * 8, hipMemcpyHostToDevice, st));
@@ -1294,6 +1295,8 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
       HIPCHK(h, up32(D.S, H.S));
       HIPCHK(h, up32(D.Ainv, H.Ainv));
       HIPCHK(h, up32(D.Sinv, H.Sinv));
+      HIPCHK(h, up32(D.AD, H.AD));
+      HIPCHK(h, up32(D.SD, H.SD));
     }
     HIPCHK(h, up32(h->pf.Bt, h->P.levels[0].Bt));
     HIPCHK(h, up32(h->pf.coarseA, h->P.coarseAinv));
