@@ -630,11 +630,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
 // ---------------------------------------------------------------------------
 // The coarse end of a V-cycle in one launch: levels t..last of the hierarchy
 // for one column per workgroup, every vector in LDS.  The steps are exactly
-// those of the per-level kernels (k_pre1's first Chebyshev step, k_cheb,
-// k_level_residual, k_restrict, k_coarse_solve, k_prolong), in the same order
-// and with the same summation order, so the result is the same as running
-// them one launch at a time; only the launches (each a few microseconds on a
-// level of a few hundred nodes) are saved.
+// those of the per-level kernels (k_cheb with its folded first step and
+// recovered increments, k_level_residual, k_restrict, k_coarse_solve,
+// k_prolong), in the same order and with the same summation order, so the
+// result is the same as running them one launch at a time; only the launches
+// (each a few microseconds on a level of a few hundred nodes) are saved.
 // ---------------------------------------------------------------------------
 namespace tail {
 
@@ -648,31 +648,22 @@ constexpr int block() { return DIM == 2 ? 1024 : 256; }
 // is the copy's first node in the level's arrays; LDS vectors hold only the
 // copy's grid nodes (local numbering).
 
-// x = d = inv_theta D^{-1} b
-template <int DIM, int C, typename T>
-__device__ inline void first_step(const LevelView<T>& L, int base, const T* b, T* x, T* d, T it) {
-  const T* Dg = C > 1 ? L.Ainv : L.Sinv;
-  for (int v = threadIdx.x; v < L.nreal; v += block<DIM>()) {
-    const int g = base + v;
-#pragma unroll
-    for (int a = 0; a < C; ++a) {
-      T z = T(0);
-#pragma unroll
-      for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * L.nn + g] * b[v * C + k];
-      z *= it;
-      x[v * C + a] = z;
-      d[v * C + a] = z;
-    }
-  }
-}
-
-// one Chebyshev step xout = xin + d, d <- c1 d + c2 D^{-1}(b - K xin)
-template <int DIM, int C, typename T>
+// One Chebyshev step xout = xin + d, d <- c1 dp + c2 D^{-1}(b - K xin), with
+// the previous increment dp and the storing of d chosen as in k_cheb:
+//   first: the step after the (unstored) first step from zero, xin formed as
+//          it D^{-1} b through the folded operators, dp = xin;
+//   dx = 2: dp = xin - xout at the node (xout holds the previous step's input
+//          and is overwritten in place);
+//   else dp = d (when c1 != 0); wd: store d.
+template <int DIM, int C, bool FIRST, typename T>
 __device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T* xin, T* xout,
-                            T* d, T c1, T c2) {
+                            T* d, T c1, T c2, T it, int dx, bool wd) {
+  constexpr bool first = FIRST;
   constexpr int W = DIM == 2 ? 7 : 15;
-  const T* K = C > 1 ? L.A : L.S;
+  const T* K = first ? (C > 1 ? L.AD : L.SD) : (C > 1 ? L.A : L.S);
   const T* Dg = C > 1 ? L.Ainv : L.Sinv;
+  const T* src = first ? b : xin;
+  const T sc = first ? it : T(1);
   const int nn = L.nn;
   for (int v = threadIdx.x; v < L.nreal; v += block<DIM>()) {
     const int g = base + v;
@@ -684,16 +675,26 @@ __device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T
       const int w = L.nbr[size_t(s) * nn + g] - base;
       T xw[C];
 #pragma unroll
-      for (int k = 0; k < C; ++k) xw[k] = xin[w * C + k];
-      if (s == 0)
+      for (int k = 0; k < C; ++k) xw[k] = src[w * C + k];
+      if (s == 0) {
 #pragma unroll
-        for (int k = 0; k < C; ++k) xs[k] = xw[k];
+        for (int a = 0; a < C; ++a) {
+          if (first) {
+            T z = T(0);
+#pragma unroll
+            for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * nn + g] * xw[k];
+            xs[a] = z * it;
+          } else {
+            xs[a] = xw[a];
+          }
+        }
+      }
 #pragma unroll
       for (int a = 0; a < C; ++a) {
         T s2 = T(0);
 #pragma unroll
         for (int k = 0; k < C; ++k) s2 += K[(size_t(s) * C * C + a * C + k) * nn + g] * xw[k];
-        acc[a] -= s2;
+        acc[a] -= sc * s2;
       }
     }
 #pragma unroll
@@ -701,8 +702,9 @@ __device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T
       T z = T(0);
 #pragma unroll
       for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * nn + g] * acc[k];
-      const T dn = (c1 != T(0) ? c1 * d[v * C + a] : T(0)) + c2 * z;
-      d[v * C + a] = dn;
+      const T dp = c1 == T(0) ? T(0) : first ? xs[a] : dx == 2 ? xs[a] - xout[v * C + a] : d[v * C + a];
+      const T dn = c1 * dp + c2 * z;
+      if (wd) d[v * C + a] = dn;
       xout[v * C + a] = xs[a] + dn;
     }
   }
@@ -734,11 +736,10 @@ __device__ inline void residual(const LevelView<T>& L, int base, const T* b, con
   }
 }
 
-// bc = P' rf (masked); with `first`, also the first Chebyshev step of the
-// coarse level (x = d = it D^{-1} bc)
+// bc = P' rf (masked)
 template <int DIM, int C, typename T>
 __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, const LevelView<T>& Lc,
-                                   int basec, const T* rf, T* bc, bool first, T* xa, T* d, T it) {
+                                   int basec, const T* rf, T* bc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
   const int bit0 = C > 1 ? 0 : DIM;
@@ -765,18 +766,6 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, const Leve
     for (int a = 0; a < C; ++a) {
       if ((fc >> (bit0 + a)) & 1) acc[a] = T(0);
       bc[I * C + a] = acc[a];
-    }
-    if (first) {
-      const T* Dg = C > 1 ? Lc.Ainv : Lc.Sinv;
-#pragma unroll
-      for (int a = 0; a < C; ++a) {
-        T z = T(0);
-#pragma unroll
-        for (int k = 0; k < C; ++k) z += Dg[size_t(a * C + k) * Lc.nn + basec + I] * acc[k];
-        z *= it;
-        xa[I * C + a] = z;
-        d[I * C + a] = z;
-      }
     }
   }
 }
@@ -812,40 +801,44 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
   const int copies = TD.L[0].copies;
   const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
   const int nl = TD.nlev;  // levels t..t+nl-1; the last one is solved densely
-  // level i's LDS block at TD.off[i]: b, x0, x1, d, r (coarsest: b, x0), each
-  // nreal_i * C values; bit i of `alt` set when level i's current iterate is x1
+  const int deg = TD.degree;
+  // level i's LDS block at TD.off[i]: b, two iterates (the free one also holds
+  // the residual) and, for degree > 2, d (coarsest: b, x), each nreal_i * C
+  // values; bit i of `alt` set when level i's current iterate is the second
   auto vec = [&](int i, int k) { return lds + TD.off[i] + k * TD.L[i].nreal * C; };
   auto base = [&](int i) { return cp * TD.L[i].nn1; };
+  T* const dnull = nullptr;
   unsigned alt = 0;
   const int n0 = TD.L[0].nreal * C;
   const size_t g0 = (size_t(c) * TD.L[0].nn + base(0)) * C;
   for (int i = threadIdx.x; i < n0; i += tail::block<DIM>()) vec(0, 0)[i] = b_t[g0 + i];
   __syncthreads();
-  // descend
+  // descend: pre-smoothing (its first step folded into the second), residual
+  // into the free iterate, restriction
   for (int i = 0; i + 1 < nl; ++i) {
     const LevelView<T>& L = TD.L[i];
     const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
-    if (i == 0) {
-      tail::first_step<DIM, C, T>(L, base(0), vec(0, 0), vec(0, 1), vec(0, 3), T(1.0 / theta));
-      __syncthreads();
-    }
-    int xi = 1;  // x0
+    T* d = deg > 2 ? vec(i, 3) : dnull;
+    int xi = 1;
     double rho = 1.0 / sigma;
-    for (int j = 2; j <= TD.degree; ++j) {
+    for (int j = 2; j <= deg; ++j) {
       const double rn = 1.0 / (2.0 * sigma - rho);
-      tail::cheb<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3),
-                            T(rn * rho), T(2.0 * rn / delta));
+      const bool first = j == 2;
+      if (first)
+        tail::cheb<DIM, C, true, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 1), d, T(rn * rho),
+                                    T(2.0 * rn / delta), T(1.0 / theta), 0, j < deg);
+      else
+        tail::cheb<DIM, C, false, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), d,
+                                     T(rn * rho), T(2.0 * rn / delta), T(0), 0, j < deg);
       __syncthreads();
       rho = rn;
-      xi = 3 - xi;
+      if (!first) xi = 3 - xi;
     }
     if (xi == 2) alt |= 1u << i;
-    tail::residual<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 4));
+    tail::residual<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi));
     __syncthreads();
-    const bool first = i + 2 < nl;
-    tail::restrict_to<DIM, C, T>(L, base(i), TD.L[i + 1], base(i + 1), vec(i, 4), vec(i + 1, 0),
-                                 first, vec(i + 1, 1), first ? vec(i + 1, 3) : nullptr,
-                                 first ? T(1.0 / TD.theta[i + 1]) : T(0));
+    tail::restrict_to<DIM, C, T>(L, base(i), TD.L[i + 1], base(i + 1), vec(i, 3 - xi),
+                                 vec(i + 1, 0));
     __syncthreads();
   }
   // coarsest level: dense inverse of this copy
@@ -862,10 +855,13 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
     }
     __syncthreads();
   }
-  // ascend: coarse-grid correction, then the post-smoothing steps
+  // ascend: coarse-grid correction into the free iterate, then the
+  // post-smoothing steps (the second recovers the first one's increment from
+  // the buffer it overwrites)
   for (int i = nl - 2; i >= 0; --i) {
     const LevelView<T>& L = TD.L[i];
     const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
+    T* d = deg > 2 ? vec(i, 3) : dnull;
     int xi = ((alt >> i) & 1u) ? 2 : 1;
     const int xci = (i + 2 == nl) ? 1 : (((alt >> (i + 1)) & 1u) ? 2 : 1);
     tail::prolong<DIM, C, T>(L, base(i), TD.L[i + 1], base(i + 1), vec(i, xi), vec(i + 1, xci),
@@ -873,15 +869,15 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
     __syncthreads();
     xi = 3 - xi;
     double rho = 1.0 / sigma;
-    for (int j = 1; j <= TD.degree; ++j) {
+    for (int j = 1; j <= deg; ++j) {
       double c1 = 0.0, c2 = 1.0 / theta, rn = rho;
       if (j > 1) {
         rn = 1.0 / (2.0 * sigma - rho);
         c1 = rn * rho;
         c2 = 2.0 * rn / delta;
       }
-      tail::cheb<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), vec(i, 3), T(c1),
-                            T(c2));
+      tail::cheb<DIM, C, false, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), d, T(c1),
+                                   T(c2), T(0), j == 2 ? 2 : 0, j > 1 && j < deg);
       __syncthreads();
       rho = rn;
       xi = 3 - xi;
@@ -1225,9 +1221,12 @@ void launch_coarse_solve(int n, int stride, int copies, const T* Minv, const T* 
                      st, n, stride, copies, Minv, b, x);
 }
 
-size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes) {
+int tail_vectors(int degree) { return degree > 2 ? 4 : 3; }
+
+size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes, int degree) {
   size_t n = 0;
-  for (int i = 0; i < nlev; ++i) n += size_t(level_nn[i]) * comps * (i + 1 < nlev ? 5 : 2);
+  for (int i = 0; i < nlev; ++i)
+    n += size_t(level_nn[i]) * comps * (i + 1 < nlev ? tail_vectors(degree) : 2);
   return n * tbytes;
 }
 
@@ -1236,7 +1235,7 @@ void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T*
                         hipStream_t st) {
   int nnl[kTailMaxLevels];
   for (int i = 0; i < TD.nlev; ++i) nnl[i] = TD.L[i].nreal;
-  const size_t lds = tail_lds_bytes(nnl, TD.nlev, comps, int(sizeof(T)));
+  const size_t lds = tail_lds_bytes(nnl, TD.nlev, comps, int(sizeof(T)), TD.degree);
   const dim3 g(nc * TD.L[0].copies);
   if (dim == 2) {
     const dim3 tb(tail::block<2>());

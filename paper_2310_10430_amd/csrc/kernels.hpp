@@ -106,7 +106,10 @@ struct TailDev {
   int off[kTailMaxLevels];  // LDS offset (in values) of each level's vectors
   const T* Minv;
 };
-size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes);
+// LDS vectors per (non-coarsest) tail level for a smoother degree, and the
+// tail's LDS bytes
+int tail_vectors(int degree);
+size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes, int degree);
 template <typename T>
 void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T* x, int nc,
                         hipStream_t st);

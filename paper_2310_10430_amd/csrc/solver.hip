@@ -210,7 +210,9 @@ void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
     if (n > kTailMaxLevels) continue;
     int nnl[kTailMaxLevels];
     for (int i = 0; i < n; ++i) nnl[i] = h->P.levels[l + i].nreal;
-    if (tail_lds_bytes(nnl, n, C, int(sizeof(T))) > std::min(kTailMaxLds, h->tail_lds)) continue;
+    if (tail_lds_bytes(nnl, n, C, int(sizeof(T)), h->opt.cheb_degree) >
+        std::min(kTailMaxLds, h->tail_lds))
+      continue;
     t = l;
     break;
   }
@@ -228,7 +230,7 @@ void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
   int off = 0;
   for (int i = 0; i < td.nlev; ++i) {
     td.off[i] = off;
-    off += h->P.levels[t + i].nreal * C * (i + 1 < td.nlev ? 5 : 2);
+    off += h->P.levels[t + i].nreal * C * (i + 1 < td.nlev ? tail_vectors(td.degree) : 2);
   }
 }
 
