@@ -115,14 +115,15 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
                                                      const ColDesc* __restrict__ cols, int nc,
                                                      T* __restrict__ ru, T* __restrict__ rp,
                                                      double* __restrict__ partials, int pstride) {
-  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
-  constexpr int NQ = DIM == 2 ? 2 : 1;
+  // columns per iteration: two in 2D, whose rows stay in registers; eight in 3D,
+  // whose rows are re-read from the caches once per group of columns
+  constexpr bool STAT = DIM == 2;
+  constexpr int NQ = STAT ? 2 : 8;
   constexpr int D1 = DIM + 1;
   constexpr int W = DIM == 2 ? 7 : 15;
-  constexpr bool STAT = DIM == 2;
   constexpr int RS = STAT ? W : 1;
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
-  __shared__ double lds[4 * 8];
+  __shared__ double lds[4 * 4 * NQ];
   const int nn = L.nn;
   for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
     const int v = nblk * kBlock + threadIdx.x;
@@ -153,10 +154,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
     for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(vv) * D1 + a] : 0.0;
 #pragma unroll 1
     for (int c = cbeg; c < cend; c += NQ) {
-      const bool two = NQ > 1 && c + 1 < cend;
+      // columns past the end of the run repeat the last one (computed, not stored)
       int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      for (int q = 0; q < NQ; ++q) cc[q] = min(c + q, cend - 1);
       const double* xc[NQ];
       const double* xp[NQ];
       double coef[NQ], au[NQ][DIM], ap[NQ], bp[NQ], cu[NQ][DIM];
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        if (!active || (q == 1 && !two)) break;
+        if (!active || c + q >= cend) break;
         const size_t cu = size_t(cc[q]) * nn * DIM;
         if (ru) {
 #pragma unroll
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
         if (threadIdx.x == 0)
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            if (q == 1 && !two) break;
+            if (c + q >= cend) break;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
               partials[(size_t(cc[q]) * pstride + nblk) * 4 + k] = qv[4 * q + k];
@@ -338,10 +339,11 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
                                                  T c1, T c2, int wd, int dx, int first, T it,
                                                  const ColDesc* __restrict__ cols,
                                                  const T* __restrict__ zu, double omega) {
-  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
-  constexpr int NQ = DIM == 2 ? 2 : 1;
+  // columns per iteration: two when the row stays in registers; eight otherwise
+  // (3D displacement), whose rows are re-read from the caches once per group
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = W * C * C <= 64;
+  constexpr int NQ = STAT ? 2 : 8;
   constexpr int RS = STAT ? W : 1;
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
@@ -371,10 +373,10 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
     for (int e = 0; e < C * C; ++e) Di[e] = Dg[size_t(e) * nn + v];
 #pragma unroll 1
     for (int c = cbeg; c < cend; c += NQ) {
-      const bool two = NQ > 1 && c + 1 < cend;
+      // columns past the end of the run repeat the last one (computed, not stored)
       int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      for (int q = 0; q < NQ; ++q) cc[q] = min(c + q, cend - 1);
       // column base pointers; offsets within a column fit in 32 bits
       const T* xq[NQ];
 #pragma unroll
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        if (q == 1 && !two) break;
+        if (c + q >= cend) break;
         const size_t base = size_t(cc[q]) * stride + size_t(v) * C;
         T xn[C];
 #pragma unroll
@@ -507,10 +509,11 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
                                                            const T* __restrict__ b,
                                                            const T* __restrict__ x,
                                                            T* __restrict__ r, int nc) {
-  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
-  constexpr int NQ = DIM == 2 ? 2 : 1;
+  // columns per iteration: two when the row stays in registers; eight otherwise
+  // (3D displacement), whose rows are re-read from the caches once per group
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = W * C * C <= 64;
+  constexpr int NQ = STAT ? 2 : 8;
   constexpr int RS = STAT ? W : 1;
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
@@ -533,10 +536,10 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
     }
 #pragma unroll 1
     for (int c = cbeg; c < cend; c += NQ) {
-      const bool two = NQ > 1 && c + 1 < cend;
+      // columns past the end of the run repeat the last one (computed, not stored)
       int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      for (int q = 0; q < NQ; ++q) cc[q] = min(c + q, cend - 1);
       T acc[NQ][C];
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
@@ -564,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        if (q == 1 && !two) break;
+        if (c + q >= cend) break;
 #pragma unroll
         for (int a = 0; a < C; ++a) r[size_t(cc[q]) * stride + size_t(v) * C + a] = acc[q][a];
       }
@@ -922,8 +925,8 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
                                                    int p1, const T* __restrict__ zu,
                                                    const T* __restrict__ rp,
                                                    T* __restrict__ t_out, int nc) {
-  // columns per iteration: two in 2D; one in 3D, whose rows do not fit in registers
-  constexpr int NQ = DIM == 2 ? 2 : 1;
+  // columns per iteration (the Bt row stays in registers)
+  constexpr int NQ = 2;
   constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
   for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
@@ -939,10 +942,10 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
     }
 #pragma unroll 1
     for (int c = cbeg; c < cend; c += NQ) {
-      const bool two = NQ > 1 && c + 1 < cend;
+      // columns past the end of the run repeat the last one (computed, not stored)
       int cc[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) cc[q] = two ? c + q : c;
+      for (int q = 0; q < NQ; ++q) cc[q] = min(c + q, cend - 1);
       T acc[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
@@ -960,7 +963,7 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        if (q == 1 && !two) break;
+        if (c + q >= cend) break;
         t_out[size_t(cc[q]) * nn + v] = acc[q];
       }
     }
@@ -1084,6 +1087,10 @@ struct OccHash {
   }
 };
 
+// default cap on resident workgroups per CU of a balanced launch (measured on
+// the 256^2 headline workload: 2, 3 and 4 give 487, 482 and 491 ms per solve)
+constexpr int kDefaultMaxWgPerCu = 3;
+
 dim3 balanced_grid(const void* fn, int nn, int nc, int wpc) {
   static std::mutex mu;
   static std::unordered_map<OccKey, int, OccHash> occ;
@@ -1107,7 +1114,9 @@ dim3 balanced_grid(const void* fn, int nn, int nc, int wpc) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fn, kBlock, 0) != hipSuccess || o < 1) o = 1;
         io = occ.emplace(OccKey{fn, dev}, o).first;
       }
-      per_cu = io->second;
+      // at most kDefaultMaxWgPerCu: light kernels reach high occupancy, but
+      // more, smaller pieces re-read each node's operator row more often
+      per_cu = std::min(io->second, kDefaultMaxWgPerCu);
     }
   }
   const long units = long(num_node_blocks(nn)) * nc;
@@ -1222,6 +1231,8 @@ void launch_coarse_solve(int n, int stride, int copies, const T* Minv, const T* 
 }
 
 int tail_vectors(int degree) { return degree > 2 ? 4 : 3; }
+
+int tail_block_threads(int dim) { return dim == 2 ? tail::block<2>() : tail::block<3>(); }
 
 size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes, int degree) {
   size_t n = 0;

@@ -109,6 +109,8 @@ struct TailDev {
 // LDS vectors per (non-coarsest) tail level for a smoother degree, and the
 // tail's LDS bytes
 int tail_vectors(int degree);
+// threads of a tail workgroup (one workgroup per column and sample copy)
+int tail_block_threads(int dim);
 size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes, int degree);
 template <typename T>
 void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T* x, int nc,

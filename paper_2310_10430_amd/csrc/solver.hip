@@ -199,6 +199,9 @@ struct Bump {
 // The coarsest levels whose V-cycle vectors fit in the LDS of one workgroup
 // (kTailMaxLds, or less if the device allows less) run as one fused launch;
 // level 0 never does (its steps are fused with the residual and the update).
+// A level joins only if it has at most two nodes per tail thread: the tail runs
+// one workgroup per column, so a larger level is faster as its own launches,
+// which spread over the whole chip.
 template <typename T>
 void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
   const int last = h->nlev - 1, C = is_A ? h->dim : 1;
@@ -208,6 +211,7 @@ void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
   for (int l = 1; l < last; ++l) {
     const int n = last - l + 1;
     if (n > kTailMaxLevels) continue;
+    if (h->P.levels[l].nreal > 2 * tail_block_threads(h->dim)) continue;
     int nnl[kTailMaxLevels];
     for (int i = 0; i < n; ++i) nnl[i] = h->P.levels[l + i].nreal;
     if (tail_lds_bytes(nnl, n, C, int(sizeof(T)), h->opt.cheb_degree) >
