@@ -276,8 +276,9 @@ def batched_oracle_errors(trajs):
 def run_batched(args):
     """64 independent samples on uneven meshes (sizes from {32,48,64,96,128},
     128..512 steps, own permeability field and moduli each), solved to the same
-    tolerance three ways: one handle per sample in FP64 (the plain GPU method),
-    and tuned batch handles (one per mesh size, split by the autotuner) in FP64
+    tolerance three ways: one handle per sample in FP64, one after another (the
+    plain GPU method), and tuned batch handles (one per mesh size, split by the
+    autotuner; each on a stream of its own, all solved concurrently) in FP64
     and with the mixed-precision preconditioner."""
     from paper_2310_10430_amd import autotune
     from paper_2310_10430_amd import workloads as W
@@ -307,9 +308,10 @@ def run_batched(args):
             for g in autotune.tuned_groups(b, ch):
                 groups.append(g)
                 wpcs.append(ch["wg_per_cu"])
-        log(f"bench: batched {prec}: {len(groups)} handles")
+        log(f"bench: batched {prec}: {len(groups)} handles, solved concurrently")
         wall, st, tr = autotune.solve_groups(groups, args.rtol, prec, wpcs=wpcs,
-                                             max_sweeps=args.max_sweeps, keep=True)
+                                             max_sweeps=args.max_sweeps, keep=True,
+                                             concurrent=True)
         diff = max(_max_rel_diff(tr[i], ref[i]) for i in ref)
         err = batched_oracle_errors(tr)
         res[f"batched_{prec}"] = {

@@ -21,6 +21,7 @@ from __future__ import annotations
 import json
 import os
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import torch
 
@@ -133,26 +134,37 @@ def tune(problems, precision: str = "mixed", depth: int = 64, splits=(1, 2), wpc
 
 
 def solve_groups(groups, rtol: float, precision: str, depth: int = 64, wpcs=None,
-                 max_sweeps: int = 2000, device="cuda:0", keep=False):
+                 max_sweeps: int = 2000, device="cuda:0", keep=False, concurrent=False):
     """Solves each group of (sample number, problem) pairs as one handle (a
     batch if it has several samples).  Handles are created, bound and warmed up
     (one pass, which captures the graphs) before the timed region; the timed
-    region resets and solves every handle to rtol in turn.  Returns the wall
+    region resets and solves every handle to rtol, in turn, or with
+    `concurrent`, all at once: each handle then runs on a stream of its own
+    (default priority) and is driven by a host thread of its own, so the small
+    launches of different mesh sizes overlap on the GPU.  Returns the wall
     time, the stats per handle and, with keep, {sample number: trajectory}."""
     handles = []
     for k, g in enumerate(groups):
         batch = [pb for _, pb in g]
         wpc = 0 if wpcs is None else wpcs[k]
-        s = BiotSolver(batch if len(batch) > 1 else batch[0], schedule="wavefront", depth=depth,
-                       wg_per_cu=wpc, precision=precision, device=device)
-        s.sweep(depth)
+        stream = torch.cuda.Stream(device=device) if concurrent else None
+        with torch.cuda.stream(stream) if concurrent else _nullctx():
+            s = BiotSolver(batch if len(batch) > 1 else batch[0], schedule="wavefront",
+                           depth=depth, wg_per_cu=wpc, precision=precision, device=device)
+            s.sweep(depth)
         handles.append((s, [i for i, _ in g]))
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for s, _ in handles:
+
+    def run(s):
         s.reset()
-        stats.append(s.solve_to_tol(rtol, max_sweeps=max_sweeps))
+        return s.solve_to_tol(rtol, max_sweeps=max_sweeps)
+
+    t0 = time.perf_counter()
+    if concurrent:
+        with ThreadPoolExecutor(max_workers=len(handles)) as ex:
+            stats = list(ex.map(run, [s for s, _ in handles]))
+    else:
+        stats = [run(s) for s, _ in handles]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     trajs = {}
@@ -163,6 +175,14 @@ def solve_groups(groups, rtol: float, precision: str, depth: int = 64, wpcs=None
     for s, _ in handles:
         s.close()
     return wall, stats, trajs
+
+
+class _nullctx:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *exc):
+        return False
 
 
 def tuned_groups(bucket, choice):

@@ -2,8 +2,10 @@
 
 Every step of the solver runs in the HIP kernels of libbiot_pint.so; this module
 only converts a `workloads.Problem` into the C structures, allocates the device
-workspace as a torch tensor and passes torch's current stream.  It raises if the
-library is not built; there is no other code path.
+workspace as a torch tensor and binds the handle to torch's current stream at
+construction (create it under `torch.cuda.stream(...)` to give it a stream of
+its own; tensors passed in and out are then ordered against the caller's
+stream).  It raises if the library is not built; there is no other code path.
 """
 from __future__ import annotations
 
@@ -180,6 +182,24 @@ class BiotSolver:
     def _check(self, rc):
         return _lib.check(self.lib, rc, self.h)
 
+    # The library enqueues on the stream the handle was bound to; tensors that
+    # cross between it and the caller's current stream are ordered both ways.
+    def _inputs_ready(self, *tensors):
+        """The handle's stream waits for the caller's work on `tensors`."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+            for t in tensors:
+                t.record_stream(self.stream)
+
+    def _outputs_ready(self, *tensors):
+        """The caller's stream waits for the handle's writes to `tensors`."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            for t in tensors:
+                t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
+
     def close(self):
         if getattr(self, "h", None):
             torch.cuda.synchronize(self.device)
@@ -211,8 +231,10 @@ class BiotSolver:
         n1 = self.sample_steps[sample] + 1 if n1 is None else n1
         out = torch.empty((n1 - n0, self.grid_nodes, self.dim + 1), dtype=torch.float64,
                           device=self.device)
+        self._inputs_ready(out)
         self._check(self.lib.biot_get_sample_trajectory(self.h, int(sample), n0, n1,
                                                         C.c_void_p(out.data_ptr()), 1))
+        self._outputs_ready(out)
         return out
 
     def solve_to_tol(self, rtol: float, max_sweeps: int = 1000, check_every: int = 4,
@@ -229,26 +251,33 @@ class BiotSolver:
         n1 = self.n_steps + 1 if n1 is None else n1
         out = torch.empty((n1 - n0, self.n_nodes, self.dim + 1), dtype=torch.float64,
                           device=self.device)
+        self._inputs_ready(out)
         self._check(self.lib.biot_get_trajectory(self.h, n0, n1, C.c_void_p(out.data_ptr()), 1))
+        self._outputs_ready(out)
         return out
 
     def set_trajectory(self, X: torch.Tensor, n0: int = 0):
         X = X.to(self.device, torch.float64).contiguous()
+        self._inputs_ready(X)
         self._check(self.lib.biot_set_trajectory(self.h, n0, n0 + X.shape[0],
                                                  C.c_void_p(X.data_ptr()), 1))
 
     def apply_operator(self, X: torch.Tensor) -> torch.Tensor:
         X = X.to(self.device, torch.float64).contiguous()
         Y = torch.empty_like(X)
+        self._inputs_ready(X, Y)
         self._check(self.lib.biot_apply_operator(self.h, C.c_void_p(X.data_ptr()),
                                                  C.c_void_p(Y.data_ptr()), X.shape[0]))
+        self._outputs_ready(Y)
         return Y
 
     def apply_precond(self, R: torch.Tensor) -> torch.Tensor:
         R = R.to(self.device, torch.float64).contiguous()
         Z = torch.empty_like(R)
+        self._inputs_ready(R, Z)
         self._check(self.lib.biot_apply_precond(self.h, C.c_void_p(R.data_ptr()),
                                                 C.c_void_p(Z.data_ptr()), R.shape[0]))
+        self._outputs_ready(Z)
         return Z
 
     def info(self) -> dict:
@@ -278,8 +307,10 @@ class BiotSolver:
         g = torch.empty((3, ne), dtype=torch.float64, device=self.device)
         st = _lib.AdjointStats()
         ptr = lambda i: C.c_void_p(g[i].data_ptr())
+        self._inputs_ready(g)
         self._check(self.lib.biot_adjoint(self.h, C.byref(obj), float(rtol), int(max_sweeps),
                                           ptr(0), ptr(1), ptr(2), 1, C.byref(st)))
+        self._outputs_ready(g)
         return dict(J=st.J, grad_logk=g[0], grad_lambda=g[1], grad_mu=g[2],
                     adjoint_sweeps=st.adjoint_sweeps, replay_sweeps=st.replay_sweeps,
                     replay_groups=st.replay_groups, adjoint_rel_resid=st.adjoint_rel_resid,
@@ -291,7 +322,9 @@ class BiotSolver:
         n1 = self.n_steps + 1 if n1 is None else n1
         out = torch.empty((n1 - n0, self.n_nodes, self.dim + 1), dtype=torch.float64,
                           device=self.device)
+        self._inputs_ready(out)
         self._check(self.lib.biot_get_adjoint(self.h, n0, n1, C.c_void_p(out.data_ptr()), 1))
+        self._outputs_ready(out)
         return out
 
     def profile(self, enable: bool = True, probes=None):

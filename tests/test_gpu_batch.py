@@ -6,7 +6,9 @@ together in every launch.
   <= 1e-8 per field, for both schedules and the mixed-precision preconditioner;
 * the batch against the same samples solved one handle at a time;
 * 3D samples;
-* the per-sample residual norms match the single-sample ones.
+* the per-sample residual norms match the single-sample ones;
+* handles of several mesh sizes solved concurrently, each on a stream of its
+  own, match the same handles solved one after another, bit for bit.
 """
 import numpy as np
 import pytest
@@ -97,3 +99,26 @@ def test_batch_residual_norms_per_sample():
         assert np.all(np.isfinite(nb[:, i]))
         np.testing.assert_allclose(nb[: pb.n_steps, i, 2], ns[:, 2], rtol=1e-12)  # ||b_u||^2
     s.close()
+
+
+def test_concurrent_handles_on_own_streams_match_sequential():
+    # handles of different mesh sizes, each bound to a stream of its own and
+    # driven by a host thread of its own, give the same trajectories bit for bit
+    from paper_2310_10430_amd import autotune
+    groups = []
+    for n, steps in ((8, (6, 9)), (12, (5, 7, 4)), (16, (8,))):
+        groups.append([(len(sum(groups, [])) + k, W.heterogeneous_problem(n, N, field_seed=50 + k))
+                       for k, N in enumerate(steps)])
+    _, st_a, a = autotune.solve_groups(groups, 1e-11, "fp64", depth=4, keep=True)
+    _, st_b, b = autotune.solve_groups(groups, 1e-11, "fp64", depth=4, keep=True, concurrent=True)
+    assert [x["sweeps"] for x in st_a] == [x["sweeps"] for x in st_b]
+    assert sorted(a) == sorted(b)
+    for i in a:
+        assert torch.equal(a[i], b[i]), i
+    # and the concurrent trajectories are the backward-Euler ones
+    for g in groups:
+        for i, pb in g:
+            orc = seq.BiotOracle(pb)
+            err = seq.relative_field_errors(fem.node_to_field_major(b[i].cpu().numpy()),
+                                            orc.solve_sequential(), orc.n_nodes, orc.dim)
+            assert err["u"] < 1e-8 and err["p"] < 1e-8, (i, err)
