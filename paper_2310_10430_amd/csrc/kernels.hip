@@ -18,6 +18,7 @@
 // node-major [node][u_x, u_y, (u_z), p] in FP64; multigrid work vectors
 // node-major [node][comp], one contiguous vector per column of the batch, of
 // type T (double, or float in the mixed-precision preconditioner).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1123,11 +1124,30 @@ dim3 balanced_grid(const void* fn, int nn, int nc, int wpc) {
   return dim3(unsigned(std::max(1L, std::min(long(ncu) * per_cu, units))));
 }
 
-#define BIOT_LAUNCH_BALANCED(kern, nn, nc, wpc, st, ...)                                   \
-  hipLaunchKernelGGL(kern, balanced_grid(reinterpret_cast<const void*>(kern), nn, nc, wpc), \
-                     dim3(kBlock), 0, st, __VA_ARGS__)
+// Events armed by set_launch_events are recorded by the next balanced launch's
+// own dispatch (kernel start and end), then disarmed.
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+#define BIOT_LAUNCH_BALANCED(kern, nn, nc, wpc, st, ...)                                          \
+  do {                                                                                           \
+    const dim3 grid_ = balanced_grid(reinterpret_cast<const void*>(kern), nn, nc, wpc);          \
+    if (g_ev_start) {                                                                            \
+      hipExtLaunchKernelGGL(kern, grid_, dim3(kBlock), 0, st, g_ev_start, g_ev_stop, 0,          \
+                            __VA_ARGS__);                                                        \
+      g_ev_start = g_ev_stop = nullptr;                                                          \
+    } else {                                                                                     \
+      hipLaunchKernelGGL(kern, grid_, dim3(kBlock), 0, st, __VA_ARGS__);                         \
+    }                                                                                            \
+  } while (0)
 
 }  // namespace
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+
+bool launch_events_armed() { return g_ev_start != nullptr; }
 
 template <int DIM, bool ADJ, typename T>
 static void residual_dispatch(const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,

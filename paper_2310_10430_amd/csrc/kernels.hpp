@@ -48,6 +48,12 @@ struct ColDesc {
   int pad;
 };
 
+// Probing: the next node-blocked launch issued by this host thread records
+// `start` and `stop` with its own dispatch (the kernel's begin and end), then
+// the pair is disarmed; launch_events_armed() tells whether it is still pending.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_armed();
+
 // Launchers (all asynchronous on `st`).  `nc` = number of columns in the batch;
 // per-column work vectors are contiguous with stride nn*comps.  The node-blocked
 // kernels split their (node block, column) units evenly over a grid of one

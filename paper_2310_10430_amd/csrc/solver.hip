@@ -519,12 +519,14 @@ int harvest(biot_handle* h) {
   return BIOT_OK;
 }
 
-// brackets one launch with events when probing; `bytes` = algorithmic bytes
+// times the one node-blocked launch issued inside it when probing: the event
+// pair is recorded by that launch's own dispatch (kernel begin and end), so the
+// time excludes the event packets; `bytes` = the launch's algorithmic bytes
 struct ProbeScope {
   biot_handle* h;
   int id;
   double bytes;
-  hipEvent_t a = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
   int rc = BIOT_OK;
   bool live = true;
   ProbeScope(biot_handle* h_, int id_, double bytes_) : h(h_), id(id_), bytes(bytes_) {
@@ -541,12 +543,20 @@ struct ProbeScope {
     }
     if (rc) return;
     a = h->ev_pool[h->ev_next++];
-    if (hipEventRecord(a, h->st) != hipSuccess) rc = fail(h, BIOT_EHIP, "hipEventRecord");
+    b = h->ev_pool[h->ev_next++];
+    set_launch_events(a, b);
+  }
+  ~ProbeScope() {
+    // a scope left before its launch (an error path) must not hand its events
+    // to an unrelated launch
+    if (live && !rc && a && launch_events_armed()) set_launch_events(nullptr, nullptr);
   }
   int end() {
     if (!live || rc) return rc;
-    hipEvent_t b = h->ev_pool[h->ev_next++];
-    if (hipEventRecord(b, h->st) != hipSuccess) return fail(h, BIOT_EHIP, "hipEventRecord");
+    if (launch_events_armed()) {
+      set_launch_events(nullptr, nullptr);
+      return fail(h, BIOT_EHIP, "probe scope without a node-blocked launch");
+    }
     h->pending.push_back({a, b, id, bytes});
     return BIOT_OK;
   }
