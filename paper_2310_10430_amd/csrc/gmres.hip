@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_multi_dot(ColVecs V, int nvec, const
     if (lane == 0) lds[wave][i] = x;
   }
   __syncthreads();
-  if (threadIdx.x < nvec) {
+  if (int(threadIdx.x) < nvec) {
     const int i = threadIdx.x;
     part[(size_t(c) * kDotBlocks + blk) * (kGmresMaxK + 1) + i] =
         ((lds[0][i] + lds[1][i]) + lds[2][i]) + lds[3][i];

@@ -297,7 +297,6 @@ void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
 
 void plan(biot_handle* h, char* base) {
   Bump b{base};
-  const int dim = h->dim;
   h->L.assign(h->nlev, LevelDev{});
   for (int l = 0; l < h->nlev; ++l) {
     const HostLevel& H = h->P.levels[l];
