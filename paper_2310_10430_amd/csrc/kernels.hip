@@ -895,28 +895,67 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
   for (int i = threadIdx.x; i < npad; i += tail::block<DIM>()) x_t[g0 + n0 + i] = T(0);
 }
 
-// coarsest level: x = M^{-1} b with the dense inverse, one workgroup per column
-// (one workgroup per column and copy; n = grid dofs of a copy, stride = dofs of a
-// copy with padding, copies of a column contiguous; padding dofs left as zero)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, int stride, int copies,
+// coarsest level: x = M^{-1} b with the dense inverses (row-major, one per
+// copy).  A workgroup stages the right-hand sides of NCB columns of one copy in
+// LDS ([NCB][n]); each of its waves takes kCoarseRows rows, its lanes striding
+// over j (consecutive addresses of a row), and sums each product over the
+// lanes in a fixed tree.  Grid (row blocks of 4 kCoarseRows, column groups,
+// copies).  n = grid dofs of a copy, stride = dofs of a copy with padding,
+// copies of a column contiguous; the padding dofs are set to zero.
+constexpr int kCoarseRows = 4;
+template <int NCB, typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, int stride, int copies, int nc,
                                                          const T* __restrict__ Minv,
                                                          const T* __restrict__ b,
                                                          T* __restrict__ x) {
+  constexpr int R = kCoarseRows;
   extern __shared__ double sb_raw[];
   T* sb = reinterpret_cast<T*>(sb_raw);
-  const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
-  const size_t base = (size_t(c) * copies + cp) * stride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cp = blockIdx.z, c0 = blockIdx.y * NCB;
+  const int ncb = min(NCB, nc - c0);
   const T* M = Minv + size_t(cp) * n * n;
-  for (int i = threadIdx.x; i < n; i += kBlock) sb[i] = b[base + i];
-  __syncthreads();
-  for (int r = threadIdx.x; r < n; r += kBlock) {
-    T acc = T(0);
-    const T* row = M + size_t(r) * n;
-    for (int j = 0; j < n; ++j) acc += row[j] * sb[j];
-    x[base + r] = acc;
+#pragma unroll
+  for (int q = 0; q < NCB; ++q) {
+    // columns past the end stage zeros (computed, not stored)
+    const size_t base = (size_t(c0 + min(q, ncb - 1)) * copies + cp) * stride;
+    for (int i = threadIdx.x; i < n; i += kBlock) sb[q * n + i] = q < ncb ? b[base + i] : T(0);
   }
-  for (int r = n + threadIdx.x; r < stride; r += kBlock) x[base + r] = T(0);
+  __syncthreads();
+  const int r0 = (blockIdx.x * (kBlock / 64) + wave) * R;
+  const T* row[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) row[k] = M + size_t(min(r0 + k, n - 1)) * n;  // past the end: not stored
+  T acc[R][NCB];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+#pragma unroll
+    for (int q = 0; q < NCB; ++q) acc[k][q] = T(0);
+#pragma unroll 2
+  for (int j = lane; j < n; j += 64) {
+    T bv[NCB];
+#pragma unroll
+    for (int q = 0; q < NCB; ++q) bv[q] = sb[q * n + j];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const T m = row[k][j];
+#pragma unroll
+      for (int q = 0; q < NCB; ++q) acc[k][q] += m * bv[q];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+#pragma unroll
+    for (int q = 0; q < NCB; ++q) {
+      T v = acc[k][q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0 && r0 + k < n && q < ncb) x[(size_t(c0 + q) * copies + cp) * stride + r0 + k] = v;
+    }
+  if (blockIdx.x == 0)
+    for (int q = 0; q < ncb; ++q)
+      for (int i = n + threadIdx.x; i < stride; i += kBlock)
+        x[(size_t(c0 + q) * copies + cp) * stride + i] = T(0);
 }
 
 // pressure stage of P1: t = B' z_u - r_p (P2: t = -r_p), the right-hand side
@@ -1246,8 +1285,16 @@ void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<
 template <typename T>
 void launch_coarse_solve(int n, int stride, int copies, const T* Minv, const T* b, T* x, int nc,
                          hipStream_t st) {
-  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nc * copies), dim3(kBlock), size_t(n) * sizeof(T),
-                     st, n, stride, copies, Minv, b, x);
+  // columns per workgroup: as many as fit 64 KB of staged right-hand sides
+  const size_t col_bytes = size_t(n) * sizeof(T);
+  const int ncb = col_bytes * 8 <= 65536 ? 8 : col_bytes * 4 <= 65536 ? 4 : col_bytes * 2 <= 65536 ? 2 : 1;
+  const int rows = (kBlock / 64) * kCoarseRows;
+  const dim3 g((n + rows - 1) / rows, (nc + ncb - 1) / ncb, copies);
+  const size_t lds = col_bytes * ncb;
+  if (ncb == 8) hipLaunchKernelGGL((k_coarse_solve<8, T>), g, dim3(kBlock), lds, st, n, stride, copies, nc, Minv, b, x);
+  else if (ncb == 4) hipLaunchKernelGGL((k_coarse_solve<4, T>), g, dim3(kBlock), lds, st, n, stride, copies, nc, Minv, b, x);
+  else if (ncb == 2) hipLaunchKernelGGL((k_coarse_solve<2, T>), g, dim3(kBlock), lds, st, n, stride, copies, nc, Minv, b, x);
+  else hipLaunchKernelGGL((k_coarse_solve<1, T>), g, dim3(kBlock), lds, st, n, stride, copies, nc, Minv, b, x);
 }
 
 int tail_vectors(int degree) { return degree > 2 ? 4 : 3; }
