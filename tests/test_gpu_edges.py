@@ -10,7 +10,11 @@ backward Euler (<= 1e-8 per field), through the C ABI:
 * a zero load: the zero trajectory is the exact solution and is reached at
   once, with a finite residual;
 * a one-sample batch through the batch entry point equals the single handle;
-* smoother degree 3, where the stored increment d is used between steps.
+* smoother degree 3, where the stored increment d is used between steps;
+* a single-level 3D hierarchy whose dense coarsest solve is large enough that
+  fewer right-hand sides fit one workgroup's LDS (4 and 2 columns per group,
+  with ragged last groups), against the oracle's preconditioner, and the same
+  hierarchy in a two-sample batch against the oracle.
 """
 import numpy as np
 import pytest
@@ -118,3 +122,46 @@ def test_preconditioner_higher_smoother_degree_matches_oracle(degree):
         Zo = P.apply(R[c])
         for sl in (slice(0, orc.nU), slice(orc.nU, None)):
             assert np.abs(Z[c, sl] - Zo[sl]).max() < 1e-11 * np.abs(Zo[sl]).max()
+
+
+@pytest.mark.parametrize("n,coarse_cells", [(7, 2), (8, 8)])
+def test_preconditioner_large_dense_coarsest_level_matches_oracle(n, coarse_cells):
+    # one level: 512 nodes (1536 displacement dofs, 4 columns per workgroup) or
+    # 729 nodes (2187 dofs, 2 per workgroup); 11 columns leave ragged groups
+    from oracle import precond
+    pb = W.terzaghi_problem(n, 3, dim=3)
+    pb.perm = pb.perm * np.exp(0.5 * np.random.default_rng(n).standard_normal(pb.n_elems))
+    orc = seq.BiotOracle(pb)
+    P = precond.BlockPreconditioner(orc, "P1", "gmg", min_cells=coarse_cells)
+    rng = np.random.default_rng(9)
+    R = rng.standard_normal((11, orc.n_dof))
+    R[:, orc.fixed] = 0.0
+    R[:, orc.nU:] *= 1e-6
+    s = BiotSolver(pb, coarse_cells=coarse_cells, max_batch=11)
+    assert s.info()["n_levels"] == 1
+    Z = _fm(s.apply_precond(torch.from_numpy(fem.field_to_node_major(R, orc.n_nodes, orc.dim)))
+            .cpu().numpy())
+    s.close()
+    for c in range(R.shape[0]):
+        Zo = P.apply(R[c])
+        for sl in (slice(0, orc.nU), slice(orc.nU, None)):
+            assert np.abs(Z[c, sl] - Zo[sl]).max() < 1e-11 * np.abs(Zo[sl]).max()
+
+
+def test_batch_with_large_dense_coarsest_level_matches_oracle():
+    # two copies of the single-level 512-node hierarchy: one coarsest solve per copy
+    pbs = []
+    for i, N in enumerate((5, 8)):
+        pb = W.terzaghi_problem(7, N, dim=3)
+        pb.perm = pb.perm * np.exp(0.5 * np.random.default_rng(70 + i).standard_normal(pb.n_elems))
+        pbs.append(pb)
+    s = BiotSolver(pbs, schedule="wavefront", depth=4)
+    st = s.solve_to_tol(1e-11, max_sweeps=600, check_every=2)
+    assert st["converged"], st
+    for i, pb in enumerate(pbs):
+        orc = seq.BiotOracle(pb)
+        Xs = orc.solve_sequential()
+        Xg = _fm(s.sample_trajectory(i).cpu().numpy())
+        err = seq.relative_field_errors(Xg, Xs, orc.n_nodes, orc.dim)
+        assert err["u"] < 1e-8 and err["p"] < 1e-8, (i, err)
+    s.close()
