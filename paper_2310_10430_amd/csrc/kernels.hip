@@ -1128,8 +1128,13 @@ struct OccHash {
 };
 
 // default cap on resident workgroups per CU of a balanced launch (measured on
-// the 256^2 headline workload: 2, 3 and 4 give 487, 482 and 491 ms per solve)
+// the 256^2 workload: 2, 3 and 4 give 487, 482 and 491 ms per solve)
 constexpr int kDefaultMaxWgPerCu = 3;
+// grids of the 3D level-0 residual and smoother launches, whose rows are re-read
+// from the caches per group of columns anyway: four workgroups per CU, i.e.
+// smaller pieces (40^3 cube: 742 -> 707 ms per solve; the coarse levels and the
+// level residual gain nothing)
+constexpr int kWgPerCu3dFine = 4;
 
 dim3 balanced_grid(const void* fn, int nn, int nc, int wpc) {
   static std::mutex mu;
@@ -1192,6 +1197,7 @@ template <int DIM, bool ADJ, typename T>
 static void residual_dispatch(const LevelDev& L, const FineDev& F, const ColDesc* cols, int nc,
                               T* ru, T* rp, double* partials, int pstride, int wpc,
                               hipStream_t st) {
+  if (DIM == 3 && wpc <= 0) wpc = kWgPerCu3dFine;
   BIOT_LAUNCH_BALANCED((k_residual<DIM, T, ADJ>), L.nn, nc, wpc, st, L, F, cols, nc, ru, rp,
                        partials, pstride);
 }
@@ -1215,6 +1221,7 @@ static void cheb_dispatch(const LevelView<T>& L, bool is_A, const T* b, const T*
                           double it, const ColDesc* cols, const T* zu, double omega, int wpc,
                           bool fine, hipStream_t st) {
   if (fine) {
+    if (DIM == 3 && wpc <= 0) wpc = kWgPerCu3dFine;
     BIOT_LAUNCH_BALANCED((k_cheb<DIM, C, UPD, true, T>), L.nn, nc, wpc, st, L, int(is_A), b, xin,
                          xout, d, nc, T(c1), T(c2), int(wd), dx, int(first), T(it), cols, zu, omega);
   } else if constexpr (!UPD) {
