@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # two rocprofv3 counter passes (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the
 # factors of a plain 1 GiB copy) over 64-column launches, and the kernel
 # source they were taken with; see profiles/level0_kernels_large_terzaghi_hbm_counters.md
-CHEB_U_TRAFFIC = {"kernels_sha256_prefix": "cb7c2105f39f876e",
+CHEB_U_TRAFFIC = {"kernels_sha256_prefix": "177f58e1db09e9b4",
                   "bytes_per_launch": 268.0e6, "launch_columns": 64,
                   "algorithmic_bytes_per_launch": 221.7e6}
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"

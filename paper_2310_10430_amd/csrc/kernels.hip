@@ -1134,9 +1134,9 @@ struct OccHash {
 // default cap on resident workgroups per CU of a balanced launch (measured on
 // the 256^2 workload: 2, 3 and 4 give 487, 482 and 491 ms per solve)
 constexpr int kDefaultMaxWgPerCu = 3;
-// grids of the 3D level-0 residual and smoother launches, whose rows are re-read
-// from the caches per group of columns anyway: four workgroups per CU, i.e.
-// smaller pieces (40^3 cube: 742 -> 707 ms per solve; the coarse levels and the
+// grids of the 3D level-0 residual and smoother launches: four workgroups per
+// CU whatever the occupancy (two or three resident in FP64), i.e. smaller
+// pieces of work (40^3 cube: 742 -> 707 ms per solve; the coarse levels and the
 // level residual gain nothing)
 constexpr int kWgPerCu3dFine = 4;
 
