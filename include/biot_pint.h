@@ -275,8 +275,11 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
 #define BIOT_PROBE_LEVRES_U 3     /* displacement residual before restriction    */
 #define BIOT_PROBE_LEVRES_P 4     /* pressure residual before restriction        */
 #define BIOT_PROBE_PSTAGE 5       /* P1 pressure stage t = B' z_u - r_p          */
-#define BIOT_PROBE_COUNT 6
-#define BIOT_PROBE_ALL 0x3F
+#define BIOT_PROBE_POST_U 6       /* displacement post-smoothing, both steps in  */
+                                  /* one launch (2D, one sample, degree 2)       */
+#define BIOT_PROBE_POST_P 7       /* the same for the pressure field             */
+#define BIOT_PROBE_COUNT 8
+#define BIOT_PROBE_ALL 0xFF
 int biot_profile_enable(biot_handle* h, int32_t mask);
 int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
                       double* total_bytes, const char** name);

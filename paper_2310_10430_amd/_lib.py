@@ -13,7 +13,7 @@ SCHED = {"jacobi": 0, "wavefront": 1}
 PRECOND = {"P1": 1, "P2": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 INNER = {"richardson": 0, "gmres": 1}
-PROBES = ["residual", "cheb_u", "cheb_p", "levres_u", "levres_p", "pstage"]
+PROBES = ["residual", "cheb_u", "cheb_p", "levres_u", "levres_p", "pstage", "post_u", "post_p"]
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)

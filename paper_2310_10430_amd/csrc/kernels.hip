@@ -468,6 +468,156 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
   });
 }
 
+// The two post-smoothing steps of degree 2 on a structured 2D level of one
+// sample, fused:
+//   x3 = x2 + c2a D^{-1}(b - K x2)                  (first step, no increment)
+//   x4 = x3 + c1b (x3 - x2) + c2b D^{-1}(b - K x3)  (second step)
+// with the arithmetic of two k_cheb launches, so the result is the same bit
+// for bit.  A workgroup takes a kPatch x kPatch patch of grid nodes, one per
+// thread, whose operator rows stay in registers over the columns: every node
+// of the patch forms x3 into LDS, then the interior (the patch without its
+// outer ring) forms x4 from its neighbours' x3 there.  Patches step by the
+// interior width, so each node is the interior of exactly one patch.  x2 and
+// x4 are different buffers (other patches gather x2 around their rings).
+// Columns are software-pipelined through two LDS buffers: between two
+// barriers a workgroup gathers and forms x3 of the next column while it forms
+// x4 of the current one, so the gathers' latency overlaps the second step
+// (one column per stage; two per stage took more registers and ran slower).
+constexpr int kPatch = 16;
+constexpr int kPatchIn = kPatch - 2;
+static_assert(kPatch * kPatch == kBlock, "one patch node per thread");
+
+template <int C, typename T>
+__global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
+                                                  const T* __restrict__ b,
+                                                  const T* __restrict__ x2,
+                                                  T* __restrict__ x4, int nc, T c2a, T c1b,
+                                                  T c2b) {
+  constexpr int W = 7, NQ = 1;
+  // per buffer: x3, and the node's own x2 and b, of the patch's nodes
+  __shared__ T sh[2][3][NQ][kBlock][C];
+  const int m = L.n_cells + 1, nn = L.nn;
+  const int per_side = (m + kPatchIn - 1) / kPatchIn;
+  const int li = threadIdx.x % kPatch, lj = threadIdx.x / kPatch;
+  const T* K = isA ? L.A : L.S;
+  const T* Dg = isA ? L.Ainv : L.Sinv;
+  const size_t stride = size_t(nn) * C;
+  int buf = 0;
+  for_each_piece(per_side * per_side, nc, [&](int patch, int cbeg, int cend) {
+    const int i0 = (patch % per_side) * kPatchIn - 1, j0 = (patch / per_side) * kPatchIn - 1;
+    const int gi = i0 + li, gj = j0 + lj;
+    const bool node = gi >= 0 && gi < m && gj >= 0 && gj < m;
+    const bool inner = node && li >= 1 && li <= kPatchIn && lj >= 1 && lj <= kPatchIn;
+    const int v = node ? gj * m + gi : 0;
+    int nb[W];
+    T kr[W][C * C], Di[C * C];
+#pragma unroll
+    for (int s = 0; s < W; ++s) {
+      nb[s] = node ? L.nbr[size_t(s) * nn + v] : 0;
+#pragma unroll
+      for (int e = 0; e < C * C; ++e) kr[s][e] = node ? K[(size_t(s) * C * C + e) * nn + v] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < C * C; ++e) Di[e] = node ? Dg[size_t(e) * nn + v] : T(0);
+    int ls[W];
+#pragma unroll
+    for (int s = 0; s < W; ++s) ls[s] = (nb[s] % m - i0) + (nb[s] / m - j0) * kPatch;
+    auto phase1 = [&](int c, int bb) {
+      if (!node) return;
+      int cc[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) cc[q] = min(c + q, cend - 1);
+      T acc[NQ][C], x2o[NQ][C];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          const T bv = b[size_t(cc[q]) * stride + size_t(v) * C + a];
+          acc[q][a] = bv;
+          sh[bb][2][q][threadIdx.x][a] = bv;
+        }
+#pragma unroll
+      for (int s = 0; s < W; ++s)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          T xw[C];
+#pragma unroll
+          for (int k = 0; k < C; ++k) xw[k] = x2[size_t(cc[q]) * stride + size_t(nb[s]) * C + k];
+          if (s == 0)
+#pragma unroll
+            for (int k = 0; k < C; ++k) x2o[q][k] = xw[k];
+#pragma unroll
+          for (int a = 0; a < C; ++a) {
+            T s2 = T(0);
+#pragma unroll
+            for (int k = 0; k < C; ++k) s2 += kr[s][a * C + k] * xw[k];
+            acc[q][a] -= T(1) * s2;
+          }
+        }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          T z = T(0);
+#pragma unroll
+          for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
+          const T dn = T(0) * T(0) + c2a * z;
+          sh[bb][0][q][threadIdx.x][a] = x2o[q][a] + dn;
+          sh[bb][1][q][threadIdx.x][a] = x2o[q][a];
+        }
+    };
+    auto phase2 = [&](int c, int bb) {
+      if (!inner) return;
+      T acc[NQ][C];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int a = 0; a < C; ++a) acc[q][a] = sh[bb][2][q][threadIdx.x][a];
+#pragma unroll
+      for (int s = 0; s < W; ++s)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          T xw[C];
+#pragma unroll
+          for (int k = 0; k < C; ++k) xw[k] = sh[bb][0][q][ls[s]][k];
+#pragma unroll
+          for (int a = 0; a < C; ++a) {
+            T s2 = T(0);
+#pragma unroll
+            for (int k = 0; k < C; ++k) s2 += kr[s][a * C + k] * xw[k];
+            acc[q][a] -= T(1) * s2;
+          }
+        }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (c + q >= cend) break;
+        const int col = c + q;
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          T z = T(0);
+#pragma unroll
+          for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
+          const T x3 = sh[bb][0][q][threadIdx.x][a];
+          const T dp = x3 - sh[bb][1][q][threadIdx.x][a];
+          const T dn = c1b * dp + c2b * z;
+          x4[size_t(col) * stride + size_t(v) * C + a] = x3 + dn;
+        }
+      }
+    };
+    __syncthreads();  // the previous piece's last reads of both buffers are done
+    // stage c: x3 of column c into buffer buf (prologue), then per column the
+    // next column's x3 into the other buffer and this column's x4
+    phase1(cbeg, buf);
+#pragma unroll 1
+    for (int c = cbeg; c < cend; c += NQ) {
+      __syncthreads();
+      if (c + NQ < cend) phase1(c + NQ, buf ^ 1);
+      phase2(c, buf);
+      buf ^= 1;
+    }
+  });
+}
+
 // xout = xin + P xc (P1 interpolation, masked) for a group of columns; the
 // parents of the node are found once and reused for every column
 template <int DIM, int C, typename T>
@@ -1257,6 +1407,19 @@ void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* 
 }
 
 template <typename T>
+void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const T* x2, T* x4,
+                  int nc, double c2a, double c1b, double c2b, int wpc, hipStream_t st) {
+  const int per_side = (L.n_cells + 1 + kPatchIn - 1) / kPatchIn;
+  const int units_nn = per_side * per_side * kBlock;  // one patch per node block of the grid
+  if (comps == 1)
+    BIOT_LAUNCH_BALANCED((k_post2<1, T>), units_nn, nc, wpc, st, L, int(is_A), b, x2, x4, nc,
+                         T(c2a), T(c1b), T(c2b));
+  else
+    BIOT_LAUNCH_BALANCED((k_post2<2, T>), units_nn, nc, wpc, st, L, int(is_A), b, x2, x4, nc,
+                         T(c2a), T(c1b), T(c2b));
+}
+
+template <typename T>
 void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
                            const T* x, T* r, int nc, int wpc, hipStream_t st) {
   if (dim == 2) {
@@ -1386,6 +1549,8 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
   template void launch_cheb<T>(int, int, const LevelView<T>&, bool, const T*, const T*, T*, T*,  \
                                int, double, double, bool, int, bool, double, const ColDesc*,     \
                                const T*, double, int, bool, hipStream_t);                         \
+  template void launch_post2<T>(int, const LevelView<T>&, bool, const T*, const T*, T*, int,    \
+                                double, double, double, int, hipStream_t);                        \
   template void launch_level_residual<T>(int, int, const LevelView<T>&, bool, const T*,          \
                                          const T*, T*, int, int, hipStream_t);                    \
   template void launch_restrict<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,     \

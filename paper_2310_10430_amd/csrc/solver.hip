@@ -498,7 +498,9 @@ const char* kProbeNames[BIOT_PROBE_COUNT] = {
     "k_cheb pressure smoothing (level 0)",
     "k_level_residual displacement (level 0)",
     "k_level_residual pressure (level 0)",
-    "k_pstage (P1 pressure stage; level 0)"};
+    "k_pstage (P1 pressure stage; level 0)",
+    "k_post2 displacement post-smoothing, two steps (level 0)",
+    "k_post2 pressure post-smoothing, two steps (level 0)"};
 
 int harvest(biot_handle* h) {
   if (h->pending.empty()) {
@@ -585,6 +587,10 @@ double bytes_levres(const biot_handle* h, int C, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W;
   return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W);
 }
+double bytes_post2(const biot_handle* h, int C, int nc, int t) {
+  const double nn = h->nn, W = h->P.levels[0].W;
+  return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W + C * C * t);  // b, x2 -> x4
+}
 double bytes_pstage(const biot_handle* h, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
   return nc * nn * t * (d + 2) + nn * (W * d * t + 4 * W);
@@ -668,6 +674,20 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   LAUNCHCHK(h);
   std::swap(cur, oth);
   rho = 1.0 / cc.sigma;
+  if (deg == 2 && !upd && h->dim == 2 && p.L[l].copies == 1) {
+    // both post-smoothing steps in one launch, into the free buffer (the
+    // pressure field's level 0, which writes the outer update, keeps two:
+    // fused it measured slower)
+    const double rn = 1.0 / (2.0 * cc.sigma - rho);
+    ProbeScope ps(h, fine ? (is_A ? BIOT_PROBE_POST_U : BIOT_PROBE_POST_P) : -1,
+                  fine ? bytes_post2(h, C, nc, tb) : 0);
+    launch_post2<T>(C, p.L[l], is_A, f.b[l], cur, oth, nc, 1.0 / cc.theta, rn * rho,
+                    2.0 * rn / cc.delta, wpc, st);
+    LAUNCHCHK(h);
+    if (fine && ps.end()) return BIOT_EHIP;
+    *out = oth;
+    return BIOT_OK;
+  }
   for (int j = 1; j <= deg; ++j) {
     double c1 = 0.0, c2 = 1.0 / cc.theta, rn = rho;
     if (j > 1) {
