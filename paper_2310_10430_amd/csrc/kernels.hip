@@ -440,7 +440,8 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
                        : dx == 1 ? xs[q][a]
                        : dx == 2 ? xs[q][a] - xout[base + a]
                                  : d[base + a];
-          const T dn = c1 * dp + c2 * z;
+          // one rounding order for the update, shared with k_post2
+          const T dn = fma(c2, z, c1 * dp);
           if (!UPD && wd) d[base + a] = dn;
           xn[a] = xs[q][a] + dn;
         }
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
           T z = T(0);
 #pragma unroll
           for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
-          const T dn = T(0) * T(0) + c2a * z;
+          const T dn = fma(c2a, z, T(0) * T(0));
           sh[bb][0][q][threadIdx.x][a] = x2o[q][a] + dn;
           sh[bb][1][q][threadIdx.x][a] = x2o[q][a];
         }
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
           for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
           const T x3 = sh[bb][0][q][threadIdx.x][a];
           const T dp = x3 - sh[bb][1][q][threadIdx.x][a];
-          const T dn = c1b * dp + c2b * z;
+          const T dn = fma(c2b, z, c1b * dp);
           x4[size_t(col) * stride + size_t(v) * C + a] = x3 + dn;
         }
       }

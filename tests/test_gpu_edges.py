@@ -11,6 +11,9 @@ backward Euler (<= 1e-8 per field), through the C ABI:
   once, with a finite residual;
 * a one-sample batch through the batch entry point equals the single handle;
 * smoother degree 3, where the stored increment d is used between steps;
+* the fused two-step post-smoothing of single 2D samples against the two
+  separate steps that batch handles run: a batch of two copies of a sample
+  equals the single handle bit for bit;
 * a single-level 3D hierarchy whose dense coarsest solve is large enough that
   fewer right-hand sides fit one workgroup's LDS (4 and 2 columns per group,
   with ragged last groups), against the oracle's preconditioner, and the same
@@ -165,3 +168,20 @@ def test_batch_with_large_dense_coarsest_level_matches_oracle():
         err = seq.relative_field_errors(Xg, Xs, orc.n_nodes, orc.dim)
         assert err["u"] < 1e-8 and err["p"] < 1e-8, (i, err)
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_post_smoothing_equals_separate_steps(precision):
+    # a single 2D sample runs both post-smoothing steps of each V-cycle level in
+    # one launch; a batch (two copies of the same sample, so the same spectral
+    # bounds) runs them as two launches with the same arithmetic
+    pb = W.heterogeneous_problem(40, 9, field_seed=17, young_seed=18)
+    a = BiotSolver(pb, schedule="wavefront", depth=4, precision=precision)
+    b = BiotSolver([pb, pb], schedule="wavefront", depth=4, precision=precision)
+    a.sweep(7)
+    b.sweep(7)
+    Xa = a.trajectory().cpu().numpy()
+    for i in range(2):
+        assert np.array_equal(Xa, b.sample_trajectory(i).cpu().numpy()), i
+    a.close()
+    b.close()
