@@ -34,13 +34,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# HBM traffic of the dominant kernel (level-0 displacement Chebyshev step) from
-# two rocprofv3 counter passes (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the
-# factors of a plain 1 GiB copy) over 64-column launches, and the kernel
+# HBM traffic per probed kernel from two rocprofv3 counter passes (FETCH_SIZE
+# x 2.00 + WRITE_SIZE x 1.00, the factors of a plain 1 GiB copy) over
+# 64-column launches, averaged over the kernel's dispatches, and the kernel
 # source they were taken with; see profiles/level0_kernels_large_terzaghi_hbm_counters.md
-CHEB_U_TRAFFIC = {"kernels_sha256_prefix": "177f58e1db09e9b4",
-                  "bytes_per_launch": 268.0e6, "launch_columns": 64,
-                  "algorithmic_bytes_per_launch": 221.7e6}
+TRAFFIC = {
+    # k_post2<2, double>: 24 dispatches (levels 0-2 of 8 batches), average
+    "post_u": {"kernels_sha256_prefix": "99da3fc1f8f3047c", "bytes_per_launch": 167.9e6,
+               "launch_columns": 64, "algorithmic_bytes_per_launch": 97.2e6},
+}
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"
 
 
@@ -49,24 +51,23 @@ def log(msg):
 
 
 def traffic_fields(probe, algo_bytes_avg):
-    """`traffic`: counter-measured HBM bytes per 64-column launch of the dominant
-    kernel (None when the kernel source changed since the counters were taken
-    or another kernel is probed), with the launch shape it was measured on and
-    the same measured/algorithmic ratio applied to the bench's average launch."""
+    """`traffic`: counter-measured HBM bytes per 64-column launch of the probed
+    kernel (None when no counters were taken for it or the kernel source changed
+    since), with the launch shape it was measured on and the same
+    measured/algorithmic ratio applied to the bench's average launch."""
     import hashlib
     out = {"traffic": None}
-    if probe != "cheb_u":
+    t = TRAFFIC.get(probe)
+    if t is None:
         return out
     src = os.path.join(ROOT, "paper_2310_10430_amd", "csrc", "kernels.hip")
     with open(src, "rb") as f:
         h = hashlib.sha256(f.read()).hexdigest()
-    if not h.startswith(CHEB_U_TRAFFIC["kernels_sha256_prefix"]):
+    if not h.startswith(t["kernels_sha256_prefix"]):
         return out
-    ratio = CHEB_U_TRAFFIC["bytes_per_launch"] / CHEB_U_TRAFFIC["algorithmic_bytes_per_launch"]
-    out.update(traffic=CHEB_U_TRAFFIC["bytes_per_launch"],
-               traffic_launch_columns=CHEB_U_TRAFFIC["launch_columns"],
-               traffic_over_algorithmic=ratio,
-               traffic_per_average_launch=ratio * algo_bytes_avg)
+    ratio = t["bytes_per_launch"] / t["algorithmic_bytes_per_launch"]
+    out.update(traffic=t["bytes_per_launch"], traffic_launch_columns=t["launch_columns"],
+               traffic_over_algorithmic=ratio, traffic_per_average_launch=ratio * algo_bytes_avg)
     return out
 
 
@@ -417,8 +418,10 @@ def main():
                     help="hardware-counter run: one Jacobi-schedule sweep of the workload in "
                          "batches of --depth columns (the bench's full-wave launch shape, few "
                          "dispatches), no timing")
-    ap.add_argument("--probe", default="cheb_u",
-                    help="kernel timed with HIP events in the timed region")
+    ap.add_argument("--probe", default="post_u",
+                    help="kernel timed with HIP events in the timed region (default: the "
+                         "kernel with the most time in a kernel trace of the solve, the fused "
+                         "displacement post-smoothing)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision and heterogeneous-permeability variants")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -474,8 +477,8 @@ def main():
     for i in range(args.warmup):
         st = solve()
         log(f"bench: warmup {i}: {st['sweeps']} sweeps, {st['seconds'] * 1e3:.1f} ms")
-    # timed region: HIP events bracket every level-0 launch of the dominant
-    # kernel (the displacement smoother) on the solver's stream
+    # timed region: HIP events bracket every launch of the dominant kernel
+    # (the fused displacement post-smoothing) on the solver's stream
     s.profile(True, probes=[args.probe])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -504,7 +507,8 @@ def main():
     kernels = {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
                    "GBps": (v["bytes"] / max(v["ms"], 1e-30)) / 1e6,
                    "share_of_solve": v["ms"] / solve_ms} for k, v in prof.items()}
-    kernels["dominant"] = dominant
+    kernels["largest_probe"] = dominant   # a probe may cover several kernels
+    kernels["roofline_kernel"] = args.probe
 
     X = s.trajectory().cpu().numpy()
     s.close()

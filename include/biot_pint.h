@@ -264,7 +264,8 @@ int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols
 int biot_get_info(const biot_handle* h, biot_info_t* info);
 
 /* Probes: HIP events recorded on the handle's stream around every level-0
- * launch of the selected kernels below, with the algorithmic bytes each launch
+ * launch (every launch for POST_U and POST_P) of the selected kernels below,
+ * with the algorithmic bytes each launch
  * moves (distinct global inputs and outputs counted once).  `mask` has bit p
  * set for probe p (0 disables); enabling or disabling clears the accumulators;
  * reading synchronizes the stream.  While probes are on, wavefront passes run
@@ -276,8 +277,11 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
 #define BIOT_PROBE_LEVRES_P 4     /* pressure residual before restriction        */
 #define BIOT_PROBE_PSTAGE 5       /* P1 pressure stage t = B' z_u - r_p          */
 #define BIOT_PROBE_POST_U 6       /* displacement post-smoothing, both steps in  */
-                                  /* one launch (2D, one sample, degree 2)       */
-#define BIOT_PROBE_POST_P 7       /* the same for the pressure field             */
+                                  /* one launch (2D, one sample, degree 2), on  */
+                                  /* every level outside the fused tail         */
+#define BIOT_PROBE_POST_P 7       /* the same for the pressure field (not on     */
+                                  /* level 0 in sweeps, whose last step writes  */
+                                  /* the outer update)                          */
 #define BIOT_PROBE_COUNT 8
 #define BIOT_PROBE_ALL 0xFF
 int biot_profile_enable(biot_handle* h, int32_t mask);

@@ -484,6 +484,11 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
 // barriers a workgroup gathers and forms x3 of the next column while it forms
 // x4 of the current one, so the gathers' latency overlaps the second step
 // (one column per stage; two per stage took more registers and ran slower).
+// Work split: the columns of each patch are cut into `groups` runs of `run`
+// columns, one workgroup each, all resident at once, so that neighbouring
+// patches walk through the same columns together and share the ring rows they
+// gather in L2; workgroup i goes to XCD i % 8, and each XCD is given a
+// contiguous range of (patch, run) pairs, i.e. neighbouring patches.
 constexpr int kPatch = 16;
 constexpr int kPatchIn = kPatch - 2;
 static_assert(kPatch * kPatch == kBlock, "one patch node per thread");
@@ -493,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
                                                   const T* __restrict__ b,
                                                   const T* __restrict__ x2,
                                                   T* __restrict__ x4, int nc, T c2a, T c1b,
-                                                  T c2b) {
+                                                  T c2b, int groups, int run) {
   constexpr int W = 7, NQ = 1;
   // per buffer: x3, and the node's own x2 and b, of the patch's nodes
   __shared__ T sh[2][3][NQ][kBlock][C];
@@ -504,7 +509,13 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
   const T* Dg = isA ? L.Ainv : L.Sinv;
   const size_t stride = size_t(nn) * C;
   int buf = 0;
-  for_each_piece(per_side * per_side, nc, [&](int patch, int cbeg, int cend) {
+  {
+    const int P = gridDim.x, i = blockIdx.x;  // P is a multiple of 8
+    const int slot = (i & 7) * (P >> 3) + (i >> 3);
+    if (slot >= per_side * per_side * groups) return;
+    const int patch = slot / groups;
+    const int cbeg = (slot % groups) * run, cend = min(nc, cbeg + run);
+    if (cbeg >= cend) return;
     const int i0 = (patch % per_side) * kPatchIn - 1, j0 = (patch / per_side) * kPatchIn - 1;
     const int gi = i0 + li, gj = j0 + lj;
     const bool node = gi >= 0 && gi < m && gj >= 0 && gj < m;
@@ -605,7 +616,6 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
         }
       }
     };
-    __syncthreads();  // the previous piece's last reads of both buffers are done
     // stage c: x3 of column c into buffer buf (prologue), then per column the
     // next column's x3 into the other buffer and this column's x4
     phase1(cbeg, buf);
@@ -616,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
       phase2(c, buf);
       buf ^= 1;
     }
-  });
+  }
 }
 
 // xout = xin + P xc (P1 interpolation, masked) for a group of columns; the
@@ -1339,6 +1349,35 @@ thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
     }                                                                                            \
   } while (0)
 
+// the same for a launch with a grid of its own
+#define BIOT_LAUNCH_GRID(kern, grid, st, ...)                                                     \
+  do {                                                                                           \
+    if (g_ev_start) {                                                                            \
+      hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, g_ev_start, g_ev_stop, 0,           \
+                            __VA_ARGS__);                                                        \
+      g_ev_start = g_ev_stop = nullptr;                                                          \
+    } else {                                                                                     \
+      hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, st, __VA_ARGS__);                          \
+    }                                                                                            \
+  } while (0)
+
+// compute units of the current device
+int num_cus() {
+  static std::mutex mu;
+  static std::unordered_map<int, int> cus;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cus.find(dev);
+  if (it == cus.end()) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+    it = cus.emplace(dev, n).first;
+  }
+  return it->second;
+}
+
 }  // namespace
 
 void set_launch_events(hipEvent_t start, hipEvent_t stop) {
@@ -1411,13 +1450,19 @@ template <typename T>
 void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const T* x2, T* x4,
                   int nc, double c2a, double c1b, double c2b, int wpc, hipStream_t st) {
   const int per_side = (L.n_cells + 1 + kPatchIn - 1) / kPatchIn;
-  const int units_nn = per_side * per_side * kBlock;  // one patch per node block of the grid
+  const int patches = per_side * per_side;
+  // runs per patch: as many as keep about one wave of resident workgroups
+  // (3 per CU) busy, at most one per column
+  const int resident = 3 * num_cus(), groups = std::max(1, std::min(nc, resident / patches));
+  const int run = (nc + groups - 1) / groups;
+  const dim3 grid(unsigned((patches * groups + 7) / 8 * 8));
+  (void)wpc;
   if (comps == 1)
-    BIOT_LAUNCH_BALANCED((k_post2<1, T>), units_nn, nc, wpc, st, L, int(is_A), b, x2, x4, nc,
-                         T(c2a), T(c1b), T(c2b));
+    BIOT_LAUNCH_GRID((k_post2<1, T>), grid, st, L, int(is_A), b, x2, x4, nc, T(c2a), T(c1b),
+                     T(c2b), groups, run);
   else
-    BIOT_LAUNCH_BALANCED((k_post2<2, T>), units_nn, nc, wpc, st, L, int(is_A), b, x2, x4, nc,
-                         T(c2a), T(c1b), T(c2b));
+    BIOT_LAUNCH_GRID((k_post2<2, T>), grid, st, L, int(is_A), b, x2, x4, nc, T(c2a), T(c1b),
+                     T(c2b), groups, run);
 }
 
 template <typename T>

@@ -499,8 +499,8 @@ const char* kProbeNames[BIOT_PROBE_COUNT] = {
     "k_level_residual displacement (level 0)",
     "k_level_residual pressure (level 0)",
     "k_pstage (P1 pressure stage; level 0)",
-    "k_post2 displacement post-smoothing, two steps (level 0)",
-    "k_post2 pressure post-smoothing, two steps (level 0)"};
+    "k_post2 displacement post-smoothing, two steps (levels 0-2)",
+    "k_post2 pressure post-smoothing, two steps (levels 1-2)"};
 
 int harvest(biot_handle* h) {
   if (h->pending.empty()) {
@@ -587,8 +587,8 @@ double bytes_levres(const biot_handle* h, int C, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W;
   return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W);
 }
-double bytes_post2(const biot_handle* h, int C, int nc, int t) {
-  const double nn = h->nn, W = h->P.levels[0].W;
+double bytes_post2(const biot_handle* h, int l, int C, int nc, int t) {
+  const double nn = h->P.levels[l].nn, W = h->P.levels[l].W;
   return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W + C * C * t);  // b, x2 -> x4
 }
 double bytes_pstage(const biot_handle* h, int nc, int t) {
@@ -679,12 +679,12 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     // pressure field's level 0, which writes the outer update, keeps two:
     // fused it measured slower)
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
-    ProbeScope ps(h, fine ? (is_A ? BIOT_PROBE_POST_U : BIOT_PROBE_POST_P) : -1,
-                  fine ? bytes_post2(h, C, nc, tb) : 0);
+    // probed on every level, as a kernel trace averages this kernel
+    ProbeScope ps(h, is_A ? BIOT_PROBE_POST_U : BIOT_PROBE_POST_P, bytes_post2(h, l, C, nc, tb));
     launch_post2<T>(C, p.L[l], is_A, f.b[l], cur, oth, nc, 1.0 / cc.theta, rn * rho,
                     2.0 * rn / cc.delta, wpc, st);
     LAUNCHCHK(h);
-    if (fine && ps.end()) return BIOT_EHIP;
+    if (ps.end()) return BIOT_EHIP;
     *out = oth;
     return BIOT_OK;
   }
