@@ -39,8 +39,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # 64-column launches, averaged over the kernel's dispatches, and the kernel
 # source they were taken with; see profiles/level0_kernels_large_terzaghi_hbm_counters.md
 TRAFFIC = {
+    # k_residual<2, double, false>: 8 dispatches; a Jacobi batch reads 65
+    # distinct state columns for its 64 (the coupling overlaps the iterates)
+    "residual": {"kernels_sha256_prefix": "086de73f7f50123a", "bytes_per_launch": 307.4e6,
+                 "launch_columns": 64, "algorithmic_bytes_per_launch": 244.9e6},
     # k_post2<2, double>: 24 dispatches (levels 0-2 of 8 batches), average
-    "post_u": {"kernels_sha256_prefix": "99da3fc1f8f3047c", "bytes_per_launch": 167.9e6,
+    "post_u": {"kernels_sha256_prefix": "086de73f7f50123a", "bytes_per_launch": 114.7e6,
                "launch_columns": 64, "algorithmic_bytes_per_launch": 97.2e6},
 }
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"
@@ -418,10 +422,10 @@ def main():
                     help="hardware-counter run: one Jacobi-schedule sweep of the workload in "
                          "batches of --depth columns (the bench's full-wave launch shape, few "
                          "dispatches), no timing")
-    ap.add_argument("--probe", default="post_u",
-                    help="kernel timed with HIP events in the timed region (default: the "
-                         "kernel with the most time in a kernel trace of the solve, the fused "
-                         "displacement post-smoothing)")
+    ap.add_argument("--probe", default="auto",
+                    help="kernel timed with HIP events in the timed region; auto: of the probes "
+                         "that each time one kernel, the one with the most time in a probed "
+                         "solve before the timed region")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision and heterogeneous-permeability variants")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -477,8 +481,16 @@ def main():
     for i in range(args.warmup):
         st = solve()
         log(f"bench: warmup {i}: {st['sweeps']} sweeps, {st['seconds'] * 1e3:.1f} ms")
-    # timed region: HIP events bracket every launch of the dominant kernel
-    # (the fused displacement post-smoothing) on the solver's stream
+    # breakdown of the probed kernels from one probed (untimed) solve, which
+    # also names the dominant kernel: the single-kernel probe with the most time
+    s.profile(True)
+    st_b = solve()
+    prof = s.profile_read()
+    if args.probe == "auto":
+        single = [k for k in prof if k != "cheb_p"]   # cheb_p times two kernels
+        args.probe = max(single, key=lambda k: prof[k]["ms"])
+    # timed region: HIP events bracket every probed launch of that kernel on the
+    # solver's stream
     s.profile(True, probes=[args.probe])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -488,10 +500,6 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof_main = s.profile_read()
-    # breakdown of the other level-0 kernels from one more (untimed) probed solve
-    s.profile(True)
-    st_b = solve()
-    prof = s.profile_read()
     s.profile(False)
     ms_per_step = 1e3 * elapsed / args.steps
     value = pb.n_dof * pb.n_steps / (elapsed / args.steps)
