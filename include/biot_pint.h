@@ -141,6 +141,9 @@ typedef struct {
   int32_t max_sensors;     /* capacity of the objective's sensor list (256)        */
   int32_t inner;           /* BIOT_INNER_* : what one unit does (RICHARDSON)       */
   int32_t gmres_k;         /* GMRES iterations per unit, 1..8 (4); omega unused    */
+  int32_t fuse_post;       /* 1: in 2D with smoother degree 2, run both post-      */
+                           /* smoothing steps of a level in one launch (same      */
+                           /* result bit for bit); 0: two launches (1)            */
 } biot_options;
 
 /* Pressure-misfit objective J = sum_{n=1..N} sum_s (p^n(node_s) - p_obs[n-1][s])^2. */

@@ -43,7 +43,8 @@ class Options(C.Structure):
                 ("coarse_cells", C.c_int32), ("use_graph", C.c_int32),
                 ("precision", C.c_int32), ("adjoint", C.c_int32), ("ckpt_stride", C.c_int32),
                 ("replay_segments", C.c_int32), ("max_sensors", C.c_int32),
-                ("inner", C.c_int32), ("gmres_k", C.c_int32)]
+                ("inner", C.c_int32), ("gmres_k", C.c_int32),
+                ("fuse_post", C.c_int32)]
 
 
 class Objective(C.Structure):

@@ -485,8 +485,9 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
   });
 }
 
-// The two post-smoothing steps of degree 2 on a structured 2D level of one
-// sample, fused:
+// The two post-smoothing steps of degree 2 on a structured 2D level, fused
+// (each sample copy of a batch has its own patches; the padding nodes of a
+// copy are not written, and hold the zeros the preceding steps wrote there):
 //   x3 = x2 + c2a D^{-1}(b - K x2)                  (first step, no increment)
 //   x4 = x3 + c1b (x3 - x2) + c2b D^{-1}(b - K x3)  (second step)
 // with the arithmetic of two k_cheb launches, so the result is the same bit
@@ -528,15 +529,16 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
   {
     const int P = gridDim.x, i = blockIdx.x;  // P is a multiple of 8
     const int slot = (i & 7) * (P >> 3) + (i >> 3);
-    if (slot >= per_side * per_side * groups) return;
-    const int patch = slot / groups;
+    const int pp = per_side * per_side;  // patches per copy (sample of a batch)
+    if (slot >= L.copies * pp * groups) return;
+    const int patch = (slot / groups) % pp, base = (slot / groups / pp) * L.nn1;
     const int cbeg = (slot % groups) * run, cend = min(nc, cbeg + run);
     if (cbeg >= cend) return;
     const int i0 = (patch % per_side) * kPatchIn - 1, j0 = (patch / per_side) * kPatchIn - 1;
     const int gi = i0 + li, gj = j0 + lj;
     const bool node = gi >= 0 && gi < m && gj >= 0 && gj < m;
     const bool inner = node && li >= 1 && li <= kPatchIn && lj >= 1 && lj <= kPatchIn;
-    const int v = node ? gj * m + gi : 0;
+    const int v = base + (node ? gj * m + gi : 0);
     int nb[W];
     T kr[W][C * C], Di[C * C];
 #pragma unroll
@@ -549,7 +551,8 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
     for (int e = 0; e < C * C; ++e) Di[e] = node ? Dg[size_t(e) * nn + v] : T(0);
     int ls[W];
 #pragma unroll
-    for (int s = 0; s < W; ++s) ls[s] = (nb[s] % m - i0) + (nb[s] / m - j0) * kPatch;
+    for (int s = 0; s < W; ++s)
+      ls[s] = ((nb[s] - base) % m - i0) + ((nb[s] - base) / m - j0) * kPatch;
     auto phase1 = [&](int c, int bb) {
       if (!node) return;
       int cc[NQ];
@@ -1476,7 +1479,7 @@ template <typename T>
 void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const T* x2, T* x4,
                   int nc, double c2a, double c1b, double c2b, int wpc, hipStream_t st) {
   const int per_side = (L.n_cells + 1 + kPatchIn - 1) / kPatchIn;
-  const int patches = per_side * per_side;
+  const int patches = L.copies * per_side * per_side;
   // runs per patch: as many as keep about one wave of resident workgroups
   // (3 per CU) busy, at most one per column
   const int resident = 3 * num_cus(), groups = std::max(1, std::min(nc, resident / patches));

@@ -90,7 +90,7 @@ void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView
 template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
                     const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st);
-// the two post-smoothing steps of degree 2 fused (2D, one sample): x2 -> x4,
+// the two post-smoothing steps of degree 2 fused (2D, any number of samples): x2 -> x4,
 // with the first step's c2 and the second step's c1, c2 (k_post2)
 template <typename T>
 void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const T* x2, T* x4,

@@ -674,7 +674,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   LAUNCHCHK(h);
   std::swap(cur, oth);
   rho = 1.0 / cc.sigma;
-  if (deg == 2 && !upd && h->dim == 2 && p.L[l].copies == 1) {
+  if (h->opt.fuse_post && deg == 2 && !upd && h->dim == 2) {
     // both post-smoothing steps in one launch, into the free buffer (the
     // pressure field's level 0, which writes the outer update, keeps two:
     // fused it measured slower)
@@ -1163,6 +1163,7 @@ int biot_default_options(biot_options* o) {
   o->max_sensors = 256;
   o->inner = BIOT_INNER_RICHARDSON;
   o->gmres_k = 4;
+  o->fuse_post = 1;
   return BIOT_OK;
 }
 
@@ -1204,6 +1205,7 @@ int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_mater
     return fail(nullptr, BIOT_EINVAL, "unknown inner solver");
   if (o.inner == BIOT_INNER_GMRES && (o.gmres_k < 1 || o.gmres_k > kGmresMaxK))
     return fail(nullptr, BIOT_EINVAL, "gmres_k must be in 1..8");
+  if (o.fuse_post != 0 && o.fuse_post != 1) return fail(nullptr, BIOT_EINVAL, "fuse_post must be 0 or 1");
   biot_handle* h = new (std::nothrow) biot_handle();
   if (!h) return fail(nullptr, BIOT_ENOMEM, "out of host memory");
   h->opt = o;

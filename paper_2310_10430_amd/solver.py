@@ -54,7 +54,7 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
                   cheb_ratio=4.0, lmax_safety=1.1, power_iters=20, max_batch=0, beta=None,
                   wg_per_cu=0, coarse_cells=2, use_graph=True, precision="fp64", lame=None,
                   adjoint=False, ckpt_stride=16, replay_segments=4, max_sensors=256,
-                  inner="richardson", gmres_k=4):
+                  inner="richardson", gmres_k=4, fuse_post=True):
     """biot_create (one problem) or biot_create_batch (a list of problems on the
     same mesh) on the host, no device work; returns (handle, options).
 
@@ -82,6 +82,7 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     opt.max_sensors = max_sensors
     opt.inner = _lib.INNER[inner]
     opt.gmres_k = gmres_k
+    opt.fuse_post = int(fuse_post)
     keep = []
     h = C.c_void_p()
     if isinstance(problem, (list, tuple)):
@@ -144,7 +145,8 @@ class BiotSolver:
                  device: str = "cuda:0", beta=None, wg_per_cu: int = 0, coarse_cells: int = 2,
                  use_graph: bool = True, precision: str = "fp64", lame=None,
                  adjoint: bool = False, ckpt_stride: int = 16, replay_segments: int = 4,
-                 max_sensors: int = 256, inner: str = "richardson", gmres_k: int = 4):
+                 max_sensors: int = 256, inner: str = "richardson", gmres_k: int = 4,
+                 fuse_post: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("BiotSolver needs a ROCm GPU (torch.cuda is not available)")
         self.lib = _lib.load()
@@ -156,7 +158,8 @@ class BiotSolver:
                                coarse_cells=coarse_cells, use_graph=use_graph,
                                precision=precision, lame=lame, adjoint=adjoint,
                                ckpt_stride=ckpt_stride, replay_segments=replay_segments,
-                               max_sensors=max_sensors, inner=inner, gmres_k=gmres_k)
+                               max_sensors=max_sensors, inner=inner, gmres_k=gmres_k,
+                               fuse_post=fuse_post)
         self.problem = problem
         self.batch = isinstance(problem, (list, tuple))
         first = problem[0] if self.batch else problem

@@ -11,9 +11,8 @@ backward Euler (<= 1e-8 per field), through the C ABI:
   once, with a finite residual;
 * a one-sample batch through the batch entry point equals the single handle;
 * smoother degree 3, where the stored increment d is used between steps;
-* the fused two-step post-smoothing of single 2D samples against the two
-  separate steps that batch handles run: a batch of two copies of a sample
-  equals the single handle bit for bit;
+* the fused two-step post-smoothing against the two separate steps
+  (options.fuse_post = 0), bit for bit, for a single sample and for a batch;
 * a single-level 3D hierarchy whose dense coarsest solve is large enough that
   fewer right-hand sides fit one workgroup's LDS (4 and 2 columns per group,
   with ragged last groups), against the oracle's preconditioner, and the same
@@ -172,16 +171,18 @@ def test_batch_with_large_dense_coarsest_level_matches_oracle():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_fused_post_smoothing_equals_separate_steps(precision):
-    # a single 2D sample runs both post-smoothing steps of each V-cycle level in
-    # one launch; a batch (two copies of the same sample, so the same spectral
-    # bounds) runs them as two launches with the same arithmetic
+    # both post-smoothing steps of each level in one launch against two launches
     pb = W.heterogeneous_problem(40, 9, field_seed=17, young_seed=18)
-    a = BiotSolver(pb, schedule="wavefront", depth=4, precision=precision)
-    b = BiotSolver([pb, pb], schedule="wavefront", depth=4, precision=precision)
-    a.sweep(7)
-    b.sweep(7)
-    Xa = a.trajectory().cpu().numpy()
-    for i in range(2):
-        assert np.array_equal(Xa, b.sample_trajectory(i).cpu().numpy()), i
-    a.close()
-    b.close()
+    for probs in (pb, [pb, W.heterogeneous_problem(40, 6, field_seed=19, young_seed=20)]):
+        out = []
+        for fuse in (True, False):
+            s = BiotSolver(probs, schedule="wavefront", depth=4, precision=precision,
+                           fuse_post=fuse)
+            s.sweep(7)
+            if isinstance(probs, list):
+                out.append([s.sample_trajectory(i).cpu().numpy() for i in range(len(probs))])
+            else:
+                out.append([s.trajectory().cpu().numpy()])
+            s.close()
+        for x, y in zip(*out):
+            assert np.array_equal(x, y)

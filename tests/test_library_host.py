@@ -141,6 +141,9 @@ def test_create_rejects_bad_input():
     assert "structured" in str(e.value)
     with pytest.raises(_lib.BiotError):
         S.create_handle(W.terzaghi_problem(4, 2), omega=-1.0)
+    with pytest.raises(_lib.BiotError) as e:
+        S.create_handle(W.terzaghi_problem(4, 2), fuse_post=2)
+    assert "fuse_post" in str(e.value)
 
 
 def test_unbound_handle_refuses_device_calls():
