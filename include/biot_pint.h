@@ -280,7 +280,7 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
 #define BIOT_PROBE_LEVRES_P 4     /* pressure residual before restriction        */
 #define BIOT_PROBE_PSTAGE 5       /* P1 pressure stage t = B' z_u - r_p          */
 #define BIOT_PROBE_POST_U 6       /* displacement post-smoothing, both steps in  */
-                                  /* one launch (2D, one sample, degree 2), on  */
+                                  /* one launch (2D, degree 2, fuse_post), on   */
                                   /* every level outside the fused tail         */
 #define BIOT_PROBE_POST_P 7       /* the same for the pressure field (not on     */
                                   /* level 0 in sweeps, whose last step writes  */
