@@ -356,13 +356,14 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
                                                  T c1, T c2, int wd, int dx, int first, T it,
                                                  const ColDesc* __restrict__ cols,
                                                  const T* __restrict__ zu, double omega) {
-  // columns per iteration: two when the row stays in registers; otherwise (3D
-  // displacement) the row is re-read from the caches once per group of eight
-  // FP64 or four FP32 columns (measured on the 40^3 cube: in FP32 the smaller
-  // group's higher occupancy outweighs the extra row reads)
+  // columns per iteration: when the row stays in registers two, or one for the
+  // FP64 pressure field (measured); otherwise (3D displacement) the row is
+  // re-read from the caches once per group of eight FP64 or four FP32 columns
+  // (measured on the 40^3 cube: in FP32 the smaller group's higher occupancy
+  // outweighs the extra row reads)
   constexpr int W = DIM == 2 ? 7 : 15;
   constexpr bool STAT = W * C * C <= 64;
-  constexpr int NQ = STAT ? 2 : (sizeof(T) == 4 ? 4 : 8);
+  constexpr int NQ = STAT ? (C == 1 && sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 4 ? 4 : 8);
   constexpr int RS = STAT ? W : 1;
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
@@ -1149,8 +1150,9 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
                                                    int p1, const T* __restrict__ zu,
                                                    const T* __restrict__ rp,
                                                    T* __restrict__ t_out, int nc) {
-  // columns per iteration (the Bt row stays in registers)
-  constexpr int NQ = 2;
+  // one column per iteration (the Bt row stays in registers; two per
+  // iteration measured 44.5 against 40.8 us per level-0 launch)
+  constexpr int NQ = 1;
   constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
   for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
