@@ -125,7 +125,8 @@ typedef struct {
   double omega;         /* damping of the outer update (0.6)                       */
   int32_t wg_per_cu;    /* workgroups per compute unit of the node-blocked kernels' */
                         /* grids, 0..32; 0: each kernel's occupancy, at most 3   */
-                        /* (3D level-0 residual and smoother: 4) (0)              */
+                        /* (3D level-0 residual and smoother: 4) (0); the fused  */
+                        /* post-smoothing sizes its own grid (fuse_post)         */
   int32_t coarse_cells; /* multigrid: halve the grid while it is even and the half */
                         /* still has >= coarse_cells cells per side (2); the last  */
                         /* level is solved with a dense inverse                    */
