@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC = {
     # k_residual<2, double, false>: 8 dispatches; a Jacobi batch reads 65
     # distinct state columns for its 64 (the coupling overlaps the iterates)
-    "residual": {"kernels_sha256_prefix": "a52052e262a04d6f", "bytes_per_launch": 307.6e6,
+    "residual": {"kernels_sha256_prefix": "9a616e5e64d494d5", "bytes_per_launch": 307.6e6,
                  "launch_columns": 64, "algorithmic_bytes_per_launch": 244.9e6},
     # k_post2<2, double>: 24 dispatches (levels 0-2 of 8 batches), average
-    "post_u": {"kernels_sha256_prefix": "a52052e262a04d6f", "bytes_per_launch": 114.1e6,
+    "post_u": {"kernels_sha256_prefix": "9a616e5e64d494d5", "bytes_per_launch": 114.1e6,
                "launch_columns": 64, "algorithmic_bytes_per_launch": 97.2e6},
 }
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"

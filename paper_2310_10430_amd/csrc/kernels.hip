@@ -68,7 +68,7 @@ __device__ inline int node_id(int i, int j, int k, int m) {
 // neighbouring blocks walk through the same columns at the same time and
 // share the stencil rows they gather in L2; used by the 3D displacement
 // kernels, whose rows are re-read per group of columns anyway (40^3 cube:
-// 707 -> 675 ms; the 2D kernels and the 3D pressure kernels were slower).
+// 707 -> 660 ms; the 2D kernels and the 3D pressure kernels were slower).
 template <bool ALIGNED = false, typename F>
 __device__ inline void for_each_piece(int nblocks, int nc, F&& f) {
   const int P = gridDim.x, i = blockIdx.x;
