@@ -265,6 +265,21 @@ int biot_apply_operator(biot_handle* h, const double* X, double* Y, int32_t ncol
 /* Z = P^{-1} R with the multigrid inner solves, for ncols device columns. */
 int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Z = P^{-1} R as biot_apply_precond, for ncols device columns
+ * [ncols][n_nodes][dim+1] (R read, Z written, both caller-owned), but the
+ * V-cycle work vectors live in a static device array of the library (64 MiB
+ * per device, held until the process ends) instead of the bound workspace.
+ * Columns are processed in batches of as many as that array holds; the part of
+ * it a batch uses is zeroed first by a fill kernel (no memset node).  The call
+ * allocates nothing and calls no allocating library routine.  BIOT_ENOMEM when
+ * one column's work vectors exceed 64 MiB (about 1.5e6 nodes in 2D, FP64).
+ * All calls on one device share that array: calls that overlap on one device
+ * (from any handle or thread) race and must be serialized by the caller.  The
+ * handle must be bound; the work is enqueued on its stream. */
+int biot_apply_precond_noalloc(biot_handle* h, const double* R, double* Z, int32_t ncols);
+
 int biot_get_info(const biot_handle* h, biot_info_t* info);
 
 /* Probes: HIP events recorded on the handle's stream around every level-0

@@ -92,6 +92,7 @@ SIGNATURES = {
                                              C.c_void_p, C.c_int32]),
     "biot_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "biot_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "biot_apply_precond_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "biot_get_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
     "biot_export_level": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -1296,6 +1296,13 @@ __global__ __launch_bounds__(kBlock) void k_pack(int nn, const T* __restrict__ z
   Z[(c * nn + v) * D1 + DIM] = double(zp[c * nn + v]);
 }
 
+// zero n16 16-byte words (grid-stride)
+__global__ __launch_bounds__(kBlock) void k_zero16(uint4* __restrict__ p, size_t n16) {
+  const size_t stride = size_t(gridDim.x) * kBlock;
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
 
 // Grid of a balanced launch (for_each_piece): one workgroup per resident
@@ -1604,6 +1611,13 @@ void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, h
   const dim3 g = col_grid(nc, nn);
   if (dim == 2) hipLaunchKernelGGL((k_pack<2, T>), g, dim3(kBlock), 0, st, nn, zu, zp, Z);
   else hipLaunchKernelGGL((k_pack<3, T>), g, dim3(kBlock), 0, st, nn, zu, zp, Z);
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return;
+  const unsigned grid = unsigned(std::min<size_t>((n16 + kBlock - 1) / kBlock, size_t(4096)));
+  hipLaunchKernelGGL(k_zero16, dim3(grid), dim3(kBlock), 0, st, static_cast<uint4*>(p), n16);
 }
 
 void launch_reduce_norms(const double* partials, int bpc, int copies, int pstride, double* norms,

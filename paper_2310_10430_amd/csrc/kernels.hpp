@@ -137,6 +137,10 @@ void launch_unpack(int dim, int nn, const double* X, T* ru, T* rp, int nc, hipSt
 template <typename T>
 void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, hipStream_t st);
 
+// zeroes `bytes` (a multiple of 16; p 16-byte aligned) with a fill kernel, which
+// unlike a memset node may sit in a captured graph
+void launch_zero(void* p, size_t bytes, hipStream_t st);
+
 // norms[c][copy][4] = sums of the block partials of each copy (blocks of a copy
 // are contiguous: bpc = blocks per copy)
 void launch_reduce_norms(const double* partials, int bpc, int copies, int partial_stride,

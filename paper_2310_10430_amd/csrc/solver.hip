@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -29,6 +30,11 @@
 #include "setup.hpp"
 
 using namespace biot;
+
+// Static device scratch of biot_apply_precond_noalloc (64 MiB per device; see
+// scratch_address below).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -155,6 +161,13 @@ struct biot_handle {
   Acc acc[BIOT_PROBE_COUNT];
   int cur_copies = 0;  // columns of the current batch that also write a second copy
   hipStream_t cap_stream = nullptr;  // stream used for graph capture
+  // allocation-free preconditioner apply: the device the handle was bound on,
+  // that device's address of the static scratch array, and host-side field
+  // tables (sized at bind) that point into it during a call
+  int dev = 0;
+  char* scratch_dev = nullptr;
+  Field<double> sfa_d, sfs_d;
+  Field<float> sfa_f, sfs_f;
 };
 
 namespace {
@@ -195,6 +208,30 @@ struct Bump {
     return p;
   }
 };
+
+// Device scratch of biot_apply_precond_noalloc: the V-cycle work vectors of
+// that entry point live here instead of in the bound workspace.  Every device
+// the library runs on holds one copy until the process ends; host code reaches
+// a device's copy only through the address hipGetSymbolAddress returns for it
+// (kept per device in g_scratch_addr), never through the array's name.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kMaxDevices] = {};
+
+// address of the current device's scratch array (looked up once per device)
+int scratch_address(biot_handle* h, int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(h, BIOT_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(h, BIOT_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return BIOT_OK;
+}
 
 // The coarsest levels whose V-cycle vectors fit in the LDS of one workgroup
 // (kTailMaxLds, or less if the device allows less) run as one fused launch;
@@ -768,6 +805,87 @@ int apply_precond_t(biot_handle* h, Prec<T>& p, const double* R, double* Z, int 
   return BIOT_OK;
 }
 
+// Work-vector bytes of the preconditioner for nc columns, laid out as in
+// plan_prec (every vector 256-byte aligned); with base != nullptr the fields
+// fa, fs and rp are pointed into base.
+template <typename T>
+size_t precond_vectors(const biot_handle* h, int nc, char* base, Field<T>* fa, Field<T>* fs,
+                       T** rp) {
+  Bump b{base};
+  for (int fi = 0; fi < 2; ++fi) {
+    Field<T>* f = fi == 0 ? fa : fs;
+    const int C = fi == 0 ? h->dim : 1;
+    for (int l = 0; l < h->nlev; ++l) {
+      const size_t n = size_t(nc) * h->P.levels[l].nn * C;
+      T* pb = b.take<T>(n);
+      T* p0 = b.take<T>(n);
+      T* p1 = b.take<T>(n);
+      T* pd = b.take<T>(n);
+      T* pr = b.take<T>(n);
+      if (base) {
+        f->b[l] = pb;
+        f->x0[l] = p0;
+        f->x1[l] = p1;
+        f->d[l] = pd;
+        f->r[l] = pr;
+      }
+    }
+  }
+  T* q = b.take<T>(size_t(nc) * h->nn);
+  if (base) *rp = q;
+  return size_t((b.off + 255) & ~uint64_t(255));
+}
+
+// Z = P^{-1} R with the work vectors in the static scratch array: the same
+// kernels as apply_precond_t, in batches of as many columns as the scratch
+// holds.  The used part of the scratch is zeroed (fill kernel) before each
+// batch, so a call does not depend on what an earlier call left there.
+template <typename T>
+int apply_precond_scratch_t(biot_handle* h, Prec<T>& p, Field<T>& sfa, Field<T>& sfs,
+                            const double* R, double* Z, int ncols) {
+  const size_t one = precond_vectors<T>(h, 1, nullptr, nullptr, nullptr, nullptr);
+  if (one > kScratchBytes)
+    return fail(h, BIOT_ENOMEM,
+                "biot_apply_precond_noalloc: one column needs " + std::to_string(one) +
+                    " bytes of work vectors; the static scratch holds " +
+                    std::to_string(kScratchBytes));
+  int nb = 1;
+  while (nb < ncols && nb < 4096 &&
+         precond_vectors<T>(h, nb + 1, nullptr, nullptr, nullptr, nullptr) <= kScratchBytes)
+    ++nb;
+  // swap the handle's work-vector tables for tables into the scratch (host
+  // pointers only; nothing is allocated) and restore them on every path
+  struct Swap {
+    Prec<T>& p;
+    Field<T>& a;
+    Field<T>& s;
+    T* rp;
+    Swap(Prec<T>& p_, Field<T>& a_, Field<T>& s_) : p(p_), a(a_), s(s_), rp(p_.rp) {
+      std::swap(p.fa, a);
+      std::swap(p.fs, s);
+    }
+    ~Swap() {
+      std::swap(p.fa, a);
+      std::swap(p.fs, s);
+      p.rp = rp;
+    }
+  } sw(p, sfa, sfs);
+  for (int c0 = 0; c0 < ncols; c0 += nb) {
+    const int nc = std::min(nb, ncols - c0);
+    const size_t used = precond_vectors<T>(h, nc, h->scratch_dev, &p.fa, &p.fs, &p.rp);
+    launch_zero(h->scratch_dev, used, h->st);
+    LAUNCHCHK(h);
+    launch_unpack<T>(h->dim, h->nn, R + size_t(c0) * h->col, p.fa.b[0], p.rp, nc, h->st);
+    LAUNCHCHK(h);
+    T *zu = nullptr, *zp = nullptr;
+    int rc = precond_batch<T>(h, p, nc, &zu, &zp, nullptr);
+    if (rc) return rc;
+    launch_pack<T>(h->dim, h->nn, zu, zp, Z + size_t(c0) * h->col, nc, h->st);
+    LAUNCHCHK(h);
+  }
+  return BIOT_OK;
+}
+
 // One unit as GMRES(k) on AA x = b (b = coupling + load of each column),
 // left-preconditioned by P (PETSc's default side for GMRES, the Krylov solver
 // K of Alg. 3) and started from X^{n,m-1}: v_0 = P^{-1}(b - AA x0)/beta; for
@@ -1294,6 +1412,17 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
     HIPCHK(h, hipGetDevice(&dev));
     HIPCHK(h, hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     h->tail_lds = std::min(kTailMaxLds, size_t(lds));
+    h->dev = dev;
+    int rc = scratch_address(h, dev, &h->scratch_dev);
+    if (rc) return rc;
+    for (auto* f : {&h->sfa_d, &h->sfs_d}) {
+      f->b.assign(h->nlev, nullptr); f->x0.assign(h->nlev, nullptr); f->x1.assign(h->nlev, nullptr);
+      f->d.assign(h->nlev, nullptr); f->r.assign(h->nlev, nullptr);
+    }
+    for (auto* f : {&h->sfa_f, &h->sfs_f}) {
+      f->b.assign(h->nlev, nullptr); f->x0.assign(h->nlev, nullptr); f->x1.assign(h->nlev, nullptr);
+      f->d.assign(h->nlev, nullptr); f->r.assign(h->nlev, nullptr);
+    }
   }
   h->ws = static_cast<char*>(device_ptr);
   h->st = static_cast<hipStream_t>(stream);
@@ -1584,6 +1713,17 @@ int biot_apply_precond(biot_handle* h, const double* R, double* Z, int32_t ncols
   if (!R || !Z || ncols < 0) return fail(h, BIOT_EINVAL, "bad arguments");
   if (h->opt.precision == BIOT_PRECISION_MIXED) return apply_precond_t<float>(h, h->pf, R, Z, ncols);
   return apply_precond_t<double>(h, h->pd, R, Z, ncols);
+}
+
+int biot_apply_precond_noalloc(biot_handle* h, const double* R, double* Z, int32_t ncols) {
+  int rc = check_bound(h);
+  if (rc) return rc;
+  if (!R || !Z || ncols < 0) return fail(h, BIOT_EINVAL, "bad arguments");
+  if (ncols == 0) return BIOT_OK;
+  if (!h->scratch_dev) return fail(h, BIOT_ESTATE, "no scratch address for the bound device");
+  if (h->opt.precision == BIOT_PRECISION_MIXED)
+    return apply_precond_scratch_t<float>(h, h->pf, h->sfa_f, h->sfs_f, R, Z, ncols);
+  return apply_precond_scratch_t<double>(h, h->pd, h->sfa_d, h->sfs_d, R, Z, ncols);
 }
 
 int biot_profile_enable(biot_handle* h, int32_t mask) {

@@ -283,6 +283,20 @@ class BiotSolver:
         self._outputs_ready(Z)
         return Z
 
+    def apply_precond_noalloc(self, R: torch.Tensor, Z: torch.Tensor) -> torch.Tensor:
+        """Z = P^{-1} R through biot_apply_precond_noalloc: the caller passes both
+        device tensors ([ncols][n_nodes][dim+1] FP64); the library's work vectors
+        are its static device scratch, so nothing is allocated."""
+        if R.dtype != torch.float64 or Z.dtype != torch.float64 or R.shape != Z.shape:
+            raise ValueError("R and Z must be float64 tensors of the same shape")
+        if not (R.is_contiguous() and Z.is_contiguous()):
+            raise ValueError("R and Z must be contiguous")
+        self._inputs_ready(R, Z)
+        self._check(self.lib.biot_apply_precond_noalloc(self.h, C.c_void_p(R.data_ptr()),
+                                                        C.c_void_p(Z.data_ptr()), R.shape[0]))
+        self._outputs_ready(Z)
+        return Z
+
     def info(self) -> dict:
         return handle_info(self.lib, self.h)
 
