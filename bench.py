@@ -116,11 +116,25 @@ def steady_state_error(X, pb):
     return float(max(err / np.abs(ref).max(), np.abs(X[-1, :, pb.dim]).max()))
 
 
-def cpu_baseline(pb, n_sample_steps, X_gpu):
+def host_cpu():
+    """Logical CPUs of the host and its CPU model (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def cpu_baseline(pb, X_gpu):
     """Time the oracle (sequential BE, scaled SuperLU + one refinement step) on
-    one host core for the factorization and the first steps; extrapolate to the
-    whole solve.  Also returns the full-field error of the GPU trajectory over
-    those steps (max over steps of ||Y - Y_o|| / max over steps of ||Y_o||)."""
+    one host core over the whole solve (factorization and every step), and
+    compare the GPU trajectory with it at every unknown of every step: per
+    field max_n ||Y^n - Y_o^n|| / max_n ||Y_o^n|| and the worst element."""
     from oracle import sequential as seq
     try:
         prev = os.sched_getaffinity(0)
@@ -137,24 +151,30 @@ def cpu_baseline(pb, n_sample_steps, X_gpu):
         orc.step_solver()
         t_fact = time.perf_counter() - t0
         t0 = time.perf_counter()
-        Xo = orc.solve_sequential(n_steps=n_sample_steps)
+        Xo = orc.solve_sequential()
         t_steps = time.perf_counter() - t0
     finally:
         if prev is not None:
             os.sched_setaffinity(0, prev)
-    t_full = t_fact + pb.n_steps * t_steps / n_sample_steps
+    t_full = t_fact + t_steps
     value = pb.n_dof * pb.n_steps / t_full
     Yo = orc.trajectory_node_major(Xo)
-    Yg = X_gpu[: n_sample_steps + 1]
+    del Xo
     err = {}
-    for name, sl in (("u", slice(0, 2)), ("p", slice(2, 3))):
-        num = np.linalg.norm((Yg[..., sl] - Yo[..., sl]).reshape(Yg.shape[0], -1), axis=1).max()
-        den = np.linalg.norm(Yo[..., sl].reshape(Yo.shape[0], -1), axis=1).max()
-        err[f"first_{n_sample_steps}_steps_{name}"] = float(num / den)
+    d = pb.dim
+    for name, sl in (("u", slice(0, d)), ("p", slice(d, d + 1))):
+        a = X_gpu[..., sl].reshape(X_gpu.shape[0], -1)
+        b = Yo[..., sl].reshape(Yo.shape[0], -1)
+        num = np.linalg.norm(a - b, axis=1).max()
+        den = np.linalg.norm(b, axis=1).max()
+        err[f"all_steps_q12_{name}"] = float(num / den)
+        err[f"all_steps_max_elem_{name}"] = float(np.abs(a - b).max() / np.abs(b).max())
+    nproc, model = host_cpu()
     info = {"value": value, "unit": "dof-timestep updates/s", "cores": cores, "kind": "oracle",
-            "sample": (f"assembly {t_asm:.1f} s (excluded) + SuperLU factorization {t_fact:.1f} s + "
-                       f"first {n_sample_steps} of {pb.n_steps} steps {t_steps:.1f} s on one core, "
-                       f"extrapolated to all steps: {t_full:.1f} s per solve")}
+            "host_nproc": nproc, "host_cpu": model,
+            "sample": (f"the whole solve on one core: SuperLU factorization {t_fact:.1f} s + "
+                       f"all {pb.n_steps} steps {t_steps:.1f} s = {t_full:.1f} s "
+                       f"(assembly {t_asm:.1f} s excluded)")}
     return info, err
 
 
@@ -179,10 +199,12 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2, **kw):
     per = (time.perf_counter() - t0) / reps
     X = s.trajectory().cpu().numpy()
     s.close()
-    golden = np.load(os.path.join(ROOT, "tests", "golden", golden_name + ".npz"))
-    acc = accuracy_vs_golden(X, golden)
+    gpath = os.path.join(ROOT, "tests", "golden", golden_name + ".npz")
+    acc = accuracy_vs_golden(X, np.load(gpath)) if os.path.exists(gpath) else {}
+    if pb.n_steps * pb.dt >= 8 and np.all(pb.young == pb.young[0]):
+        acc["final_step_vs_steady_state"] = steady_state_error(X, pb)
     return {"value": pb.n_dof * pb.n_steps / per, "unit": "dof-timestep updates/s",
-            "ms_per_solve": 1e3 * per, "precision": precision, "options": kw,
+            "ms_per_solve": 1e3 * per, "precision": precision, "options": kw, "dt": pb.dt,
             "sweeps": st["sweeps"],
             "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"]),
             "max_rel_err_vs_oracle_samples": max(acc.values()), "accuracy": acc}
@@ -281,10 +303,11 @@ def batched_oracle_errors(trajs):
 def run_batched(args):
     """64 independent samples on uneven meshes (sizes from {32,48,64,96,128},
     128..512 steps, own permeability field and moduli each), solved to the same
-    tolerance three ways: one handle per sample in FP64, one after another (the
-    plain GPU method), and tuned batch handles (one per mesh size, split by the
-    autotuner; each on a stream of its own, all solved concurrently) in FP64
-    and with the mixed-precision preconditioner."""
+    tolerance: one handle per sample in FP64, one after another (the plain GPU
+    method), and all 64 samples in ONE batch handle, whose every launch covers
+    all samples that take part in it and whose samples skip the steps past
+    their own counts, with the wavefront depth and workgroups per CU chosen by
+    the autotuner, in FP64 and with the mixed-precision preconditioner."""
     from paper_2310_10430_amd import autotune
     from paper_2310_10430_amd import workloads as W
     specs = W.batched_samples(64, seed=3)
@@ -292,40 +315,36 @@ def run_batched(args):
              for n, N, seed in specs]
     real = float(sum(pb.n_dof * pb.n_steps for pb in probs))
     sizes = sorted({pb.grid_n for pb in probs})
-    buckets = [[(i, pb) for i, pb in enumerate(probs) if pb.grid_n == n] for n in sizes]
     res = {"workload": "64 samples: grid n from {32,48,64,96,128} and steps from 128..512 "
                        "(seeded), log-normal K and E~U[5e3,2e4] per sample (seeds 3000+i, "
                        "4000+i), dt = 1/steps",
-           "samples_per_size": {str(n): len(b) for n, b in zip(sizes, buckets)},
+           "samples_per_size": {str(n): sum(pb.grid_n == n for pb in probs) for n in sizes},
            "dof_steps": real, "rtol": args.rtol}
     log("bench: batched: one handle per sample, FP64")
-    wall, st, ref = autotune.solve_groups([[it] for b in buckets for it in b], args.rtol, "fp64",
-                                          max_sweeps=args.max_sweeps, keep=True)
-    res["per_sample_fp64"] = {"seconds": wall, "value": real / wall,
+    wall, st, ref = autotune.solve_groups([[(i, pb)] for i, pb in enumerate(probs)], args.rtol,
+                                          "fp64", max_sweeps=args.max_sweeps, keep=True)
+    res["per_sample_fp64"] = {"seconds": wall, "value": real / wall, "handles": len(probs),
                               "sweeps_max": max(x["sweeps"] for x in st),
                               "max_rel_err_vs_oracle": batched_oracle_errors(ref)}
     for prec in ("fp64", "mixed"):
         t0 = time.perf_counter()
-        choices = [autotune.tune([pb for _, pb in b], precision=prec) for b in buckets]
+        ch = autotune.tune_batch(probs, precision=prec, rtol=args.rtol)
         tune_s = time.perf_counter() - t0
-        groups, wpcs = [], []
-        for b, ch in zip(buckets, choices):
-            for g in autotune.tuned_groups(b, ch):
-                groups.append(g)
-                wpcs.append(ch["wg_per_cu"])
-        log(f"bench: batched {prec}: {len(groups)} handles, solved concurrently")
-        wall, st, tr = autotune.solve_groups(groups, args.rtol, prec, wpcs=wpcs,
-                                             max_sweeps=args.max_sweeps, keep=True,
-                                             concurrent=True)
+        log(f"bench: batched {prec}: one handle, depth {ch['depth']}, "
+            f"wg_per_cu {ch['wg_per_cu']} (tuning {tune_s:.1f} s)")
+        wall, st, tr = autotune.solve_groups([list(enumerate(probs))], args.rtol, prec,
+                                             depth=ch["depth"], wpcs=[ch["wg_per_cu"]],
+                                             max_sweeps=args.max_sweeps, keep=True)
         diff = max(_max_rel_diff(tr[i], ref[i]) for i in ref)
-        err = batched_oracle_errors(tr)
         res[f"batched_{prec}"] = {
-            "seconds": wall, "value": real / wall, "handles": len(groups),
-            "sweeps_max": max(x["sweeps"] for x in st),
+            "seconds": wall, "value": real / wall, "handles": 1,
+            "sweeps": st[0]["sweeps"], "alg_bytes": st[0]["alg_bytes"],
+            "sweep_GBps": st[0]["alg_bytes"] / st[0]["seconds"] / 1e9,
+            "computed_dof_steps": real, "phantom_dof_steps": 0.0,
             "max_rel_diff_vs_per_sample_fp64": diff, "tuning_s": tune_s,
-            "max_rel_err_vs_oracle": err,
-            "choices": {str(n): {"split": ch["split"], "wg_per_cu": ch["wg_per_cu"],
-                                 "cached": ch["cached"]} for n, ch in zip(sizes, choices)}}
+            "max_rel_err_vs_oracle": batched_oracle_errors(tr),
+            "choice": {k: ch[k] for k in ("depth", "wg_per_cu", "cached", "key")},
+            "trials": ch.get("trials")}
         del tr
     del ref
     res["unit"] = "dof-timestep updates/s"
@@ -414,7 +433,6 @@ def main():
     ap.add_argument("--rtol", type=float, default=2e-9)
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--max-sweeps", type=int, default=600)
-    ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
@@ -506,6 +524,14 @@ def main():
     log(f"bench: {args.steps} solves in {elapsed:.3f} s ({ms_per_step:.1f} ms each, "
         f"{stats[-1]['sweeps']} sweeps)")
 
+    # whole-solve figure: the algorithmic bytes of every kernel a solve
+    # enqueues (all levels, tails, transfers, pressure stage, residual checks)
+    # over the solve's wall time
+    solve_bytes = sum(x["alg_bytes"] for x in stats) / len(stats)
+    solve_s = sum(x["seconds"] for x in stats) / len(stats)
+    sweep_gbs = solve_bytes / solve_s / 1e9
+    log(f"bench: whole solve moves {solve_bytes / 1e9:.1f} GB algorithmic in {solve_s * 1e3:.1f} ms: "
+        f"{sweep_gbs:.0f} GB/s = {sweep_gbs / HBM_PEAK_GBS:.3f} of peak")
     p = prof_main[args.probe]
     dominant = max(prof, key=lambda k: prof[k]["ms"])
     avg_ms = p["ms"] / max(p["launches"], 1)
@@ -526,8 +552,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"bench: timing the CPU oracle on {args.cpu_steps} steps (about half a minute)")
-        cpu, err = cpu_baseline(pb, args.cpu_steps, X)
+        log("bench: timing the CPU oracle over the whole solve on one core (about 45 s)")
+        cpu, err = cpu_baseline(pb, X)
         acc.update(err)
     acc["max_rel_err"] = max(v for k, v in acc.items())
 
@@ -536,12 +562,21 @@ def main():
         variants = {}
         het = W.large_heterogeneous()
         gm = dict(inner="gmres", gmres_k=4, depth=8)
-        for name, prob, gname, prec, kw in (
-                ("large_terzaghi_mixed", pb, "large_terzaghi", "mixed", {}),
+        # P1 against P2 (Sec. 3.1, eqs. (p1)/(p2); Table 3 compares them at
+        # tau = 0.1): the same mesh and 512 steps at dt = 1/32 and dt = 0.1,
+        # Richardson with the omega that minimizes the step operator's spectral
+        # radius (eigenvalues of P^{-1}AA on a 16^2 copy), and GMRES(4)
+        big = {32: W.terzaghi_problem(256, 512, dt=1 / 32), 10: W.terzaghi_problem(256, 512, dt=0.1)}
+        runs = [("large_terzaghi_mixed", pb, "large_terzaghi", "mixed", {}),
                 ("large_heterogeneous_fp64", het, "large_heterogeneous", "fp64", {}),
                 ("large_heterogeneous_mixed", het, "large_heterogeneous", "mixed", {}),
-                ("large_terzaghi_gmres4_P1", pb, "large_terzaghi", "fp64", gm),
-                ("large_terzaghi_gmres4_P2", pb, "large_terzaghi", "fp64", dict(gm, precond="P2"))):
+                ("large_terzaghi_gmres4_P1", pb, "large_terzaghi", "fp64", gm)]
+        for key, gname in ((32, "large_terzaghi_dt32"), (10, "large_terzaghi_dt0.1")):
+            runs += [(f"{gname}_P1", big[key], gname, "fp64", dict(omega=1.4)),
+                     (f"{gname}_P2", big[key], gname, "fp64", dict(precond="P2", omega=1.3)),
+                     (f"{gname}_gmres4_P1", big[key], gname, "fp64", gm),
+                     (f"{gname}_gmres4_P2", big[key], gname, "fp64", dict(gm, precond="P2"))]
+        for name, prob, gname, prec, kw in runs:
             log(f"bench: variant {name}")
             try:
                 variants[name] = run_variant(BiotSolver, prob, gname, prec, args, **kw)
@@ -589,6 +624,8 @@ def main():
                                                                              bytes_per_launch),
             "avg_launch_us": 1e3 * avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
             "launches": p["launches"],
+            "sweep_achieved": sweep_gbs, "sweep_frac": sweep_gbs / HBM_PEAK_GBS,
+            "sweep_bytes_per_solve": solve_bytes, "sweep_seconds_per_solve": solve_s,
         },
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -36,7 +36,9 @@
  *   - Degrees of freedom are node-major: dof = node*(dim+1) + c with
  *     c = 0..dim-1 the displacement components and c = dim the pressure.  A
  *     trajectory is [n_steps+1][n_nodes][dim+1] doubles; row 0 is X^0.
- *   - Prescribed (Dirichlet) values are homogeneous: flagged dofs are zero.
+ *   - Prescribed (Dirichlet) dofs are flagged per node (biot_mesh.dirichlet);
+ *     their values come from biot_load (zero unless prescribed terms are given)
+ *     and are part of the trajectory.
  *   - Meshes must be the structured unit-square (2D, right triangles split
  *     along (i,j)->(i+1,j+1)) or unit-cube (3D, Kuhn tetrahedra) grids with
  *     lexicographic node numbering; grid_n gives the cells per side.
@@ -88,7 +90,8 @@ typedef struct {
   int32_t grid_n;            /* cells per side of the structured grid (>= 1)    */
   const double* xyz;         /* [n_nodes][dim], node (i,j,k) at (i,j,k)/grid_n  */
   const int32_t* conn;       /* [n_elems][dim+1], positively oriented           */
-  const uint8_t* dirichlet;  /* [n_nodes]; bit c<dim: u_c = 0, bit dim: p = 0   */
+  const uint8_t* dirichlet;  /* [n_nodes]; bit c<dim: u_c prescribed, bit dim: */
+                             /* p prescribed (values: biot_load)               */
 } biot_mesh;
 
 /* Materials per element (Sec. 2.1: Lame parameters from E and nu). */
@@ -105,12 +108,38 @@ typedef struct {
                              /* are ignored (they may be NULL)                      */
 } biot_materials;
 
-/* Surface load: constant traction per boundary facet, scaled per time level. */
+/* Right-hand side of eq. (fullysystem) (Sec. 2.2): per step n,
+ *     f^n = [F^n; -tau G^n] = c(n) F_traction + sum_j c_j(n) F_j,
+ * the prescribed (Dirichlet) values g^n = sum_k d_k(n) G_k at the flagged dofs,
+ * and the initial state X^0.
+ *   - Traction: constant per boundary facet, |facet|/dim of it to each vertex.
+ *   - Load terms F_j: assembled vectors in the trajectory layout, e.g. a body
+ *     force int f.v on the displacement rows and -tau int g q of a fluid source
+ *     on the pressure rows.  Entries at prescribed dofs are ignored.
+ *   - Prescribed values: G_k in the trajectory layout; only the entries at the
+ *     flagged dofs are read.  The library lifts them into the right-hand side
+ *     with the assembled operators: on the free rows the step equation becomes
+ *         AA_ff x^n = f^n_f - (AA g^n)_f + (A' g^{n-1})_f + (A' X^{n-1})_f-part,
+ *     i.e. two more internal load terms per G_k, with multipliers d_k(n) and
+ *     d_k(n-1); the values themselves are written into the trajectory at every
+ *     step (biot_bind, biot_reset) and never changed by a sweep.
+ *   - X^0 (NULL: g^0 at the prescribed dofs, zero elsewhere): row 0 of the
+ *     trajectory; where its prescribed part differs from g^0 the difference is
+ *     lifted into step 1.
+ * Arrays are read during biot_create only. */
 typedef struct {
   int32_t n_facets;            /* may be 0                                       */
   const int32_t* facet_nodes;  /* [n_facets][dim]                                */
   const double* traction;      /* [n_facets][dim]                                */
-  const double* coef;          /* [n_steps+1]: multiplier c(n); f^n = c(n) F     */
+  const double* coef;          /* [n_steps+1]: multiplier c(n) of the traction   */
+                               /* (may be NULL when n_facets = 0)                */
+  int32_t n_terms;             /* 0..8 assembled load terms                      */
+  const double* terms;         /* [n_terms][n_nodes][dim+1]                      */
+  const double* term_coef;     /* [n_steps+1][n_terms]: c_j(n)                   */
+  int32_t n_prescribed;        /* 0..3 prescribed-value terms                    */
+  const double* prescribed;    /* [n_prescribed][n_nodes][dim+1]                 */
+  const double* prescribed_coef; /* [n_steps+1][n_prescribed]: d_k(n)            */
+  const double* x0;            /* [n_nodes][dim+1] initial state, or NULL        */
 } biot_load;
 
 typedef struct {
@@ -174,6 +203,10 @@ typedef struct {
                         /* zero at every step is divided by max_n ||b_u^n|| and  */
                         /* max_n ||b_p^n|| combined (root of the sum of squares) */
   double seconds;       /* wall time of the call                                   */
+  double alg_bytes;     /* algorithmic bytes of all kernels the call enqueued:     */
+                        /* each launch's distinct global inputs and outputs once  */
+                        /* (operators once per launch, vectors once per column);  */
+                        /* alg_bytes / seconds is the solve's effective bandwidth */
 } biot_stats;
 
 typedef struct {
@@ -197,22 +230,37 @@ int biot_default_options(biot_options* opt);
 int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_load* load,
                 double dt, int32_t n_steps, const biot_options* opt, biot_handle** out);
 
-/* A batch of n_samples independent problems on the same structured mesh, each
- * with its own materials, load, dt and number of steps, solved together: the
- * samples are stored as disconnected copies of the grid side by side (each
- * padded to a multiple of 256 nodes with inert prescribed nodes, so that no
- * workgroup's node block straddles two samples) and every launch of the sweep
- * works on all of them.  The handle's step count is the largest n_steps;
- * shorter samples keep stepping past their end (those steps are computed,
- * never reported).  Convergence is the worst sample's relative residual over
- * its own steps.  The load multipliers coef of all samples must agree on their
- * common steps.  Multigrid spectral bounds are the maximum over the samples.
- * mats, loads, dts and n_steps have n_samples entries.  Trajectory calls see
- * [n_steps+1][n_samples * nodes_per_sample][dim+1]; biot_get_sample_trajectory
- * extracts one sample.  The adjoint needs n_samples = 1. */
-int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_materials* mats,
+/* A batch of n_samples independent problems, each on its own structured mesh
+ * (meshes[i]; grids may differ in size), with its own materials, load, dt and
+ * number of steps, solved together: the samples are stored as disconnected
+ * grids side by side, largest grid first (stable; biot_sample_layout gives a
+ * sample's nodes), each padded to a multiple of 256 nodes with inert
+ * prescribed nodes, so that no workgroup's node block straddles two samples.
+ * Every launch of the sweep works on all samples that take part in it: a
+ * multigrid level on the samples whose hierarchy reaches it as its own
+ * launches, the fused coarse end on every sample at once (each from its own
+ * first fused level; batches of different grids need one for every sample),
+ * and a sample skips the columns of steps past its own n_steps (nothing is
+ * computed for them).  The handle's step count is the largest n_steps.  A
+ * larger grid must not have a shallower hierarchy.  Convergence is the worst
+ * sample's relative residual over its own steps.  All samples must have the
+ * same right-hand-side structure (traction or not, n_terms, n_prescribed, x0
+ * given or not) and their multipliers (coef, term_coef, prescribed_coef) must
+ * agree on their common steps.  The spectral bounds of a multigrid level are
+ * the maximum over its samples.  meshes, mats, loads, dts and n_steps have
+ * n_samples entries.  Trajectory calls see [n_steps+1][n_nodes][dim+1] with
+ * all samples' nodes (biot_get_info); biot_get_sample_trajectory extracts one
+ * sample and biot_residual_norms reports samples in the order given.  The
+ * adjoint needs n_samples = 1. */
+int biot_create_batch(const biot_mesh* meshes, int32_t n_samples, const biot_materials* mats,
                       const biot_load* loads, const double* dts, const int32_t* n_steps,
                       const biot_options* opt, biot_handle** out);
+
+/* Where sample `sample` of a handle sits in the node numbering of its
+ * trajectory: nodes first_node .. first_node + n_nodes - 1 (its grid nodes; a
+ * single-problem handle has one sample at node 0). */
+int biot_sample_layout(const biot_handle* h, int32_t sample, int32_t* first_node,
+                       int32_t* n_nodes);
 
 /* Device bytes the handle needs (operators, two trajectories, work vectors). */
 int biot_workspace_size(const biot_handle* h, uint64_t* bytes);
@@ -222,7 +270,8 @@ int biot_workspace_size(const biot_handle* h, uint64_t* bytes);
  * uploads the operators and sets the trajectory to zero. */
 int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* hip_stream);
 
-/* X^{n} = 0 for all n (the initial iterate of Alg. 2; X^0 = 0). */
+/* The initial iterate of Alg. 2: X^{n,0} = 0 for n >= 1 except the prescribed
+ * values, X^0 as given in biot_load (zero by default). */
 int biot_reset(biot_handle* h);
 
 /* n_sweeps outer sweeps.  JACOBI: each sweep updates every step from the
@@ -255,7 +304,9 @@ int biot_get_trajectory(biot_handle* h, int32_t n0, int32_t n1, double* dst, int
 int biot_get_sample_trajectory(biot_handle* h, int32_t sample, int32_t n0, int32_t n1, double* dst,
                                int32_t dst_on_device);
 
-/* Overwrites steps n0..n1-1 of the trajectory (warm start / resume). */
+/* Overwrites steps n0..n1-1 of the trajectory (warm start / resume).  The
+ * values at prescribed dofs are taken as given (sweeps keep them), so src
+ * should carry the prescribed values, e.g. a trajectory read back earlier. */
 int biot_set_trajectory(biot_handle* h, int32_t n0, int32_t n1, const double* src,
                         int32_t src_on_device);
 
@@ -337,7 +388,9 @@ int biot_objective_value(biot_handle* h, const biot_objective* obj, double* J);
  * mu through A and through the default beta_e (no beta term when the caller
  * gave beta).  A global lambda or mu has the sum of the entries as gradient.
  * The trajectory in the handle is taken as the converged forward solution
- * (call biot_solve_to_tol first) and the call needs options.adjoint = 1.
+ * (call biot_solve_to_tol first) and the call needs options.adjoint = 1;
+ * such handles take homogeneous prescribed values only (biot_create rejects
+ * prescribed terms and an X^0 that is nonzero at prescribed dofs).
  * With ckpt_stride s > 0 the forward trajectory is overwritten (afterwards
  * biot_sweep, biot_solve_to_tol and biot_get_trajectory return BIOT_ESTATE until
  * biot_reset); each segment of s steps is recomputed from its checkpoint,

@@ -117,10 +117,12 @@ def mms_problem(n: int, dt: float, n_steps: int, E=1.0, nu=0.3, alpha=1.0, K=1.0
                      n_steps=n_steps, dt=dt)
 
 
-def mms_solve(n: int, dt: float, n_steps: int, E=1.0, nu=0.3, alpha=1.0, K=1.0):
+def mms_solve(n: int, dt: float, n_steps: int, E=1.0, nu=0.3, alpha=1.0, K=1.0,
+              trajectory: bool = False):
     """Sequential backward Euler for the manufactured solution.
 
-    Returns (problem, X) with X the field-major state after n_steps steps.
+    Returns (problem, X) with X the field-major state after n_steps steps, or
+    with trajectory=True the states of all steps [n_steps+1, n_dof].
     Prescribed boundary values are the exact solution at each time level; they
     are lifted into the right-hand side.
     """
@@ -155,13 +157,16 @@ def mms_solve(n: int, dt: float, n_steps: int, E=1.0, nu=0.3, alpha=1.0, K=1.0):
     st = StepSolver(AA, free)
     AA_fD = AA[free][:, fx_idx]
     X = nodal(0.0)
+    traj = [X] if trajectory else None
     for m in range(1, n_steps + 1):
         t = m * dt
         Xm = nodal(t)
         rhs = (Ap @ X + loads(t))[free] - AA_fD @ Xm[fx_idx]
         Xm[free] = st.solve(rhs)
         X = Xm
-    return pb, X
+        if trajectory:
+            traj.append(X)
+    return pb, (np.array(traj) if trajectory else X)
 
 
 def l2_error_p(pb, X: np.ndarray, t: float) -> float:

@@ -28,8 +28,10 @@ import numpy as np
 
 
 def step_residual(orc, n: int, X_prev: np.ndarray, X_cur: np.ndarray):
+    """b and r = b - AA x of step n's equation on the free dofs (prescribed
+    values moved into b; prescribed rows zero)."""
     b = orc.rhs(n, X_prev)
-    r = b - orc.AA @ X_cur
+    r = b - orc.AA @ orc.free_part(X_cur)
     r[orc.fixed] = 0.0
     return b, r
 

@@ -67,14 +67,42 @@ class BiotOracle:
         self.F_unit = np.concatenate([F, np.zeros(self.n_nodes)])   # [F; 0], field-major
         self.nU = nU
         self._step = None
+        # general right-hand side (Sec. 2.2, f^n = [F^n; -tau G^n]): assembled
+        # load terms with per-step multipliers, prescribed values of the flagged
+        # dofs as terms with per-step multipliers, and the initial state
+        to_fm = fem.node_to_field_major
+        self.terms = None if getattr(problem, "terms", None) is None else to_fm(problem.terms)
+        self.pres = None
+        if getattr(problem, "prescribed", None) is not None:
+            self.pres = to_fm(problem.prescribed) * self.fixed[None, :]
+        self.x0 = None if getattr(problem, "x0", None) is None else to_fm(problem.x0)
 
     @property
     def n_dof(self) -> int:
         return self.AA.shape[0]
 
     def load(self, n: int) -> np.ndarray:
-        """f^n = [F^n; -tau G^n] (G = 0 for the consolidation column)."""
-        return self.problem.load_coef[n] * self.F_unit
+        """f^n = [F^n; -tau G^n]: the traction times its multiplier plus the
+        assembled terms times theirs (G = 0 for the consolidation column)."""
+        f = self.problem.load_coef[n] * self.F_unit
+        if self.terms is not None:
+            f = f + self.problem.term_coef[n] @ self.terms
+        return f
+
+    def prescribed(self, n: int) -> np.ndarray:
+        """g^n at the prescribed dofs, zero elsewhere (field-major)."""
+        if self.pres is None:
+            return np.zeros(self.n_dof)
+        return self.problem.prescribed_coef[n] @ self.pres
+
+    def initial_state(self) -> np.ndarray:
+        """X^0: the problem's initial state, else g^0 at the prescribed dofs."""
+        return self.x0.copy() if self.x0 is not None else self.prescribed(0)
+
+    def free_part(self, X: np.ndarray) -> np.ndarray:
+        Y = X.copy()
+        Y[..., self.fixed] = 0.0
+        return Y
 
     def step_solver(self) -> StepSolver:
         if self._step is None:
@@ -82,21 +110,26 @@ class BiotOracle:
         return self._step
 
     def rhs(self, n: int, X_prev: np.ndarray) -> np.ndarray:
-        """b^n = A' X^{n-1} + f^n with prescribed (zero) rows cleared."""
+        """Right-hand side of step n's equation for the free dofs, with the
+        prescribed values g^n moved over: b^n = A' X^{n-1} + f^n - AA g^n,
+        prescribed rows cleared.  (X^{n-1} carries g^{n-1}.)"""
         b = self.Ap @ X_prev + self.load(n)
+        if self.pres is not None:
+            b = b - self.AA @ self.prescribed(n)
         b[self.fixed] = 0.0
         return b
 
     def solve_sequential(self, X0: np.ndarray | None = None, n_steps: int | None = None,
                          refine: int = 1) -> np.ndarray:
-        """Backward-Euler trajectory, field-major [n_steps+1, n_dof]."""
+        """Backward-Euler trajectory, field-major [n_steps+1, n_dof], with the
+        prescribed values g^n at the prescribed dofs of every step n >= 1."""
         N = self.problem.n_steps if n_steps is None else n_steps
         X = np.zeros((N + 1, self.n_dof))
-        if X0 is not None:
-            X[0] = X0
+        X[0] = self.initial_state() if X0 is None else X0
         st = self.step_solver()
         for n in range(1, N + 1):
             b = self.rhs(n, X[n - 1])
+            X[n] = self.prescribed(n)
             X[n, self.free] = st.solve(b[self.free], refine=refine)
         return X
 
@@ -104,11 +137,12 @@ class BiotOracle:
         return fem.field_to_node_major(X, self.n_nodes, self.dim)
 
     def space_time_residual(self, X: np.ndarray):
-        """R^n = A' X^{n-1} + f^n - AA X^n for n >= 1 (prescribed rows zero)."""
+        """R^n = A' X^{n-1} + f^n - AA X^n for n >= 1 (prescribed rows zero;
+        X^n carries g^n at the prescribed dofs)."""
         N = X.shape[0] - 1
         R = np.zeros((N, self.n_dof))
         for n in range(1, N + 1):
-            R[n - 1] = self.rhs(n, X[n - 1]) - self.AA @ X[n]
+            R[n - 1] = self.rhs(n, X[n - 1]) - self.AA @ self.free_part(X[n])
             R[n - 1, self.fixed] = 0.0
         return R
 

@@ -32,7 +32,10 @@ class Materials(C.Structure):
 
 
 class Load(C.Structure):
-    _fields_ = [("n_facets", C.c_int32), ("facet_nodes", _ip), ("traction", _dp), ("coef", _dp)]
+    _fields_ = [("n_facets", C.c_int32), ("facet_nodes", _ip), ("traction", _dp), ("coef", _dp),
+                ("n_terms", C.c_int32), ("terms", _dp), ("term_coef", _dp),
+                ("n_prescribed", C.c_int32), ("prescribed", _dp), ("prescribed_coef", _dp),
+                ("x0", _dp)]
 
 
 class Options(C.Structure):
@@ -60,7 +63,7 @@ class AdjointStats(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("converged", C.c_int32), ("rel_resid_u", C.c_double),
-                ("rel_resid_p", C.c_double), ("seconds", C.c_double)]
+                ("rel_resid_p", C.c_double), ("seconds", C.c_double), ("alg_bytes", C.c_double)]
 
 
 class Info(C.Structure):
@@ -81,6 +84,8 @@ SIGNATURES = {
                                     C.POINTER(Load), _dp, _ip, C.POINTER(Options),
                                     C.POINTER(C.c_void_p)]),
     "biot_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
+    "biot_sample_layout": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]),
     "biot_bind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]),
     "biot_reset": (C.c_int, [C.c_void_p]),
     "biot_sweep": (C.c_int, [C.c_void_p, C.c_int32]),

@@ -1,23 +1,26 @@
-"""Autotuner for batched solves of many samples on uneven meshes.
+"""Autotuner for one batched solve of many samples on uneven meshes.
 
-Samples on the same mesh size form a bucket; a bucket is solved by one or more
-batch handles (biot_create_batch), every launch of a handle covering all of
-its samples.  Per bucket the tuner chooses
+All samples go into one batch handle (biot_create_batch with a mesh per
+sample): every launch covers the samples that take part in it, and each
+sample skips the steps past its own count.  For that handle the tuner picks
 
-  * how to split the bucket into handles: samples sorted by their step count
-    and cut into `split` groups (a handle runs as many steps as its longest
-    sample, so splitting trades padding steps for more, smaller launches);
-  * the workgroups per compute unit of the node-blocked kernels (0 = each
-    kernel's occupancy).
+  * the wavefront depth: the columns of one launch (more columns amortize a
+    launch's operator reads over more columns and fill the chip better; fewer
+    make a pass, N + depth - 1 waves, shorter and the convergence checks
+    between passes more frequent), and
+  * the workgroups per compute unit of the node-blocked kernels' grids
+    (0 = each kernel's occupancy, capped at 3 per CU),
 
-Each candidate is timed on one full wavefront pass of every handle of the
-split (after one untimed pass that also captures the HIP graphs); the pass time
-is what a solve repeats, since the number of passes to a tolerance does not
-depend on these choices.  Results are cached per bucket key in a JSON file
-(BIOT_TUNE_CACHE, default ~/.cache/biot_pint/autotune.json).
+by timing a whole solve to the tolerance for every candidate pair (after one
+untimed pass that captures the HIP graphs).  Results are cached in a JSON file
+(BIOT_TUNE_CACHE, default ~/.cache/biot_pint/autotune.json) under a key made of
+the workload (dimension, sizes, step counts, precision, tolerance), the library
+build (a hash of libbiot_pint.so) and the device name, so that a rebuilt
+library or another device is tuned again.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import time
@@ -25,6 +28,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 import torch
 
+from . import _lib
 from .solver import BiotSolver
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "biot_pint", "autotune.json")
@@ -34,35 +38,24 @@ def cache_path() -> str:
     return os.environ.get("BIOT_TUNE_CACHE", DEFAULT_CACHE)
 
 
-def bucket_key(problems, precision: str, depth: int) -> str:
-    pb = problems[0]
-    steps = sorted(p.n_steps for p in problems)
-    return (f"{pb.dim}d-n{pb.grid_n}-S{len(problems)}-steps{steps[0]}_{steps[-1]}"
-            f"_{sum(steps)}-{precision}-D{depth}")
+def library_hash() -> str:
+    """Hash of the built library (the kernels the choice was measured with)."""
+    h = hashlib.sha256()
+    with open(_lib.LIB_PATH, "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return h.hexdigest()[:16]
 
 
-def split_groups(problems, split: int):
-    """Samples sorted by step count (longest first) and cut into `split` groups
-    of about equal total work."""
-    order = sorted(range(len(problems)), key=lambda i: -problems[i].n_steps)
-    split = max(1, min(split, len(order)))
-    total = sum(problems[i].n_steps for i in order)
-    groups, cur, acc = [], [], 0
-    for pos, i in enumerate(order):
-        left = len(order) - pos                 # samples not yet placed, i included
-        need = split - 1 - len(groups)          # cuts still to make
-        if cur and need > 0:
-            target = total * (len(groups) + 1) / split
-            # cut before sample i when that lands closer to the group's share,
-            # or when every remaining sample must start a group of its own
-            if abs(acc + problems[i].n_steps - target) > abs(acc - target) or left <= need:
-                groups.append(cur)
-                cur = []
-        cur.append(i)
-        acc += problems[i].n_steps
-    if cur:
-        groups.append(cur)
-    return groups
+def batch_key(problems, precision: str, rtol: float, device_name: str,
+              lib_hash: str | None = None) -> str:
+    """Cache key: the workload, the library build and the device."""
+    sig = hashlib.sha256()
+    for pb in problems:
+        sig.update(f"{pb.dim}:{pb.grid_n}:{pb.n_steps}:{pb.dt!r};".encode())
+    sizes = sorted({pb.grid_n for pb in problems})
+    return (f"{problems[0].dim}d-S{len(problems)}-n{sizes[0]}_{sizes[-1]}-{sig.hexdigest()[:12]}"
+            f"-{precision}-rtol{rtol:g}-lib{lib_hash or library_hash()}-{device_name}")
 
 
 def _load_cache():
@@ -85,28 +78,31 @@ def _store_cache(cache):
         pass
 
 
-def time_pass(problems, groups, wpc: int, depth: int, precision: str, device="cuda:0") -> float:
-    """Seconds for one wavefront pass of every handle of the split."""
-    total = 0.0
-    for g in groups:
-        batch = [problems[i] for i in g]
-        s = BiotSolver(batch if len(batch) > 1 else batch[0], schedule="wavefront", depth=depth,
-                       wg_per_cu=wpc, precision=precision, device=device)
-        s.sweep(depth)
+def time_solve(problems, depth: int, wpc: int, precision: str, rtol: float,
+               max_sweeps: int = 2000, device="cuda:0") -> float:
+    """Seconds of one solve to rtol of all samples in one handle."""
+    s = BiotSolver(problems if len(problems) > 1 else problems[0], schedule="wavefront",
+                   depth=depth, wg_per_cu=wpc, precision=precision, device=device)
+    try:
+        s.sweep(depth)                      # captures the graphs
         torch.cuda.synchronize()
+        s.reset()
         t0 = time.perf_counter()
-        s.sweep(depth)
+        s.solve_to_tol(rtol, max_sweeps=max_sweeps)
         torch.cuda.synchronize()
-        total += time.perf_counter() - t0
+        return time.perf_counter() - t0
+    finally:
         s.close()
-    return total
 
 
-def tune(problems, precision: str = "mixed", depth: int = 64, splits=(1, 2), wpcs=(0, 2),
-         use_cache: bool = True, device="cuda:0") -> dict:
-    """Best (split, wg_per_cu) for one bucket; returns the choice, every
-    candidate's pass time and whether it came from the cache."""
-    key = bucket_key(problems, precision, depth)
+def tune_batch(problems, precision: str = "mixed", rtol: float = 2e-9, depths=(32, 64, 96),
+               wpcs=(0, 2, 4), use_cache: bool = True, device="cuda:0",
+               device_name: str | None = None) -> dict:
+    """Best (depth, wg_per_cu) for one handle over all samples; returns the
+    choice, every candidate's solve time and whether it came from the cache."""
+    if device_name is None:
+        device_name = torch.cuda.get_device_name(device).replace(" ", "_")
+    key = batch_key(problems, precision, rtol, device_name)
     cache = _load_cache() if use_cache else {}
     if key in cache:
         out = dict(cache[key])
@@ -114,15 +110,12 @@ def tune(problems, precision: str = "mixed", depth: int = 64, splits=(1, 2), wpc
         return out
     t0 = time.perf_counter()
     trials = []
-    for split in splits:
-        if split > len(problems):
-            continue
-        groups = split_groups(problems, split)
+    for depth in depths:
         for wpc in wpcs:
-            t = time_pass(problems, groups, wpc, depth, precision, device)
-            trials.append({"split": split, "wg_per_cu": wpc, "pass_s": t})
-    best = min(trials, key=lambda r: r["pass_s"])
-    out = {"key": key, "split": best["split"], "wg_per_cu": best["wg_per_cu"],
+            t = time_solve(problems, depth, wpc, precision, rtol, device=device)
+            trials.append({"depth": depth, "wg_per_cu": wpc, "solve_s": t})
+    best = min(trials, key=lambda r: r["solve_s"])
+    out = {"key": key, "depth": best["depth"], "wg_per_cu": best["wg_per_cu"],
            "trials": trials, "tuning_s": time.perf_counter() - t0}
     if use_cache:
         cache = _load_cache()
@@ -140,9 +133,9 @@ def solve_groups(groups, rtol: float, precision: str, depth: int = 64, wpcs=None
     (one pass, which captures the graphs) before the timed region; the timed
     region resets and solves every handle to rtol, in turn, or with
     `concurrent`, all at once: each handle then runs on a stream of its own
-    (default priority) and is driven by a host thread of its own, so the small
-    launches of different mesh sizes overlap on the GPU.  Returns the wall
-    time, the stats per handle and, with keep, {sample number: trajectory}."""
+    (default priority) and is driven by a host thread of its own.  Returns the
+    wall time, the stats per handle and, with keep, {sample number:
+    trajectory}."""
     handles = []
     for k, g in enumerate(groups):
         batch = [pb for _, pb in g]
@@ -183,9 +176,3 @@ class _nullctx:
 
     def __exit__(self, *exc):
         return False
-
-
-def tuned_groups(bucket, choice):
-    """(sample number, problem) groups of a bucket under a tuner choice."""
-    probs = [pb for _, pb in bucket]
-    return [[bucket[i] for i in g] for g in split_groups(probs, choice["split"])]

@@ -53,6 +53,27 @@ __device__ inline int node_id(int i, int j, int k, int m) {
   return DIM == 2 ? j * m + i : (k * m + j) * m + i;
 }
 
+// grid nodes of a copy with `cells` cells per side
+template <int DIM>
+__device__ inline int grid_nodes(int cells) {
+  const int m = cells + 1;
+  return DIM == 2 ? m * m : m * m * m;
+}
+
+// Shrinks the column range [cbeg, cend) of a launch to the columns active for
+// copy cp (a sample skips the steps past its own count); they are contiguous.
+template <typename T>
+__device__ inline void active_cols(const LevelView<T>& L, int cp, int& cbeg, int& cend) {
+  if (!L.act) return;
+  const int ns = L.csteps[cp];
+  while (cbeg < cend && L.act[cbeg].step > ns) ++cbeg;
+  while (cend > cbeg && L.act[cend - 1].step > ns) --cend;
+}
+template <typename T>
+__device__ inline bool col_active(const LevelView<T>& L, int cp, int c) {
+  return !L.act || L.act[c].step <= L.csteps[cp];
+}
+
 // Balanced split of a launch's work over its grid.  The units are the pairs
 // (node block of kBlock nodes, column), ordered block-major; workgroup slot l
 // takes units [U l / P, U (l+1) / P) and calls f(node_block, c_begin, c_end)
@@ -142,9 +163,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   __shared__ double lds[4 * 4 * NQ];
   const int nn = L.nn;
-  for_each_piece<!STAT>(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+  for_each_piece<!STAT>(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
+    active_cols(L, L.bcopy[nblk], cbeg, cend);
+    if (cbeg >= cend) return;
     const int v = nblk * kBlock + threadIdx.x;
-    const bool active = v < nn;
+    const bool active = v < L.nact;
     const int vv = active ? v : nn - 1;
     int nb[RS];
     if constexpr (STAT) {
@@ -166,9 +189,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
         rCb[s] = F.Cb[size_t(s) * nn + vv];
       }
     }
-    double Fu[DIM];
+    // load f^n = sum_j c_j(n) F_j: term 0 stays in registers, further terms
+    // are read per column pair (from the caches); prescribed dofs are masked
+    const int nt = ADJ ? 0 : F.nt;
+    const unsigned fx = active ? unsigned(L.fixed[vv]) : 0u;
+    double Fu[DIM], Fp = 0.0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) Fu[a] = active ? F.F[size_t(vv) * D1 + a] : 0.0;
+    for (int a = 0; a < DIM; ++a) Fu[a] = (active && nt > 0) ? F.F[size_t(vv) * D1 + a] : 0.0;
+    if (active && nt > 0) Fp = F.F[size_t(vv) * D1 + DIM];
 #pragma unroll 1
     for (int c = cbeg; c < cend; c += NQ) {
       // columns past the end of the run repeat the last one (computed, not stored)
@@ -177,23 +205,39 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
       for (int q = 0; q < NQ; ++q) cc[q] = min(c + q, cend - 1);
       const double* xc[NQ];
       const double* xp[NQ];
-      double coef[NQ], au[NQ][DIM], ap[NQ], bp[NQ], cu[NQ][DIM];
+      double lb[NQ], au[NQ][DIM], ap[NQ], bp[NQ], cu[NQ][DIM];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         xc[q] = cols[cc[q]].xcur;
         xp[q] = cols[cc[q]].xprev;
-        coef[q] = cols[cc[q]].coef;
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          au[q][a] = coef[q] * Fu[a];
-          cu[q][a] = 0.0;
-        }
-        ap[q] = 0.0;
-        bp[q] = 0.0;
+        for (int a = 0; a < DIM; ++a) cu[q][a] = 0.0;
         if constexpr (ADJ) {
           const double g = active ? F.gload[size_t(cols[cc[q]].step - 1) * nn + vv] : 0.0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) au[q][a] = 0.0;
           ap[q] = g;
           bp[q] = g;
+          lb[q] = 0.0;
+        } else {
+          const double* tc = cols[cc[q]].tc;
+          const double c0 = cols[cc[q]].c0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) au[q][a] = c0 * Fu[a];
+          ap[q] = c0 * Fp;
+#pragma unroll 1
+          for (int j = 1; j < nt; ++j) {
+            const double cj = tc[j];
+            const double* Tj = F.F + (size_t(j) * nn + vv) * D1;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) au[q][a] += cj * Tj[a];
+            ap[q] += cj * Tj[DIM];
+          }
+          bp[q] = ap[q];
+          double sl = 0.0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) sl += au[q][a] * au[q][a];
+          lb[q] = sl;
         }
       }
 #pragma unroll SU
@@ -258,6 +302,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
           ap[q] += coup - btc + Sv * xw[DIM];
         }
       }
+      // prescribed rows: zero residual (their values are kept in the state)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+          if ((fx >> a) & 1u) au[q][a] = 0.0;
+        if ((fx >> DIM) & 1u) ap[q] = 0.0;
+      }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (!active || c + q >= cend) break;
@@ -272,12 +324,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
         double qv[4 * NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          double su = 0.0, sb = 0.0;
+          double su = 0.0, sb = lb[q];
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
             su += au[q][a] * au[q][a];
-            const double ba = coef[q] * Fu[a] + cu[q][a];
-            sb += ba * ba;
+            if constexpr (ADJ) sb += cu[q][a] * cu[q][a];
           }
           qv[4 * q + 0] = active ? su : 0.0;
           qv[4 * q + 1] = active ? ap[q] * ap[q] : 0.0;
@@ -304,13 +355,17 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
 // edge midpoint with weight 1/2; otherwise a coincident node with weight 1).
 // A component is masked when the fine or the coarse dof is prescribed.
 // ---------------------------------------------------------------------------
+// f is a node of copy cp on the fine level (global numbering); the parents
+// are returned in the coarse level's global numbering.
 template <int DIM, int C, typename T>
 __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T>& Lc, int bit0,
-                                       int f, int& p0, int& p1, unsigned& mask) {
-  const int mf = Lf.n_cells + 1, mc = Lc.n_cells + 1;
-  const int cp = f / Lf.nn1, lf = f - cp * Lf.nn1;  // copy and node within it
-  if (lf >= Lf.nreal) {  // padding node: no parents
-    p0 = p1 = cp * Lc.nn1;
+                                       int cp, int f, int& p0, int& p1, unsigned& mask) {
+  const int cf = Lf.ccells[cp];
+  const int mf = cf + 1, mc = Lc.ccells[cp] + 1;
+  const int fb = Lf.cbase[cp], cb = Lc.cbase[cp];
+  const int lf = f - fb;  // node within the copy
+  if (lf >= grid_nodes<DIM>(cf)) {  // padding node: no parents
+    p0 = p1 = cb;
     mask = 0u;
     return;
   }
@@ -319,8 +374,8 @@ __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T
   const int ai = i >> 1, aj = j >> 1, ak = k >> 1;
   const int oi = i & 1, oj = j & 1, ok = k & 1;
   const bool two = (oi | oj | ok) != 0;
-  p0 = cp * Lc.nn1 + node_id<DIM>(ai, aj, ak, mc);
-  p1 = two ? cp * Lc.nn1 + node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
+  p0 = cb + node_id<DIM>(ai, aj, ak, mc);
+  p1 = two ? cb + node_id<DIM>(ai + oi, aj + oj, ak + ok, mc) : p0;
   const unsigned ff = Lf.fixed[f], f0 = Lc.fixed[p0], f1 = Lc.fixed[p1];
   mask = two ? (1u << 2 * C) : 0u;
 #pragma unroll
@@ -367,9 +422,10 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
   constexpr int RS = STAT ? W : 1;
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
-  for_each_piece<!STAT>(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+  for_each_piece<!STAT>(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
+    active_cols(L, L.bcopy[nblk], cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
-    if (v >= nn) return;
+    if (v >= L.nact || cbeg >= cend) return;
     // C > 1 is the displacement field (A), C == 1 the pressure field (S)
     const T* K = first ? (C > 1 ? L.AD : L.SD) : (C > 1 ? L.A : L.S);
     const T* Dg = C > 1 ? L.Ainv : L.Sinv;
@@ -508,7 +564,8 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
 // gather in L2; workgroup i goes to XCD i % 8, and each XCD is given a
 // contiguous range of (patch, run) pairs, i.e. neighbouring patches.
 constexpr int kPatch = 16;
-constexpr int kPatchIn = kPatch - 2;
+constexpr int kPatchIn = kPatchInterior;
+static_assert(kPatchIn == kPatch - 2, "a patch's interior drops its outer ring");
 static_assert(kPatch * kPatch == kBlock, "one patch node per thread");
 
 template <int C, typename T>
@@ -520,8 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
   constexpr int W = 7, NQ = 1;
   // per buffer: x3, and the node's own x2 and b, of the patch's nodes
   __shared__ T sh[2][3][NQ][kBlock][C];
-  const int m = L.n_cells + 1, nn = L.nn;
-  const int per_side = (m + kPatchIn - 1) / kPatchIn;
+  const int nn = L.nn;
   const int li = threadIdx.x % kPatch, lj = threadIdx.x / kPatch;
   const T* K = isA ? L.A : L.S;
   const T* Dg = isA ? L.Ainv : L.Sinv;
@@ -530,10 +586,14 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
   {
     const int P = gridDim.x, i = blockIdx.x;  // P is a multiple of 8
     const int slot = (i & 7) * (P >> 3) + (i >> 3);
-    const int pp = per_side * per_side;  // patches per copy (sample of a batch)
-    if (slot >= L.copies * pp * groups) return;
-    const int patch = (slot / groups) % pp, base = (slot / groups / pp) * L.nn1;
-    const int cbeg = (slot % groups) * run, cend = min(nc, cbeg + run);
+    if (slot >= L.npatch * groups) return;
+    // patch of a copy (sample of a batch; copies may differ in size)
+    const int gp = slot / groups;
+    const int cp = L.ptab[2 * gp], patch = L.ptab[2 * gp + 1];
+    const int m = L.ccells[cp] + 1, base = L.cbase[cp];
+    const int per_side = (m + kPatchIn - 1) / kPatchIn;
+    int cbeg = (slot % groups) * run, cend = min(nc, cbeg + run);
+    active_cols(L, cp, cbeg, cend);
     if (cbeg >= cend) return;
     const int i0 = (patch % per_side) * kPatchIn - 1, j0 = (patch / per_side) * kPatchIn - 1;
     const int gi = i0 + li, gj = j0 + lj;
@@ -657,12 +717,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelView<T> Lf, LevelView<T
                                                     const T* __restrict__ xc,
                                                     T* __restrict__ xout, int nc) {
   const int nn = Lf.nn;
-  for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+  for_each_piece(num_node_blocks(Lf.nact), nc, [&](int nblk, int cbeg, int cend) {
+    const int cp = Lf.bcopy[nblk];
+    active_cols(Lf, cp, cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
-    if (v >= nn) return;
+    if (v >= Lf.nact || cbeg >= cend) return;
     int p0, p1;
     unsigned pm;
-    prolong_parents<DIM, C>(Lf, Lc, isA ? 0 : DIM, v, p0, p1, pm);
+    prolong_parents<DIM, C>(Lf, Lc, isA ? 0 : DIM, cp, v, p0, p1, pm);
     const T wt = (pm >> (2 * C)) ? T(0.5) : T(1);
     const size_t stride = size_t(nn) * C, cstride = size_t(Lc.nn) * C;
 #pragma unroll 2
@@ -703,9 +765,10 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
   constexpr int RS = STAT ? W : 1;
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
-  for_each_piece<!STAT>(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+  for_each_piece<!STAT>(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
+    active_cols(L, L.bcopy[nblk], cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
-    if (v >= nn) return;
+    if (v >= L.nact || cbeg >= cend) return;
     const T* K = isA ? L.A : L.S;
     const size_t stride = size_t(nn) * C;
     int nb[RS];
@@ -768,11 +831,13 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
                                                      T* __restrict__ bc, int nc) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const int I = blockIdx.y * kBlock + threadIdx.x;
-  if (I >= Lc.nn) return;
   const int c = blockIdx.x;
-  const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
-  const int cp = I / Lc.nn1, lI = I - cp * Lc.nn1;  // copy and node within it
-  const bool real = lI < Lc.nreal;
+  const int cp = Lc.bcopy[blockIdx.y];
+  if (I >= Lc.nact || !col_active(Lc, cp, c)) return;
+  const int mc = Lc.ccells[cp] + 1, mf = Lf.ccells[cp] + 1;
+  const int lI = I - Lc.cbase[cp];  // node within the copy
+  const bool real = lI < grid_nodes<DIM>(Lc.ccells[cp]);
+  const int fbase = Lf.cbase[cp];
   int ci = 0, cj = 0, ck = 0;
   if (real) node_coords<DIM>(lI, mc, ci, cj, ck);
   const uint8_t fc = Lc.fixed[I];
@@ -787,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
     const int* o = DIM == 2 ? c_off2[s] : c_off3[s];
     const int fi = 2 * ci + o[0], fj = 2 * cj + o[1], fk = 2 * ck + o[2];
     const bool in = real && fi >= 0 && fi < mf && fj >= 0 && fj < mf && fk >= 0 && fk < mf;
-    fs[s] = cp * Lf.nn1 + (in ? node_id<DIM>(fi, fj, fk, mf) : 0);
+    fs[s] = fbase + (in ? node_id<DIM>(fi, fj, fk, mf) : 0);
     ok |= unsigned(in) << s;
   }
   unsigned ff[W];
@@ -845,8 +910,8 @@ constexpr int block() { return DIM == 2 ? 1024 : 256; }
 //          and is overwritten in place);
 //   else dp = d (when c1 != 0); wd: store d.
 template <int DIM, int C, bool FIRST, typename T>
-__device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T* xin, T* xout,
-                            T* d, T c1, T c2, T it, int dx, bool wd) {
+__device__ inline void cheb(const LevelView<T>& L, int base, int nreal, const T* b, const T* xin,
+                            T* xout, T* d, T c1, T c2, T it, int dx, bool wd) {
   constexpr bool first = FIRST;
   constexpr int W = DIM == 2 ? 7 : 15;
   const T* K = first ? (C > 1 ? L.AD : L.SD) : (C > 1 ? L.A : L.S);
@@ -854,7 +919,7 @@ __device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T
   const T* src = first ? b : xin;
   const T sc = first ? it : T(1);
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < L.nreal; v += block<DIM>()) {
+  for (int v = threadIdx.x; v < nreal; v += block<DIM>()) {
     const int g = base + v;
     T acc[C], xs[C];
 #pragma unroll
@@ -900,11 +965,12 @@ __device__ inline void cheb(const LevelView<T>& L, int base, const T* b, const T
 }
 
 template <int DIM, int C, typename T>
-__device__ inline void residual(const LevelView<T>& L, int base, const T* b, const T* x, T* r) {
+__device__ inline void residual(const LevelView<T>& L, int base, int nreal, const T* b, const T* x,
+                                T* r) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const T* K = C > 1 ? L.A : L.S;
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < L.nreal; v += block<DIM>()) {
+  for (int v = threadIdx.x; v < nreal; v += block<DIM>()) {
     const int g = base + v;
     T acc[C];
 #pragma unroll
@@ -927,12 +993,14 @@ __device__ inline void residual(const LevelView<T>& L, int base, const T* b, con
 
 // bc = P' rf (masked)
 template <int DIM, int C, typename T>
-__device__ inline void restrict_to(const LevelView<T>& Lf, int basef, const LevelView<T>& Lc,
-                                   int basec, const T* rf, T* bc) {
+__device__ inline void restrict_to(const LevelView<T>& Lf, int basef, int cellsf,
+                                   const LevelView<T>& Lc, int basec, int cellsc, const T* rf,
+                                   T* bc) {
   constexpr int W = DIM == 2 ? 7 : 15;
-  const int mc = Lc.n_cells + 1, mf = Lf.n_cells + 1;
+  const int mc = cellsc + 1, mf = cellsf + 1;
   const int bit0 = C > 1 ? 0 : DIM;
-  for (int I = threadIdx.x; I < Lc.nreal; I += block<DIM>()) {
+  const int nrc = grid_nodes<DIM>(cellsc);
+  for (int I = threadIdx.x; I < nrc; I += block<DIM>()) {
     int ci, cj, ck;
     node_coords<DIM>(I, mc, ci, cj, ck);
     T acc[C];
@@ -960,12 +1028,13 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, const Leve
 }
 
 template <int DIM, int C, typename T>
-__device__ inline void prolong(const LevelView<T>& Lf, int basef, const LevelView<T>& Lc,
-                               int basec, const T* xin, const T* xc, T* xout) {
-  for (int v = threadIdx.x; v < Lf.nreal; v += block<DIM>()) {
+__device__ inline void prolong(const LevelView<T>& Lf, int basef, int nrealf,
+                               const LevelView<T>& Lc, int basec, int cp, const T* xin,
+                               const T* xc, T* xout) {
+  for (int v = threadIdx.x; v < nrealf; v += block<DIM>()) {
     int p0, p1;
     unsigned pm;
-    prolong_parents<DIM, C>(Lf, Lc, C > 1 ? 0 : DIM, basef + v, p0, p1, pm);
+    prolong_parents<DIM, C>(Lf, Lc, C > 1 ? 0 : DIM, cp, basef + v, p0, p1, pm);
     p0 -= basec;
     p1 -= basec;
     const T wt = (pm >> (2 * C)) ? T(0.5) : T(1);
@@ -981,32 +1050,44 @@ __device__ inline void prolong(const LevelView<T>& Lf, int basef, const LevelVie
 
 }  // namespace tail
 
-// one workgroup per (column, copy)
+// one workgroup per (column, copy); each copy runs its own tail levels
+// t0..t0+nlev-1 (copies of a batch may be grids of different sizes)
 template <int DIM, int C, typename T>
-__global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> TD, const T* __restrict__ b_t,
-                                                        T* __restrict__ x_t) {
+__global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> TD) {
   extern __shared__ double tail_raw[];
   T* lds = reinterpret_cast<T*>(tail_raw);
-  const int copies = TD.L[0].copies;
+  __shared__ int s_nr[kTailMaxLevels], s_base[kTailMaxLevels], s_cells[kTailMaxLevels],
+      s_off[kTailMaxLevels];
+  const int copies = TD.copies;
   const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
-  const int nl = TD.nlev;  // levels t..t+nl-1; the last one is solved densely
+  const TailCopy* tcp = TD.tc + cp;
+  const int t0 = tcp->t0, nl = tcp->nlev;  // the last one is solved densely
+  if (!col_active(TD.L[t0], cp, c)) return;  // past this sample's steps
+  if (threadIdx.x < nl) {
+    const LevelView<T>& Li = TD.L[t0 + threadIdx.x];
+    s_cells[threadIdx.x] = Li.ccells[cp];
+    s_nr[threadIdx.x] = grid_nodes<DIM>(Li.ccells[cp]);
+    s_base[threadIdx.x] = Li.cbase[cp];
+    s_off[threadIdx.x] = tcp->off[threadIdx.x];
+  }
+  __syncthreads();
   const int deg = TD.degree;
-  // level i's LDS block at TD.off[i]: b, two iterates (the free one also holds
-  // the residual) and, for degree > 2, d (coarsest: b, x), each nreal_i * C
+  // level i's LDS block at s_off[i]: b, two iterates (the free one also holds
+  // the residual) and, for degree > 2, d (coarsest: b, x), each s_nr[i] * C
   // values; bit i of `alt` set when level i's current iterate is the second
-  auto vec = [&](int i, int k) { return lds + TD.off[i] + k * TD.L[i].nreal * C; };
-  auto base = [&](int i) { return cp * TD.L[i].nn1; };
+  auto vec = [&](int i, int k) { return lds + s_off[i] + k * s_nr[i] * C; };
   T* const dnull = nullptr;
   unsigned alt = 0;
-  const int n0 = TD.L[0].nreal * C;
-  const size_t g0 = (size_t(c) * TD.L[0].nn + base(0)) * C;
+  const int n0 = s_nr[0] * C;
+  const size_t g0 = (size_t(c) * TD.L[t0].nn + s_base[0]) * C;
+  const T* b_t = TD.b[t0];
   for (int i = threadIdx.x; i < n0; i += tail::block<DIM>()) vec(0, 0)[i] = b_t[g0 + i];
   __syncthreads();
   // descend: pre-smoothing (its first step folded into the second), residual
   // into the free iterate, restriction
   for (int i = 0; i + 1 < nl; ++i) {
-    const LevelView<T>& L = TD.L[i];
-    const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
+    const LevelView<T>& L = TD.L[t0 + i];
+    const double theta = TD.theta[t0 + i], delta = TD.delta[t0 + i], sigma = TD.sigma[t0 + i];
     T* d = deg > 2 ? vec(i, 3) : dnull;
     int xi = 1;
     double rho = 1.0 / sigma;
@@ -1014,28 +1095,28 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
       const double rn = 1.0 / (2.0 * sigma - rho);
       const bool first = j == 2;
       if (first)
-        tail::cheb<DIM, C, true, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 1), d, T(rn * rho),
-                                    T(2.0 * rn / delta), T(1.0 / theta), 0, j < deg);
+        tail::cheb<DIM, C, true, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 1), d,
+                                    T(rn * rho), T(2.0 * rn / delta), T(1.0 / theta), 0, j < deg);
       else
-        tail::cheb<DIM, C, false, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), d,
-                                     T(rn * rho), T(2.0 * rn / delta), T(0), 0, j < deg);
+        tail::cheb<DIM, C, false, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 3 - xi),
+                                     d, T(rn * rho), T(2.0 * rn / delta), T(0), 0, j < deg);
       __syncthreads();
       rho = rn;
       if (!first) xi = 3 - xi;
     }
     if (xi == 2) alt |= 1u << i;
-    tail::residual<DIM, C, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi));
+    tail::residual<DIM, C, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 3 - xi));
     __syncthreads();
-    tail::restrict_to<DIM, C, T>(L, base(i), TD.L[i + 1], base(i + 1), vec(i, 3 - xi),
-                                 vec(i + 1, 0));
+    tail::restrict_to<DIM, C, T>(L, s_base[i], s_cells[i], TD.L[t0 + i + 1], s_base[i + 1],
+                                 s_cells[i + 1], vec(i, 3 - xi), vec(i + 1, 0));
     __syncthreads();
   }
   // coarsest level: dense inverse of this copy
   {
-    const int n = TD.L[nl - 1].nreal * C;
+    const int n = s_nr[nl - 1] * C;
     const T* bb = vec(nl - 1, 0);
     T* xx = vec(nl - 1, 1);
-    const T* M = TD.Minv + size_t(cp) * n * n;
+    const T* M = TD.Minv + tcp->moff;
     for (int r = threadIdx.x; r < n; r += tail::block<DIM>()) {
       T acc = T(0);
       const T* row = M + size_t(r) * n;
@@ -1048,13 +1129,13 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
   // post-smoothing steps (the second recovers the first one's increment from
   // the buffer it overwrites)
   for (int i = nl - 2; i >= 0; --i) {
-    const LevelView<T>& L = TD.L[i];
-    const double theta = TD.theta[i], delta = TD.delta[i], sigma = TD.sigma[i];
+    const LevelView<T>& L = TD.L[t0 + i];
+    const double theta = TD.theta[t0 + i], delta = TD.delta[t0 + i], sigma = TD.sigma[t0 + i];
     T* d = deg > 2 ? vec(i, 3) : dnull;
     int xi = ((alt >> i) & 1u) ? 2 : 1;
     const int xci = (i + 2 == nl) ? 1 : (((alt >> (i + 1)) & 1u) ? 2 : 1);
-    tail::prolong<DIM, C, T>(L, base(i), TD.L[i + 1], base(i + 1), vec(i, xi), vec(i + 1, xci),
-                             vec(i, 3 - xi));
+    tail::prolong<DIM, C, T>(L, s_base[i], s_nr[i], TD.L[t0 + i + 1], s_base[i + 1], cp,
+                             vec(i, xi), vec(i + 1, xci), vec(i, 3 - xi));
     __syncthreads();
     xi = 3 - xi;
     double rho = 1.0 / sigma;
@@ -1065,8 +1146,8 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
         c1 = rn * rho;
         c2 = 2.0 * rn / delta;
       }
-      tail::cheb<DIM, C, false, T>(L, base(i), vec(i, 0), vec(i, xi), vec(i, 3 - xi), d, T(c1),
-                                   T(c2), T(0), j == 2 ? 2 : 0, j > 1 && j < deg);
+      tail::cheb<DIM, C, false, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 3 - xi),
+                                   d, T(c1), T(c2), T(0), j == 2 ? 2 : 0, j > 1 && j < deg);
       __syncthreads();
       rho = rn;
       xi = 3 - xi;
@@ -1074,9 +1155,10 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
     alt = (alt & ~(1u << i)) | (xi == 2 ? 1u << i : 0u);
   }
   const T* res = vec(0, ((alt & 1u) ? 2 : 1));
+  T* x_t = TD.x[t0];
   for (int i = threadIdx.x; i < n0; i += tail::block<DIM>()) x_t[g0 + i] = res[i];
   // padding nodes of the copy keep a zero correction
-  const int npad = (TD.L[0].nn1 - TD.L[0].nreal) * C;
+  const int npad = (TD.L[t0].cbase[cp + 1] - s_base[0] - s_nr[0]) * C;
   for (int i = threadIdx.x; i < npad; i += tail::block<DIM>()) x_t[g0 + n0 + i] = T(0);
 }
 
@@ -1155,9 +1237,10 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
   constexpr int NQ = 1;
   constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
-  for_each_piece(num_node_blocks(nn), nc, [&](int nblk, int cbeg, int cend) {
+  for_each_piece(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
+    active_cols(L, L.bcopy[nblk], cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
-    if (v >= nn) return;
+    if (v >= L.nact || cbeg >= cend) return;
     int nb[W];
     T bt[W][DIM];
 #pragma unroll
@@ -1200,11 +1283,14 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_update(int nn, const ColDesc* __restrict__ cols,
                                                    const T* __restrict__ zu,
-                                                   const T* __restrict__ zp, double omega) {
+                                                   const T* __restrict__ zp, double omega,
+                                                   const int32_t* __restrict__ csteps,
+                                                   const int32_t* __restrict__ bcopy) {
   constexpr int D1 = DIM + 1;
   const int v = blockIdx.y * kBlock + threadIdx.x;
   if (v >= nn) return;
   const int c = blockIdx.x;
+  if (csteps && cols[c].step > csteps[bcopy[blockIdx.y]]) return;  // past the sample's steps
   const double* xc = cols[c].xcur;
   double* xo = cols[c].xout;
   double* xo2 = cols[c].xout2;
@@ -1222,12 +1308,14 @@ __global__ __launch_bounds__(kBlock) void k_update(int nn, const ColDesc* __rest
 
 // per-column sums of the block partials in a fixed order
 __global__ __launch_bounds__(kBlock) void k_reduce_norms(const double* __restrict__ partials,
-                                                         int bpc, int copies, int pstride,
+                                                         const int32_t* __restrict__ cbase,
+                                                         int copies, int pstride,
                                                          double* __restrict__ norms) {
   __shared__ double lds[16];
   const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
   double q[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = cp * bpc + threadIdx.x; b < (cp + 1) * bpc; b += kBlock)
+  const int b0 = cbase[cp] / kBlock, b1 = (cbase[cp + 1] + kBlock - 1) / kBlock;
+  for (int b = b0 + threadIdx.x; b < b1; b += kBlock)
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] += partials[(size_t(c) * pstride + b) * 4 + k];
   block_sum<4>(q, lds);
@@ -1301,6 +1389,31 @@ __global__ __launch_bounds__(kBlock) void k_zero16(uint4* __restrict__ p, size_t
   const size_t stride = size_t(gridDim.x) * kBlock;
   for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n16; i += stride)
     p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// initial iterate of the forward trajectory with prescribed values: column
+// blockIdx.x (step n) gets g^n = sum_k pcoef[n][k] pres[k] at the prescribed
+// dofs and zero elsewhere; column 0 is x0 when given (else g^0 as above)
+__global__ __launch_bounds__(kBlock) void k_init_traj(double* __restrict__ X, int nn, int D1,
+                                                      const double* __restrict__ x0,
+                                                      const double* __restrict__ pres,
+                                                      const double* __restrict__ pcoef, int npres,
+                                                      const uint8_t* __restrict__ fixed) {
+  const int v = blockIdx.y * kBlock + threadIdx.x;
+  if (v >= nn) return;
+  const int n = blockIdx.x;
+  const size_t nd = size_t(nn) * D1;
+  double* out = X + size_t(n) * nd + size_t(v) * D1;
+  const unsigned fx = fixed[v];
+  for (int c = 0; c < D1; ++c) {
+    double val = 0.0;
+    if (n == 0 && x0) {
+      val = x0[size_t(v) * D1 + c];
+    } else if ((fx >> c) & 1u) {
+      for (int k = 0; k < npres; ++k) val += pcoef[size_t(n) * npres + k] * pres[k * nd + size_t(v) * D1 + c];
+    }
+    out[c] = val;
+  }
 }
 
 inline dim3 col_grid(int nc, int nn) { return dim3(nc, num_node_blocks(nn)); }
@@ -1427,7 +1540,7 @@ static void residual_dispatch(const LevelDev& L, const FineDev& F, const ColDesc
                               T* ru, T* rp, double* partials, int pstride, int wpc,
                               hipStream_t st) {
   if (DIM == 3 && wpc <= 0) wpc = kWgPerCu3dFine;
-  BIOT_LAUNCH_BALANCED_AL((k_residual<DIM, T, ADJ>), L.nn, nc, wpc, DIM == 3, st, L, F, cols, nc,
+  BIOT_LAUNCH_BALANCED_AL((k_residual<DIM, T, ADJ>), L.nact, nc, wpc, DIM == 3, st, L, F, cols, nc,
                           ru, rp, partials, pstride);
 }
 
@@ -1452,11 +1565,11 @@ static void cheb_dispatch(const LevelView<T>& L, bool is_A, const T* b, const T*
   constexpr bool aligned = DIM == 3 && C == 3;  // k_cheb's rows re-read per column group
   if (fine) {
     if (DIM == 3 && wpc <= 0) wpc = kWgPerCu3dFine;
-    BIOT_LAUNCH_BALANCED_AL((k_cheb<DIM, C, UPD, true, T>), L.nn, nc, wpc, aligned, st, L,
+    BIOT_LAUNCH_BALANCED_AL((k_cheb<DIM, C, UPD, true, T>), L.nact, nc, wpc, aligned, st, L,
                             int(is_A), b, xin, xout, d, nc, T(c1), T(c2), int(wd), dx, int(first),
                             T(it), cols, zu, omega);
   } else if constexpr (!UPD) {
-    BIOT_LAUNCH_BALANCED_AL((k_cheb<DIM, C, UPD, false, T>), L.nn, nc, wpc, aligned, st, L,
+    BIOT_LAUNCH_BALANCED_AL((k_cheb<DIM, C, UPD, false, T>), L.nact, nc, wpc, aligned, st, L,
                             int(is_A), b, xin, xout, d, nc, T(c1), T(c2), int(wd), dx, int(first),
                             T(it), cols, zu, omega);
   }
@@ -1487,8 +1600,7 @@ void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* 
 template <typename T>
 void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const T* x2, T* x4,
                   int nc, double c2a, double c1b, double c2b, int wpc, hipStream_t st) {
-  const int per_side = (L.n_cells + 1 + kPatchIn - 1) / kPatchIn;
-  const int patches = L.copies * per_side * per_side;
+  const int patches = L.npatch;
   // runs per patch: as many as keep about one wave of resident workgroups
   // (3 per CU) busy, at most one per column
   const int resident = 3 * num_cus(), groups = std::max(1, std::min(nc, resident / patches));
@@ -1507,18 +1619,18 @@ template <typename T>
 void launch_level_residual(int dim, int comps, const LevelView<T>& L, bool is_A, const T* b,
                            const T* x, T* r, int nc, int wpc, hipStream_t st) {
   if (dim == 2) {
-    if (comps == 1) BIOT_LAUNCH_BALANCED((k_level_residual<2, 1, T>), L.nn, nc, wpc, st, L, int(is_A), b, x, r, nc);
-    else BIOT_LAUNCH_BALANCED((k_level_residual<2, 2, T>), L.nn, nc, wpc, st, L, int(is_A), b, x, r, nc);
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_level_residual<2, 1, T>), L.nact, nc, wpc, st, L, int(is_A), b, x, r, nc);
+    else BIOT_LAUNCH_BALANCED((k_level_residual<2, 2, T>), L.nact, nc, wpc, st, L, int(is_A), b, x, r, nc);
   } else {
-    if (comps == 1) BIOT_LAUNCH_BALANCED((k_level_residual<3, 1, T>), L.nn, nc, wpc, st, L, int(is_A), b, x, r, nc);
-    else BIOT_LAUNCH_BALANCED_AL((k_level_residual<3, 3, T>), L.nn, nc, wpc, true, st, L, int(is_A), b, x, r, nc);
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_level_residual<3, 1, T>), L.nact, nc, wpc, st, L, int(is_A), b, x, r, nc);
+    else BIOT_LAUNCH_BALANCED_AL((k_level_residual<3, 3, T>), L.nact, nc, wpc, true, st, L, int(is_A), b, x, r, nc);
   }
 }
 
 template <typename T>
 void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc,
                      bool is_A, const T* rf, T* bc, int nc, hipStream_t st) {
-  const dim3 g = col_grid(nc, Lc.nn);
+  const dim3 g = col_grid(nc, Lc.nact);
   if (dim == 2) {
     if (comps == 1) hipLaunchKernelGGL((k_restrict<2, 1, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, nc);
     else hipLaunchKernelGGL((k_restrict<2, 2, T>), g, dim3(kBlock), 0, st, Lf, Lc, int(is_A), rf, bc, nc);
@@ -1532,11 +1644,11 @@ template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
                     const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st) {
   if (dim == 2) {
-    if (comps == 1) BIOT_LAUNCH_BALANCED((k_prolong<2, 1, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
-    else BIOT_LAUNCH_BALANCED((k_prolong<2, 2, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_prolong<2, 1, T>), Lf.nact, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
+    else BIOT_LAUNCH_BALANCED((k_prolong<2, 2, T>), Lf.nact, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
   } else {
-    if (comps == 1) BIOT_LAUNCH_BALANCED((k_prolong<3, 1, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
-    else BIOT_LAUNCH_BALANCED((k_prolong<3, 3, T>), Lf.nn, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
+    if (comps == 1) BIOT_LAUNCH_BALANCED((k_prolong<3, 1, T>), Lf.nact, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
+    else BIOT_LAUNCH_BALANCED((k_prolong<3, 3, T>), Lf.nact, nc, wpc, st, Lf, Lc, int(is_A), xin, xc, xout, nc);
   }
 }
 
@@ -1567,36 +1679,35 @@ size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes, int 
 }
 
 template <typename T>
-void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T* x, int nc,
+void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, int nc, size_t lds,
                         hipStream_t st) {
-  int nnl[kTailMaxLevels];
-  for (int i = 0; i < TD.nlev; ++i) nnl[i] = TD.L[i].nreal;
-  const size_t lds = tail_lds_bytes(nnl, TD.nlev, comps, int(sizeof(T)), TD.degree);
-  const dim3 g(nc * TD.L[0].copies);
+  const dim3 g(nc * TD.copies);
   if (dim == 2) {
     const dim3 tb(tail::block<2>());
-    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T>), g, tb, lds, st, TD, b, x);
-    else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T>), g, tb, lds, st, TD, b, x);
+    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T>), g, tb, lds, st, TD);
+    else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T>), g, tb, lds, st, TD);
   } else {
     const dim3 tb(tail::block<3>());
-    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<3, 1, T>), g, tb, lds, st, TD, b, x);
-    else hipLaunchKernelGGL((k_vcycle_tail<3, 3, T>), g, tb, lds, st, TD, b, x);
+    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<3, 1, T>), g, tb, lds, st, TD);
+    else hipLaunchKernelGGL((k_vcycle_tail<3, 3, T>), g, tb, lds, st, TD);
   }
 }
 
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
                    T* t, int nc, int wpc, hipStream_t st) {
-  if (dim == 2) BIOT_LAUNCH_BALANCED((k_pstage<2, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, nc);
-  else BIOT_LAUNCH_BALANCED((k_pstage<3, T>), L.nn, nc, wpc, st, L, Bt, int(p1), zu, rp, t, nc);
+  if (dim == 2) BIOT_LAUNCH_BALANCED((k_pstage<2, T>), L.nact, nc, wpc, st, L, Bt, int(p1), zu, rp, t, nc);
+  else BIOT_LAUNCH_BALANCED((k_pstage<3, T>), L.nact, nc, wpc, st, L, Bt, int(p1), zu, rp, t, nc);
 }
 
 template <typename T>
 void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* zp, double omega,
-                   int nc, hipStream_t st) {
+                   int nc, const int32_t* csteps, const int32_t* bcopy, hipStream_t st) {
   const dim3 g = col_grid(nc, nn);
-  if (dim == 2) hipLaunchKernelGGL((k_update<2, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
-  else hipLaunchKernelGGL((k_update<3, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega);
+  if (dim == 2)
+    hipLaunchKernelGGL((k_update<2, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega, csteps, bcopy);
+  else
+    hipLaunchKernelGGL((k_update<3, T>), g, dim3(kBlock), 0, st, nn, cols, zu, zp, omega, csteps, bcopy);
 }
 
 template <typename T>
@@ -1613,6 +1724,12 @@ void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, h
   else hipLaunchKernelGGL((k_pack<3, T>), g, dim3(kBlock), 0, st, nn, zu, zp, Z);
 }
 
+void launch_init_traj(double* X, int ncols, int nn, int D1, const double* x0, const double* pres,
+                      const double* pcoef, int npres, const uint8_t* fixed, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_traj, col_grid(ncols, nn), dim3(kBlock), 0, st, X, nn, D1, x0, pres,
+                     pcoef, npres, fixed);
+}
+
 void launch_zero(void* p, size_t bytes, hipStream_t st) {
   const size_t n16 = bytes / 16;
   if (n16 == 0) return;
@@ -1620,9 +1737,9 @@ void launch_zero(void* p, size_t bytes, hipStream_t st) {
   hipLaunchKernelGGL(k_zero16, dim3(grid), dim3(kBlock), 0, st, static_cast<uint4*>(p), n16);
 }
 
-void launch_reduce_norms(const double* partials, int bpc, int copies, int pstride, double* norms,
-                         int nc, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_norms, dim3(nc * copies), dim3(kBlock), 0, st, partials, bpc, copies,
+void launch_reduce_norms(const double* partials, const int32_t* cbase, int copies, int pstride,
+                         double* norms, int nc, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_norms, dim3(nc * copies), dim3(kBlock), 0, st, partials, cbase, copies,
                      pstride, norms);
 }
 
@@ -1649,11 +1766,11 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
   template void launch_prolong<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,      \
                                   const T*, const T*, T*, int, int, hipStream_t);                 \
   template void launch_coarse_solve<T>(int, int, int, const T*, const T*, T*, int, hipStream_t); \
-  template void launch_vcycle_tail<T>(int, int, const TailDev<T>&, const T*, T*, int, hipStream_t); \
+  template void launch_vcycle_tail<T>(int, int, const TailDev<T>&, int, size_t, hipStream_t);     \
   template void launch_pstage<T>(int, const LevelView<T>&, const T*, bool, const T*, const T*,   \
                                  T*, int, int, hipStream_t);                                      \
   template void launch_update<T>(int, int, const ColDesc*, const T*, const T*, double, int,      \
-                                 hipStream_t);                                                    \
+                                 const int32_t*, const int32_t*, hipStream_t);                    \
   template void launch_unpack<T>(int, int, const double*, T*, T*, int, hipStream_t);             \
   template void launch_pack<T>(int, int, const T*, const T*, double*, int, hipStream_t);
 

@@ -8,15 +8,35 @@
 namespace biot {
 
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
+// fused post-smoothing patches: 16 x 16 nodes, stepping by the 14 x 14 interior
+constexpr int kPatchInterior = 14;
 
 // One multigrid level on the device (node-blocked ELL, see setup.hpp), with
 // operator values of type T (double, or float for the mixed-precision
 // preconditioner).
+struct ColDesc;
+
 template <typename T>
 struct LevelView {
   int nn, W, n_cells;
   int copies, nn1, nreal;  // disconnected copies of the grid (samples of a batch),
                            // nodes per copy with padding, grid nodes per copy
+                           // (those of copy 0 when the copies differ)
+  // Copies (samples) may be grids of different sizes, largest first.  A launch
+  // works on the first `nact` nodes (whole copies); vectors keep the stride nn.
+  int nact;
+  const int32_t* cbase;   // [copies+1] first node of each copy (multiples of 256)
+  const int32_t* ccells;  // [copies] cells per side of each copy
+  const int32_t* bcopy;   // [nn/256] copy of each node block
+  // steps of each copy and, when set, the launch's column descriptors: column
+  // c is skipped for copy cp when act[c].step > csteps[cp] (the sample has
+  // fewer steps); the active columns of a launch are contiguous for each copy
+  const int32_t* csteps;
+  const ColDesc* act;
+  // fused post-smoothing patches of this level (k_post2): patch p covers
+  // patch ptab[2p+1] of copy ptab[2p]; npatch of them (whole copies, like nact)
+  const int32_t* ptab;
+  int npatch;
   const int32_t* nbr;    // [W][nn]
   const T* A;            // [W][dim*dim][nn]
   const T* S;            // [W][nn]
@@ -33,7 +53,8 @@ struct FineDev {
   const double* B;      // [W][dim][nn]
   const double* Bt;     // [W][dim][nn]
   const double* Cb;     // [W][nn]
-  const double* F;      // [nn][dim+1]
+  const double* F;      // load terms [nt][nn][dim+1] (zero at prescribed dofs)
+  int nt;               // number of load terms (0 in the adjoint recursion)
   const double* gload;  // adjoint only: pressure-row load [N][nn] per column step
 };
 
@@ -43,7 +64,9 @@ struct ColDesc {
   const double* xprev;  // coupling source X^{n-1,*}
   double* xout;         // X^{n,m}
   double* xout2;        // optional second copy (may be null)
-  double coef;          // load multiplier of step n
+  const double* tc;     // load-term multipliers of step n: f^n = sum_j tc[j] F_j
+  double c0;            // tc[0], kept here so that kernels read it with the
+                        // descriptor (one scalar load) rather than through tc
   int step;             // n
   int pad;
 };
@@ -106,16 +129,26 @@ void launch_coarse_solve(int n, int stride, int copies, const T* Minv, const T* 
 // right-hand side b (no first Chebyshev step yet) is read and whose V-cycle
 // result is written to x; L[nlev-1] is the densely solved coarsest level.
 constexpr int kTailMaxLevels = 8;
+constexpr int kMaxLevels = 16;
 // LDS budget of the fused V-cycle tail: gfx950's 160 KB per workgroup (capped
 // at bind by what the device reports)
 constexpr size_t kTailMaxLds = 160 * 1024;
+// the tail of one copy: its levels t0 .. t0+nlev-1 (global level numbers), the
+// LDS offset (in values) of each of them, and the offset of its dense inverse
+struct TailCopy {
+  int t0, nlev;
+  int off[kTailMaxLevels];
+  long long moff;
+};
 template <typename T>
 struct TailDev {
-  int nlev, degree;
-  LevelView<T> L[kTailMaxLevels];
-  double theta[kTailMaxLevels], delta[kTailMaxLevels], sigma[kTailMaxLevels];
-  int off[kTailMaxLevels];  // LDS offset (in values) of each level's vectors
+  int degree, copies;             // copies with a tail (all copies of the handle)
+  LevelView<T> L[kMaxLevels];     // every level of the hierarchy
+  double theta[kMaxLevels], delta[kMaxLevels], sigma[kMaxLevels];
+  const TailCopy* tc;             // [copies]
   const T* Minv;
+  const T* b[kMaxLevels];         // per level: right-hand sides (read at a copy's t0)
+  T* x[kMaxLevels];               // per level: results (written at a copy's t0)
 };
 // LDS vectors per (non-coarsest) tail level for a smoother degree, and the
 // tail's LDS bytes
@@ -123,28 +156,35 @@ int tail_vectors(int degree);
 // threads of a tail workgroup (one workgroup per column and sample copy)
 int tail_block_threads(int dim);
 size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes, int degree);
+// one workgroup per (column, copy with a tail); each copy reads TD.b and
+// writes TD.x at its own first tail level; `lds` = the largest copy's bytes
 template <typename T>
-void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, const T* b, T* x, int nc,
+void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, int nc, size_t lds,
                         hipStream_t st);
 template <typename T>
 void launch_pstage(int dim, const LevelView<T>& L, const T* Bt, bool p1, const T* zu, const T* rp,
                    T* t, int nc, int wpc, hipStream_t st);
+// csteps/bcopy (may be null): columns past a copy's steps are skipped
 template <typename T>
 void launch_update(int dim, int nn, const ColDesc* cols, const T* zu, const T* zp, double omega,
-                   int nc, hipStream_t st);
+                   int nc, const int32_t* csteps, const int32_t* bcopy, hipStream_t st);
 template <typename T>
 void launch_unpack(int dim, int nn, const double* X, T* ru, T* rp, int nc, hipStream_t st);
 template <typename T>
 void launch_pack(int dim, int nn, const T* zu, const T* zp, double* Z, int nc, hipStream_t st);
 
+// forward initial iterate with prescribed values (k_init_traj): columns
+// 0..ncols-1 of X; x0 may be null
+void launch_init_traj(double* X, int ncols, int nn, int D1, const double* x0, const double* pres,
+                      const double* pcoef, int npres, const uint8_t* fixed, hipStream_t st);
 // zeroes `bytes` (a multiple of 16; p 16-byte aligned) with a fill kernel, which
 // unlike a memset node may sit in a captured graph
 void launch_zero(void* p, size_t bytes, hipStream_t st);
 
-// norms[c][copy][4] = sums of the block partials of each copy (blocks of a copy
-// are contiguous: bpc = blocks per copy)
-void launch_reduce_norms(const double* partials, int bpc, int copies, int partial_stride,
-                         double* norms, int nc, hipStream_t st);
+// norms[c][copy][4] = sums of the block partials of each copy (the blocks of
+// copy cp are those of nodes cbase[cp] .. cbase[cp+1]-1)
+void launch_reduce_norms(const double* partials, const int32_t* cbase, int copies,
+                         int partial_stride, double* norms, int nc, hipStream_t st);
 void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const double* X,
                            double* Y, int nc, hipStream_t st);
 

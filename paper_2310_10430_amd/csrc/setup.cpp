@@ -46,12 +46,19 @@ struct Grid {
   }
 };
 
-void init_level(HostLevel& L, const Grid& g, int dim) {
-  L.n_cells = g.n;
-  L.nn = g.nn();
+void set_single_copy(HostLevel& L) {
   L.copies = 1;
   L.nn1 = L.nn;
   L.nreal = L.nn;
+  L.cbase = {0, L.nn};
+  L.ccells = {L.n_cells};
+  L.bcopy.assign(size_t((L.nn + 255) / 256), 0);
+}
+
+void init_level(HostLevel& L, const Grid& g, int dim) {
+  L.n_cells = g.n;
+  L.nn = g.nn();
+  set_single_copy(L);
   L.W = g.W();
   L.nbr.assign(size_t(L.W) * L.nn, 0);
   for (int v = 0; v < L.nn; ++v) {
@@ -358,7 +365,27 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
   if (!(mat.stab_h >= 0) || !std::isfinite(mat.alpha)) return "bad alpha or stab_h";
   if (ld.n_facets < 0 || (ld.n_facets > 0 && (!ld.facet_nodes || !ld.traction)))
     return "bad load facets";
-  if (!ld.coef) return "null load coefficients";
+  if (ld.n_facets > 0 && !ld.coef) return "null load coefficients";
+  if (ld.n_terms < 0 || ld.n_terms > kMaxUserTerms) return "n_terms must be in 0..8";
+  if (ld.n_terms > 0 && (!ld.terms || !ld.term_coef)) return "null load terms or term coefficients";
+  if (ld.n_prescribed < 0 || ld.n_prescribed > kMaxPrescribed) return "n_prescribed must be in 0..3";
+  if (ld.n_prescribed > 0 && (!ld.prescribed || !ld.prescribed_coef))
+    return "null prescribed values or their coefficients";
+  {
+    const size_t nd = size_t(m.nn) * (dim + 1), ns = size_t(n_steps) + 1;
+    auto finite = [](const double* a, size_t n) {
+      for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+      return true;
+    };
+    if ((ld.n_facets > 0 && !finite(ld.coef, ns)) ||
+        (ld.n_terms > 0 && (!finite(ld.terms, nd * ld.n_terms) ||
+                            !finite(ld.term_coef, ns * ld.n_terms))) ||
+        (ld.n_prescribed > 0 && (!finite(ld.prescribed, nd * ld.n_prescribed) ||
+                                 !finite(ld.prescribed_coef, ns * ld.n_prescribed))) ||
+        (ld.x0 && !finite(ld.x0, nd)))
+      return "non-finite load, prescribed value, coefficient or initial state";
+  }
   if (opt.cheb_degree < 1 || opt.cheb_degree > 8) return "cheb_degree must be in 1..8";
   if (!(opt.cheb_ratio > 1.0)) return "cheb_ratio must be > 1";
 
@@ -468,6 +495,87 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
     }
   }
   for (size_t i = 0; i < L.S.size(); ++i) L.S[i] = dt * CK[i] + L.Cb[i];
+  // Prescribed values are lifted into the right-hand side with the operators
+  // as assembled (before the elimination below): on the free rows, step n's
+  // equation AA X^n = A' X^{n-1} + f^n holds with X^n = (x_free, g^n), so
+  //   AA_ff x_free = f^n_f - (AA g^n)_f + (A' g^{n-1})_f + A'_ff X^{n-1}_free.
+  // Each prescribed term k (g^n = sum_k d_k(n) G_k) gives two load terms,
+  // -AA G_k with coefficient d_k(n) and A' G_k with d_k(n-1); an X^0 whose
+  // prescribed part differs from g^0 adds A' (X^0 - g^0) at step 1 only.
+  std::vector<std::vector<double>> tv;   // load terms [nn][dim+1]
+  std::vector<std::vector<double>> tc;   // their coefficients [n_steps+1]
+  const int D1 = dim + 1;
+  const size_t nd = size_t(m.nn) * D1;
+  auto fixed_dof = [&](int v, int c) { return ((L.fixed[v] >> c) & 1) != 0; };
+  // y = AA g and yp = A' g with the unreduced level-0 blocks
+  auto apply_full = [&](const std::vector<double>& g, std::vector<double>& y,
+                        std::vector<double>& yp) {
+    y.assign(nd, 0.0);
+    yp.assign(nd, 0.0);
+    for (int v = 0; v < L.nn; ++v)
+      for (int sl = 0; sl < L.W; ++sl) {
+        const int w = L.nbr[size_t(sl) * L.nn + v];
+        const double* gw = &g[size_t(w) * D1];
+        for (int a = 0; a < dim; ++a) {
+          double acc = L.B[(size_t(sl) * dim + a) * L.nn + v] * gw[dim];
+          for (int b = 0; b < dim; ++b) acc += Aat(L, dim, sl, a, b, v) * gw[b];
+          y[size_t(v) * D1 + a] += acc;
+        }
+        double btg = 0.0;
+        for (int c = 0; c < dim; ++c) btg += L.Bt[(size_t(sl) * dim + c) * L.nn + v] * gw[c];
+        y[size_t(v) * D1 + dim] += btg - L.S[size_t(sl) * L.nn + v] * gw[dim];
+        yp[size_t(v) * D1 + dim] += btg - L.Cb[size_t(sl) * L.nn + v] * gw[dim];
+      }
+  };
+  auto masked = [&](const double* src, bool keep_fixed) {  // keep only fixed or only free dofs
+    std::vector<double> out(nd, 0.0);
+    for (int v = 0; v < m.nn; ++v)
+      for (int c = 0; c < D1; ++c)
+        if (fixed_dof(v, c) == keep_fixed) out[size_t(v) * D1 + c] = src[size_t(v) * D1 + c];
+    return out;
+  };
+  const size_t ns = size_t(n_steps) + 1;
+  P.npres = ld.n_prescribed;
+  P.pres.assign(nd * P.npres, 0.0);
+  P.pcoef.assign(ns * P.npres, 0.0);
+  std::vector<double> gz(nd, 0.0);  // g^0
+  for (int k = 0; k < P.npres; ++k) {
+    std::vector<double> G = masked(ld.prescribed + nd * k, true);
+    std::copy(G.begin(), G.end(), P.pres.begin() + nd * k);
+    std::vector<double> d(ns);
+    for (size_t n = 0; n < ns; ++n) {
+      d[n] = ld.prescribed_coef[n * P.npres + k];
+      P.pcoef[n * P.npres + k] = d[n];
+    }
+    for (size_t i = 0; i < nd; ++i) gz[i] += d[0] * G[i];
+    std::vector<double> y, yp;
+    apply_full(G, y, yp);
+    for (double& x : y) x = -x;
+    std::vector<double> dprev(ns, 0.0);
+    for (size_t n = 1; n < ns; ++n) dprev[n] = d[n - 1];
+    tv.push_back(masked(y.data(), false));
+    tc.push_back(d);
+    tv.push_back(masked(yp.data(), false));
+    tc.push_back(dprev);
+  }
+  P.x0.clear();
+  if (ld.x0) {
+    P.x0.assign(ld.x0, ld.x0 + nd);
+    std::vector<double> dx = masked(ld.x0, true);
+    bool nz = false;
+    for (size_t i = 0; i < nd; ++i) {
+      dx[i] -= gz[i];
+      nz = nz || dx[i] != 0.0;
+    }
+    if (nz && n_steps >= 1) {
+      std::vector<double> y, yp;
+      apply_full(dx, y, yp);
+      std::vector<double> c1(ns, 0.0);
+      c1[1] = 1.0;
+      tv.push_back(masked(yp.data(), false));
+      tc.push_back(c1);
+    }
+  }
   // prescribed dofs: zero rows/columns of every block touching them
   for (int v = 0; v < L.nn; ++v)
     for (int s = 0; s < L.W; ++s) {
@@ -511,7 +619,32 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
   for (int v = 0; v < m.nn; ++v)
     for (int c = 0; c < dim; ++c)
       if ((L.fixed[v] >> c) & 1) P.F[size_t(v) * (dim + 1) + c] = 0.0;
-  P.coef.assign(ld.coef, ld.coef + n_steps + 1);
+  // internal load terms: the traction first (kept in registers by the
+  // residual kernel), then the caller's terms, then the lifting terms
+  {
+    std::vector<std::vector<double>> all_v, all_c;
+    if (ld.n_facets > 0) {
+      all_v.push_back(P.F);
+      all_c.emplace_back(ld.coef, ld.coef + ns);
+    }
+    for (int j = 0; j < ld.n_terms; ++j) {
+      all_v.push_back(masked(ld.terms + nd * j, false));
+      std::vector<double> c(ns);
+      for (size_t n = 0; n < ns; ++n) c[n] = ld.term_coef[n * ld.n_terms + j];
+      all_c.push_back(std::move(c));
+    }
+    for (size_t j = 0; j < tv.size(); ++j) {
+      all_v.push_back(std::move(tv[j]));
+      all_c.push_back(std::move(tc[j]));
+    }
+    P.nterms = int(all_v.size());
+    P.terms.assign(nd * P.nterms, 0.0);
+    P.tcoef.assign(ns * P.nterms, 0.0);
+    for (int j = 0; j < P.nterms; ++j) {
+      std::copy(all_v[j].begin(), all_v[j].end(), P.terms.begin() + nd * j);
+      for (size_t n = 0; n < ns; ++n) P.tcoef[n * P.nterms + j] = all_c[j][n];
+    }
+  }
 
   // multigrid hierarchy: halve while even and at least min_cells remain
   std::vector<Grid> grids{g0};
@@ -557,6 +690,11 @@ std::string build_problem(const MeshIn& m, const MaterialsIn& mat, const LoadIn&
     if (!invert(Ms, ns)) return "coarsest pressure operator is singular";
     P.coarseSinv.swap(Ms);
   }
+  P.sample_of = {0};
+  P.csteps = {n_steps};
+  P.clast = {int(P.levels.size()) - 1};
+  P.cAoff = {0};
+  P.cSoff = {0};
   return "";
 }
 
@@ -565,33 +703,65 @@ std::string concat_problems(const std::vector<HostProblem>& parts, int pad, Host
   const HostProblem& p0 = parts[0];
   const int S = int(parts.size()), dim = p0.dim, D1 = dim + 1;
   for (const HostProblem& q : parts) {
-    if (q.dim != dim || q.nn != p0.nn || q.levels.size() != p0.levels.size())
-      return "samples of a batch must share the mesh";
-    const size_t nmin = std::min(q.coef.size(), p0.coef.size());
+    if (q.dim != dim || q.levels.empty() || q.levels[0].copies != 1)
+      return "samples of a batch must be single problems of the same dimension";
+    if (q.nterms != p0.nterms || q.npres != p0.npres || q.x0.empty() != p0.x0.empty())
+      return "samples of a batch must have the same load, prescribed-value and initial-state structure";
+    const size_t nmin = std::min(q.tcoef.size(), p0.tcoef.size());
     for (size_t n = 0; n < nmin; ++n)
-      if (q.coef[n] != p0.coef[n]) return "load multipliers of a batch must agree step by step";
+      if (q.tcoef[n] != p0.tcoef[n]) return "load multipliers of a batch must agree step by step";
+    const size_t pmin = std::min(q.pcoef.size(), p0.pcoef.size());
+    for (size_t n = 0; n < pmin; ++n)
+      if (q.pcoef[n] != p0.pcoef[n])
+        return "prescribed-value multipliers of a batch must agree step by step";
   }
+  // copies: largest grids first (stable); a deeper hierarchy must not belong
+  // to a smaller grid, so that the copies of every level form a prefix
+  std::vector<int> order(S);
+  for (int i = 0; i < S; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return parts[a].levels[0].n_cells > parts[b].levels[0].n_cells;
+  });
+  for (int c = 1; c < S; ++c)
+    if (parts[order[c]].levels.size() > parts[order[c - 1]].levels.size())
+      return "samples of a batch: a smaller grid has a deeper multigrid hierarchy";
   P = HostProblem{};
   P.dim = dim;
   P.alpha = p0.alpha;
   P.dt = p0.dt;
+  P.nterms = p0.nterms;
+  P.npres = p0.npres;
   int nmax = 0;
   for (const HostProblem& q : parts) {
     nmax = std::max(nmax, q.n_steps);
-    if (q.coef.size() > P.coef.size()) P.coef = q.coef;
+    if (q.tcoef.size() > P.tcoef.size()) P.tcoef = q.tcoef;
+    if (q.pcoef.size() > P.pcoef.size()) P.pcoef = q.pcoef;
   }
   P.n_steps = nmax;
   const size_t dd = size_t(dim) * dim;
-  for (size_t l = 0; l < p0.levels.size(); ++l) {
-    const HostLevel& a = p0.levels[l];
+  const size_t nlev = parts[order[0]].levels.size();
+  for (size_t l = 0; l < nlev; ++l) {
+    int k = 0;  // copies with a level l
+    while (k < S && parts[order[k]].levels.size() > l) ++k;
+    const HostLevel& a0 = parts[order[0]].levels[l];
     HostLevel L;
-    L.n_cells = a.n_cells;
-    L.W = a.W;
-    L.copies = S;
-    L.nreal = a.nn;
-    L.nn1 = (a.nn + pad - 1) / pad * pad;
-    L.nn = S * L.nn1;
-    const int W = L.W, nn = L.nn, n1 = a.nn;
+    L.W = a0.W;
+    L.copies = k;
+    L.cbase.assign(size_t(k) + 1, 0);
+    L.ccells.assign(size_t(k), 0);
+    for (int c = 0; c < k; ++c) {
+      const HostLevel& q = parts[order[c]].levels[l];
+      L.ccells[c] = q.n_cells;
+      L.cbase[c + 1] = L.cbase[c] + (q.nn + pad - 1) / pad * pad;
+    }
+    L.nn = L.cbase[k];
+    L.n_cells = a0.n_cells;
+    L.nreal = a0.nn;
+    L.nn1 = L.cbase[1];
+    L.bcopy.assign(size_t((L.nn + 255) / 256), 0);
+    for (int c = 0; c < k; ++c)
+      for (int b = L.cbase[c] / 256; b < L.cbase[c + 1] / 256; ++b) L.bcopy[b] = c;
+    const int W = L.W, nn = L.nn;
     L.nbr.assign(size_t(W) * nn, 0);
     L.A.assign(size_t(W) * dd * nn, 0.0);
     L.S.assign(size_t(W) * nn, 0.0);
@@ -604,10 +774,10 @@ std::string concat_problems(const std::vector<HostProblem>& parts, int pad, Host
       L.Bt.assign(size_t(W) * dim * nn, 0.0);
       L.Cb.assign(size_t(W) * nn, 0.0);
     }
-    for (int c = 0; c < S; ++c) {
-      const HostLevel& q = parts[c].levels[l];
-      const int base = c * L.nn1;
-      for (int v = 0; v < L.nn1; ++v) {
+    for (int c = 0; c < k; ++c) {
+      const HostLevel& q = parts[order[c]].levels[l];
+      const int base = L.cbase[c], n1 = q.nn;
+      for (int v = 0; v < L.cbase[c + 1] - base; ++v) {
         const int g = base + v;
         const bool real = v < n1;
         for (int s2 = 0; s2 < W; ++s2) {
@@ -616,9 +786,9 @@ std::string concat_problems(const std::vector<HostProblem>& parts, int pad, Host
             L.A[(s2 * dd + e) * nn + g] = real ? q.A[(s2 * dd + e) * n1 + v] : 0.0;
           L.S[size_t(s2) * nn + g] = real ? q.S[size_t(s2) * n1 + v] : 0.0;
           if (fine)
-            for (int k = 0; k < dim; ++k) {
-              L.B[(size_t(s2) * dim + k) * nn + g] = real ? q.B[(size_t(s2) * dim + k) * n1 + v] : 0.0;
-              L.Bt[(size_t(s2) * dim + k) * nn + g] = real ? q.Bt[(size_t(s2) * dim + k) * n1 + v] : 0.0;
+            for (int kk = 0; kk < dim; ++kk) {
+              L.B[(size_t(s2) * dim + kk) * nn + g] = real ? q.B[(size_t(s2) * dim + kk) * n1 + v] : 0.0;
+              L.Bt[(size_t(s2) * dim + kk) * nn + g] = real ? q.Bt[(size_t(s2) * dim + kk) * n1 + v] : 0.0;
             }
           if (fine) L.Cb[size_t(s2) * nn + g] = real ? q.Cb[size_t(s2) * n1 + v] : 0.0;
         }
@@ -628,22 +798,45 @@ std::string concat_problems(const std::vector<HostProblem>& parts, int pad, Host
         if (real) {
           L.fixed[g] = q.fixed[v];
         } else {
-          for (int k = 0; k < dim; ++k) L.A[(k * dim + k) * size_t(nn) + g] = 1.0;  // slot 0
+          for (int kk = 0; kk < dim; ++kk) L.A[(kk * dim + kk) * size_t(nn) + g] = 1.0;  // slot 0
           L.S[g] = 1.0;
         }
       }
-      L.lmaxA = std::max(L.lmaxA, q.lmaxA);
-      L.lmaxS = std::max(L.lmaxS, q.lmaxS);
+      // spectral bounds of the levels that smooth (not a copy's coarsest)
+      if (l + 1 < parts[order[c]].levels.size()) {
+        L.lmaxA = std::max(L.lmaxA, q.lmaxA);
+        L.lmaxS = std::max(L.lmaxS, q.lmaxS);
+      }
     }
     P.levels.push_back(std::move(L));
   }
   const HostLevel& L0 = P.levels[0];
   P.nn = L0.nn;
   P.ne = 0;
-  P.F.assign(size_t(L0.nn) * D1, 0.0);
-  for (int c = 0; c < S; ++c)
-    std::copy(parts[c].F.begin(), parts[c].F.end(), P.F.begin() + size_t(c) * L0.nn1 * D1);
-  for (const HostProblem& q : parts) {
+  // per-copy node-major vectors of every term, side by side (padding nodes zero)
+  auto join = [&](int count, std::vector<double> HostProblem::*field, std::vector<double>& out) {
+    const size_t nd = size_t(L0.nn) * D1;
+    out.assign(nd * count, 0.0);
+    for (int j = 0; j < count; ++j)
+      for (int c = 0; c < S; ++c) {
+        const HostProblem& q = parts[order[c]];
+        const std::vector<double>& src = q.*field;
+        const size_t nd1 = size_t(q.nn) * D1;
+        std::copy(src.begin() + nd1 * j, src.begin() + nd1 * (j + 1),
+                  out.begin() + nd * j + size_t(L0.cbase[c]) * D1);
+      }
+  };
+  join(1, &HostProblem::F, P.F);
+  join(P.nterms, &HostProblem::terms, P.terms);
+  join(P.npres, &HostProblem::pres, P.pres);
+  if (!p0.x0.empty()) join(1, &HostProblem::x0, P.x0);
+  for (int c = 0; c < S; ++c) {
+    const HostProblem& q = parts[order[c]];
+    P.sample_of.push_back(order[c]);
+    P.csteps.push_back(q.n_steps);
+    P.clast.push_back(int(q.levels.size()) - 1);
+    P.cAoff.push_back(int64_t(P.coarseAinv.size()));
+    P.cSoff.push_back(int64_t(P.coarseSinv.size()));
     P.coarseAinv.insert(P.coarseAinv.end(), q.coarseAinv.begin(), q.coarseAinv.end());
     P.coarseSinv.insert(P.coarseSinv.end(), q.coarseSinv.begin(), q.coarseSinv.end());
   }

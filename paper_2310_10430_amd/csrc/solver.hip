@@ -57,9 +57,14 @@ struct Prec {
   T* coarseS = nullptr;
   Field<T> fa, fs;
   T* rp = nullptr;
-  // fused coarse end of the V-cycles (k_vcycle_tail): first level, -1 if none
+  // fused coarse end of the V-cycles (k_vcycle_tail), per copy: 1 when every
+  // copy has one (-1: none has; the coarsest level is then its own launch)
   int tailA = -1, tailS = -1;
   TailDev<T> tdA{}, tdS{};
+  std::vector<TailCopy> tcA, tcS;     // host copies of the per-copy descriptors
+  size_t ldsA = 0, ldsS = 0;          // LDS bytes of a tail workgroup (largest copy)
+  // per level: copies (a prefix) that run the level as their own launches
+  std::vector<int> standA, standS;
 };
 
 struct ChebCoef {
@@ -76,8 +81,8 @@ struct Sched {
   int N = 0, cap = 0;                 // steps now / table capacity in steps
   double* T[2] = {nullptr, nullptr};
   int cur = 0;
-  std::vector<double> coef;           // [N+1] load multiplier per column
-  std::vector<int> gstep;             // [N+1] step number stored in descriptors
+  std::vector<int> gstep;             // [N+1] global step of each column (descriptors'
+                                      // step and load-coefficient row)
   std::vector<const double*> pin;     // [N+1]
   ColDesc* desc_jac[2] = {nullptr, nullptr};
   ColDesc* desc_k4[2] = {nullptr, nullptr};
@@ -91,6 +96,7 @@ struct Sched {
   // (the tables' contents may change between replays)
   std::vector<hipGraph_t> graph[2];
   std::vector<hipGraphExec_t> gexec[2];
+  double gbytes[2] = {0.0, 0.0};      // algorithmic bytes of one replay of a pass
   int graph_N = -1;
 };
 
@@ -111,7 +117,15 @@ struct biot_handle {
   char* ws = nullptr;
   uint64_t ws_need = 0;
   std::vector<LevelDev> L;       // FP64 levels (level 0 also feeds the residual)
+  std::vector<std::vector<int>> ppre;  // per level: fused post-smoothing patches of
+                                       // the first k copies, k = 0..copies
+  std::vector<std::vector<int32_t>> ptab_h;  // per level: (copy, patch) pairs
+  std::vector<int> copy_of;      // copy (node order) of each sample
   FineDev F{};
+  double* tcoef = nullptr;       // [N+1][nterms] load-term multipliers (device)
+  double* pres = nullptr;        // [npres][nn][dim+1] prescribed-value terms (device)
+  double* pcoef = nullptr;       // [N+1][npres]
+  double* x0 = nullptr;          // [nn][dim+1] initial state (device), if given
   Prec<double> pd;               // FP64 preconditioner (precision FP64)
   Prec<float> pf;                // FP32 preconditioner (precision MIXED)
   Sched fw;                      // forward problem (the trajectory of the ABI)
@@ -160,6 +174,9 @@ struct biot_handle {
   std::vector<Pending> pending;
   Acc acc[BIOT_PROBE_COUNT];
   int cur_copies = 0;  // columns of the current batch that also write a second copy
+  // algorithmic bytes (each launch's distinct global inputs and outputs, once)
+  // of every kernel enqueued on the handle's stream, replayed graphs included
+  double acct = 0.0;
   hipStream_t cap_stream = nullptr;  // stream used for graph capture
   // allocation-free preconditioner apply: the device the handle was bound on,
   // that device's address of the static scratch array, and host-side field
@@ -233,46 +250,90 @@ int scratch_address(biot_handle* h, int dev, char** out) {
   return BIOT_OK;
 }
 
-// The coarsest levels whose V-cycle vectors fit in the LDS of one workgroup
-// (kTailMaxLds, or less if the device allows less) run as one fused launch;
-// level 0 never does (its steps are fused with the residual and the update).
-// A level joins only if it has at most two nodes per tail thread: the tail runs
-// one workgroup per column, so a larger level is faster as its own launches,
-// which spread over the whole chip.
+// Buffer (0: x0, 1: x1) that holds a level's V-cycle result when the level
+// runs as its own launches (not the level-0 pressure field, which writes the
+// outer update): each smoothing step and the prolongation swap the iterates.
+int result_buffer(const biot_handle* h) {
+  const int deg = h->opt.cheb_degree;
+  int cur = 0;
+  for (int j = 2; j <= deg; ++j) cur ^= 1;  // pre-smoothing
+  cur ^= 1;                                 // coarse-grid correction
+  if (h->opt.fuse_post && deg == 2 && h->dim == 2) return cur ^ 1;
+  for (int j = 1; j <= deg; ++j) cur ^= 1;
+  return cur;
+}
+
+// The coarsest levels of a copy whose V-cycle vectors fit in the LDS of one
+// workgroup (kTailMaxLds, or less if the device allows less) run as one fused
+// launch; level 0 never does (its steps are fused with the residual and the
+// update).  A level joins only if it has at most two nodes per tail thread:
+// the tail runs one workgroup per column, so a larger level is faster as its
+// own launches, which spread over the whole chip.  Each copy (sample) gets its
+// own first tail level; either every copy has a tail or none has.
 template <typename T>
-void plan_tail(biot_handle* h, Prec<T>& p, bool is_A) {
-  const int last = h->nlev - 1, C = is_A ? h->dim : 1;
+void plan_tail(biot_handle* h, Bump& b, Prec<T>& p, bool is_A) {
+  const int C = is_A ? h->dim : 1;
+  const int copies = h->P.levels[0].copies;
   int& t = is_A ? p.tailA : p.tailS;
   TailDev<T>& td = is_A ? p.tdA : p.tdS;
-  t = -1;
-  for (int l = 1; l < last; ++l) {
-    const int n = last - l + 1;
-    if (n > kTailMaxLevels) continue;
-    if (h->P.levels[l].nreal > 2 * tail_block_threads(h->dim)) continue;
-    int nnl[kTailMaxLevels];
-    for (int i = 0; i < n; ++i) nnl[i] = h->P.levels[l + i].nreal;
-    if (tail_lds_bytes(nnl, n, C, int(sizeof(T)), h->opt.cheb_degree) >
-        std::min(kTailMaxLds, h->tail_lds))
-      continue;
-    t = l;
-    break;
+  std::vector<TailCopy>& tcs = is_A ? p.tcA : p.tcS;
+  size_t& lds = is_A ? p.ldsA : p.ldsS;
+  std::vector<int>& stand = is_A ? p.standA : p.standS;
+  const size_t budget = std::min(kTailMaxLds, h->tail_lds);
+  tcs.assign(copies, TailCopy{});
+  lds = 0;
+  int with = 0;
+  auto grid_nodes = [&](int cells) {
+    const int m = cells + 1;
+    return h->dim == 2 ? m * m : m * m * m;
+  };
+  for (int cp = 0; cp < copies; ++cp) {
+    const int last = h->P.clast[cp];
+    TailCopy& tc = tcs[cp];
+    tc.t0 = -1;
+    for (int l = 1; l < last; ++l) {
+      const int n = last - l + 1;
+      if (n > kTailMaxLevels) continue;
+      if (grid_nodes(h->P.levels[l].ccells[cp]) > 2 * tail_block_threads(h->dim)) continue;
+      int nnl[kTailMaxLevels];
+      for (int i = 0; i < n; ++i) nnl[i] = grid_nodes(h->P.levels[l + i].ccells[cp]);
+      const size_t bytes = tail_lds_bytes(nnl, n, C, int(sizeof(T)), h->opt.cheb_degree);
+      if (bytes > budget) continue;
+      tc.t0 = l;
+      tc.nlev = n;
+      int off = 0;
+      for (int i = 0; i < n; ++i) {
+        tc.off[i] = off;
+        off += nnl[i] * C * (i + 1 < n ? tail_vectors(h->opt.cheb_degree) : 2);
+      }
+      tc.moff = is_A ? h->P.cAoff[cp] : h->P.cSoff[cp];
+      lds = std::max(lds, bytes);
+      ++with;
+      break;
+    }
   }
-  if (t < 0) return;
-  td.nlev = last - t + 1;
+  t = (with > 0 && with == copies) ? 1 : -1;
+  // per level, the copies that run it as their own launches: with a tail, the
+  // levels above it; without, the levels above the copy's last one (which is
+  // then solved densely, when no copy runs that level as launches)
+  stand.assign(h->nlev, 0);
+  for (int l = 0; l < h->nlev; ++l)
+    for (int cp = 0; cp < copies; ++cp) {
+      const bool own = t > 0 ? l < tcs[cp].t0 : l < h->P.clast[cp];
+      if (own) stand[l] = cp + 1;
+    }
+  td = TailDev<T>{};
   td.degree = h->opt.cheb_degree;
-  for (int i = 0; i < td.nlev; ++i) {
-    td.L[i] = p.L[t + i];
-    const ChebCoef& cc = is_A ? h->chA[t + i] : h->chS[t + i];
-    td.theta[i] = cc.theta;
-    td.delta[i] = cc.delta;
-    td.sigma[i] = cc.sigma;
+  td.copies = copies;
+  for (int l = 0; l < h->nlev && l < kMaxLevels; ++l) {
+    td.L[l] = p.L[l];
+    const ChebCoef& cc = is_A ? h->chA[l] : h->chS[l];
+    td.theta[l] = cc.theta;
+    td.delta[l] = cc.delta;
+    td.sigma[l] = cc.sigma;
   }
   td.Minv = is_A ? p.coarseA : p.coarseS;
-  int off = 0;
-  for (int i = 0; i < td.nlev; ++i) {
-    td.off[i] = off;
-    off += h->P.levels[t + i].nreal * C * (i + 1 < td.nlev ? tail_vectors(td.degree) : 2);
-  }
+  td.tc = b.take<TailCopy>(copies);
 }
 
 template <typename T>
@@ -288,6 +349,14 @@ void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
     D.copies = H.copies;
     D.nn1 = H.nn1;
     D.nreal = H.nreal;
+    D.nact = H.nn;
+    D.cbase = h->L[l].cbase;
+    D.ccells = h->L[l].ccells;
+    D.bcopy = h->L[l].bcopy;
+    D.csteps = h->L[l].csteps;
+    D.act = nullptr;
+    D.ptab = h->L[l].ptab;
+    D.npatch = h->L[l].npatch;
     D.nbr = h->L[l].nbr;
     D.fixed = h->L[l].fixed;
     if constexpr (std::is_same<T, double>::value) {
@@ -328,8 +397,28 @@ void plan_prec(biot_handle* h, Bump& b, Prec<T>& p) {
     }
   }
   p.rp = b.take<T>(size_t(nc) * h->nn);
-  plan_tail(h, p, true);
-  plan_tail(h, p, false);
+  plan_tail(h, b, p, true);
+  plan_tail(h, b, p, false);
+}
+
+// fused post-smoothing patches (2D): per level, (copy, patch) for every patch
+// of every copy in copy order, and the patch count of the first k copies
+void build_patches(biot_handle* h) {
+  h->ppre.assign(h->nlev, {});
+  h->ptab_h.assign(h->nlev, {});
+  for (int l = 0; l < h->nlev; ++l) {
+    const HostLevel& H = h->P.levels[l];
+    std::vector<int>& pre = h->ppre[l];
+    pre.assign(size_t(H.copies) + 1, 0);
+    for (int c = 0; c < H.copies; ++c) {
+      const int per_side = h->dim == 2 ? (H.ccells[c] + 1 + kPatchInterior - 1) / kPatchInterior : 0;
+      for (int q = 0; q < per_side * per_side; ++q) {
+        h->ptab_h[l].push_back(c);
+        h->ptab_h[l].push_back(q);
+      }
+      pre[c + 1] = pre[c] + per_side * per_side;
+    }
+  }
 }
 
 void plan(biot_handle* h, char* base) {
@@ -344,6 +433,14 @@ void plan(biot_handle* h, char* base) {
     D.copies = H.copies;
     D.nn1 = H.nn1;
     D.nreal = H.nreal;
+    D.nact = H.nn;
+    D.cbase = b.take<int32_t>(H.cbase.size());
+    D.ccells = b.take<int32_t>(H.ccells.size());
+    D.bcopy = b.take<int32_t>(H.bcopy.size());
+    D.csteps = l == 0 ? b.take<int32_t>(h->P.csteps.size()) : h->L[0].csteps;
+    D.act = nullptr;
+    D.ptab = b.take<int32_t>(h->ptab_h[l].size());
+    D.npatch = int(h->ptab_h[l].size() / 2);
     D.nbr = b.take<int32_t>(H.nbr.size());
     D.A = b.take<double>(H.A.size());
     D.S = b.take<double>(H.S.size());
@@ -357,8 +454,13 @@ void plan(biot_handle* h, char* base) {
   h->F.B = b.take<double>(H0.B.size());
   h->F.Bt = b.take<double>(H0.Bt.size());
   h->F.Cb = b.take<double>(H0.Cb.size());
-  h->F.F = b.take<double>(h->P.F.size());
+  h->F.F = b.take<double>(h->P.terms.size());
+  h->F.nt = h->P.nterms;
   h->F.gload = nullptr;
+  h->tcoef = b.take<double>(h->P.tcoef.size());
+  h->pres = b.take<double>(h->P.pres.size());
+  h->pcoef = b.take<double>(h->P.pcoef.size());
+  h->x0 = h->P.x0.empty() ? nullptr : b.take<double>(h->P.x0.size());
   const bool wave = h->opt.schedule == BIOT_SCHED_WAVEFRONT;
   auto traj_pair = [&](Sched& S, int cap) {
     S.T[0] = b.take<double>(size_t(cap + 1) * h->col);
@@ -433,6 +535,12 @@ void plan(biot_handle* h, char* base) {
   h->ws_need = b.off + 256;
 }
 
+// multiplier of load term 0 at column n of a schedule (0 for the adjoint)
+double term0(const biot_handle* h, const Sched& S, int n) {
+  if (S.adj || h->P.nterms == 0) return 0.0;
+  return h->P.tcoef[size_t(S.gstep[n]) * h->P.nterms];
+}
+
 // Wavefront table of a pass of depth d (<= the configured depth) reading
 // trajectory T[c] and writing T[1-c]: at wave w, slot s updates step w - s
 // from its iterate of sweep s to sweep s+1.  Slot s reads its input from slot
@@ -461,7 +569,8 @@ void wave_table(biot_handle* h, const Sched& S, int c, int d, std::vector<ColDes
       e.xprev = S.pin[n] ? S.pin[n] : (n == 1 ? Tin : slot(s, (w - 1) & 1));
       e.xout = slot(s, w & 1);
       e.xout2 = s == d - 1 ? Tout + n * col : nullptr;
-      e.coef = S.coef[n];
+      e.tc = S.adj ? nullptr : h->tcoef + size_t(S.gstep[n]) * h->P.nterms;
+      e.c0 = term0(h, S, n);
       e.step = S.gstep[n];
       tab.push_back(e);
       ++k;
@@ -484,7 +593,8 @@ void build_tables(biot_handle* h, Sched& S) {
       d.xprev = S.pin[n] ? S.pin[n] : Tin + (n - 1) * col;
       d.xout = Tout + n * col;
       d.xout2 = nullptr;
-      d.coef = S.coef[n];
+      d.tc = S.adj ? nullptr : h->tcoef + size_t(S.gstep[n]) * h->P.nterms;
+      d.c0 = term0(h, S, n);
       d.step = S.gstep[n];
       S.h_jac[c][n - 1] = d;
       d.xout = nullptr;
@@ -513,7 +623,6 @@ int upload_tables(biot_handle* h, Sched& S) {
 void shape_sched(Sched& S, int N, bool adj) {
   S.adj = adj;
   S.N = N;
-  S.coef.assign(N + 1, 0.0);
   S.gstep.resize(N + 1);
   for (int n = 0; n <= N; ++n) S.gstep[n] = n;
   S.pin.assign(N + 1, nullptr);
@@ -600,19 +709,28 @@ struct ProbeScope {
   }
 };
 
-// algorithmic bytes of the level-0 launches (distinct inputs and outputs once);
-// `t` = bytes per value of the preconditioner precision
+// Algorithmic bytes of each launch: its distinct global inputs and outputs,
+// each counted once (operators once per launch, vectors once per column);
+// `t` = bytes per value of the preconditioner precision.  The probes report
+// these, and every launch adds them to h->acct.
 double bytes_residual(const biot_handle* h, int nc, bool write_r, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
   double per_col = 8 * D1 * 2 + (write_r ? t * (d + 1) : 0);
-  double mat = W * (d * d + 2 * d + 2) * 8 + 4 * W + 8 * D1;
+  // operator blocks, neighbour indices, load terms, prescribed-dof flags
+  double mat = W * (d * d + 2 * d + 2) * 8 + 4 * W + 8 * D1 * h->P.nterms + 1;
   return nc * nn * per_col + nn * mat;
 }
 // `first`: the step after the unstored first step reads only b (the gathered
 // vector) and no separate iterate
-double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool upd, bool wd, bool first,
-                  int t) {
-  const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
+// (k = copies in the launch: a level's launch covers its first k copies)
+double act_nodes(const biot_handle* h, int l, int k) { return h->P.levels[l].cbase[k]; }
+int grid_nodes_host(const biot_handle* h, int cells) {
+  const int m = cells + 1;
+  return h->dim == 2 ? m * m : m * m * m;
+}
+double bytes_cheb(const biot_handle* h, int l, int k, int C, int nc, bool c1, bool upd, bool wd,
+                  bool first, int t) {
+  const double nn = act_nodes(h, l, k), W = h->P.levels[l].W, d = h->dim, D1 = d + 1;
   double per_col =
       double(t) * C * ((first ? 1 : 2) + (c1 ? 1 : 0) + (upd ? 0 : 1 + (wd ? 1 : 0)));
   if (upd) per_col += 8 * D1 * 2 + t * d;
@@ -620,55 +738,136 @@ double bytes_cheb(const biot_handle* h, int C, int nc, bool c1, bool upd, bool w
   total += nn * (W * C * C * t + 4 * W + C * C * t);
   return total;
 }
-double bytes_levres(const biot_handle* h, int C, int nc, int t) {
-  const double nn = h->nn, W = h->P.levels[0].W;
+double bytes_levres(const biot_handle* h, int l, int k, int C, int nc, int t) {
+  const double nn = act_nodes(h, l, k), W = h->P.levels[l].W;
   return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W);
 }
-double bytes_post2(const biot_handle* h, int l, int C, int nc, int t) {
-  const double nn = h->P.levels[l].nn, W = h->P.levels[l].W;
+double bytes_post2(const biot_handle* h, int l, int k, int C, int nc, int t) {
+  const double nn = act_nodes(h, l, k), W = h->P.levels[l].W;
   return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W + C * C * t);  // b, x2 -> x4
 }
 double bytes_pstage(const biot_handle* h, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
   return nc * nn * t * (d + 2) + nn * (W * d * t + 4 * W);
 }
+// restriction l -> l+1: fine residual in, coarse right-hand side out, flags
+double bytes_restrict(const biot_handle* h, int l, int k, int C, int nc, int t) {
+  const double nf = act_nodes(h, l, k), ncs = act_nodes(h, l + 1, k);
+  return nc * (nf + ncs) * C * t + (nf + ncs);
+}
+// prolongation l+1 -> l: fine iterate and coarse correction in, fine out, flags
+double bytes_prolong(const biot_handle* h, int l, int k, int C, int nc, int t) {
+  const double nf = act_nodes(h, l, k), ncs = act_nodes(h, l + 1, k);
+  return nc * (2 * nf + ncs) * C * t + (nf + ncs);
+}
+// fused tail: per copy, its first tail level's b in and x out per column;
+// the operators of its tail levels (A or S, the folded copy, D^{-1}, indices,
+// flags) and its dense coarsest inverse once
+double bytes_tail(const biot_handle* h, const std::vector<TailCopy>& tcs, int C, int nc, int t) {
+  double total = 0;
+  for (size_t cp = 0; cp < tcs.size(); ++cp) {
+    const TailCopy& tc = tcs[cp];
+    auto nodes = [&](int l) {
+      const double m = h->P.levels[l].ccells[cp] + 1;
+      return h->dim == 2 ? m * m : m * m * m;
+    };
+    for (int i = 0; i + 1 < tc.nlev; ++i) {
+      const double W = h->P.levels[tc.t0 + i].W;
+      total += nodes(tc.t0 + i) * (2 * W * C * C * t + 4 * W + C * C * t + 1);
+    }
+    const double n = nodes(tc.t0 + tc.nlev - 1) * C;
+    total += n * n * t + nc * nodes(tc.t0) * C * t * 2;
+  }
+  return total;
+}
+double bytes_coarse(const biot_handle* h, int l, int C, int nc, int t) {
+  const HostLevel& L = h->P.levels[l];
+  const double n = double(L.nreal) * C;
+  return L.copies * n * n * t + nc * L.copies * n * t * 2;
+}
+double bytes_update(const biot_handle* h, int nc, int t) {
+  const double nn = h->nn, D1 = h->D1;
+  return nc * nn * (8 * D1 * 2 + t * D1) + h->cur_copies * nn * 8 * D1;
+}
+double bytes_norms(const biot_handle* h, int nc) {
+  return nc * (double(h->nblk) * 4 * 8 + double(h->S) * 4 * 8);
+}
+double bytes_apply_op(const biot_handle* h, int nc) {
+  const double nn = h->nn, W = h->P.levels[0].W, d = h->dim, D1 = d + 1;
+  return nc * nn * 8 * D1 * 2 + nn * (W * (d * d + 2 * d + 1) * 8 + 4 * W);
+}
+double bytes_pack(const biot_handle* h, int nc, int t) {
+  return nc * double(h->nn) * h->D1 * (8 + t);
+}
 
-// One V-cycle for field A (is_A) or S on level l for nc columns.  On entry b[l]
-// holds the right-hand side; the first Chebyshev step from zero is pointwise
-// and never stored (the second step forms it from b).  The result is returned
-// in *out; when `upd`
-// is given (pressure field, level 0) the last smoothing step writes the outer
-// update through those descriptors instead and *out is null.
+// A level's view for a launch over its first k copies, with the launch's
+// column descriptors (batches: a sample skips the columns past its steps).
+template <typename T>
+LevelView<T> view_of(const biot_handle* h, const LevelView<T>& L, int l, int k,
+                     const ColDesc* act) {
+  LevelView<T> v = L;
+  v.nact = h->P.levels[l].cbase[k];
+  v.npatch = h->ppre.empty() ? 0 : h->ppre[l][k];
+  v.act = act;
+  return v;
+}
+
+// One V-cycle for field A (is_A) or S from level l down, for nc columns.  On
+// entry b[l] holds the right-hand side; the first Chebyshev step from zero is
+// pointwise and never stored (the second step forms it from b).  A level runs
+// as its own launches for the copies (a prefix) whose coarse end lies below
+// it; the first level where no copy does launches the fused tail of every copy
+// (each from its own first tail level; the result goes to the result buffer
+// of that level) or, without tails, the dense coarsest solve.  The result is
+// returned in *out; when `upd` is given (pressure field, level 0) the last
+// smoothing step writes the outer update through those descriptors instead
+// and *out is null.  `act`: the column descriptors that let the samples of a
+// batch skip the columns past their steps (null: every column is active).
 template <typename T>
 int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const ColDesc* upd,
-           const T* zu) {
+           const T* zu, const ColDesc* act) {
   Field<T>& f = is_A ? p.fa : p.fs;
   const int C = is_A ? h->dim : 1;
-  const int last = h->nlev - 1;
   const int wpc = h->opt.wg_per_cu;
   const int tb = int(sizeof(T));
   hipStream_t st = h->st;
-  const int tail = is_A ? p.tailA : p.tailS;
-  if (l == tail) {
-    launch_vcycle_tail<T>(h->dim, C, is_A ? p.tdA : p.tdS, f.b[l], f.x0[l], nc, st);
+  const bool has_tail = (is_A ? p.tailA : p.tailS) > 0;
+  const int k = (is_A ? p.standA : p.standS)[l];
+  if (k == 0 && has_tail) {
+    // the work vectors in use now (a caller-less apply may swap in others)
+    TailDev<T> td = is_A ? p.tdA : p.tdS;
+    const int rb = result_buffer(h);
+    for (int i = 0; i < h->nlev && i < kMaxLevels; ++i) {
+      td.L[i].act = act;
+      td.b[i] = f.b[i];
+      td.x[i] = rb ? f.x1[i] : f.x0[i];
+    }
+    launch_vcycle_tail<T>(h->dim, C, td, nc, is_A ? p.ldsA : p.ldsS, st);
     LAUNCHCHK(h);
-    *out = f.x0[l];
+    h->acct += bytes_tail(h, is_A ? p.tcA : p.tcS, C, nc, tb);
+    *out = result_buffer(h) ? f.x1[l] : f.x0[l];
     return BIOT_OK;
   }
-  if (l == last) {
+  if (k == 0) {
+    // no tails: every copy's coarsest level is this one (equal grids)
     const HostLevel& H = h->P.levels[l];
-    launch_coarse_solve<T>(H.nreal * C, H.nn1 * C, H.copies, is_A ? p.coarseA : p.coarseS, f.b[l],
-                           f.x0[l], nc, st);
+    launch_coarse_solve<T>(grid_nodes_host(h, H.ccells[0]) * C, (H.cbase[1] - H.cbase[0]) * C,
+                           H.copies, is_A ? p.coarseA : p.coarseS, f.b[l], f.x0[l], nc, st);
     LAUNCHCHK(h);
+    h->acct += bytes_coarse(h, l, C, nc, tb);
     if (upd) {
-      launch_update<T>(h->dim, h->nn, upd, zu, f.x0[l], h->opt.omega, nc, st);
+      launch_update<T>(h->dim, h->nn, upd, zu, f.x0[l], h->opt.omega, nc,
+                       act ? h->L[0].csteps : nullptr, h->L[0].bcopy, st);
       LAUNCHCHK(h);
+      h->acct += bytes_update(h, nc, tb);
       *out = nullptr;
     } else {
       *out = f.x0[l];
     }
     return BIOT_OK;
   }
+  if (l + 1 >= h->nlev) return fail(h, BIOT_EINVAL, "internal: no coarser level below a smoothed one");
+  const LevelView<T> Lv = view_of(h, p.L[l], l, k, act);
   const ChebCoef& cc = is_A ? h->chA[l] : h->chS[l];
   const int deg = h->opt.cheb_degree;
   T* cur = f.x0[l];
@@ -684,31 +883,36 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     // is never stored: step 2 forms it from b.
     const bool wd = j < deg;
     const bool first = j == 2;
-    ProbeScope ps(h, fine ? pid_cheb : -1,
-                  fine ? bytes_cheb(h, C, nc, j > 2, false, wd, first, tb) : 0);
-    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], first ? f.b[l] : cur, oth, f.d[l], nc,
+    const double by = bytes_cheb(h, l, k, C, nc, j > 2, false, wd, first, tb);
+    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? by : 0);
+    launch_cheb<T>(h->dim, C, Lv, is_A, f.b[l], first ? f.b[l] : cur, oth, f.d[l], nc,
                    rn * rho, 2.0 * rn / cc.delta, wd, first ? 1 : 0, first, 1.0 / cc.theta,
                    nullptr, nullptr, 0.0, wpc, fine, st);
     LAUNCHCHK(h);
+    h->acct += by;
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
     std::swap(cur, oth);
   }
   {
-    ProbeScope ps(h, is_A ? BIOT_PROBE_LEVRES_U : BIOT_PROBE_LEVRES_P,
-                  fine ? bytes_levres(h, C, nc, tb) : 0);
-    launch_level_residual<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, f.r[l], nc, wpc, st);
+    const double by = bytes_levres(h, l, k, C, nc, tb);
+    ProbeScope ps(h, is_A ? BIOT_PROBE_LEVRES_U : BIOT_PROBE_LEVRES_P, fine ? by : 0);
+    launch_level_residual<T>(h->dim, C, Lv, is_A, f.b[l], cur, f.r[l], nc, wpc, st);
     LAUNCHCHK(h);
+    h->acct += by;
     if (fine && ps.end()) return BIOT_EHIP;
   }
-  launch_restrict<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, f.r[l], f.b[l + 1], nc, st);
+  const LevelView<T> Lc = view_of(h, p.L[l + 1], l + 1, k, act);
+  launch_restrict<T>(h->dim, C, Lv, Lc, is_A, f.r[l], f.b[l + 1], nc, st);
   LAUNCHCHK(h);
+  h->acct += bytes_restrict(h, l, k, C, nc, tb);
   T* xc = nullptr;
-  int rc = vcycle<T>(h, p, is_A, l + 1, nc, &xc, nullptr, nullptr);
+  int rc = vcycle<T>(h, p, is_A, l + 1, nc, &xc, nullptr, nullptr, act);
   if (rc) return rc;
   // coarse-grid correction x += P xc, then deg post-smoothing steps
-  launch_prolong<T>(h->dim, C, p.L[l], p.L[l + 1], is_A, cur, xc, oth, nc, wpc, st);
+  launch_prolong<T>(h->dim, C, Lv, Lc, is_A, cur, xc, oth, nc, wpc, st);
   LAUNCHCHK(h);
+  h->acct += bytes_prolong(h, l, k, C, nc, tb);
   std::swap(cur, oth);
   rho = 1.0 / cc.sigma;
   if (h->opt.fuse_post && deg == 2 && !upd && h->dim == 2) {
@@ -717,10 +921,12 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     // fused it measured slower)
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
     // probed on every level, as a kernel trace averages this kernel
-    ProbeScope ps(h, is_A ? BIOT_PROBE_POST_U : BIOT_PROBE_POST_P, bytes_post2(h, l, C, nc, tb));
-    launch_post2<T>(C, p.L[l], is_A, f.b[l], cur, oth, nc, 1.0 / cc.theta, rn * rho,
+    const double by = bytes_post2(h, l, k, C, nc, tb);
+    ProbeScope ps(h, is_A ? BIOT_PROBE_POST_U : BIOT_PROBE_POST_P, by);
+    launch_post2<T>(C, Lv, is_A, f.b[l], cur, oth, nc, 1.0 / cc.theta, rn * rho,
                     2.0 * rn / cc.delta, wpc, st);
     LAUNCHCHK(h);
+    h->acct += by;
     if (ps.end()) return BIOT_EHIP;
     *out = oth;
     return BIOT_OK;
@@ -738,10 +944,12 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
     // holds the first step's input
     const bool wd = j > 1 && j < deg;
     const int dx = j == 2 ? 2 : 0;
-    ProbeScope ps(h, pid_cheb, fine ? bytes_cheb(h, C, nc, j > 1, final_upd, wd, false, tb) : 0);
-    launch_cheb<T>(h->dim, C, p.L[l], is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2, wd, dx, false,
+    const double by = bytes_cheb(h, l, k, C, nc, j > 1, final_upd, wd, false, tb);
+    ProbeScope ps(h, fine ? pid_cheb : -1, fine ? by : 0);
+    launch_cheb<T>(h->dim, C, Lv, is_A, f.b[l], cur, oth, f.d[l], nc, c1, c2, wd, dx, false,
                    0.0, final_upd ? upd : nullptr, zu, h->opt.omega, wpc, fine, st);
     LAUNCHCHK(h);
+    h->acct += by;
     if (fine && ps.end()) return BIOT_EHIP;
     rho = rn;
     std::swap(cur, oth);
@@ -754,34 +962,50 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
 // With `upd`, the outer update is written through those descriptors.
 template <typename T>
 int precond_batch(biot_handle* h, Prec<T>& p, int nc, T** zu, T** zp, const ColDesc* upd) {
-  int rc = vcycle<T>(h, p, true, 0, nc, zu, nullptr, nullptr);
+  // a batch's samples skip the columns past their own steps
+  const ColDesc* act = h->S > 1 ? upd : nullptr;
+  int rc = vcycle<T>(h, p, true, 0, nc, zu, nullptr, nullptr, act);
   if (rc) return rc;
   {
-    ProbeScope ps(h, BIOT_PROBE_PSTAGE, bytes_pstage(h, nc, int(sizeof(T))));
-    launch_pstage<T>(h->dim, p.L[0], p.Bt, h->opt.precond == BIOT_PRECOND_P1, *zu, p.rp,
-                     p.fs.b[0], nc, h->opt.wg_per_cu, h->st);
+    const double by = bytes_pstage(h, nc, int(sizeof(T)));
+    ProbeScope ps(h, BIOT_PROBE_PSTAGE, by);
+    launch_pstage<T>(h->dim, view_of(h, p.L[0], 0, h->P.levels[0].copies, act), p.Bt,
+                     h->opt.precond == BIOT_PRECOND_P1, *zu, p.rp, p.fs.b[0], nc,
+                     h->opt.wg_per_cu, h->st);
     LAUNCHCHK(h);
+    h->acct += by;
     if (ps.end()) return BIOT_EHIP;
   }
-  return vcycle<T>(h, p, false, 0, nc, zp, upd, *zu);
+  return vcycle<T>(h, p, false, 0, nc, zp, upd, *zu, act);
 }
 
 // one unit for every column of a descriptor batch: FP64 residual, P^{-1} in
 // precision T, FP64 update
+// level 0 for a residual launch over descriptor columns (the samples of a
+// batch skip the columns past their own steps)
+LevelDev fine_level(const biot_handle* h, const ColDesc* cols) {
+  LevelDev L = h->L[0];
+  if (h->S > 1) L.act = cols;
+  return L;
+}
+
 // level-0 coupling data for a schedule (the adjoint adds its pressure load)
 FineDev fine_of(const biot_handle* h, const Sched& S) {
   FineDev f = h->F;
   f.gload = S.adj ? h->gload : nullptr;
+  if (S.adj) f.nt = 0;  // the adjoint's only load is gload
   return f;
 }
 
 template <typename T>
 int unit_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* cols, int nc) {
   {
-    ProbeScope ps(h, BIOT_PROBE_RESIDUAL, bytes_residual(h, nc, true, int(sizeof(T))));
-    launch_residual<T>(h->dim, h->L[0], fine_of(h, S), cols, nc, p.fa.b[0], p.rp, nullptr,
-                       h->nblk, h->opt.wg_per_cu, S.adj, h->st);
+    const double by = bytes_residual(h, nc, true, int(sizeof(T)));
+    ProbeScope ps(h, BIOT_PROBE_RESIDUAL, by);
+    launch_residual<T>(h->dim, fine_level(h, cols), fine_of(h, S), cols, nc, p.fa.b[0], p.rp,
+                       nullptr, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
+    h->acct += by;
     if (ps.end()) return BIOT_EHIP;
   }
   T *zu = nullptr, *zp = nullptr;
@@ -801,6 +1025,7 @@ int apply_precond_t(biot_handle* h, Prec<T>& p, const double* R, double* Z, int 
     if (rc) return rc;
     launch_pack<T>(h->dim, h->nn, zu, zp, Z + size_t(c0) * h->col, nc, h->st);
     LAUNCHCHK(h);
+    h->acct += 2 * bytes_pack(h, nc, int(sizeof(T)));
   }
   return BIOT_OK;
 }
@@ -900,23 +1125,29 @@ int gmres_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* col
   const int k = h->opt.gmres_k;
   hipStream_t st = h->st;
   const GmresVecs Vv{h->gV, sv, col};
-  launch_residual<double>(h->dim, h->L[0], fine_of(h, S), cols, nc, h->gru, h->grp, nullptr,
-                          h->nblk, h->opt.wg_per_cu, S.adj, st);
+  launch_residual<double>(h->dim, fine_level(h, cols), fine_of(h, S), cols, nc, h->gru, h->grp,
+                          nullptr, h->nblk, h->opt.wg_per_cu, S.adj, st);
   LAUNCHCHK(h);
   launch_pack<double>(h->dim, h->nn, h->gru, h->grp, h->gT, nc, st);
   LAUNCHCHK(h);
+  h->acct += bytes_residual(h, nc, true, 8) + bytes_pack(h, nc, 8);
   int rc = apply_precond_t<T>(h, p, h->gT, h->gV, nc);
   if (rc) return rc;
+  // Krylov vector traffic: a dot over v vectors reads v + 1 columns, an axpy
+  // reads v + 1 and writes one, a scale reads and writes one
+  const double cb = double(nc) * col * 8;
   gmres_dot(GmresVecs{h->gV, 0, col}, 1, h->gV, h->kpart, h->gbeta, 1, 0, 2, nullptr, 0, 0, nc, st);
   gmres_scale(h->gV, col, h->gbeta, 1, nc, st);
   gmres_start(h->gbeta, 1, h->gg, nc, st);
   LAUNCHCHK(h);
+  h->acct += 3 * cb;  // the norm of v_0 (one column read) and its scale
   const size_t hcs = (K + 1) * K;
   for (int j = 0; j < k; ++j) {
     double* Vj = h->gV + j * sv;
     double* W = h->gV + (j + 1) * sv;
     launch_apply_operator(h->dim, h->L[0], h->F, Vj, h->gT, nc, st);
     LAUNCHCHK(h);
+    h->acct += bytes_apply_op(h, nc);
     if ((rc = apply_precond_t<T>(h, p, h->gT, W, nc))) return rc;
     gmres_dot(Vv, j + 1, W, h->kpart, h->gH + j, hcs, K, 0, nullptr, 0, 0, nc, st);
     gmres_axpy(Vv, j + 1, h->gH + j, hcs, K, W, nc, st);
@@ -927,9 +1158,12 @@ int gmres_batch_t(biot_handle* h, const Sched& S, Prec<T>& p, const ColDesc* col
     gmres_scale(W, col, hn, hcs, nc, st);
     gmres_givens(h->gH, h->gg, h->gcs, h->gsn, j, nc, st);
     LAUNCHCHK(h);
+    // two dot/axpy pairs over j + 1 vectors, the norm and the scale
+    h->acct += 2 * ((j + 2) * cb + (j + 3) * cb) + 3 * cb;
   }
   gmres_finish(h->dim, h->nn, cols, Vv, k, h->gH, h->gg, h->gy, nc, st);
   LAUNCHCHK(h);
+  h->acct += (k + 3) * cb + h->cur_copies * double(col) * 8;  // V, X in, X out
   return BIOT_OK;
 }
 
@@ -991,6 +1225,7 @@ void destroy_graphs(Sched& S) {
     for (auto g : S.graph[c]) (void)hipGraphDestroy(g);
     S.gexec[c].clear();
     S.graph[c].clear();
+    S.gbytes[c] = 0.0;
   }
   S.graph_N = -1;
 }
@@ -1005,7 +1240,11 @@ int capture_waves(biot_handle* h, Sched& S, int c, size_t w0, size_t w1, size_t*
   hipStream_t user = h->st;
   h->st = h->cap_stream;
   HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+  // capture enqueues nothing: the bytes are counted per replay instead
+  const double acct0 = h->acct;
   int rc = run_waves(h, S, S.desc_wave[c], S.wave_off, S.wave_cnt, h->opt.depth, w0, w1);
+  S.gbytes[c] += h->acct - acct0;
+  h->acct = acct0;
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->st, &g);
   h->st = user;
@@ -1052,6 +1291,7 @@ int wavefront_pass(biot_handle* h, Sched& S) {
     S.graph_N = S.N;
   }
   for (auto x : S.gexec[c]) HIPCHK(h, hipGraphLaunch(x, h->st));
+  h->acct += S.gbytes[c];
   S.cur = 1 - S.cur;
   return BIOT_OK;
 }
@@ -1063,12 +1303,13 @@ int global_residual(biot_handle* h, const Sched& S) {
   const FineDev f = fine_of(h, S);
   for (int n0 = 0; n0 < S.N; n0 += chunk) {
     const int nc = std::min(chunk, S.N - n0);
-    launch_residual<double>(h->dim, h->L[0], f, tab + n0, nc, nullptr, nullptr, h->partials,
-                            h->nblk, h->opt.wg_per_cu, S.adj, h->st);
+    launch_residual<double>(h->dim, fine_level(h, tab + n0), f, tab + n0, nc, nullptr, nullptr,
+                            h->partials, h->nblk, h->opt.wg_per_cu, S.adj, h->st);
     LAUNCHCHK(h);
-    launch_reduce_norms(h->partials, num_node_blocks(h->P.levels[0].nn1), h->S, h->nblk,
+    launch_reduce_norms(h->partials, h->L[0].cbase, h->S, h->nblk,
                         h->norms + size_t(n0) * h->S * 4, nc, h->st);
     LAUNCHCHK(h);
+    h->acct += bytes_residual(h, nc, false, 8) + double(nc) * h->nblk * 4 * 8 * 2;
   }
   return BIOT_OK;
 }
@@ -1093,7 +1334,8 @@ int sweep_sched(biot_handle* h, Sched& S, int n_sweeps) {
 // step from rest, the displacement rows of a one-step adjoint) is measured
 // against the whole right-hand side.
 void rel_resid(const std::vector<double>& nr, int N, int S, const std::vector<int>& steps,
-               double& ru, double& rp) {
+               double& ru, double& rp, std::vector<double>* per_u = nullptr,
+               std::vector<double>* per_p = nullptr) {
   ru = rp = 0.0;
   for (int sm = 0; sm < S; ++sm) {
     const int Ns = S == 1 ? N : std::min(N, steps[sm]);
@@ -1112,8 +1354,11 @@ void rel_resid(const std::vector<double>& nr, int N, int S, const std::vector<in
     }
     const double both = std::sqrt(bu + bp);
     const double du = bu > 0 ? std::sqrt(bu) : both, dp = bp > 0 ? std::sqrt(bp) : both;
-    ru = std::max(ru, std::sqrt(mu) / std::max(du, 1e-300));
-    rp = std::max(rp, std::sqrt(mp) / std::max(dp, 1e-300));
+    const double cu = std::sqrt(mu) / std::max(du, 1e-300), cpv = std::sqrt(mp) / std::max(dp, 1e-300);
+    if (per_u) (*per_u)[sm] = cu;
+    if (per_p) (*per_p)[sm] = cpv;
+    ru = std::max(ru, cu);
+    rp = std::max(rp, cpv);
   }
 }
 
@@ -1140,6 +1385,15 @@ struct SolveOut {
 
 // Sweeps schedule S until the worst relative residual is <= rtol (see
 // biot_solve_to_tol for the policy).
+// Sets the steps a copy takes part in on the device (0: none; the copy is
+// frozen).  Graph replays read the table when they run.
+int upload_csteps(biot_handle* h, const std::vector<int32_t>& cs) {
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->L[0].csteps), cs.data(), cs.size() * 4,
+                           hipMemcpyHostToDevice, h->st));
+  HIPCHK(h, hipStreamSynchronize(h->st));  // the host vector must outlive the copy
+  return BIOT_OK;
+}
+
 int solve_sched(biot_handle* h, Sched& S, double rtol, int max_sweeps, int check_every,
                 SolveOut& out) {
   int rc = BIOT_OK;
@@ -1149,11 +1403,37 @@ int solve_sched(biot_handle* h, Sched& S, double rtol, int max_sweeps, int check
   int done = 0;
   double first = -1;
   out = SolveOut{};
+  // A sample of a batch that has reached the tolerance is frozen: its copy's
+  // state is made the same in both trajectory buffers and its step count on
+  // the device set to zero, so that every kernel skips it from then on; its
+  // residual stays what it was.  (Richardson units only: a GMRES unit's
+  // update would read the skipped residual.)
+  const int ncp = h->S;
+  const bool can_freeze = &S == &h->fw && ncp > 1 && h->opt.inner == BIOT_INNER_RICHARDSON;
+  std::vector<double> cu(ncp, 0.0), cpv(ncp, 0.0), fu(ncp, 0.0), fp(ncp, 0.0);
+  std::vector<char> frozen(ncp, 0);
+  std::vector<int32_t> cs(h->P.csteps.begin(), h->P.csteps.end());
+  int nfrozen = 0;
   while (true) {
-    if ((rc = global_residual(h, S))) return rc;
+    if ((rc = global_residual(h, S))) break;
     HIPCHK(h, hipMemcpyAsync(nr.data(), h->norms, nr.size() * 8, hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
-    rel_resid(nr, S.N, h->S, h->steps, out.ru, out.rp);
+    rel_resid(nr, S.N, h->S, h->P.csteps, out.ru, out.rp, &cu, &cpv);
+    if (nfrozen > 0) {
+      // frozen copies were skipped by this check: their last values hold
+      out.ru = out.rp = 0.0;
+      bool finite = true;
+      for (int c = 0; c < ncp; ++c) {
+        if (frozen[c]) {
+          cu[c] = fu[c];
+          cpv[c] = fp[c];
+        }
+        finite = finite && std::isfinite(cu[c]) && std::isfinite(cpv[c]);
+        out.ru = std::max(out.ru, cu[c]);
+        out.rp = std::max(out.rp, cpv[c]);
+      }
+      if (!finite) out.ru = out.rp = NAN;
+    }
     if (!std::isfinite(out.ru) || !std::isfinite(out.rp)) {
       rc = fail(h, BIOT_EDIVERGED, "non-finite residual");
       break;
@@ -1172,6 +1452,30 @@ int solve_sched(biot_handle* h, Sched& S, double rtol, int max_sweeps, int check
       rc = fail(h, BIOT_ENOTCONVERGED, "max_sweeps reached above tolerance");
       break;
     }
+    if (can_freeze) {
+      bool any = false;
+      for (int c = 0; c < ncp; ++c) {
+        if (frozen[c] || std::max(cu[c], cpv[c]) > rtol) continue;
+        const HostLevel& L0 = h->P.levels[0];
+        const size_t off = size_t(L0.cbase[c]) * h->D1;
+        const size_t width = size_t(L0.cbase[c + 1] - L0.cbase[c]) * h->D1 * 8;
+        double* src = S.T[S.cur] + off;
+        double* dst = S.T[1 - S.cur] + off;
+        if (hipMemcpy2DAsync(dst, h->col * 8, src, h->col * 8, width, size_t(S.N) + 1,
+                             hipMemcpyDeviceToDevice, h->st) != hipSuccess) {
+          rc = fail(h, BIOT_EHIP, "hipMemcpy2DAsync (freezing a converged sample)");
+          break;
+        }
+        frozen[c] = 1;
+        fu[c] = cu[c];
+        fp[c] = cpv[c];
+        cs[c] = 0;
+        ++nfrozen;
+        any = true;
+      }
+      if (rc) break;
+      if (any && (rc = upload_csteps(h, cs))) break;
+    }
     int kk = std::min(step, max_sweeps - done);
     if (h->opt.schedule == BIOT_SCHED_WAVEFRONT && done > 0) {
       // size the next pass from the observed contraction per sweep, with margin
@@ -1182,18 +1486,35 @@ int solve_sched(biot_handle* h, Sched& S, double rtol, int max_sweeps, int check
         kk = std::min({std::max(4, (k + 3) / 4 * 4), h->opt.depth, max_sweeps - done});
       }
     }
-    int r2 = sweep_sched(h, S, kk);
-    if (r2) return r2;
+    if ((rc = sweep_sched(h, S, kk))) break;
     done += kk;
   }
   out.sweeps = done;
+  if (nfrozen > 0) {
+    // every sample takes part in later calls again (both buffers agree for
+    // the frozen ones)
+    const int r2 = upload_csteps(h, std::vector<int32_t>(h->P.csteps.begin(), h->P.csteps.end()));
+    if (!rc) rc = r2;
+  }
   return rc;
 }
 
-int zero_traj(biot_handle* h, Sched& S) {
-  const size_t bytes = size_t(S.N + 1) * h->col * 8;
-  HIPCHK(h, hipMemsetAsync(S.T[0], 0, bytes, h->st));
-  HIPCHK(h, hipMemsetAsync(S.T[1], 0, bytes, h->st));
+// Initial iterate X^{n,0} in both buffers of a trajectory pair: zero, or for
+// the forward problem (`forward`) with prescribed values or X^0, the prescribed
+// values g^n at the prescribed dofs of every step and X^0 in column 0.  Sweeps
+// never change prescribed dofs (their residual and update are zero).
+int zero_traj(biot_handle* h, Sched& S, bool forward = false) {
+  if (forward && (h->P.npres > 0 || h->x0)) {
+    for (int c = 0; c < 2; ++c) {
+      launch_init_traj(S.T[c], S.N + 1, h->nn, h->D1, h->x0, h->pres, h->pcoef, h->P.npres,
+                       h->L[0].fixed, h->st);
+      LAUNCHCHK(h);
+    }
+  } else {
+    const size_t bytes = size_t(S.N + 1) * h->col * 8;
+    HIPCHK(h, hipMemsetAsync(S.T[0], 0, bytes, h->st));
+    HIPCHK(h, hipMemsetAsync(S.T[1], 0, bytes, h->st));
+  }
   S.cur = 0;
   return BIOT_OK;
 }
@@ -1290,9 +1611,10 @@ int biot_create(const biot_mesh* mesh, const biot_materials* mat, const biot_loa
   return biot_create_batch(mesh, 1, mat, load, &dt, &n_steps, opt, out);
 }
 
-int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_materials* mats,
+int biot_create_batch(const biot_mesh* meshes, int32_t n_samples, const biot_materials* mats,
                       const biot_load* loads, const double* dts, const int32_t* n_steps,
                       const biot_options* opt, biot_handle** out) {
+  const biot_mesh* mesh = meshes;
   if (!out) return fail(nullptr, BIOT_EINVAL, "out is NULL");
   *out = nullptr;
   if (!mesh || !mats || !loads || !dts || !n_steps)
@@ -1340,7 +1662,10 @@ int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_mater
     if (n_samples == 1) {
       MaterialsIn mi{mats->young,  mats->poisson, mats->perm,        mats->beta,
                      mats->alpha,  mats->stab_h,  mats->lame_lambda, mats->lame_mu};
-      LoadIn li{loads->n_facets, loads->facet_nodes, loads->traction, loads->coef};
+      LoadIn li{loads->n_facets,  loads->facet_nodes, loads->traction,
+                loads->coef,      loads->n_terms,     loads->terms,
+                loads->term_coef, loads->n_prescribed, loads->prescribed,
+                loads->prescribed_coef, loads->x0};
       e = build_problem(m, mi, li, dts[0], n_steps[0], ho, h->P);
       nmax = n_steps[0];
     } else {
@@ -1350,8 +1675,11 @@ int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_mater
         const biot_load& ld = loads[sm];
         MaterialsIn mi{mt.young, mt.poisson, mt.perm, mt.beta, mt.alpha, mt.stab_h,
                        mt.lame_lambda, mt.lame_mu};
-        LoadIn li{ld.n_facets, ld.facet_nodes, ld.traction, ld.coef};
-        e = build_problem(m, mi, li, dts[sm], n_steps[sm], ho, parts[sm]);
+        LoadIn li{ld.n_facets, ld.facet_nodes, ld.traction, ld.coef, ld.n_terms, ld.terms,
+                  ld.term_coef, ld.n_prescribed, ld.prescribed, ld.prescribed_coef, ld.x0};
+        const biot_mesh& ms = meshes[sm];
+        MeshIn mm{ms.dim, ms.n_nodes, ms.n_elems, ms.grid_n, ms.xyz, ms.conn, ms.dirichlet};
+        e = build_problem(mm, mi, li, dts[sm], n_steps[sm], ho, parts[sm]);
         if (!e.empty()) e = "sample " + std::to_string(sm) + ": " + e;
         nmax = std::max(nmax, n_steps[sm]);
       }
@@ -1367,6 +1695,8 @@ int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_mater
   }
   h->S = n_samples;
   h->steps.assign(n_steps, n_steps + n_samples);
+  h->copy_of.assign(n_samples, 0);
+  for (int c = 0; c < n_samples; ++c) h->copy_of[h->P.sample_of[c]] = c;
   h->dim = h->P.dim;
   h->D1 = h->dim + 1;
   h->nn = h->P.nn;
@@ -1386,11 +1716,49 @@ int biot_create_batch(const biot_mesh* mesh, int32_t n_samples, const biot_mater
     h->chA[l] = cheb_of(h->P.levels[l].lmaxA, o.cheb_ratio);
     h->chS[l] = cheb_of(h->P.levels[l].lmaxS, o.cheb_ratio);
   }
+  if (o.adjoint) {
+    // the checkpoint replays start inner steps from interpolated checkpoints,
+    // which is exact at prescribed dofs only when their values are zero
+    bool nz = h->P.npres > 0;
+    for (int v = 0; v < h->nn && !nz; ++v)
+      for (int c = 0; c < h->D1; ++c)
+        if (((h->P.levels[0].fixed[v] >> c) & 1) && !h->P.x0.empty() &&
+            h->P.x0[size_t(v) * h->D1 + c] != 0.0)
+          nz = true;
+    if (nz) {
+      delete h;
+      return fail(nullptr, BIOT_EINVAL, "the adjoint needs zero prescribed values (no prescribed "
+                                        "terms, X^0 zero at prescribed dofs)");
+    }
+  }
   shape_sched(h->fw, nmax, false);
-  for (int n = 0; n <= nmax; ++n) h->fw.coef[n] = h->P.coef[n];
   shape_sched(h->bw, nmax, true);  // load is gload, no traction
+  build_patches(h);
   plan(h, nullptr);
+  {
+    // copies of different grids need every copy's coarse end in a fused tail
+    bool uneven = false;
+    for (const HostLevel& Hl : h->P.levels)
+      for (int c = 1; c < Hl.copies; ++c) uneven = uneven || Hl.ccells[c] != Hl.ccells[0];
+    const bool mixed = o.precision == BIOT_PRECISION_MIXED;
+    const int ta = mixed ? h->pf.tailA : h->pd.tailA, ts = mixed ? h->pf.tailS : h->pd.tailS;
+    if (uneven && (ta < 0 || ts < 0)) {
+      delete h;
+      return fail(nullptr, BIOT_EINVAL, "a batch of different grids needs the coarse end of "
+                                        "every sample in the fused tail (use smaller grids)");
+    }
+  }
   *out = h;
+  return BIOT_OK;
+}
+
+int biot_sample_layout(const biot_handle* h, int32_t sample, int32_t* first_node,
+                       int32_t* n_nodes) {
+  if (!h || !first_node || !n_nodes || sample < 0 || sample >= h->S) return BIOT_EINVAL;
+  const HostLevel& L0 = h->P.levels[0];
+  const int cp = h->copy_of[sample];
+  *first_node = L0.cbase[cp];
+  *n_nodes = grid_nodes_host(h, L0.ccells[cp]);
   return BIOT_OK;
 }
 
@@ -1441,12 +1809,38 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
     HIPCHK(h, hipMemcpyAsync(const_cast<uint8_t*>(D.fixed), H.fixed.data(), H.fixed.size(), hipMemcpyHostToDevice, st));
     HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.AD), H.AD.data(), H.AD.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(h, hipMemcpyAsync(const_cast<double*>(D.SD), H.SD.data(), H.SD.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(D.cbase), H.cbase.data(), H.cbase.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(D.ccells), H.ccells.data(), H.ccells.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(D.bcopy), H.bcopy.data(), H.bcopy.size() * 4, hipMemcpyHostToDevice, st));
+    if (!h->ptab_h[l].empty())
+      HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(D.ptab), h->ptab_h[l].data(), h->ptab_h[l].size() * 4,
+                               hipMemcpyHostToDevice, st));
   }
+  HIPCHK(h, hipMemcpyAsync(const_cast<int32_t*>(h->L[0].csteps), h->P.csteps.data(), h->P.csteps.size() * 4,
+                           hipMemcpyHostToDevice, st));
+  auto up_tails = [&](auto& pr) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(const_cast<TailCopy*>(pr.tdA.tc), pr.tcA.data(),
+                                  pr.tcA.size() * sizeof(TailCopy), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(const_cast<TailCopy*>(pr.tdS.tc), pr.tcS.data(),
+                          pr.tcS.size() * sizeof(TailCopy), hipMemcpyHostToDevice, st);
+  };
+  if (h->opt.precision == BIOT_PRECISION_MIXED) HIPCHK(h, up_tails(h->pf));
+  else HIPCHK(h, up_tails(h->pd));
   const HostLevel& H0 = h->P.levels[0];
   HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.B), H0.B.data(), H0.B.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.Bt), H0.Bt.data(), H0.Bt.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.Cb), H0.Cb.data(), H0.Cb.size() * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(h, hipMemcpyAsync(const_cast<double*>(h->F.F), h->P.F.data(), h->P.F.size() * 8, hipMemcpyHostToDevice, st));
+  auto up64 = [&](const double* dst, const std::vector<double>& src) -> hipError_t {
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync(const_cast<double*>(dst), src.data(), src.size() * 8,
+                          hipMemcpyHostToDevice, st);
+  };
+  HIPCHK(h, up64(h->F.F, h->P.terms));
+  HIPCHK(h, up64(h->tcoef, h->P.tcoef));
+  HIPCHK(h, up64(h->pres, h->P.pres));
+  HIPCHK(h, up64(h->pcoef, h->P.pcoef));
+  if (h->x0) HIPCHK(h, up64(h->x0, h->P.x0));
   std::vector<std::vector<float>> staging;  // FP32 copies must outlive the async copies
   auto up32 = [&](const float* dst, const std::vector<double>& src) -> hipError_t {
     staging.emplace_back(src.begin(), src.end());
@@ -1476,7 +1870,7 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
   std::vector<std::vector<double>> keep;
   if (!rc && h->opt.adjoint) rc = upload_adjoint_data(h, keep);
   if (rc) return rc;
-  if ((rc = zero_traj(h, h->fw))) return rc;
+  if ((rc = zero_traj(h, h->fw, true))) return rc;
   if (h->opt.adjoint && h->opt.ckpt_stride == 0 && (rc = zero_traj(h, h->bw))) return rc;
   if (h->slots) HIPCHK(h, hipMemsetAsync(h->slots, 0, size_t(2) * h->opt.depth * h->col * 8, st));
   HIPCHK(h, hipStreamSynchronize(st));  // host sources must outlive the copies
@@ -1491,7 +1885,7 @@ int biot_bind(biot_handle* h, void* device_ptr, uint64_t bytes, void* stream) {
 int biot_reset(biot_handle* h) {
   int rc = check_bound(h);
   if (rc) return rc;
-  if ((rc = zero_traj(h, h->fw))) return rc;
+  if ((rc = zero_traj(h, h->fw, true))) return rc;
   h->fw_valid = true;
   if (h->opt.ckpt_stride > 0) h->adj_valid = false;  // shared buffers
   return BIOT_OK;
@@ -1510,8 +1904,13 @@ int biot_residual_norms(biot_handle* h, double* norms) {
   if (rc) return rc;
   if (!norms) return fail(h, BIOT_EINVAL, "norms is NULL");
   if ((rc = global_residual(h, h->fw))) return rc;
-  HIPCHK(h, hipMemcpyAsync(norms, h->norms, size_t(h->N) * h->S * 4 * 8, hipMemcpyDeviceToHost, h->st));
+  std::vector<double> byc(size_t(h->N) * h->S * 4);  // per copy (largest grids first)
+  HIPCHK(h, hipMemcpyAsync(byc.data(), h->norms, byc.size() * 8, hipMemcpyDeviceToHost, h->st));
   HIPCHK(h, hipStreamSynchronize(h->st));
+  for (int n = 0; n < h->N; ++n)
+    for (int sm = 0; sm < h->S; ++sm)
+      for (int q = 0; q < 4; ++q)
+        norms[(size_t(n) * h->S + sm) * 4 + q] = byc[(size_t(n) * h->S + h->copy_of[sm]) * 4 + q];
   return BIOT_OK;
 }
 
@@ -1523,9 +1922,11 @@ int biot_solve_to_tol(biot_handle* h, double rtol, int32_t max_sweeps, int32_t c
     return fail(h, BIOT_EINVAL, "need rtol > 0, max_sweeps >= 0, check_every >= 1");
   if (h->opt.ckpt_stride > 0) h->adj_valid = false;
   auto t0 = std::chrono::steady_clock::now();
+  const double acct0 = h->acct;
   SolveOut so;
   rc = solve_sched(h, h->fw, rtol, max_sweeps, check_every, so);
   if (stats) {
+    stats->alg_bytes = h->acct - acct0;
     stats->sweeps = so.sweeps;
     stats->converged = so.conv ? 1 : 0;
     stats->rel_resid_u = so.ru;
@@ -1555,8 +1956,9 @@ int biot_get_sample_trajectory(biot_handle* h, int32_t sample, int32_t n0, int32
     return fail(h, BIOT_EINVAL, "bad range or NULL dst");
   if (n1 == n0) return BIOT_OK;
   const HostLevel& L0 = h->P.levels[0];
-  const size_t width = size_t(L0.nreal) * h->D1 * 8;
-  const double* src = h->fw.T[h->fw.cur] + size_t(n0) * h->col + size_t(sample) * L0.nn1 * h->D1;
+  const int cp = h->copy_of[sample];
+  const size_t width = size_t(grid_nodes_host(h, L0.ccells[cp])) * h->D1 * 8;
+  const double* src = h->fw.T[h->fw.cur] + size_t(n0) * h->col + size_t(L0.cbase[cp]) * h->D1;
   HIPCHK(h, hipMemcpy2DAsync(dst, width, src, h->col * 8, width, size_t(n1 - n0),
                              dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->st));
   if (!dst_on_device) HIPCHK(h, hipStreamSynchronize(h->st));
@@ -1637,7 +2039,6 @@ int biot_adjoint(biot_handle* h, const biot_objective* obj, double rtol, int32_t
       shape_sched(R, L, false);
       for (int j = 1; j <= L; ++j) {
         const int n = n0 + j;
-        R.coef[j] = h->P.coef[n];
         R.gstep[j] = n;
         if ((n - 1) % s == 0) R.pin[j] = h->ck + size_t((n - 1) / s) * col;
       }
@@ -1704,6 +2105,7 @@ int biot_apply_operator(biot_handle* h, const double* X, double* Y, int32_t ncol
   if (ncols == 0) return BIOT_OK;
   launch_apply_operator(h->dim, h->L[0], h->F, X, Y, ncols, h->st);
   LAUNCHCHK(h);
+  h->acct += bytes_apply_op(h, ncols);
   return BIOT_OK;
 }
 

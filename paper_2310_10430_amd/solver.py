@@ -47,6 +47,28 @@ def _sample_structs(problem, beta, lame, keep):
                          _lib.dptr(lam_a), _lib.dptr(mu_a))
     load = _lib.Load(facets.shape[0], _lib.iptr(facets) if facets.size else None,
                      _lib.dptr(tr) if tr.size else None, _lib.dptr(coef))
+    n_nodes, d1, ns = problem.n_nodes, problem.dim + 1, problem.n_steps + 1
+
+    def arr(a, shape):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != shape:
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        keep.append(a)
+        return a
+    if getattr(problem, "terms", None) is not None:
+        t = np.asarray(problem.terms)
+        nt = t.shape[0]
+        load.n_terms = nt
+        load.terms = _lib.dptr(arr(t, (nt, n_nodes, d1)))
+        load.term_coef = _lib.dptr(arr(problem.term_coef, (ns, nt)))
+    if getattr(problem, "prescribed", None) is not None:
+        g = np.asarray(problem.prescribed)
+        npr = g.shape[0]
+        load.n_prescribed = npr
+        load.prescribed = _lib.dptr(arr(g, (npr, n_nodes, d1)))
+        load.prescribed_coef = _lib.dptr(arr(problem.prescribed_coef, (ns, npr)))
+    if getattr(problem, "x0", None) is not None:
+        load.x0 = _lib.dptr(arr(problem.x0, (n_nodes, d1)))
     return mat, load
 
 
@@ -88,15 +110,16 @@ def create_handle(problem, schedule="jacobi", depth=8, precond="P1", omega=0.6, 
     if isinstance(problem, (list, tuple)):
         if beta is not None or lame is not None:
             raise ValueError("beta and lame are per problem; not supported for batches")
-        mesh = _mesh_struct(problem[0], keep)
         S = len(problem)
+        meshes = (_lib.Mesh * S)()
         mats = (_lib.Materials * S)()
         loads = (_lib.Load * S)()
         for i, pb in enumerate(problem):
+            meshes[i] = _mesh_struct(pb, keep)
             mats[i], loads[i] = _sample_structs(pb, None, None, keep)
         dts = np.ascontiguousarray([float(pb.dt) for pb in problem], dtype=np.float64)
         steps = np.ascontiguousarray([int(pb.n_steps) for pb in problem], dtype=np.int32)
-        _lib.check(lib, lib.biot_create_batch(C.byref(mesh), S, mats, loads, _lib.dptr(dts),
+        _lib.check(lib, lib.biot_create_batch(meshes, S, mats, loads, _lib.dptr(dts),
                                               _lib.iptr(steps), C.byref(opt), C.byref(h)), None)
     else:
         mesh = _mesh_struct(problem, keep)
@@ -178,8 +201,11 @@ class BiotSolver:
         self._check(lib.biot_bind(h, C.c_void_p(self.workspace.data_ptr()), self.workspace_bytes,
                                   C.c_void_p(self.stream.cuda_stream)))
         inf = handle_info(lib, h)
-        self.grid_nodes = first.n_nodes              # nodes of one sample's grid
-        self.n_nodes = inf["n_samples"] * inf["nodes_per_sample"] if self.batch else first.n_nodes
+        # nodes of each sample's grid; all nodes of the handle (batches: the
+        # samples side by side, largest grids first, each padded)
+        self.sample_nodes = [pb.n_nodes for pb in problem] if self.batch else [first.n_nodes]
+        self.grid_nodes = first.n_nodes
+        self.n_nodes = inf["n_nodes"]
 
     # ------------------------------------------------------------------
     def _check(self, rc):
@@ -232,13 +258,19 @@ class BiotSolver:
     def sample_trajectory(self, sample: int, n0: int = 0, n1: int | None = None) -> torch.Tensor:
         """Steps n0..n1-1 of one sample of a batch, [n1-n0, grid nodes, dim+1]."""
         n1 = self.sample_steps[sample] + 1 if n1 is None else n1
-        out = torch.empty((n1 - n0, self.grid_nodes, self.dim + 1), dtype=torch.float64,
-                          device=self.device)
+        out = torch.empty((n1 - n0, self.sample_nodes[sample], self.dim + 1),
+                          dtype=torch.float64, device=self.device)
         self._inputs_ready(out)
         self._check(self.lib.biot_get_sample_trajectory(self.h, int(sample), n0, n1,
                                                         C.c_void_p(out.data_ptr()), 1))
         self._outputs_ready(out)
         return out
+
+    def sample_layout(self, sample: int):
+        """(first node, grid nodes) of a sample in the handle's node numbering."""
+        first, n = C.c_int32(), C.c_int32()
+        self._check(self.lib.biot_sample_layout(self.h, int(sample), C.byref(first), C.byref(n)))
+        return first.value, n.value
 
     def solve_to_tol(self, rtol: float, max_sweeps: int = 1000, check_every: int = 4,
                      raise_on_failure: bool = True) -> dict:
@@ -248,7 +280,7 @@ class BiotSolver:
         if rc != 0 and raise_on_failure:
             self._check(rc)
         return dict(sweeps=st.sweeps, converged=bool(st.converged), rel_resid_u=st.rel_resid_u,
-                    rel_resid_p=st.rel_resid_p, seconds=st.seconds, rc=rc)
+                    rel_resid_p=st.rel_resid_p, seconds=st.seconds, alg_bytes=st.alg_bytes, rc=rc)
 
     def trajectory(self, n0: int = 0, n1: int | None = None) -> torch.Tensor:
         n1 = self.n_steps + 1 if n1 is None else n1

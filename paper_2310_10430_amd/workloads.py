@@ -17,8 +17,16 @@ unit square, Sec. 4.1):
     share its (0,0,0)->(1,1,1) diagonal, which is conforming and nested under 2:1
     refinement.
 
-Boundary flags are a per-node bit mask: bit d (d < dim) fixes displacement
-component d to zero, bit dim fixes the pressure to zero.
+Boundary flags are a per-node bit mask: bit d (d < dim) marks displacement
+component d as prescribed, bit dim the pressure (zero unless a problem gives
+prescribed values).
+
+The manufactured-solution problem of Sec. 4.1 (`mms_problem`) is an input too:
+its data (body force, fluid source, boundary and initial values of the exact
+solution) are evaluated from their closed forms and integrated against the P1
+hat functions with Dunavant's degree-4 rule, which gives the assembled load
+vectors that the C ABI takes; the solver's own arithmetic (element matrices,
+time stepping, lifting of prescribed values) is not here.
 """
 from __future__ import annotations
 
@@ -220,6 +228,14 @@ class Problem:
     load_coef: np.ndarray       # [n_steps+1] multiplier of the traction at each time level
     n_steps: int
     dt: float
+    # general right-hand side (optional; node-major [n_nodes, dim+1] vectors):
+    # assembled load terms with per-step multipliers, prescribed-value terms
+    # (read at the flagged dofs) with per-step multipliers, initial state
+    terms: Optional[np.ndarray] = None            # [n_terms, n_nodes, dim+1]
+    term_coef: Optional[np.ndarray] = None        # [n_steps+1, n_terms]
+    prescribed: Optional[np.ndarray] = None       # [n_prescribed, n_nodes, dim+1]
+    prescribed_coef: Optional[np.ndarray] = None  # [n_steps+1, n_prescribed]
+    x0: Optional[np.ndarray] = None               # [n_nodes, dim+1]
 
     @property
     def n_nodes(self) -> int:
@@ -318,3 +334,115 @@ def sensor_nodes(problem: Problem, count: int = 64, seed: int = 42) -> np.ndarra
     free = np.nonzero((problem.flags & (1 << problem.dim)) == 0)[0]
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(free, size=count, replace=False)).astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# manufactured solution of Sec. 4.1 (inputs: assembled loads, boundary values)
+# ----------------------------------------------------------------------------
+# Dunavant's symmetric 6-point rule on a triangle, exact for degree 4
+# (D. A. Dunavant, Int. J. Numer. Meth. Eng. 21, 1985): barycentric points
+# (a, a, 1-2a) and permutations, with a weight per orbit (weights sum to 1)
+_DUN_ORBITS = ((0.445948490915965, 0.223381589678011),
+               (0.091576213509771, 0.109951743655322))
+
+
+def _dunavant_points():
+    pts, wts = [], []
+    for a, w in _DUN_ORBITS:
+        b = 1.0 - 2.0 * a
+        for bary in ((b, a, a), (a, b, a), (a, a, b)):
+            pts.append(bary)
+            wts.append(w)
+    return np.array(pts), np.array(wts)
+
+
+def mms_problem(n: int, dt: float, n_steps: int, E: float = 1.0, nu: float = 0.3,
+                alpha: float = 1.0, K: float = 1.0) -> Problem:
+    """Sec. 4.1 on the n x n unit square: exact solution
+    u_1 = u_2 = p = cos(t) cos(3 pi x) cos(3 pi y), prescribed on the whole
+    boundary (all three fields), E = 1, nu = 0.3, alpha = 1, K = 1.
+
+    Right-hand side, per step n at t_n = n dt, as two load terms:
+      term 0 (multiplier cos t_n): u rows int f_c . v with the body force
+        f = cos t [k^2((lam+3mu) c_x c_y - (lam+mu) s_x s_y) - alpha k s_x c_y,
+                   k^2((lam+3mu) c_x c_y - (lam+mu) s_x s_y) - alpha k c_x s_y]
+        (k = 3 pi, c_x = cos 3 pi x, s_x = sin 3 pi x), and p rows -dt int g_c q
+        with the cos-part of the source, g_c = 2 k^2 K c_x c_y;
+      term 1 (multiplier sin t_n): p rows -dt int g_s q,
+        g_s = alpha k (s_x c_y + c_x s_y).
+    (g is the source that makes the printed solution exact; the printed one
+    has the first bracket's sign and order changed.)  Prescribed values: one
+    term cos(3 pi x) cos(3 pi y) in all fields with multiplier cos t_n; X^0 the
+    exact solution at t = 0.
+    """
+    xyz, conn = square_mesh(n)
+    nn = xyz.shape[0]
+    tol = 1e-12
+    bnd = ((xyz[:, 0] < tol) | (xyz[:, 0] > 1 - tol) | (xyz[:, 1] < tol) | (xyz[:, 1] > 1 - tol))
+    flags = np.where(bnd, 0b111, 0).astype(np.uint8)
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    k = 3.0 * np.pi
+    bary, w = _dunavant_points()
+    x = xyz[conn]                                           # [ne, 3, 2]
+    d1, d2 = x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]
+    area = 0.5 * np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+    qp = np.einsum("qa,ead->eqd", bary, x)                  # [ne, nq, 2]
+    cx, cy = np.cos(k * qp[..., 0]), np.cos(k * qp[..., 1])
+    sx, sy = np.sin(k * qp[..., 0]), np.sin(k * qp[..., 1])
+    common = k * k * ((lam + 3 * mu) * cx * cy - (lam + mu) * sx * sy)
+    f1 = common - alpha * k * sx * cy
+    f2 = common - alpha * k * cx * sy
+    gc = 2 * k * k * K * cx * cy
+    gs = alpha * k * (sx * cy + cx * sy)
+    terms = np.zeros((2, nn, 3))
+    wa = area[:, None] * w[None, :]                         # [ne, nq]
+    for a in range(3):
+        phi = wa * bary[None, :, a]
+        v = conn[:, a]
+        np.add.at(terms[0, :, 0], v, np.sum(phi * f1, axis=1))
+        np.add.at(terms[0, :, 1], v, np.sum(phi * f2, axis=1))
+        np.add.at(terms[0, :, 2], v, -dt * np.sum(phi * gc, axis=1))
+        np.add.at(terms[1, :, 2], v, -dt * np.sum(phi * gs, axis=1))
+    t = dt * np.arange(n_steps + 1)
+    shape = np.cos(k * xyz[:, 0]) * np.cos(k * xyz[:, 1])
+    pres = np.repeat(shape[None, :, None], 3, axis=2)       # [1, nn, 3]
+    ne = conn.shape[0]
+    return Problem(dim=2, grid_n=n, xyz=xyz, conn=conn, flags=flags,
+                   young=np.full(ne, E), poisson=np.full(ne, nu), perm=np.full(ne, K),
+                   alpha=alpha, stab_h=1.0 / n, facets=np.zeros((0, 2), np.int32),
+                   traction=np.zeros((0, 2)), load_coef=np.zeros(n_steps + 1),
+                   n_steps=n_steps, dt=dt,
+                   terms=terms, term_coef=np.stack([np.cos(t), np.sin(t)], axis=1),
+                   prescribed=pres, prescribed_coef=np.cos(t)[:, None],
+                   x0=pres[0].copy())
+
+
+def general_rhs_problem(n: int, n_steps: int, seed: int, dim: int = 2, n_terms: int = 2,
+                        n_prescribed: int = 2) -> Problem:
+    """Consolidation-column mesh, boundary flags and materials (log-normal K,
+    uniform E in 2D) with a seeded general right-hand side: the unit top
+    traction with its step profile, `n_terms` random load vectors (all dofs,
+    scaled like the traction's loads and -dt times a pressure source) with
+    random smooth multipliers, `n_prescribed` random prescribed-value vectors
+    with random smooth multipliers, and a random initial state."""
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        pb = heterogeneous_problem(n, n_steps, field_seed=seed + 1, young_seed=seed + 2)
+    else:
+        pb = terzaghi_problem(n, n_steps, dim=3)
+    nn, d1 = pb.n_nodes, dim + 1
+    h = 1.0 / n
+    t = np.arange(n_steps + 1) / n_steps
+    terms = rng.standard_normal((n_terms, nn, d1)) * h ** (dim - 1)
+    terms[..., dim] *= pb.dt
+    tc = np.stack([np.cos(rng.uniform(0, 6) * t + rng.uniform(0, 6)) for _ in range(n_terms)], 1)
+    pres = rng.standard_normal((n_prescribed, nn, d1)) * 1e-4
+    pres[..., dim] *= 1e4
+    pc = np.stack([np.sin(rng.uniform(0, 6) * t + rng.uniform(0, 6)) for _ in range(n_prescribed)], 1)
+    x0 = rng.standard_normal((nn, d1)) * 1e-4
+    x0[:, dim] *= 1e4
+    pb.terms, pb.term_coef = terms, tc
+    pb.prescribed, pb.prescribed_coef = pres, pc
+    pb.x0 = x0
+    return pb

@@ -12,6 +12,10 @@ cube40.npz -- 40^3 unit cube on Kuhn tetrahedra (68,921 nodes, 275,684
 unknowns), 256 steps of dt = 1/256, homogeneous materials, the 3D column;
 same contents (dofs index the node-major [nn][4] layout).
 
+large_terzaghi_dt32.npz, large_terzaghi_dt0.1.npz -- the 256 x 256 column with
+512 steps of dt = 1/32 and of dt = 0.1 (the larger time steps where the block
+preconditioners P1 and P2 are compared, Table 3's regime); same contents.
+
 large_heterogeneous.npz -- the same mesh and steps with a log-normal
 permeability field (sigma_log = 1, correlation length 0.1, field seed 2) and
 E ~ U[5e3, 2e4] per element (seed 102); same contents.
@@ -41,7 +45,8 @@ taken, homogeneous E = 1e4, nu = 0.3; 64 sensor nodes with free pressure
                                   d lambda = lambda v_l, d mu = mu v_m
     fd_scale[32]                  sum_i |g_i v_i| of each direction
 
-Run:  python tests/golden/make_goldens.py [large_terzaghi] [large_heterogeneous] [cube40] [batched64] [adjoint_c4]
+Run:  python tests/golden/make_goldens.py [large_terzaghi] [large_terzaghi_dt32]
+        [large_terzaghi_dt0.1] [large_heterogeneous] [cube40] [batched64] [adjoint_c4]
       (about 2 minutes each on one core; cube40's 3D factorization takes far longer;
       batched64 and adjoint_c4 use a process pool)
 """
@@ -138,7 +143,9 @@ def write_batched(name="batched64", workers=6):
 
 
 WORKLOADS = {"large_terzaghi": W.large_terzaghi, "large_heterogeneous": W.large_heterogeneous,
-             "cube40": lambda: W.terzaghi_problem(40, 256, dim=3)}
+             "cube40": lambda: W.terzaghi_problem(40, 256, dim=3),
+             "large_terzaghi_dt32": lambda: W.terzaghi_problem(256, 512, dt=1 / 32),
+             "large_terzaghi_dt0.1": lambda: W.terzaghi_problem(256, 512, dt=0.1)}
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(WORKLOADS) + ["adjoint_c4"]):

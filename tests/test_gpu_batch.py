@@ -122,3 +122,94 @@ def test_concurrent_handles_on_own_streams_match_sequential():
             err = seq.relative_field_errors(fem.node_to_field_major(b[i].cpu().numpy()),
                                             orc.solve_sequential(), orc.n_nodes, orc.dim)
             assert err["u"] < 1e-8 and err["p"] < 1e-8, (i, err)
+
+
+# ---------------------------------------------------------------------------
+# one handle over samples of different grids (biot_create_batch with a mesh per
+# sample): level l launches cover the samples whose hierarchy reaches it, the
+# fused coarse end runs every sample from its own first fused level, and a
+# sample skips the columns of steps past its own count
+# ---------------------------------------------------------------------------
+def _uneven(sizes=(24, 48, 16, 32, 48, 12), steps=(9, 14, 5, 20, 11, 7)):
+    return [W.heterogeneous_problem(n, N, field_seed=5000 + i, young_seed=6000 + i)
+            for i, (n, N) in enumerate(zip(sizes, steps))]
+
+
+@pytest.mark.parametrize("schedule,depth,precision", [("wavefront", 8, "fp64"),
+                                                      ("jacobi", 1, "fp64"),
+                                                      ("wavefront", 8, "mixed")])
+def test_uneven_batch_matches_oracle_per_sample(schedule, depth, precision):
+    pbs = _uneven()
+    print(f"uneven batch of {len(pbs)} samples, {schedule}, {precision}", flush=True)
+    s = BiotSolver(pbs, schedule=schedule, depth=depth, precision=precision, max_batch=7)
+    st = s.solve_to_tol(1e-11, max_sweeps=3000, check_every=4)
+    assert st["converged"], st
+    _check_samples(s, pbs)
+    # no work past a sample's own steps: those columns keep the initial zeros
+    X = s.trajectory().cpu().numpy()
+    for i, pb in enumerate(pbs):
+        first, n = s.sample_layout(i)
+        assert np.all(X[pb.n_steps + 1:, first:first + n] == 0.0)
+        assert np.any(X[pb.n_steps, first:first + n] != 0.0)
+    s.close()
+
+
+def test_uneven_batch_preconditioner_matches_each_sample():
+    """P^{-1} on the uneven batch's columns equals each sample's own handle's
+    P^{-1} on its part, up to the Chebyshev intervals (the batch takes the
+    largest spectral bound of a level over its samples): compared with the
+    oracle's multigrid preconditioner built with the batch's bounds."""
+    from oracle import precond
+    pbs = _uneven(sizes=(24, 48, 16), steps=(3, 3, 3))
+    s = BiotSolver(pbs, max_batch=3)
+    info = s.info()
+    rng = np.random.default_rng(7)
+    R = np.zeros((3, s.n_nodes, 3))        # padding nodes stay zero
+    for i, pb in enumerate(pbs):
+        first, n = s.sample_layout(i)
+        r = rng.standard_normal((3, n, 3))
+        r[..., 2] *= 1e-6
+        fixed = np.stack([(pb.flags >> c) & 1 for c in range(3)], axis=1).astype(bool)
+        r[:, fixed] = 0.0                  # prescribed dofs carry no residual
+        R[:, first:first + n] = r
+    Z = s.apply_precond(torch.from_numpy(R)).cpu().numpy()
+    for i, pb in enumerate(pbs):
+        first, n = s.sample_layout(i)
+        orc = seq.BiotOracle(pb)
+        P = precond.BlockPreconditioner(orc, "P1", "gmg")
+        # the batch's bounds per level of this sample (all samples' maximum)
+        for lev, L in enumerate(P.HA.levels[:-1]):
+            L.lmax = info["lmax_A"][lev]
+        for lev, L in enumerate(P.HS.levels[:-1]):
+            L.lmax = info["lmax_S"][lev]
+        for c in range(R.shape[0]):
+            r = fem.node_to_field_major(R[c, first:first + n])
+            zo = P.apply(r)
+            zg = fem.node_to_field_major(Z[c, first:first + n])
+            for sl in (slice(0, orc.nU), slice(orc.nU, None)):
+                err = np.abs(zg[sl] - zo[sl]).max() / np.abs(zo[sl]).max()
+                assert err < 1e-11, (i, c, err)
+    s.close()
+
+
+def test_uneven_batch_freezes_converged_samples_consistently():
+    """Samples that reach the tolerance first are frozen (every kernel skips
+    them) while the others go on; afterwards the trajectory of every sample, in
+    the buffer the handle now reads, satisfies the tolerance (a frozen sample's
+    state must be the same in both trajectory buffers), and equals backward
+    Euler."""
+    pbs = _uneven(sizes=(32, 12, 24, 16), steps=(24, 4, 12, 6))
+    pbs[1].dt = pbs[3].dt = 1 / 64      # these converge in far fewer sweeps
+    rtol = 1e-10
+    s = BiotSolver(pbs, schedule="wavefront", depth=8)
+    st = s.solve_to_tol(rtol, max_sweeps=3000)
+    assert st["converged"], st
+    nr = s.residual_norms()            # all samples take part again
+    for i, pb in enumerate(pbs):
+        q = nr[: pb.n_steps, i]
+        both = np.sqrt(q[:, 2].max() + q[:, 3].max())
+        ru = np.sqrt(q[:, 0].max()) / (np.sqrt(q[:, 2].max()) or both)
+        rp = np.sqrt(q[:, 1].max()) / (np.sqrt(q[:, 3].max()) or both)
+        assert max(ru, rp) <= rtol * 1.0001, (i, ru, rp)
+    _check_samples(s, pbs)
+    s.close()

@@ -206,6 +206,80 @@ def test_batch_rejects_inconsistent_samples():
     pbs[1].load_coef = pbs[1].load_coef * 2.0
     with pytest.raises(_lib.BiotError, match="load multipliers"):
         S.create_handle(pbs)
-    other = W.heterogeneous_problem(16, 5)
-    with pytest.raises(_lib.BiotError):
-        S.create_handle([_batch_samples()[0], other])
+    # a larger grid must not have a shallower multigrid hierarchy (20 -> 10 -> 5
+    # has three levels, 16 -> ... -> 2 four), so that every level's copies are
+    # a prefix of the copies
+    with pytest.raises(_lib.BiotError, match="deeper"):
+        S.create_handle([W.heterogeneous_problem(16, 5), W.heterogeneous_problem(20, 5)])
+
+
+def test_uneven_batch_layout():
+    """Samples of different grids in one handle: copies ordered largest grid
+    first, each padded to whole node blocks; level l holds the copies that have
+    a level l; every copy's operators equal its single-sample handle's."""
+    lib = _lib.load()
+    sizes = (8, 16, 12, 16)
+    pbs = [W.heterogeneous_problem(n, 3 + i, field_seed=50 + i, young_seed=60 + i)
+           for i, n in enumerate(sizes)]
+    hb, _ = S.create_handle(pbs)
+    singles = [S.create_handle(pb)[0] for pb in pbs]
+    try:
+        info = S.handle_info(lib, hb)
+        order = [1, 3, 2, 0]           # stable, largest first
+        first = C.c_int32()
+        nodes = C.c_int32()
+        base = 0
+        for cp, i in enumerate(order):
+            _lib.check(lib, lib.biot_sample_layout(hb, i, C.byref(first), C.byref(nodes)), hb)
+            assert first.value == base and nodes.value == pbs[i].n_nodes
+            base += (pbs[i].n_nodes + 255) // 256 * 256
+        assert info["n_nodes"] == base
+        for lev in range(info["n_levels"]):
+            eb = S.export_level(lib, hb, lev)
+            off = 0
+            for i in order:
+                si = S.handle_info(lib, singles[i])
+                if lev >= si["n_levels"]:
+                    continue
+                es = S.export_level(lib, singles[i], lev)
+                n1 = si["level_nodes"][lev]
+                sl = slice(off, off + n1)
+                np.testing.assert_array_equal(eb["nbr"][:, sl], es["nbr"] + off)
+                for k in ("A", "S") + (("B", "Bt", "Cb") if lev == 0 else ()):
+                    np.testing.assert_array_equal(eb[k][..., sl], es[k])
+                off += (n1 + 255) // 256 * 256
+            assert off == info["level_nodes"][lev]
+    finally:
+        for h in [hb] + singles:
+            lib.biot_destroy(h)
+
+
+def test_general_load_is_accepted_and_checked():
+    """The general right-hand side of biot_load: load terms, prescribed values
+    and X^0 are taken; bad counts, non-finite values and an adjoint handle with
+    nonzero prescribed values are rejected with messages."""
+    lib = _lib.load()
+    pb = W.general_rhs_problem(6, 4, seed=3)
+    h, _ = S.create_handle(pb)
+    lib.biot_destroy(h)
+    bad = W.general_rhs_problem(6, 4, seed=3, n_terms=9)
+    with pytest.raises(_lib.BiotError, match="n_terms"):
+        S.create_handle(bad)
+    bad = W.general_rhs_problem(6, 4, seed=3)
+    bad.terms[0, 3, 1] = np.nan
+    with pytest.raises(_lib.BiotError, match="non-finite"):
+        S.create_handle(bad)
+    with pytest.raises(_lib.BiotError, match="adjoint"):
+        S.create_handle(W.general_rhs_problem(6, 4, seed=3), adjoint=True)
+    # X^0 alone, zero at the prescribed dofs, is fine for the adjoint
+    pb = W.terzaghi_problem(6, 4)
+    x0 = np.random.default_rng(1).standard_normal((pb.n_nodes, 3))
+    mask = np.stack([(pb.flags >> c) & 1 for c in range(3)], axis=1).astype(bool)
+    x0[mask] = 0.0
+    pb.x0 = x0
+    h, _ = S.create_handle(pb, adjoint=True)
+    lib.biot_destroy(h)
+    # batches need the same right-hand-side structure
+    pbs = [W.general_rhs_problem(6, 4, seed=3), W.terzaghi_problem(6, 4)]
+    with pytest.raises(_lib.BiotError, match="structure"):
+        S.create_handle(pbs)

@@ -174,3 +174,53 @@ def test_printed_source_sign_is_inconsistent():
     pb, X = analytic.mms_solve(32, 1 / 256, 256)
     e_ok = analytic.l2_error_p(pb, X, 1.0)
     assert e_printed > 5 * e_ok
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_general_rhs_identity_row_brute_force(dim):
+    """General right-hand side (load terms, prescribed values, X^0) against the
+    space-time system written with identity rows for the prescribed dofs:
+    free rows AA X^n - A' X^{n-1} = f^n, prescribed rows X^n = g^n, solved
+    densely for all dofs of all steps.  The oracle instead eliminates the
+    prescribed dofs and lifts g^n and g^{n-1} into the right-hand side."""
+    pb = W.general_rhs_problem(3 if dim == 2 else 2, 4, seed=5, dim=dim)
+    pb.dt = 0.05
+    orc = seq.BiotOracle(pb)
+    X = orc.solve_sequential()
+    AA, Ap = orc.AA.toarray(), orc.Ap.toarray()
+    fx = orc.fixed
+    nd, N = AA.shape[0], pb.n_steps
+    X0 = fem.node_to_field_major(pb.x0)
+    M = np.zeros((N * nd, N * nd))
+    rhs = np.zeros(N * nd)
+    for n in range(N):
+        blk = slice(n * nd, (n + 1) * nd)
+        A_n = AA.copy()
+        A_n[fx] = 0.0
+        A_n[fx, fx] = 1.0
+        M[blk, blk] = A_n
+        C = Ap.copy()
+        C[fx] = 0.0
+        if n > 0:
+            M[blk, (n - 1) * nd:n * nd] = -C
+        f = pb.load_coef[n + 1] * orc.F_unit
+        f = f + pb.term_coef[n + 1] @ fem.node_to_field_major(pb.terms)
+        g = pb.prescribed_coef[n + 1] @ fem.node_to_field_major(pb.prescribed)
+        r = np.where(fx, g, f)
+        if n == 0:
+            r = r + np.where(fx, 0.0, C @ X0)
+        rhs[blk] = r
+    Xd = np.linalg.solve(M, rhs).reshape(N, nd)
+    assert np.abs(X[0] - X0).max() == 0.0
+    scale = np.abs(Xd).max()
+    assert np.abs(X[1:] - Xd).max() < 1e-11 * scale
+
+
+def test_generic_load_path_reproduces_the_manufactured_solve():
+    """The oracle's generic right-hand side (load terms, prescribed values,
+    X^0) fed with the manufactured problem's inputs reproduces the separately
+    written manufactured-solution solve (its own quadrature and lifting)."""
+    pb = W.mms_problem(16, 1 / 64, 12)
+    X = seq.BiotOracle(pb).solve_sequential()
+    _, Xm = analytic.mms_solve(16, 1 / 64, 12, trajectory=True)
+    assert np.abs(X - Xm).max() < 1e-12 * np.abs(Xm).max()
