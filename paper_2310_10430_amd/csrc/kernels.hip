@@ -60,6 +60,22 @@ __device__ inline int grid_nodes(int cells) {
   return DIM == 2 ? m * m : m * m * m;
 }
 
+// Copy of a node block, a copy's first node and its cells per side; a level
+// with one copy (a single problem) takes them from the kernel arguments
+// rather than from the tables, which saves a dependent load per piece.
+template <typename T>
+__device__ inline int block_copy(const LevelView<T>& L, int nblk) {
+  return L.copies == 1 ? 0 : L.bcopy[nblk];
+}
+template <typename T>
+__device__ inline int copy_base(const LevelView<T>& L, int cp) {
+  return L.copies == 1 ? 0 : L.cbase[cp];
+}
+template <typename T>
+__device__ inline int copy_cells(const LevelView<T>& L, int cp) {
+  return L.copies == 1 ? L.n_cells : L.ccells[cp];
+}
+
 // Shrinks the column range [cbeg, cend) of a launch to the columns active for
 // copy cp (a sample skips the steps past its own count); they are contiguous.
 template <typename T>
@@ -164,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
   __shared__ double lds[4 * 4 * NQ];
   const int nn = L.nn;
   for_each_piece<!STAT>(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
-    active_cols(L, L.bcopy[nblk], cbeg, cend);
+    if (L.act) active_cols(L, L.bcopy[nblk], cbeg, cend);
     if (cbeg >= cend) return;
     const int v = nblk * kBlock + threadIdx.x;
     const bool active = v < L.nact;
@@ -360,9 +376,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
 template <int DIM, int C, typename T>
 __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T>& Lc, int bit0,
                                        int cp, int f, int& p0, int& p1, unsigned& mask) {
-  const int cf = Lf.ccells[cp];
-  const int mf = cf + 1, mc = Lc.ccells[cp] + 1;
-  const int fb = Lf.cbase[cp], cb = Lc.cbase[cp];
+  const int cf = copy_cells(Lf, cp);
+  const int mf = cf + 1, mc = copy_cells(Lc, cp) + 1;
+  const int fb = copy_base(Lf, cp), cb = copy_base(Lc, cp);
   const int lf = f - fb;  // node within the copy
   if (lf >= grid_nodes<DIM>(cf)) {  // padding node: no parents
     p0 = p1 = cb;
@@ -423,7 +439,7 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
   for_each_piece<!STAT>(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
-    active_cols(L, L.bcopy[nblk], cbeg, cend);
+    if (L.act) active_cols(L, L.bcopy[nblk], cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
     if (v >= L.nact || cbeg >= cend) return;
     // C > 1 is the displacement field (A), C == 1 the pressure field (S)
@@ -589,11 +605,12 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
     if (slot >= L.npatch * groups) return;
     // patch of a copy (sample of a batch; copies may differ in size)
     const int gp = slot / groups;
-    const int cp = L.ptab[2 * gp], patch = L.ptab[2 * gp + 1];
-    const int m = L.ccells[cp] + 1, base = L.cbase[cp];
+    const bool one = L.copies == 1;
+    const int cp = one ? 0 : L.ptab[2 * gp], patch = one ? gp : L.ptab[2 * gp + 1];
+    const int m = copy_cells(L, cp) + 1, base = copy_base(L, cp);
     const int per_side = (m + kPatchIn - 1) / kPatchIn;
     int cbeg = (slot % groups) * run, cend = min(nc, cbeg + run);
-    active_cols(L, cp, cbeg, cend);
+    if (L.act) active_cols(L, cp, cbeg, cend);
     if (cbeg >= cend) return;
     const int i0 = (patch % per_side) * kPatchIn - 1, j0 = (patch / per_side) * kPatchIn - 1;
     const int gi = i0 + li, gj = j0 + lj;
@@ -718,8 +735,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelView<T> Lf, LevelView<T
                                                     T* __restrict__ xout, int nc) {
   const int nn = Lf.nn;
   for_each_piece(num_node_blocks(Lf.nact), nc, [&](int nblk, int cbeg, int cend) {
-    const int cp = Lf.bcopy[nblk];
-    active_cols(Lf, cp, cbeg, cend);
+    const int cp = block_copy(Lf, nblk);
+    if (Lf.act) active_cols(Lf, cp, cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
     if (v >= Lf.nact || cbeg >= cend) return;
     int p0, p1;
@@ -766,7 +783,7 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelView<T> L, int i
   constexpr int SU = STAT ? W : 3;  // slot-loop unrolling (full when the row is in registers)
   const int nn = L.nn;
   for_each_piece<!STAT>(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
-    active_cols(L, L.bcopy[nblk], cbeg, cend);
+    if (L.act) active_cols(L, L.bcopy[nblk], cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
     if (v >= L.nact || cbeg >= cend) return;
     const T* K = isA ? L.A : L.S;
@@ -832,12 +849,13 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
   constexpr int W = DIM == 2 ? 7 : 15;
   const int I = blockIdx.y * kBlock + threadIdx.x;
   const int c = blockIdx.x;
-  const int cp = Lc.bcopy[blockIdx.y];
+  const int cp = block_copy(Lc, blockIdx.y);
   if (I >= Lc.nact || !col_active(Lc, cp, c)) return;
-  const int mc = Lc.ccells[cp] + 1, mf = Lf.ccells[cp] + 1;
-  const int lI = I - Lc.cbase[cp];  // node within the copy
-  const bool real = lI < grid_nodes<DIM>(Lc.ccells[cp]);
-  const int fbase = Lf.cbase[cp];
+  const int ccl = copy_cells(Lc, cp);
+  const int mc = ccl + 1, mf = copy_cells(Lf, cp) + 1;
+  const int lI = I - copy_base(Lc, cp);  // node within the copy
+  const bool real = lI < grid_nodes<DIM>(ccl);
+  const int fbase = copy_base(Lf, cp);
   int ci = 0, cj = 0, ck = 0;
   if (real) node_coords<DIM>(lI, mc, ci, cj, ck);
   const uint8_t fc = Lc.fixed[I];
@@ -1059,7 +1077,7 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
   __shared__ int s_nr[kTailMaxLevels], s_base[kTailMaxLevels], s_cells[kTailMaxLevels],
       s_off[kTailMaxLevels];
   const int copies = TD.copies;
-  const int c = blockIdx.x / copies, cp = blockIdx.x - c * copies;
+  const int c = blockIdx.x / copies, cp = TD.cp0 + (blockIdx.x - c * copies);
   const TailCopy* tcp = TD.tc + cp;
   const int t0 = tcp->t0, nl = tcp->nlev;  // the last one is solved densely
   if (!col_active(TD.L[t0], cp, c)) return;  // past this sample's steps
@@ -1238,7 +1256,7 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
   constexpr int W = DIM == 2 ? 7 : 15;
   const int nn = L.nn;
   for_each_piece(num_node_blocks(L.nact), nc, [&](int nblk, int cbeg, int cend) {
-    active_cols(L, L.bcopy[nblk], cbeg, cend);
+    if (L.act) active_cols(L, L.bcopy[nblk], cbeg, cend);
     const int v = nblk * kBlock + threadIdx.x;
     if (v >= L.nact || cbeg >= cend) return;
     int nb[W];

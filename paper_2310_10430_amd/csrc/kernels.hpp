@@ -142,7 +142,8 @@ struct TailCopy {
 };
 template <typename T>
 struct TailDev {
-  int degree, copies;             // copies with a tail (all copies of the handle)
+  int degree;
+  int cp0, copies;                // the launch covers copies cp0 .. cp0+copies-1
   LevelView<T> L[kMaxLevels];     // every level of the hierarchy
   double theta[kMaxLevels], delta[kMaxLevels], sigma[kMaxLevels];
   const TailCopy* tc;             // [copies]

@@ -63,6 +63,10 @@ struct Prec {
   TailDev<T> tdA{}, tdS{};
   std::vector<TailCopy> tcA, tcS;     // host copies of the per-copy descriptors
   size_t ldsA = 0, ldsS = 0;          // LDS bytes of a tail workgroup (largest copy)
+  // tail launches: runs of consecutive copies with the same tail shape, each
+  // launched with its own LDS size (first copy, copies, LDS bytes)
+  struct TailGroup { int cp0, n; size_t lds; };
+  std::vector<TailGroup> tgA, tgS;
   // per level: copies (a prefix) that run the level as their own launches
   std::vector<int> standA, standS;
 };
@@ -279,6 +283,8 @@ void plan_tail(biot_handle* h, Bump& b, Prec<T>& p, bool is_A) {
   std::vector<TailCopy>& tcs = is_A ? p.tcA : p.tcS;
   size_t& lds = is_A ? p.ldsA : p.ldsS;
   std::vector<int>& stand = is_A ? p.standA : p.standS;
+  auto& groups = is_A ? p.tgA : p.tgS;
+  groups.clear();
   const size_t budget = std::min(kTailMaxLds, h->tail_lds);
   tcs.assign(copies, TailCopy{});
   lds = 0;
@@ -309,6 +315,11 @@ void plan_tail(biot_handle* h, Bump& b, Prec<T>& p, bool is_A) {
       tc.moff = is_A ? h->P.cAoff[cp] : h->P.cSoff[cp];
       lds = std::max(lds, bytes);
       ++with;
+      // copies are ordered largest first: a new group where the shape changes
+      if (groups.empty() || groups.back().lds != bytes ||
+          tcs[groups.back().cp0].t0 != tc.t0 || groups.back().cp0 + groups.back().n != cp)
+        groups.push_back({cp, 0, bytes});
+      groups.back().n += 1;
       break;
     }
   }
@@ -324,6 +335,7 @@ void plan_tail(biot_handle* h, Bump& b, Prec<T>& p, bool is_A) {
     }
   td = TailDev<T>{};
   td.degree = h->opt.cheb_degree;
+  td.cp0 = 0;
   td.copies = copies;
   for (int l = 0; l < h->nlev && l < kMaxLevels; ++l) {
     td.L[l] = p.L[l];
@@ -842,8 +854,14 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
       td.b[i] = f.b[i];
       td.x[i] = rb ? f.x1[i] : f.x0[i];
     }
-    launch_vcycle_tail<T>(h->dim, C, td, nc, is_A ? p.ldsA : p.ldsS, st);
-    LAUNCHCHK(h);
+    // one launch per run of copies with the same tail shape, each with the
+    // LDS its copies need (small grids then keep more workgroups resident)
+    for (const auto& g : is_A ? p.tgA : p.tgS) {
+      td.cp0 = g.cp0;
+      td.copies = g.n;
+      launch_vcycle_tail<T>(h->dim, C, td, nc, g.lds, st);
+      LAUNCHCHK(h);
+    }
     h->acct += bytes_tail(h, is_A ? p.tcA : p.tcS, C, nc, tb);
     *out = result_buffer(h) ? f.x1[l] : f.x0[l];
     return BIOT_OK;
