@@ -171,9 +171,10 @@ typedef struct {
   int32_t max_sensors;     /* capacity of the objective's sensor list (256)        */
   int32_t inner;           /* BIOT_INNER_* : what one unit does (RICHARDSON)       */
   int32_t gmres_k;         /* GMRES iterations per unit, 1..8 (4); omega unused    */
-  int32_t fuse_post;       /* 1: in 2D with smoother degree 2, run both post-      */
-                           /* smoothing steps of a level in one launch (same      */
-                           /* result bit for bit); 0: two launches (1)            */
+  int32_t fuse_post;       /* 1: in 2D with smoother degree 2, run a level's      */
+                           /* coarse-grid correction and both post-smoothing      */
+                           /* steps in one launch (same result bit for bit);      */
+                           /* 0: three launches (1)                               */
 } biot_options;
 
 /* Pressure-misfit objective J = sum_{n=1..N} sum_s (p^n(node_s) - p_obs[n-1][s])^2. */
@@ -346,9 +347,10 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
 #define BIOT_PROBE_LEVRES_U 3     /* displacement residual before restriction    */
 #define BIOT_PROBE_LEVRES_P 4     /* pressure residual before restriction        */
 #define BIOT_PROBE_PSTAGE 5       /* P1 pressure stage t = B' z_u - r_p          */
-#define BIOT_PROBE_POST_U 6       /* displacement post-smoothing, both steps in  */
-                                  /* one launch (2D, degree 2, fuse_post), on   */
-                                  /* every level outside the fused tail         */
+#define BIOT_PROBE_POST_U 6       /* displacement coarse-grid correction and     */
+                                  /* post-smoothing, both steps in one launch   */
+                                  /* (2D, degree 2, fuse_post), on every level  */
+                                  /* outside the fused tail                     */
 #define BIOT_PROBE_POST_P 7       /* the same for the pressure field (not on     */
                                   /* level 0 in sweeps, whose last step writes  */
                                   /* the outer update)                          */

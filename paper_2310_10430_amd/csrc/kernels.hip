@@ -558,46 +558,65 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
   });
 }
 
-// The two post-smoothing steps of degree 2 on a structured 2D level, fused
-// (each sample copy of a batch has its own patches; the padding nodes of a
-// copy are not written, and hold the zeros the preceding steps wrote there):
+// A workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for its global stores (which __syncthreads also waits for,
+// to publish them to the workgroup; nothing here reads them back).
+__device__ inline void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// The coarse-grid correction and the two post-smoothing steps of degree 2 on
+// a structured 2D level, fused (each sample copy of a batch has its own
+// patches; the padding nodes of a copy are not written, and hold the zeros the
+// level residual wrote to x4's buffer there):
+//   x2 = x + P xc                                   (coarse-grid correction)
 //   x3 = x2 + c2a D^{-1}(b - K x2)                  (first step, no increment)
 //   x4 = x3 + c1b (x3 - x2) + c2b D^{-1}(b - K x3)  (second step)
-// with the arithmetic of two k_cheb launches, so the result is the same bit
-// for bit.  A workgroup takes a kPatch x kPatch patch of grid nodes, one per
-// thread, whose operator rows stay in registers over the columns: every node
-// of the patch forms x3 into LDS, then the interior (the patch without its
-// outer ring) forms x4 from its neighbours' x3 there.  Patches step by the
-// interior width, so each node is the interior of exactly one patch.  x2 and
-// x4 are different buffers (other patches gather x2 around their rings).
-// Columns are software-pipelined through two LDS buffers: between two
-// barriers a workgroup gathers and forms x3 of the next column while it forms
-// x4 of the current one, so the gathers' latency overlaps the second step
-// (one column per stage; two per stage took more registers and ran slower).
+// with the arithmetic of k_prolong and two k_cheb launches, so the result is
+// the same bit for bit.  A workgroup takes a kPatch x kPatch patch of grid
+// nodes, one per thread, whose operator rows stay in registers over the
+// columns.  Per column, the workgroup forms x2 over the patch and one more
+// ring (kReg x kReg nodes, into LDS; x2 never goes to global memory), then
+// every node of the patch forms x3 from x2 there (into LDS), then the interior
+// (the patch without its outer ring) forms x4 from its neighbours' x3.
+// Patches step by the interior width, so each node is the interior of exactly
+// one patch.  x and x4 are different buffers (other patches read x around
+// their rings).
+// Columns are software-pipelined: between two barriers a workgroup loads and
+// forms x2 of the next column while it forms x4 of the current one, so the
+// loads' latency overlaps the second step; x3 sits in two LDS buffers.
 // Work split: the columns of each patch are cut into `groups` runs of `run`
 // columns, one workgroup each, all resident at once, so that neighbouring
 // patches walk through the same columns together and share the ring rows they
-// gather in L2; workgroup i goes to XCD i % 8, and each XCD is given a
+// read in L2; workgroup i goes to XCD i % 8, and each XCD is given a
 // contiguous range of (patch, run) pairs, i.e. neighbouring patches.
 constexpr int kPatch = 16;
 constexpr int kPatchIn = kPatchInterior;
+constexpr int kReg = kPatch + 2;  // x2 region: the patch and one more ring
 static_assert(kPatchIn == kPatch - 2, "a patch's interior drops its outer ring");
 static_assert(kPatch * kPatch == kBlock, "one patch node per thread");
+static_assert(kReg * kReg <= 2 * kBlock, "two x2 region nodes per thread at most");
+
+template <int DIM, int C, typename T>
+__device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T>& Lc, int bit0,
+                                       int cp, int f, int& p0, int& p1, unsigned& mask);
 
 template <int C, typename T>
-__global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
+__global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, LevelView<T> Lc, int isA,
                                                   const T* __restrict__ b,
-                                                  const T* __restrict__ x2,
+                                                  const T* __restrict__ xin,
+                                                  const T* __restrict__ xc,
                                                   T* __restrict__ x4, int nc, T c2a, T c1b,
                                                   T c2b, int groups, int run) {
-  constexpr int W = 7, NQ = 1;
+  constexpr int W = 7;
   // per buffer: x3, and the node's own x2 and b, of the patch's nodes
-  __shared__ T sh[2][3][NQ][kBlock][C];
+  __shared__ T sh[2][3][kBlock][C];
+  __shared__ T sx2[kReg * kReg][C];  // x2 over the region
   const int nn = L.nn;
   const int li = threadIdx.x % kPatch, lj = threadIdx.x / kPatch;
   const T* K = isA ? L.A : L.S;
   const T* Dg = isA ? L.Ainv : L.Sinv;
-  const size_t stride = size_t(nn) * C;
+  const size_t stride = size_t(nn) * C, cstride = size_t(Lc.nn) * C;
   int buf = 0;
   {
     const int P = gridDim.x, i = blockIdx.x;  // P is a multiple of 8
@@ -627,100 +646,142 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, int isA,
     }
 #pragma unroll
     for (int e = 0; e < C * C; ++e) Di[e] = node ? Dg[size_t(e) * nn + v] : T(0);
-    int ls[W];
+    // neighbours in the patch (x3) and in the region (x2), and the node's own
+    // place in the region
+    int ls[W], lr[W];
 #pragma unroll
-    for (int s = 0; s < W; ++s)
-      ls[s] = ((nb[s] - base) % m - i0) + ((nb[s] - base) / m - j0) * kPatch;
-    auto phase1 = [&](int c, int bb) {
-      if (!node) return;
-      int cc[NQ];
+    for (int s = 0; s < W; ++s) {
+      const int ni = (nb[s] - base) % m, nj = (nb[s] - base) / m;
+      ls[s] = (ni - i0) + (nj - j0) * kPatch;
+      lr[s] = (ni - i0 + 1) + (nj - j0 + 1) * kReg;
+    }
+    const int own = (li + 1) + (lj + 1) * kReg;
+    // this thread's region nodes (r = threadIdx.x, threadIdx.x + kBlock) and
+    // their parents on the coarse level, for every column
+    int rf[2], rp0[2], rp1[2];
+    unsigned rpm[2];
+    bool rv[2];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) cc[q] = min(c + q, cend - 1);
-      T acc[NQ][C], x2o[NQ][C];
+    for (int k = 0; k < 2; ++k) {
+      const int r = threadIdx.x + k * kBlock;
+      const int ri = i0 - 1 + r % kReg, rj = j0 - 1 + r / kReg;
+      rv[k] = r < kReg * kReg && ri >= 0 && ri < m && rj >= 0 && rj < m;
+      rf[k] = base + (rv[k] ? rj * m + ri : 0);
+      rp0[k] = rp1[k] = copy_base(Lc, cp);
+      rpm[k] = 0u;
+      if (rv[k]) prolong_parents<2, C>(L, Lc, isA ? 0 : 2, cp, rf[k], rp0[k], rp1[k], rpm[k]);
+    }
+    // x2 = x + P xc over the region (k_prolong's arithmetic): the loads, with
+    // the node's b (kept for phase1, which runs after a barrier), are issued
+    // before phase2 of the previous column and the sums stored after it
+    T bnext[C], xv[2][C], q0[2][C], q1[2][C];
+    auto phase0_load = [&](int c) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
+      for (int a = 0; a < C; ++a) bnext[a] = node ? b[size_t(c) * stride + size_t(v) * C + a] : T(0);
+      // unconditional (a region node outside the grid reads the copy's first
+      // node and its value is not used), so that all are in flight together
 #pragma unroll
-        for (int a = 0; a < C; ++a) {
-          const T bv = b[size_t(cc[q]) * stride + size_t(v) * C + a];
-          acc[q][a] = bv;
-          sh[bb][2][q][threadIdx.x][a] = bv;
-        }
-#pragma unroll
-      for (int s = 0; s < W; ++s)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          T xw[C];
-#pragma unroll
-          for (int k = 0; k < C; ++k) xw[k] = x2[size_t(cc[q]) * stride + size_t(nb[s]) * C + k];
-          if (s == 0)
-#pragma unroll
-            for (int k = 0; k < C; ++k) x2o[q][k] = xw[k];
-#pragma unroll
-          for (int a = 0; a < C; ++a) {
-            T s2 = T(0);
-#pragma unroll
-            for (int k = 0; k < C; ++k) s2 += kr[s][a * C + k] * xw[k];
-            acc[q][a] -= T(1) * s2;
-          }
-        }
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
+      for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int a = 0; a < C; ++a) {
-          T z = T(0);
-#pragma unroll
-          for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
-          const T dn = fma(c2a, z, T(0) * T(0));
-          sh[bb][0][q][threadIdx.x][a] = x2o[q][a] + dn;
-          sh[bb][1][q][threadIdx.x][a] = x2o[q][a];
+          xv[k][a] = xin[size_t(c) * stride + size_t(rf[k]) * C + a];
+          q0[k][a] = xc[size_t(c) * cstride + size_t(rp0[k]) * C + a];
+          q1[k][a] = xc[size_t(c) * cstride + size_t(rp1[k]) * C + a];
         }
     };
-    auto phase2 = [&](int c, int bb) {
-      if (!inner) return;
-      T acc[NQ][C];
+    auto phase0_store = [&]() {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int a = 0; a < C; ++a) acc[q][a] = sh[bb][2][q][threadIdx.x][a];
-#pragma unroll
-      for (int s = 0; s < W; ++s)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          T xw[C];
-#pragma unroll
-          for (int k = 0; k < C; ++k) xw[k] = sh[bb][0][q][ls[s]][k];
-#pragma unroll
-          for (int a = 0; a < C; ++a) {
-            T s2 = T(0);
-#pragma unroll
-            for (int k = 0; k < C; ++k) s2 += kr[s][a * C + k] * xw[k];
-            acc[q][a] -= T(1) * s2;
-          }
-        }
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if (c + q >= cend) break;
-        const int col = c + q;
+      for (int k = 0; k < 2; ++k) {
+        if (!rv[k]) continue;
+        const T wt = (rpm[k] >> (2 * C)) ? T(0.5) : T(1);
 #pragma unroll
         for (int a = 0; a < C; ++a) {
-          T z = T(0);
-#pragma unroll
-          for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[q][k];
-          const T x3 = sh[bb][0][q][threadIdx.x][a];
-          const T dp = x3 - sh[bb][1][q][threadIdx.x][a];
-          const T dn = fma(c2b, z, c1b * dp);
-          x4[size_t(col) * stride + size_t(v) * C + a] = x3 + dn;
+          T x = xv[k][a];
+          if ((rpm[k] >> a) & 1u) x += wt * q0[k][a];
+          if ((rpm[k] >> (C + a)) & 1u) x += wt * q1[k][a];
+          sx2[threadIdx.x + k * kBlock][a] = x;
         }
       }
     };
-    // stage c: x3 of column c into buffer buf (prologue), then per column the
-    // next column's x3 into the other buffer and this column's x4
+    // x3 of the patch's nodes from x2 in LDS
+    auto phase1 = [&](int c, int bb) {
+      if (!node) return;
+      T acc[C], x2o[C];
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        const T bv = bnext[a];  // b of column c, loaded by phase0(c)
+        acc[a] = bv;
+        sh[bb][2][threadIdx.x][a] = bv;
+        x2o[a] = sx2[own][a];
+      }
+#pragma unroll
+      for (int s = 0; s < W; ++s) {
+        T xw[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) xw[k] = sx2[lr[s]][k];
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          T s2 = T(0);
+#pragma unroll
+          for (int k = 0; k < C; ++k) s2 += kr[s][a * C + k] * xw[k];
+          acc[a] -= T(1) * s2;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        T z = T(0);
+#pragma unroll
+        for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[k];
+        const T dn = fma(c2a, z, T(0) * T(0));
+        sh[bb][0][threadIdx.x][a] = x2o[a] + dn;
+        sh[bb][1][threadIdx.x][a] = x2o[a];
+      }
+    };
+    // x4 of the interior from x3 in LDS
+    auto phase2 = [&](int c, int bb) {
+      if (!inner) return;
+      T acc[C];
+#pragma unroll
+      for (int a = 0; a < C; ++a) acc[a] = sh[bb][2][threadIdx.x][a];
+#pragma unroll
+      for (int s = 0; s < W; ++s) {
+        T xw[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) xw[k] = sh[bb][0][ls[s]][k];
+#pragma unroll
+        for (int a = 0; a < C; ++a) {
+          T s2 = T(0);
+#pragma unroll
+          for (int k = 0; k < C; ++k) s2 += kr[s][a * C + k] * xw[k];
+          acc[a] -= T(1) * s2;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < C; ++a) {
+        T z = T(0);
+#pragma unroll
+        for (int k = 0; k < C; ++k) z += Di[a * C + k] * acc[k];
+        const T x3 = sh[bb][0][threadIdx.x][a];
+        const T dp = x3 - sh[bb][1][threadIdx.x][a];
+        const T dn = fma(c2b, z, c1b * dp);
+        x4[size_t(c) * stride + size_t(v) * C + a] = x3 + dn;
+      }
+    };
+    // prologue: x2 and x3 of the first column; then per column, x2 of the next
+    // column with x4 of this one, and after a barrier x3 of the next column
+    phase0_load(cbeg);
+    phase0_store();
+    __syncthreads();
     phase1(cbeg, buf);
 #pragma unroll 1
-    for (int c = cbeg; c < cend; c += NQ) {
-      __syncthreads();
-      if (c + NQ < cend) phase1(c + NQ, buf ^ 1);
+    for (int c = cbeg; c < cend; ++c) {
+      lds_barrier();
+      const bool more = c + 1 < cend;
+      if (more) phase0_load(c + 1);
       phase2(c, buf);
+      if (more) phase0_store();
+      lds_barrier();
+      if (more) phase1(c + 1, buf ^ 1);
       buf ^= 1;
     }
   }
@@ -1277,16 +1338,26 @@ __global__ __launch_bounds__(kBlock) void k_pstage(LevelView<T> L, const T* __re
 #pragma unroll
       for (int q = 0; q < NQ; ++q) acc[q] = -rp[size_t(cc[q]) * nn + v];
       if (p1) {
+        // all neighbour loads first: left to itself the compiler interleaves
+        // them with the sums (to stay within the registers of 8 waves per
+        // SIMD), one load in flight at a time (35.7 against 43.4 us per
+        // level-0 launch of 64 columns)
+        T z[W][NQ][DIM];
 #pragma unroll
-        for (int s = 0; s < W; ++s) {
-          const int w = nb[s];
+        for (int s = 0; s < W; ++s)
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            const size_t base = size_t(cc[q]) * nn * DIM + size_t(w) * DIM;
+            const size_t base = size_t(cc[q]) * nn * DIM + size_t(nb[s]) * DIM;
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) acc[q] += bt[s][k] * zu[base + k];
+            for (int k = 0; k < DIM; ++k) z[s][q][k] = zu[base + k];
           }
-        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < W; ++s)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) acc[q] += bt[s][k] * z[s][q][k];
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -1616,8 +1687,9 @@ void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* 
 }
 
 template <typename T>
-void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const T* x2, T* x4,
-                  int nc, double c2a, double c1b, double c2b, int wpc, hipStream_t st) {
+void launch_post2(int comps, const LevelView<T>& L, const LevelView<T>& Lc, bool is_A, const T* b,
+                  const T* xin, const T* xc, T* x4, int nc, double c2a, double c1b, double c2b,
+                  int wpc, hipStream_t st) {
   const int patches = L.npatch;
   // runs per patch: as many as keep about one wave of resident workgroups
   // (3 per CU) busy, at most one per column
@@ -1626,11 +1698,11 @@ void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const
   const dim3 grid(unsigned((patches * groups + 7) / 8 * 8));
   (void)wpc;
   if (comps == 1)
-    BIOT_LAUNCH_GRID((k_post2<1, T>), grid, st, L, int(is_A), b, x2, x4, nc, T(c2a), T(c1b),
-                     T(c2b), groups, run);
+    BIOT_LAUNCH_GRID((k_post2<1, T>), grid, st, L, Lc, int(is_A), b, xin, xc, x4, nc, T(c2a),
+                     T(c1b), T(c2b), groups, run);
   else
-    BIOT_LAUNCH_GRID((k_post2<2, T>), grid, st, L, int(is_A), b, x2, x4, nc, T(c2a), T(c1b),
-                     T(c2b), groups, run);
+    BIOT_LAUNCH_GRID((k_post2<2, T>), grid, st, L, Lc, int(is_A), b, xin, xc, x4, nc, T(c2a),
+                     T(c1b), T(c2b), groups, run);
 }
 
 template <typename T>
@@ -1775,8 +1847,9 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
   template void launch_cheb<T>(int, int, const LevelView<T>&, bool, const T*, const T*, T*, T*,  \
                                int, double, double, bool, int, bool, double, const ColDesc*,     \
                                const T*, double, int, bool, hipStream_t);                         \
-  template void launch_post2<T>(int, const LevelView<T>&, bool, const T*, const T*, T*, int,    \
-                                double, double, double, int, hipStream_t);                        \
+  template void launch_post2<T>(int, const LevelView<T>&, const LevelView<T>&, bool, const T*,  \
+                                const T*, const T*, T*, int, double, double, double, int,         \
+                                hipStream_t);                                                     \
   template void launch_level_residual<T>(int, int, const LevelView<T>&, bool, const T*,          \
                                          const T*, T*, int, int, hipStream_t);                    \
   template void launch_restrict<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,     \

@@ -113,11 +113,13 @@ void launch_restrict(int dim, int comps, const LevelView<T>& Lf, const LevelView
 template <typename T>
 void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<T>& Lc, bool is_A,
                     const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st);
-// the two post-smoothing steps of degree 2 fused (2D, any number of samples): x2 -> x4,
-// with the first step's c2 and the second step's c1, c2 (k_post2)
+// the coarse-grid correction x2 = x + P xc and the two post-smoothing steps of
+// degree 2, fused (2D, any number of samples): x, xc -> x4, with the first
+// step's c2 and the second step's c1, c2 (k_post2); x2 is not stored
 template <typename T>
-void launch_post2(int comps, const LevelView<T>& L, bool is_A, const T* b, const T* x2, T* x4,
-                  int nc, double c2a, double c1b, double c2b, int wpc, hipStream_t st);
+void launch_post2(int comps, const LevelView<T>& L, const LevelView<T>& Lc, bool is_A, const T* b,
+                  const T* xin, const T* xc, T* x4, int nc, double c2a, double c1b, double c2b,
+                  int wpc, hipStream_t st);
 // dense coarsest solve per column and copy: n grid dofs per copy, `stride` dofs
 // per copy with padding, Minv = copies dense inverses
 template <typename T>

@@ -254,17 +254,21 @@ int scratch_address(biot_handle* h, int dev, char** out) {
   return BIOT_OK;
 }
 
-// Buffer (0: x0, 1: x1) that holds a level's V-cycle result when the level
-// runs as its own launches (not the level-0 pressure field, which writes the
-// outer update): each smoothing step and the prolongation swap the iterates.
-int result_buffer(const biot_handle* h) {
+// Vector that holds a level's V-cycle result, whether the level runs as its
+// own launches (not the level-0 pressure field, which writes the outer update)
+// or in the fused tail: with the fused coarse-grid correction and
+// post-smoothing (2D, degree 2) the level's residual buffer, free after the
+// restriction; otherwise x0 or x1, as each smoothing step and the
+// prolongation swap the iterates.
+template <typename T>
+T* result_vec(const biot_handle* h, const Field<T>& f, int l) {
   const int deg = h->opt.cheb_degree;
+  if (h->opt.fuse_post && deg == 2 && h->dim == 2) return f.r[l];
   int cur = 0;
   for (int j = 2; j <= deg; ++j) cur ^= 1;  // pre-smoothing
   cur ^= 1;                                 // coarse-grid correction
-  if (h->opt.fuse_post && deg == 2 && h->dim == 2) return cur ^ 1;
   for (int j = 1; j <= deg; ++j) cur ^= 1;
-  return cur;
+  return cur ? f.x1[l] : f.x0[l];
 }
 
 // The coarsest levels of a copy whose V-cycle vectors fit in the LDS of one
@@ -754,9 +758,12 @@ double bytes_levres(const biot_handle* h, int l, int k, int C, int nc, int t) {
   const double nn = act_nodes(h, l, k), W = h->P.levels[l].W;
   return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W);
 }
+// the coarse-grid correction and both post-smoothing steps: b, x, xc in, x4
+// out; the operator row, D^{-1}, indices and the fine and coarse flags once
 double bytes_post2(const biot_handle* h, int l, int k, int C, int nc, int t) {
-  const double nn = act_nodes(h, l, k), W = h->P.levels[l].W;
-  return nc * nn * C * t * 3 + nn * (W * C * C * t + 4 * W + C * C * t);  // b, x2 -> x4
+  const double nn = act_nodes(h, l, k), ncs = act_nodes(h, l + 1, k), W = h->P.levels[l].W;
+  return nc * (nn * C * t * 3 + ncs * C * t) + nn * (W * C * C * t + 4 * W + C * C * t) +
+         (nn + ncs);
 }
 double bytes_pstage(const biot_handle* h, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
@@ -848,11 +855,10 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   if (k == 0 && has_tail) {
     // the work vectors in use now (a caller-less apply may swap in others)
     TailDev<T> td = is_A ? p.tdA : p.tdS;
-    const int rb = result_buffer(h);
     for (int i = 0; i < h->nlev && i < kMaxLevels; ++i) {
       td.L[i].act = act;
       td.b[i] = f.b[i];
-      td.x[i] = rb ? f.x1[i] : f.x0[i];
+      td.x[i] = result_vec(h, f, i);
     }
     // one launch per run of copies with the same tail shape, each with the
     // LDS its copies need (small grids then keep more workgroups resident)
@@ -863,7 +869,7 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
       LAUNCHCHK(h);
     }
     h->acct += bytes_tail(h, is_A ? p.tcA : p.tcS, C, nc, tb);
-    *out = result_buffer(h) ? f.x1[l] : f.x0[l];
+    *out = result_vec(h, f, l);
     return BIOT_OK;
   }
   if (k == 0) {
@@ -928,27 +934,27 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   int rc = vcycle<T>(h, p, is_A, l + 1, nc, &xc, nullptr, nullptr, act);
   if (rc) return rc;
   // coarse-grid correction x += P xc, then deg post-smoothing steps
-  launch_prolong<T>(h->dim, C, Lv, Lc, is_A, cur, xc, oth, nc, wpc, st);
-  LAUNCHCHK(h);
-  h->acct += bytes_prolong(h, l, k, C, nc, tb);
-  std::swap(cur, oth);
   rho = 1.0 / cc.sigma;
   if (h->opt.fuse_post && deg == 2 && !upd && h->dim == 2) {
-    // both post-smoothing steps in one launch, into the free buffer (the
-    // pressure field's level 0, which writes the outer update, keeps two:
-    // fused it measured slower)
+    // the correction and both post-smoothing steps in one launch, into the
+    // residual buffer (free after the restriction); the pressure field's
+    // level 0, which writes the outer update, keeps separate launches
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
     // probed on every level, as a kernel trace averages this kernel
     const double by = bytes_post2(h, l, k, C, nc, tb);
     ProbeScope ps(h, is_A ? BIOT_PROBE_POST_U : BIOT_PROBE_POST_P, by);
-    launch_post2<T>(C, Lv, is_A, f.b[l], cur, oth, nc, 1.0 / cc.theta, rn * rho,
+    launch_post2<T>(C, Lv, Lc, is_A, f.b[l], cur, xc, f.r[l], nc, 1.0 / cc.theta, rn * rho,
                     2.0 * rn / cc.delta, wpc, st);
     LAUNCHCHK(h);
     h->acct += by;
     if (ps.end()) return BIOT_EHIP;
-    *out = oth;
+    *out = f.r[l];
     return BIOT_OK;
   }
+  launch_prolong<T>(h->dim, C, Lv, Lc, is_A, cur, xc, oth, nc, wpc, st);
+  LAUNCHCHK(h);
+  h->acct += bytes_prolong(h, l, k, C, nc, tb);
+  std::swap(cur, oth);
   for (int j = 1; j <= deg; ++j) {
     double c1 = 0.0, c2 = 1.0 / cc.theta, rn = rho;
     if (j > 1) {
