@@ -351,9 +351,9 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
                                   /* post-smoothing, both steps in one launch   */
                                   /* (2D, degree 2, fuse_post), on every level  */
                                   /* outside the fused tail                     */
-#define BIOT_PROBE_POST_P 7       /* the same for the pressure field (not on     */
-                                  /* level 0 in sweeps, whose last step writes  */
-                                  /* the outer update)                          */
+#define BIOT_PROBE_POST_P 7       /* the same for the pressure field (on level 0 */
+                                  /* in sweeps the last step writes the outer   */
+                                  /* update)                                    */
 #define BIOT_PROBE_COUNT 8
 #define BIOT_PROBE_ALL 0xFF
 int biot_profile_enable(biot_handle* h, int32_t mask);

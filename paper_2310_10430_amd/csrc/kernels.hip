@@ -76,6 +76,19 @@ __device__ inline int copy_cells(const LevelView<T>& L, int cp) {
   return L.copies == 1 ? L.n_cells : L.ccells[cp];
 }
 
+// Loads and stores through pointers read from memory (the column
+// descriptors' state columns) in the global address space: through a generic
+// pointer they compile to flat operations, which a wait for LDS traffic
+// (lgkmcnt) also waits for.
+template <typename V>
+__device__ inline V gld(const V* p) {
+  return *(const __attribute__((address_space(1))) V*)p;
+}
+template <typename V>
+__device__ inline void gst(V* p, V v) {
+  *(__attribute__((address_space(1))) V*)p = v;
+}
+
 // Shrinks the column range [cbeg, cend) of a launch to the columns active for
 // copy cp (a sample skips the steps past its own count); they are contiguous.
 template <typename T>
@@ -286,8 +299,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev L, FineDev F,
           double xw[D1], xpw[D1];
 #pragma unroll
           for (int k = 0; k < D1; ++k) {
-            xw[k] = xc[q][size_t(w) * D1 + k];
-            xpw[k] = xp[q][size_t(w) * D1 + k];
+            xw[k] = gld(xc[q] + size_t(w) * D1 + k);
+            xpw[k] = gld(xp[q] + size_t(w) * D1 + k);
           }
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
@@ -544,14 +557,14 @@ __global__ __launch_bounds__(kBlock, DIM == 2 ? BIOT_CHEB_MIN_WAVES : 1) void k_
           double out[D1];
 #pragma unroll
           for (int a = 0; a < DIM; ++a)
-            out[a] = cd.xcur[size_t(v) * D1 + a] +
+            out[a] = gld(cd.xcur + size_t(v) * D1 + a) +
                      omega * double(zu[(size_t(cc[q]) * nn + v) * DIM + a]);
-          out[DIM] = cd.xcur[size_t(v) * D1 + DIM] + omega * double(xn[0]);
+          out[DIM] = gld(cd.xcur + size_t(v) * D1 + DIM) + omega * double(xn[0]);
 #pragma unroll
-          for (int a = 0; a < D1; ++a) cd.xout[size_t(v) * D1 + a] = out[a];
+          for (int a = 0; a < D1; ++a) gst(cd.xout + size_t(v) * D1 + a, out[a]);
           if (cd.xout2)
 #pragma unroll
-            for (int a = 0; a < D1; ++a) cd.xout2[size_t(v) * D1 + a] = out[a];
+            for (int a = 0; a < D1; ++a) gst(cd.xout2 + size_t(v) * D1 + a, out[a]);
         }
       }
     }
@@ -601,14 +614,21 @@ template <int DIM, int C, typename T>
 __device__ inline void prolong_parents(const LevelView<T>& Lf, const LevelView<T>& Lc, int bit0,
                                        int cp, int f, int& p0, int& p1, unsigned& mask);
 
-template <int C, typename T>
+// UPD (pressure field, level 0, C == 1): instead of storing x4, write the
+// outer update X^{n,m} = X^{n,m-1} + omega [z_u; x4] through the column
+// descriptors, as k_cheb's last step does (the copies' padding nodes get
+// X^{n,m-1} + omega [z_u; 0]).
+template <int C, bool UPD, typename T>
 __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, LevelView<T> Lc, int isA,
                                                   const T* __restrict__ b,
                                                   const T* __restrict__ xin,
                                                   const T* __restrict__ xc,
                                                   T* __restrict__ x4, int nc, T c2a, T c1b,
-                                                  T c2b, int groups, int run) {
-  constexpr int W = 7;
+                                                  T c2b, int groups, int run,
+                                                  const ColDesc* __restrict__ cols,
+                                                  const T* __restrict__ zu, double omega) {
+  constexpr int W = 7, DIM = 2, D1 = 3;
+  static_assert(!UPD || C == 1, "the outer update follows the pressure field");
   // per buffer: x3, and the node's own x2 and b, of the patch's nodes
   __shared__ T sh[2][3][kBlock][C];
   __shared__ T sx2[kReg * kReg][C];  // x2 over the region
@@ -703,9 +723,19 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, LevelView<T> L
         }
       }
     };
+    // UPD: the state column and z_u of the node for phase2 of column c,
+    // loaded by phase1(c) (after phase2 of the previous column)
+    double xold[D1], zun[DIM];
     // x3 of the patch's nodes from x2 in LDS
     auto phase1 = [&](int c, int bb) {
       if (!node) return;
+      if constexpr (UPD) {
+        const double* xcur = cols[c].xcur;
+#pragma unroll
+        for (int a = 0; a < D1; ++a) xold[a] = gld(xcur + size_t(v) * D1 + a);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) zun[a] = double(zu[(size_t(c) * nn + v) * DIM + a]);
+      }
       T acc[C], x2o[C];
 #pragma unroll
       for (int a = 0; a < C; ++a) {
@@ -764,7 +794,40 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, LevelView<T> L
         const T x3 = sh[bb][0][threadIdx.x][a];
         const T dp = x3 - sh[bb][1][threadIdx.x][a];
         const T dn = fma(c2b, z, c1b * dp);
-        x4[size_t(c) * stride + size_t(v) * C + a] = x3 + dn;
+        if constexpr (UPD) {
+          const ColDesc cd = cols[c];
+          double out[D1];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) out[k] = xold[k] + omega * zun[k];
+          out[DIM] = xold[DIM] + omega * double(x3 + dn);
+#pragma unroll
+          for (int k = 0; k < D1; ++k) gst(cd.xout + size_t(v) * D1 + k, out[k]);
+          if (cd.xout2)
+#pragma unroll
+            for (int k = 0; k < D1; ++k) gst(cd.xout2 + size_t(v) * D1 + k, out[k]);
+        } else {
+          x4[size_t(c) * stride + size_t(v) * C + a] = x3 + dn;
+        }
+      }
+    };
+    // UPD: the copy's padding nodes, by the workgroups of its first patch
+    auto padding = [&](int c) {
+      if constexpr (UPD) {
+        if (one || patch != 0) return;
+        const int p0 = base + m * m, p1 = L.cbase[cp + 1];
+        const ColDesc cd = cols[c];
+        for (int u = p0 + int(threadIdx.x); u < p1; u += kBlock) {
+          double out[D1];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k)
+            out[k] = gld(cd.xcur + size_t(u) * D1 + k) + omega * double(zu[(size_t(c) * nn + u) * DIM + k]);
+          out[DIM] = gld(cd.xcur + size_t(u) * D1 + DIM) + omega * double(T(0));
+#pragma unroll
+          for (int k = 0; k < D1; ++k) gst(cd.xout + size_t(u) * D1 + k, out[k]);
+          if (cd.xout2)
+#pragma unroll
+            for (int k = 0; k < D1; ++k) gst(cd.xout2 + size_t(u) * D1 + k, out[k]);
+        }
       }
     };
     // prologue: x2 and x3 of the first column; then per column, x2 of the next
@@ -779,6 +842,7 @@ __global__ __launch_bounds__(kBlock) void k_post2(LevelView<T> L, LevelView<T> L
       const bool more = c + 1 < cend;
       if (more) phase0_load(c + 1);
       phase2(c, buf);
+      padding(c);
       if (more) phase0_store();
       lds_barrier();
       if (more) phase1(c + 1, buf ^ 1);
@@ -1689,7 +1753,7 @@ void launch_cheb(int dim, int comps, const LevelView<T>& L, bool is_A, const T* 
 template <typename T>
 void launch_post2(int comps, const LevelView<T>& L, const LevelView<T>& Lc, bool is_A, const T* b,
                   const T* xin, const T* xc, T* x4, int nc, double c2a, double c1b, double c2b,
-                  int wpc, hipStream_t st) {
+                  const ColDesc* upd, const T* zu, double omega, int wpc, hipStream_t st) {
   const int patches = L.npatch;
   // runs per patch: as many as keep about one wave of resident workgroups
   // (3 per CU) busy, at most one per column
@@ -1697,12 +1761,15 @@ void launch_post2(int comps, const LevelView<T>& L, const LevelView<T>& Lc, bool
   const int run = (nc + groups - 1) / groups;
   const dim3 grid(unsigned((patches * groups + 7) / 8 * 8));
   (void)wpc;
-  if (comps == 1)
-    BIOT_LAUNCH_GRID((k_post2<1, T>), grid, st, L, Lc, int(is_A), b, xin, xc, x4, nc, T(c2a),
-                     T(c1b), T(c2b), groups, run);
+  if (upd)
+    BIOT_LAUNCH_GRID((k_post2<1, true, T>), grid, st, L, Lc, int(is_A), b, xin, xc, x4, nc,
+                     T(c2a), T(c1b), T(c2b), groups, run, upd, zu, omega);
+  else if (comps == 1)
+    BIOT_LAUNCH_GRID((k_post2<1, false, T>), grid, st, L, Lc, int(is_A), b, xin, xc, x4, nc,
+                     T(c2a), T(c1b), T(c2b), groups, run, upd, zu, omega);
   else
-    BIOT_LAUNCH_GRID((k_post2<2, T>), grid, st, L, Lc, int(is_A), b, xin, xc, x4, nc, T(c2a),
-                     T(c1b), T(c2b), groups, run);
+    BIOT_LAUNCH_GRID((k_post2<2, false, T>), grid, st, L, Lc, int(is_A), b, xin, xc, x4, nc,
+                     T(c2a), T(c1b), T(c2b), groups, run, upd, zu, omega);
 }
 
 template <typename T>
@@ -1848,8 +1915,8 @@ void launch_apply_operator(int dim, const LevelDev& L, const FineDev& F, const d
                                int, double, double, bool, int, bool, double, const ColDesc*,     \
                                const T*, double, int, bool, hipStream_t);                         \
   template void launch_post2<T>(int, const LevelView<T>&, const LevelView<T>&, bool, const T*,  \
-                                const T*, const T*, T*, int, double, double, double, int,         \
-                                hipStream_t);                                                     \
+                                const T*, const T*, T*, int, double, double, double,              \
+                                const ColDesc*, const T*, double, int, hipStream_t);              \
   template void launch_level_residual<T>(int, int, const LevelView<T>&, bool, const T*,          \
                                          const T*, T*, int, int, hipStream_t);                    \
   template void launch_restrict<T>(int, int, const LevelView<T>&, const LevelView<T>&, bool,     \

@@ -115,11 +115,13 @@ void launch_prolong(int dim, int comps, const LevelView<T>& Lf, const LevelView<
                     const T* xin, const T* xc, T* xout, int nc, int wpc, hipStream_t st);
 // the coarse-grid correction x2 = x + P xc and the two post-smoothing steps of
 // degree 2, fused (2D, any number of samples): x, xc -> x4, with the first
-// step's c2 and the second step's c1, c2 (k_post2); x2 is not stored
+// step's c2 and the second step's c1, c2 (k_post2); x2 is not stored.  With
+// `upd` (pressure field, level 0) the last step writes the outer update
+// X^{n,m} = X^{n,m-1} + omega [zu; x4] through the descriptors instead of x4.
 template <typename T>
 void launch_post2(int comps, const LevelView<T>& L, const LevelView<T>& Lc, bool is_A, const T* b,
                   const T* xin, const T* xc, T* x4, int nc, double c2a, double c1b, double c2b,
-                  int wpc, hipStream_t st);
+                  const ColDesc* upd, const T* zu, double omega, int wpc, hipStream_t st);
 // dense coarsest solve per column and copy: n grid dofs per copy, `stride` dofs
 // per copy with padding, Minv = copies dense inverses
 template <typename T>

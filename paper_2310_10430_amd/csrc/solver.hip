@@ -760,10 +760,14 @@ double bytes_levres(const biot_handle* h, int l, int k, int C, int nc, int t) {
 }
 // the coarse-grid correction and both post-smoothing steps: b, x, xc in, x4
 // out; the operator row, D^{-1}, indices and the fine and coarse flags once
-double bytes_post2(const biot_handle* h, int l, int k, int C, int nc, int t) {
+double bytes_post2(const biot_handle* h, int l, int k, int C, int nc, int t, bool upd) {
   const double nn = act_nodes(h, l, k), ncs = act_nodes(h, l + 1, k), W = h->P.levels[l].W;
-  return nc * (nn * C * t * 3 + ncs * C * t) + nn * (W * C * C * t + 4 * W + C * C * t) +
-         (nn + ncs);
+  const double d = h->dim, D1 = d + 1;
+  // with the outer update: no x4, but X^{m-1} and z_u in, X^m out (and the
+  // trajectory copy of the last slot)
+  const double per_col = upd ? nn * (C * t * 2 + 8 * D1 * 2 + t * d) : nn * C * t * 3;
+  return nc * (per_col + ncs * C * t) + nn * (W * C * C * t + 4 * W + C * C * t) + (nn + ncs) +
+         (upd ? h->cur_copies * nn * 8 * D1 : 0.0);
 }
 double bytes_pstage(const biot_handle* h, int nc, int t) {
   const double nn = h->nn, W = h->P.levels[0].W, d = h->dim;
@@ -935,20 +939,20 @@ int vcycle(biot_handle* h, Prec<T>& p, bool is_A, int l, int nc, T** out, const 
   if (rc) return rc;
   // coarse-grid correction x += P xc, then deg post-smoothing steps
   rho = 1.0 / cc.sigma;
-  if (h->opt.fuse_post && deg == 2 && !upd && h->dim == 2) {
+  if (h->opt.fuse_post && deg == 2 && h->dim == 2) {
     // the correction and both post-smoothing steps in one launch, into the
-    // residual buffer (free after the restriction); the pressure field's
-    // level 0, which writes the outer update, keeps separate launches
+    // residual buffer (free after the restriction); on the pressure field's
+    // level 0 the last step writes the outer update
     const double rn = 1.0 / (2.0 * cc.sigma - rho);
     // probed on every level, as a kernel trace averages this kernel
-    const double by = bytes_post2(h, l, k, C, nc, tb);
+    const double by = bytes_post2(h, l, k, C, nc, tb, upd != nullptr);
     ProbeScope ps(h, is_A ? BIOT_PROBE_POST_U : BIOT_PROBE_POST_P, by);
     launch_post2<T>(C, Lv, Lc, is_A, f.b[l], cur, xc, f.r[l], nc, 1.0 / cc.theta, rn * rho,
-                    2.0 * rn / cc.delta, wpc, st);
+                    2.0 * rn / cc.delta, upd, zu, h->opt.omega, wpc, st);
     LAUNCHCHK(h);
     h->acct += by;
     if (ps.end()) return BIOT_EHIP;
-    *out = f.r[l];
+    *out = upd ? nullptr : f.r[l];
     return BIOT_OK;
   }
   launch_prolong<T>(h->dim, C, Lv, Lc, is_A, cur, xc, oth, nc, wpc, st);
