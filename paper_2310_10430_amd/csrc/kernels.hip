@@ -1035,9 +1035,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelView<T> Lf, LevelView<
 // ---------------------------------------------------------------------------
 namespace tail {
 
-// workgroup size of the fused tail: the levels are small, so a phase is one or
-// two nodes per thread and its cost is the latency of the operator loads;
-// more threads keep more of them in flight (3D rows need the registers of 256)
+// workgroup size of the fused tail for a few columns: the levels are small, so
+// a phase is one or two nodes per thread and its cost is the latency of the
+// operator loads; more threads keep more of them in flight (3D rows need the
+// registers of 256).  Launches of many workgroups (batches) take fewer threads
+// (kTailSmallBlock).
 template <int DIM>
 constexpr int block() { return DIM == 2 ? 1024 : 256; }
 
@@ -1052,7 +1054,7 @@ constexpr int block() { return DIM == 2 ? 1024 : 256; }
 //   dx = 2: dp = xin - xout at the node (xout holds the previous step's input
 //          and is overwritten in place);
 //   else dp = d (when c1 != 0); wd: store d.
-template <int DIM, int C, bool FIRST, typename T>
+template <int DIM, int C, bool FIRST, typename T, int BS>
 __device__ inline void cheb(const LevelView<T>& L, int base, int nreal, const T* b, const T* xin,
                             T* xout, T* d, T c1, T c2, T it, int dx, bool wd) {
   constexpr bool first = FIRST;
@@ -1062,7 +1064,7 @@ __device__ inline void cheb(const LevelView<T>& L, int base, int nreal, const T*
   const T* src = first ? b : xin;
   const T sc = first ? it : T(1);
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < nreal; v += block<DIM>()) {
+  for (int v = threadIdx.x; v < nreal; v += BS) {
     const int g = base + v;
     T acc[C], xs[C];
 #pragma unroll
@@ -1107,13 +1109,13 @@ __device__ inline void cheb(const LevelView<T>& L, int base, int nreal, const T*
   }
 }
 
-template <int DIM, int C, typename T>
+template <int DIM, int C, typename T, int BS>
 __device__ inline void residual(const LevelView<T>& L, int base, int nreal, const T* b, const T* x,
                                 T* r) {
   constexpr int W = DIM == 2 ? 7 : 15;
   const T* K = C > 1 ? L.A : L.S;
   const int nn = L.nn;
-  for (int v = threadIdx.x; v < nreal; v += block<DIM>()) {
+  for (int v = threadIdx.x; v < nreal; v += BS) {
     const int g = base + v;
     T acc[C];
 #pragma unroll
@@ -1135,7 +1137,7 @@ __device__ inline void residual(const LevelView<T>& L, int base, int nreal, cons
 }
 
 // bc = P' rf (masked)
-template <int DIM, int C, typename T>
+template <int DIM, int C, typename T, int BS>
 __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, int cellsf,
                                    const LevelView<T>& Lc, int basec, int cellsc, const T* rf,
                                    T* bc) {
@@ -1143,7 +1145,7 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, int cellsf
   const int mc = cellsc + 1, mf = cellsf + 1;
   const int bit0 = C > 1 ? 0 : DIM;
   const int nrc = grid_nodes<DIM>(cellsc);
-  for (int I = threadIdx.x; I < nrc; I += block<DIM>()) {
+  for (int I = threadIdx.x; I < nrc; I += BS) {
     int ci, cj, ck;
     node_coords<DIM>(I, mc, ci, cj, ck);
     T acc[C];
@@ -1170,11 +1172,11 @@ __device__ inline void restrict_to(const LevelView<T>& Lf, int basef, int cellsf
   }
 }
 
-template <int DIM, int C, typename T>
+template <int DIM, int C, typename T, int BS>
 __device__ inline void prolong(const LevelView<T>& Lf, int basef, int nrealf,
                                const LevelView<T>& Lc, int basec, int cp, const T* xin,
                                const T* xc, T* xout) {
-  for (int v = threadIdx.x; v < nrealf; v += block<DIM>()) {
+  for (int v = threadIdx.x; v < nrealf; v += BS) {
     int p0, p1;
     unsigned pm;
     prolong_parents<DIM, C>(Lf, Lc, C > 1 ? 0 : DIM, cp, basef + v, p0, p1, pm);
@@ -1195,8 +1197,9 @@ __device__ inline void prolong(const LevelView<T>& Lf, int basef, int nrealf,
 
 // one workgroup per (column, copy); each copy runs its own tail levels
 // t0..t0+nlev-1 (copies of a batch may be grids of different sizes)
-template <int DIM, int C, typename T>
-__global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> TD) {
+template <int DIM, int C, typename T, int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 4 : 1)))
+void k_vcycle_tail(TailDev<T> TD) {
   extern __shared__ double tail_raw[];
   T* lds = reinterpret_cast<T*>(tail_raw);
   __shared__ int s_nr[kTailMaxLevels], s_base[kTailMaxLevels], s_cells[kTailMaxLevels],
@@ -1224,7 +1227,7 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
   const int n0 = s_nr[0] * C;
   const size_t g0 = (size_t(c) * TD.L[t0].nn + s_base[0]) * C;
   const T* b_t = TD.b[t0];
-  for (int i = threadIdx.x; i < n0; i += tail::block<DIM>()) vec(0, 0)[i] = b_t[g0 + i];
+  for (int i = threadIdx.x; i < n0; i += BS) vec(0, 0)[i] = b_t[g0 + i];
   __syncthreads();
   // descend: pre-smoothing (its first step folded into the second), residual
   // into the free iterate, restriction
@@ -1238,20 +1241,22 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
       const double rn = 1.0 / (2.0 * sigma - rho);
       const bool first = j == 2;
       if (first)
-        tail::cheb<DIM, C, true, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 1), d,
-                                    T(rn * rho), T(2.0 * rn / delta), T(1.0 / theta), 0, j < deg);
+        tail::cheb<DIM, C, true, T, BS>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 1),
+                                        d, T(rn * rho), T(2.0 * rn / delta), T(1.0 / theta), 0,
+                                        j < deg);
       else
-        tail::cheb<DIM, C, false, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 3 - xi),
-                                     d, T(rn * rho), T(2.0 * rn / delta), T(0), 0, j < deg);
+        tail::cheb<DIM, C, false, T, BS>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi),
+                                         vec(i, 3 - xi), d, T(rn * rho), T(2.0 * rn / delta), T(0),
+                                         0, j < deg);
       __syncthreads();
       rho = rn;
       if (!first) xi = 3 - xi;
     }
     if (xi == 2) alt |= 1u << i;
-    tail::residual<DIM, C, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 3 - xi));
+    tail::residual<DIM, C, T, BS>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 3 - xi));
     __syncthreads();
-    tail::restrict_to<DIM, C, T>(L, s_base[i], s_cells[i], TD.L[t0 + i + 1], s_base[i + 1],
-                                 s_cells[i + 1], vec(i, 3 - xi), vec(i + 1, 0));
+    tail::restrict_to<DIM, C, T, BS>(L, s_base[i], s_cells[i], TD.L[t0 + i + 1], s_base[i + 1],
+                                     s_cells[i + 1], vec(i, 3 - xi), vec(i + 1, 0));
     __syncthreads();
   }
   // coarsest level: dense inverse of this copy
@@ -1260,7 +1265,7 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
     const T* bb = vec(nl - 1, 0);
     T* xx = vec(nl - 1, 1);
     const T* M = TD.Minv + tcp->moff;
-    for (int r = threadIdx.x; r < n; r += tail::block<DIM>()) {
+    for (int r = threadIdx.x; r < n; r += BS) {
       T acc = T(0);
       const T* row = M + size_t(r) * n;
       for (int j = 0; j < n; ++j) acc += row[j] * bb[j];
@@ -1277,8 +1282,8 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
     T* d = deg > 2 ? vec(i, 3) : dnull;
     int xi = ((alt >> i) & 1u) ? 2 : 1;
     const int xci = (i + 2 == nl) ? 1 : (((alt >> (i + 1)) & 1u) ? 2 : 1);
-    tail::prolong<DIM, C, T>(L, s_base[i], s_nr[i], TD.L[t0 + i + 1], s_base[i + 1], cp,
-                             vec(i, xi), vec(i + 1, xci), vec(i, 3 - xi));
+    tail::prolong<DIM, C, T, BS>(L, s_base[i], s_nr[i], TD.L[t0 + i + 1], s_base[i + 1], cp,
+                                 vec(i, xi), vec(i + 1, xci), vec(i, 3 - xi));
     __syncthreads();
     xi = 3 - xi;
     double rho = 1.0 / sigma;
@@ -1289,8 +1294,9 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
         c1 = rn * rho;
         c2 = 2.0 * rn / delta;
       }
-      tail::cheb<DIM, C, false, T>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi), vec(i, 3 - xi),
-                                   d, T(c1), T(c2), T(0), j == 2 ? 2 : 0, j > 1 && j < deg);
+      tail::cheb<DIM, C, false, T, BS>(L, s_base[i], s_nr[i], vec(i, 0), vec(i, xi),
+                                       vec(i, 3 - xi), d, T(c1), T(c2), T(0), j == 2 ? 2 : 0,
+                                       j > 1 && j < deg);
       __syncthreads();
       rho = rn;
       xi = 3 - xi;
@@ -1299,10 +1305,10 @@ __global__ __launch_bounds__(tail::block<DIM>()) void k_vcycle_tail(TailDev<T> T
   }
   const T* res = vec(0, ((alt & 1u) ? 2 : 1));
   T* x_t = TD.x[t0];
-  for (int i = threadIdx.x; i < n0; i += tail::block<DIM>()) x_t[g0 + i] = res[i];
+  for (int i = threadIdx.x; i < n0; i += BS) x_t[g0 + i] = res[i];
   // padding nodes of the copy keep a zero correction
   const int npad = (TD.L[t0].cbase[cp + 1] - s_base[0] - s_nr[0]) * C;
-  for (int i = threadIdx.x; i < npad; i += tail::block<DIM>()) x_t[g0 + n0 + i] = T(0);
+  for (int i = threadIdx.x; i < npad; i += BS) x_t[g0 + n0 + i] = T(0);
 }
 
 // coarsest level: x = M^{-1} b with the dense inverses (row-major, one per
@@ -1828,6 +1834,13 @@ int tail_vectors(int degree) { return degree > 2 ? 4 : 3; }
 
 int tail_block_threads(int dim) { return dim == 2 ? tail::block<2>() : tail::block<3>(); }
 
+// 2D tails launched with at least as many workgroups as compute units (a
+// batch of samples) use workgroups of kTailSmallBlock threads: four of them
+// are resident per compute unit, and fewer threads idle on the levels of a few
+// hundred nodes (64-sample batch: 2.81 s against 3.03 s with 1024 threads,
+// 2.87 s with 128 and 3.06 s with 64, whose LDS then limits residency)
+constexpr int kTailSmallBlock = 256;
+
 size_t tail_lds_bytes(const int* level_nn, int nlev, int comps, int tbytes, int degree) {
   size_t n = 0;
   for (int i = 0; i < nlev; ++i)
@@ -1840,13 +1853,21 @@ void launch_vcycle_tail(int dim, int comps, const TailDev<T>& TD, int nc, size_t
                         hipStream_t st) {
   const dim3 g(nc * TD.copies);
   if (dim == 2) {
-    const dim3 tb(tail::block<2>());
-    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T>), g, tb, lds, st, TD);
-    else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T>), g, tb, lds, st, TD);
+    // a few columns: one workgroup of 1024 threads each, whose phases are
+    // latency-bound; many (a batch of samples): kTailSmallBlock threads each
+    if (int(g.x) >= num_cus()) {
+      constexpr int bs = kTailSmallBlock;
+      if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T, bs>), g, dim3(bs), lds, st, TD);
+      else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T, bs>), g, dim3(bs), lds, st, TD);
+    } else {
+      constexpr int bs = tail::block<2>();
+      if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<2, 1, T, bs>), g, dim3(bs), lds, st, TD);
+      else hipLaunchKernelGGL((k_vcycle_tail<2, 2, T, bs>), g, dim3(bs), lds, st, TD);
+    }
   } else {
-    const dim3 tb(tail::block<3>());
-    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<3, 1, T>), g, tb, lds, st, TD);
-    else hipLaunchKernelGGL((k_vcycle_tail<3, 3, T>), g, tb, lds, st, TD);
+    constexpr int bs = tail::block<3>();
+    if (comps == 1) hipLaunchKernelGGL((k_vcycle_tail<3, 1, T, bs>), g, dim3(bs), lds, st, TD);
+    else hipLaunchKernelGGL((k_vcycle_tail<3, 3, T, bs>), g, dim3(bs), lds, st, TD);
   }
 }
 
