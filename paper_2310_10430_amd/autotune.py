@@ -12,7 +12,11 @@ sample skips the steps past its own count.  For that handle the tuner picks
     (0 = each kernel's occupancy, capped at 3 per CU),
 
 by timing a whole solve to the tolerance for every candidate pair (after one
-untimed pass that captures the HIP graphs).  Results are cached in a JSON file
+untimed pass that captures the HIP graphs).  The time is not smooth in the
+depth (64-sample batch, FP64, 4 workgroups per CU: 2.93, 2.61, 2.57, 2.64,
+2.72, 2.81 s at depths 72, 76, 80, 84, 88, 96, and depths past the sweeps the
+samples need add passes), hence the grid of depths around the usual sweep
+counts.  Results are cached in a JSON file
 (BIOT_TUNE_CACHE, default ~/.cache/biot_pint/autotune.json) under a key made of
 the workload (dimension, sizes, step counts, precision, tolerance), the library
 build (a hash of libbiot_pint.so) and the device name, so that a rebuilt
@@ -95,8 +99,8 @@ def time_solve(problems, depth: int, wpc: int, precision: str, rtol: float,
         s.close()
 
 
-def tune_batch(problems, precision: str = "mixed", rtol: float = 2e-9, depths=(32, 64, 96),
-               wpcs=(0, 2, 4), use_cache: bool = True, device="cuda:0",
+def tune_batch(problems, precision: str = "mixed", rtol: float = 2e-9,
+               depths=(64, 72, 80, 88, 96), wpcs=(0, 4), use_cache: bool = True, device="cuda:0",
                device_name: str | None = None) -> dict:
     """Best (depth, wg_per_cu) for one handle over all samples; returns the
     choice, every candidate's solve time and whether it came from the cache."""
