@@ -41,11 +41,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC = {
     # k_residual<2, double, false>: 8 dispatches; a Jacobi batch reads 65
     # distinct state columns for its 64 (the coupling overlaps the iterates)
-    "residual": {"kernels_sha256_prefix": "467a442fbfa81c5d", "bytes_per_launch": 307.9e6,
+    "residual": {"kernels_sha256_prefix": "958ea774ab53d6d8", "bytes_per_launch": 308.1e6,
                  "launch_columns": 64, "algorithmic_bytes_per_launch": 244.9e6},
     # k_post2<2, false, double> (coarse-grid correction and both post-smoothing
     # steps): 24 dispatches (levels 0-2 of 8 batches), average
-    "post_u": {"kernels_sha256_prefix": "467a442fbfa81c5d", "bytes_per_launch": 122.7e6,
+    "post_u": {"kernels_sha256_prefix": "958ea774ab53d6d8", "bytes_per_launch": 122.7e6,
                "launch_columns": 64, "algorithmic_bytes_per_launch": 104.8e6},
 }
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"
