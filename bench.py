@@ -441,6 +441,9 @@ def main():
                     help="hardware-counter run: one Jacobi-schedule sweep of the workload in "
                          "batches of --depth columns (the bench's full-wave launch shape, few "
                          "dispatches), no timing")
+    ap.add_argument("--probe-stride", type=int, default=8,
+                    help="probe every k-th wave of a pass in the timed region, replaying the "
+                         "others as graphs (1: every wave, all eager)")
     ap.add_argument("--probe", default="auto",
                     help="kernel timed with HIP events in the timed region; auto: of the probes "
                          "that each time one kernel, the one with the most time in a probed "
@@ -509,9 +512,15 @@ def main():
         # post_p times two kernels (level 0 writes the outer update)
         single = [k for k in prof if k != "post_p"]
         args.probe = max(single, key=lambda k: prof[k]["ms"])
-    # timed region: HIP events bracket every probed launch of that kernel on the
-    # solver's stream
-    s.profile(True, probes=[args.probe])
+    # timed region: HIP events bracket the probed launches of that kernel on
+    # the solver's stream, in every probe_stride-th wave of a pass (the waves
+    # between them replay captured graphs; 1: every wave, all eager); one
+    # untimed solve first captures the graphs of that layout, and enabling
+    # again clears the accumulators
+    s.profile(True, probes=[args.probe], stride=args.probe_stride)
+    if args.probe_stride > 1:
+        solve()
+        s.profile(True, probes=[args.probe], stride=args.probe_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -625,7 +634,7 @@ def main():
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, **traffic_fields(args.probe,
                                                                              bytes_per_launch),
             "avg_launch_us": 1e3 * avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-            "launches": p["launches"],
+            "launches": p["launches"], "probed_wave_stride": args.probe_stride,
             "sweep_achieved": sweep_gbs, "sweep_frac": sweep_gbs / HBM_PEAK_GBS,
             "sweep_bytes_per_solve": solve_bytes, "sweep_seconds_per_solve": solve_s,
         },

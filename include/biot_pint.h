@@ -340,7 +340,11 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
  * moves (distinct global inputs and outputs counted once).  `mask` has bit p
  * set for probe p (0 disables); enabling or disabling clears the accumulators;
  * reading synchronizes the stream.  While probes are on, wavefront passes run
- * their launches eagerly instead of replaying a captured graph. */
+ * their launches eagerly instead of replaying a captured graph, unless bits
+ * BIOT_PROBE_STRIDE_SHIFT.. +7 of `mask` hold a stride k > 1: then only the
+ * waves w with w mod k = k/2 run eagerly and are probed, and the waves between
+ * them replay captured graphs (so a timed solve keeps most of the graph
+ * replay's speed while its probes sample every k-th wave). */
 #define BIOT_PROBE_RESIDUAL 0     /* fused residual + coupling + norms           */
 #define BIOT_PROBE_CHEB_U 1       /* displacement Chebyshev smoothing steps      */
 #define BIOT_PROBE_CHEB_P 2       /* pressure Chebyshev smoothing steps          */
@@ -356,6 +360,7 @@ int biot_get_info(const biot_handle* h, biot_info_t* info);
                                   /* update)                                    */
 #define BIOT_PROBE_COUNT 8
 #define BIOT_PROBE_ALL 0xFF
+#define BIOT_PROBE_STRIDE_SHIFT 16
 int biot_profile_enable(biot_handle* h, int32_t mask);
 int biot_profile_read(biot_handle* h, int32_t probe, uint64_t* launches, double* total_ms,
                       double* total_bytes, const char** name);

@@ -14,6 +14,7 @@ PRECOND = {"P1": 1, "P2": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 INNER = {"richardson": 0, "gmres": 1}
 PROBES = ["residual", "cheb_u", "cheb_p", "levres_u", "levres_p", "pstage", "post_u", "post_p"]
+PROBE_STRIDE_SHIFT = 16  # BIOT_PROBE_STRIDE_SHIFT: bits of the probe mask holding the wave stride
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)

@@ -100,8 +100,10 @@ struct Sched {
   // (the tables' contents may change between replays)
   std::vector<hipGraph_t> graph[2];
   std::vector<hipGraphExec_t> gexec[2];
+  std::vector<size_t> gfirst[2], gend[2];  // waves [first, end) of each graph, in wave order
   double gbytes[2] = {0.0, 0.0};      // algorithmic bytes of one replay of a pass
   int graph_N = -1;
+  int graph_stride = 0;               // probe stride the graphs leave out (0: none)
 };
 
 }  // namespace
@@ -172,6 +174,7 @@ struct biot_handle {
   struct Acc { uint64_t launches = 0; double ms = 0, bytes = 0; };
   bool prof = false;
   unsigned prof_mask = 0;  // which probes record events
+  int prof_stride = 0;     // > 1: only every prof_stride-th wave of a pass is probed
   size_t tail_lds = kTailMaxLds;  // LDS a fused tail may use (device limit, at bind)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
@@ -1253,9 +1256,12 @@ void destroy_graphs(Sched& S) {
     for (auto g : S.graph[c]) (void)hipGraphDestroy(g);
     S.gexec[c].clear();
     S.graph[c].clear();
+    S.gfirst[c].clear();
+    S.gend[c].clear();
     S.gbytes[c] = 0.0;
   }
   S.graph_N = -1;
+  S.graph_stride = 0;
 }
 
 // kernel nodes per captured graph: a pass of several hundred waves, each of up
@@ -1282,6 +1288,8 @@ int capture_waves(biot_handle* h, Sched& S, int c, size_t w0, size_t w1, size_t*
   }
   if (e != hipSuccess) return fail(h, BIOT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   S.graph[c].push_back(g);
+  S.gfirst[c].push_back(w0);
+  S.gend[c].push_back(w1);
   if (nodes) HIPCHK(h, hipGraphGetNodes(g, nullptr, nodes));
   hipGraphExec_t x = nullptr;
   HIPCHK(h, hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
@@ -1293,32 +1301,65 @@ int capture_waves(biot_handle* h, Sched& S, int c, size_t w0, size_t w1, size_t*
 // pass is captured once per trajectory parity (the descriptor tables, whose
 // device buffers are fixed, hold every pointer) and replayed: the first wave
 // alone, which measures the launches per wave, then chunks of waves of about
-// kGraphNodeBudget launches.
+// kGraphNodeBudget launches.  Probes read HIP events recorded by a launch's
+// own dispatch, which a replayed graph cannot carry: with probes on, a pass
+// runs eagerly, or with a probe stride k > 1 only its waves w = k/2 (mod k)
+// run eagerly (and are probed) and the waves between them are replayed.
+bool probed_wave(int stride, size_t w) { return stride > 1 && int(w % size_t(stride)) == stride / 2; }
+
 int wavefront_pass(biot_handle* h, Sched& S) {
-  // probes read HIP events, which cannot be timed inside a replayed graph, so
-  // a probed pass runs its launches eagerly
-  if (!h->opt.use_graph || h->prof) {
+  const int stride = h->prof ? h->prof_stride : 0;
+  if (!h->opt.use_graph || (h->prof && stride < 2)) {
     int rc = wavefront_pass_eager(h, S);
     if (rc) return rc;
     S.cur = 1 - S.cur;
     return BIOT_OK;
   }
-  if (S.graph_N != S.N) destroy_graphs(S);
+  if (S.graph_N != S.N || S.graph_stride != stride) destroy_graphs(S);
   const int c = S.cur;
+  const size_t waves = S.wave_off.size();
   if (S.gexec[c].empty()) {
-    const size_t waves = S.wave_off.size();
-    size_t per_wave = 0;
-    int rc = capture_waves(h, S, c, 0, 1, &per_wave);
-    const size_t chunk = std::max<size_t>(1, kGraphNodeBudget / std::max<size_t>(per_wave, 1));
-    for (size_t w0 = 1; !rc && w0 < waves; w0 += chunk)
-      rc = capture_waves(h, S, c, w0, std::min(waves, w0 + chunk), nullptr);
+    // captured without probes; each run of unprobed waves becomes graphs of
+    // at most `chunk` waves
+    const bool prof = h->prof;
+    h->prof = false;
+    size_t per_wave = 0, chunk = 1;
+    int rc = BIOT_OK;
+    size_t w = 0;
+    while (!rc && w < waves) {
+      if (probed_wave(stride, w)) {
+        ++w;
+        continue;
+      }
+      size_t w1 = w + 1;
+      if (per_wave > 0)
+        while (w1 < waves && w1 - w < chunk && !probed_wave(stride, w1)) ++w1;
+      rc = capture_waves(h, S, c, w, w1, per_wave == 0 ? &per_wave : nullptr);
+      if (!rc && chunk == 1) chunk = std::max<size_t>(1, kGraphNodeBudget / std::max<size_t>(per_wave, 1));
+      w = w1;
+    }
+    h->prof = prof;
     if (rc) {
       destroy_graphs(S);
       return rc;
     }
     S.graph_N = S.N;
+    S.graph_stride = stride;
   }
-  for (auto x : S.gexec[c]) HIPCHK(h, hipGraphLaunch(x, h->st));
+  // replay, with the probed waves (those no graph covers) run eagerly
+  size_t w = 0;
+  for (size_t i = 0; i < S.gexec[c].size(); ++i) {
+    for (; w < S.gfirst[c][i]; ++w) {
+      int rc = run_waves(h, S, S.desc_wave[c], S.wave_off, S.wave_cnt, h->opt.depth, w, w + 1);
+      if (rc) return rc;
+    }
+    HIPCHK(h, hipGraphLaunch(S.gexec[c][i], h->st));
+    w = S.gend[c][i];
+  }
+  for (; w < waves; ++w) {
+    int rc = run_waves(h, S, S.desc_wave[c], S.wave_off, S.wave_cnt, h->opt.depth, w, w + 1);
+    if (rc) return rc;
+  }
   h->acct += S.gbytes[c];
   S.cur = 1 - S.cur;
   return BIOT_OK;
@@ -2171,6 +2212,7 @@ int biot_profile_enable(biot_handle* h, int32_t mask) {
   }
   h->prof = enable != 0;
   h->prof_mask = unsigned(mask) & ((1u << BIOT_PROBE_COUNT) - 1);
+  h->prof_stride = int((unsigned(mask) >> BIOT_PROBE_STRIDE_SHIFT) & 0xFFu);
   return BIOT_OK;
 }
 

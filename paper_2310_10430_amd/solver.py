@@ -376,15 +376,21 @@ class BiotSolver:
         self._outputs_ready(out)
         return out
 
-    def profile(self, enable: bool = True, probes=None):
+    def profile(self, enable: bool = True, probes=None, stride: int = 0):
         """Start (or stop) the HIP-event probes around level-0 launches; `probes`
-        selects a subset by name (see _lib.PROBES), default all."""
+        selects a subset by name (see _lib.PROBES), default all.  `stride` k > 1
+        probes only every k-th wave of a wavefront pass and replays the waves
+        between them as captured graphs; otherwise a probed pass runs eagerly."""
+        if not 0 <= stride <= 255:
+            raise ValueError("stride must be in 0..255")
         if not enable:
             mask = 0
         elif probes is None:
             mask = (1 << len(_lib.PROBES)) - 1
         else:
             mask = sum(1 << _lib.PROBES.index(p) for p in probes)
+        if enable:
+            mask |= stride << _lib.PROBE_STRIDE_SHIFT
         self._check(self.lib.biot_profile_enable(self.h, mask))
 
     def profile_read(self) -> dict:

@@ -223,6 +223,36 @@ def test_graph_replays_match_eager_passes():
     graph.close()
 
 
+def test_sampled_probes_replay_the_waves_between_them():
+    """With a probe stride k, only the waves w = k/2 (mod k) run eagerly and are
+    probed; the others replay captured graphs.  The trajectory equals the eager
+    passes bit for bit, a change of stride recaptures, and the probe counts the
+    probed waves' launches only."""
+    pb = W.heterogeneous_problem(16, 9)
+    depth = 3
+    waves = pb.n_steps + depth - 1
+    eager = BiotSolver(pb, schedule="wavefront", depth=depth, omega=0.6, use_graph=False)
+    graph = BiotSolver(pb, schedule="wavefront", depth=depth, omega=0.6, use_graph=True)
+    for stride in (4, 3, 4):
+        graph.profile(True, probes=["residual"], stride=stride)
+        for p in range(3):
+            eager.sweep(depth)
+            graph.sweep(depth)
+            torch.cuda.synchronize()
+            assert torch.equal(eager.trajectory(), graph.trajectory()), (stride, p)
+        prof = graph.profile_read()
+        probed = sum(1 for w in range(waves) if w % stride == stride // 2)
+        assert prof["residual"]["launches"] == 3 * probed, (stride, prof["residual"])
+        assert prof["residual"]["ms"] > 0 and prof["residual"]["bytes"] > 0
+        assert prof["cheb_u"]["launches"] == 0
+    graph.profile(False)
+    eager.sweep(depth)
+    graph.sweep(depth)
+    assert torch.equal(eager.trajectory(), graph.trajectory())
+    eager.close()
+    graph.close()
+
+
 def test_mixed_precision_preconditioner_is_fp32_rounding_of_oracle():
     """The FP32 preconditioner equals the oracle's FP64 one to FP32 accuracy."""
     pb = W.heterogeneous_problem(24, 3)
