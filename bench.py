@@ -185,7 +185,7 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2, **kw):
     samples.  `kw` overrides solver options (inner solver, preconditioner,
     depth)."""
     import torch
-    opts = dict(schedule=args.schedule, depth=args.depth, omega=args.omega,
+    opts = dict(schedule=args.schedule, depth=args.variant_depth, omega=args.omega,
                 wg_per_cu=args.wg_per_cu, precision=precision)
     opts.update(kw)
     s = BiotSolver(pb, **opts)
@@ -245,7 +245,7 @@ def run_adjoint(BiotSolver, args, reps=2):
                        "log K_e and lambda_e, mu_e",
            "rtol": args.rtol}
     for stride in (16, 0):
-        s = BiotSolver(pb, schedule=args.schedule, depth=args.depth, omega=args.omega,
+        s = BiotSolver(pb, schedule=args.schedule, depth=args.variant_depth, omega=args.omega,
                        wg_per_cu=args.wg_per_cu, adjoint=True, ckpt_stride=stride,
                        replay_segments=4, max_sensors=64)
 
@@ -366,7 +366,7 @@ def run_cube(args):
     res["oracle_golden"] = golden is not None
     for prec in ("fp64", "mixed"):
         t0 = time.perf_counter()
-        s = BiotSolver(pb, schedule="wavefront", depth=args.depth, omega=args.omega,
+        s = BiotSolver(pb, schedule="wavefront", depth=args.variant_depth, omega=args.omega,
                        precision=prec)
         setup = time.perf_counter() - t0
         s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
@@ -427,7 +427,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--schedule", default="wavefront", choices=["wavefront", "jacobi"])
-    ap.add_argument("--depth", type=int, default=64)
+    ap.add_argument("--depth", type=int, default=0,
+                    help="wavefront depth; 0: the fastest of --depths, timed by the autotuner")
+    ap.add_argument("--depths", default="56,58,60,62,64",
+                    help="candidate depths when --depth is 0")
     ap.add_argument("--omega", type=float, default=0.6)
     ap.add_argument("--wg-per-cu", type=int, default=0,
                     help="workgroups per CU of the node-blocked kernels (0: occupancy)")
@@ -480,13 +483,32 @@ def main():
     if args.pmc_run:
         # the wavefront's full-wave launch shape (64 columns) in few dispatches:
         # one Jacobi sweep in batches of 64 time-step columns
+        cols = args.depth if args.depth > 0 else 64
         s = BiotSolver(pb, schedule="jacobi", omega=args.omega, wg_per_cu=args.wg_per_cu,
-                       max_batch=args.depth)
+                       max_batch=cols)
         s.sweep(1)
         torch.cuda.synchronize()
         s.close()
-        log(f"bench: counter run done (1 Jacobi sweep in batches of {args.depth} columns)")
+        log(f"bench: counter run done (1 Jacobi sweep in batches of {cols} columns)")
         return
+    depth_choice = None
+    # the other legs (variants, adjoint, cube) keep depth 64 unless one is given
+    args.variant_depth = args.depth if args.depth > 0 else 64
+    if args.schedule == "wavefront" and args.depth <= 0:
+        # a pass gives every step `depth` sweeps: the fastest depth is about the
+        # smallest at which one pass reaches the tolerance (a shallower one
+        # needs further, partial passes); timed, not assumed
+        from paper_2310_10430_amd import autotune
+        t0 = time.perf_counter()
+        ch = autotune.tune_batch([pb], precision="fp64", rtol=args.rtol,
+                                 depths=tuple(int(x) for x in args.depths.split(",")),
+                                 wpcs=(args.wg_per_cu,), omega=args.omega)
+        args.depth = ch["depth"]
+        depth_choice = {"tuned_over": args.depths, "tuning_s": time.perf_counter() - t0,
+                        "trials": ch.get("trials"), "cached": ch["cached"]}
+        log(f"bench: depth {args.depth} (tuned over {args.depths}, {depth_choice['tuning_s']:.1f} s)")
+    elif args.depth <= 0:
+        args.depth = 64
     log(f"bench: workload 256x256, {pb.n_steps} steps, {pb.n_dof} unknowns; "
         f"schedule={args.schedule} depth={args.depth} omega={args.omega} rtol={args.rtol}")
     t0 = time.perf_counter()
@@ -626,7 +648,7 @@ def main():
             "omega": args.omega, "precond": "P1 with one multigrid V-cycle per inner solve",
             "rtol": args.rtol, "sweeps": stats[-1]["sweeps"],
             "rel_resid": max(stats[-1]["rel_resid_u"], stats[-1]["rel_resid_p"]),
-            "setup_s": setup_s, "wg_per_cu": args.wg_per_cu,
+            "setup_s": setup_s, "wg_per_cu": args.wg_per_cu, "depth_choice": depth_choice,
         },
         "accuracy": acc,
         "roofline": {

@@ -4,10 +4,14 @@ All samples go into one batch handle (biot_create_batch with a mesh per
 sample): every launch covers the samples that take part in it, and each
 sample skips the steps past its own count.  For that handle the tuner picks
 
-  * the wavefront depth: the columns of one launch (more columns amortize a
-    launch's operator reads over more columns and fill the chip better; fewer
-    make a pass, N + depth - 1 waves, shorter and the convergence checks
-    between passes more frequent), and
+  * the wavefront depth: the columns of one launch and the sweeps one pass
+    gives every step (more columns amortize a launch's operator reads over
+    more columns and fill the chip better; fewer make a pass, N + depth - 1
+    waves, shorter and the convergence checks between passes more frequent; a
+    single problem is fastest at about the smallest depth at which one pass
+    reaches the tolerance: 256^2 consolidation column, 383 ms at depth 60
+    against 403 ms at 64 and 506 ms at 58, which needs a partial second
+    pass), and
   * the workgroups per compute unit of the node-blocked kernels' grids
     (0 = each kernel's occupancy, capped at 3 per CU),
 
@@ -52,14 +56,16 @@ def library_hash() -> str:
 
 
 def batch_key(problems, precision: str, rtol: float, device_name: str,
-              lib_hash: str | None = None) -> str:
-    """Cache key: the workload, the library build and the device."""
+              lib_hash: str | None = None, omega: float = 0.6) -> str:
+    """Cache key: the workload (with the damping when it is not the default
+    0.6), the library build and the device."""
     sig = hashlib.sha256()
     for pb in problems:
         sig.update(f"{pb.dim}:{pb.grid_n}:{pb.n_steps}:{pb.dt!r};".encode())
     sizes = sorted({pb.grid_n for pb in problems})
+    w = "" if omega == 0.6 else f"-w{omega:g}"
     return (f"{problems[0].dim}d-S{len(problems)}-n{sizes[0]}_{sizes[-1]}-{sig.hexdigest()[:12]}"
-            f"-{precision}-rtol{rtol:g}-lib{lib_hash or library_hash()}-{device_name}")
+            f"-{precision}{w}-rtol{rtol:g}-lib{lib_hash or library_hash()}-{device_name}")
 
 
 def _load_cache():
@@ -83,10 +89,10 @@ def _store_cache(cache):
 
 
 def time_solve(problems, depth: int, wpc: int, precision: str, rtol: float,
-               max_sweeps: int = 2000, device="cuda:0") -> float:
+               max_sweeps: int = 2000, device="cuda:0", omega: float = 0.6) -> float:
     """Seconds of one solve to rtol of all samples in one handle."""
     s = BiotSolver(problems if len(problems) > 1 else problems[0], schedule="wavefront",
-                   depth=depth, wg_per_cu=wpc, precision=precision, device=device)
+                   depth=depth, wg_per_cu=wpc, precision=precision, device=device, omega=omega)
     try:
         s.sweep(depth)                      # captures the graphs
         torch.cuda.synchronize()
@@ -101,12 +107,12 @@ def time_solve(problems, depth: int, wpc: int, precision: str, rtol: float,
 
 def tune_batch(problems, precision: str = "mixed", rtol: float = 2e-9,
                depths=(64, 72, 80, 88, 96), wpcs=(0, 4), use_cache: bool = True, device="cuda:0",
-               device_name: str | None = None) -> dict:
+               device_name: str | None = None, omega: float = 0.6) -> dict:
     """Best (depth, wg_per_cu) for one handle over all samples; returns the
     choice, every candidate's solve time and whether it came from the cache."""
     if device_name is None:
         device_name = torch.cuda.get_device_name(device).replace(" ", "_")
-    key = batch_key(problems, precision, rtol, device_name)
+    key = batch_key(problems, precision, rtol, device_name, omega=omega)
     cache = _load_cache() if use_cache else {}
     if key in cache:
         out = dict(cache[key])
@@ -116,7 +122,7 @@ def tune_batch(problems, precision: str = "mixed", rtol: float = 2e-9,
     trials = []
     for depth in depths:
         for wpc in wpcs:
-            t = time_solve(problems, depth, wpc, precision, rtol, device=device)
+            t = time_solve(problems, depth, wpc, precision, rtol, device=device, omega=omega)
             trials.append({"depth": depth, "wg_per_cu": wpc, "solve_s": t})
     best = min(trials, key=lambda r: r["solve_s"])
     out = {"key": key, "depth": best["depth"], "wg_per_cu": best["wg_per_cu"],
