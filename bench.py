@@ -49,6 +49,9 @@ TRAFFIC = {
                "launch_columns": 64, "algorithmic_bytes_per_launch": 104.8e6},
 }
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"
+# candidate wavefront depths of the variants' Richardson solves (the headline's
+# come from --depths)
+VARIANT_DEPTHS = (40, 48, 56, 60, 64, 72, 80, 96)
 
 
 def log(msg):
@@ -188,6 +191,17 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2, **kw):
     opts = dict(schedule=args.schedule, depth=args.variant_depth, omega=args.omega,
                 wg_per_cu=args.wg_per_cu, precision=precision)
     opts.update(kw)
+    tuned = None
+    if args.depth_auto and args.schedule == "wavefront" and "depth" not in kw:
+        # Richardson units: the depth tuned like the headline's, over depths
+        # that cover these variants' sweep counts (about 40-96)
+        from paper_2310_10430_amd import autotune
+        extra = {k: v for k, v in kw.items() if k != "omega"}
+        ch = autotune.tune_batch([pb], precision=precision, rtol=args.rtol,
+                                 depths=VARIANT_DEPTHS, wpcs=(args.wg_per_cu,),
+                                 omega=opts["omega"], solver_kw=extra)
+        opts["depth"] = ch["depth"]
+        tuned = {"over": list(VARIANT_DEPTHS), "trials": ch.get("trials")}
     s = BiotSolver(pb, **opts)
     s.reset()
     s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
@@ -206,7 +220,7 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2, **kw):
         acc["final_step_vs_steady_state"] = steady_state_error(X, pb)
     return {"value": pb.n_dof * pb.n_steps / per, "unit": "dof-timestep updates/s",
             "ms_per_solve": 1e3 * per, "precision": precision, "options": kw, "dt": pb.dt,
-            "sweeps": st["sweeps"],
+            "depth": opts["depth"], "depth_tuned": tuned, "sweeps": st["sweeps"],
             "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"]),
             "max_rel_err_vs_oracle_samples": max(acc.values()), "accuracy": acc}
 
@@ -492,8 +506,10 @@ def main():
         log(f"bench: counter run done (1 Jacobi sweep in batches of {cols} columns)")
         return
     depth_choice = None
-    # the other legs (variants, adjoint, cube) keep depth 64 unless one is given
+    # the adjoint and cube legs keep depth 64 unless one is given; the variants'
+    # Richardson solves tune theirs
     args.variant_depth = args.depth if args.depth > 0 else 64
+    args.depth_auto = args.depth <= 0
     if args.schedule == "wavefront" and args.depth <= 0:
         # a pass gives every step `depth` sweeps: the fastest depth is about the
         # smallest at which one pass reaches the tolerance (a shallower one

@@ -34,6 +34,7 @@ import os
 import time
 from concurrent.futures import ThreadPoolExecutor
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -56,14 +57,19 @@ def library_hash() -> str:
 
 
 def batch_key(problems, precision: str, rtol: float, device_name: str,
-              lib_hash: str | None = None, omega: float = 0.6) -> str:
-    """Cache key: the workload (with the damping when it is not the default
-    0.6), the library build and the device."""
+              lib_hash: str | None = None, omega: float = 0.6, solver_kw=None) -> str:
+    """Cache key: the workload (sizes, steps, time step and material fields;
+    the damping when it is not the default 0.6 and any further solver
+    options), the library build and the device."""
     sig = hashlib.sha256()
     for pb in problems:
-        sig.update(f"{pb.dim}:{pb.grid_n}:{pb.n_steps}:{pb.dt!r};".encode())
+        sig.update(f"{pb.dim}:{pb.grid_n}:{pb.n_steps}:{pb.dt!r}:{pb.alpha!r};".encode())
+        for a in (pb.young, pb.poisson, pb.perm):
+            sig.update(np.ascontiguousarray(a, dtype=np.float64).tobytes())
     sizes = sorted({pb.grid_n for pb in problems})
     w = "" if omega == 0.6 else f"-w{omega:g}"
+    if solver_kw:
+        w += "-" + ",".join(f"{k}={solver_kw[k]}" for k in sorted(solver_kw))
     return (f"{problems[0].dim}d-S{len(problems)}-n{sizes[0]}_{sizes[-1]}-{sig.hexdigest()[:12]}"
             f"-{precision}{w}-rtol{rtol:g}-lib{lib_hash or library_hash()}-{device_name}")
 
@@ -89,10 +95,13 @@ def _store_cache(cache):
 
 
 def time_solve(problems, depth: int, wpc: int, precision: str, rtol: float,
-               max_sweeps: int = 2000, device="cuda:0", omega: float = 0.6) -> float:
-    """Seconds of one solve to rtol of all samples in one handle."""
+               max_sweeps: int = 2000, device="cuda:0", omega: float = 0.6,
+               solver_kw=None) -> float:
+    """Seconds of one solve to rtol of all samples in one handle (`solver_kw`:
+    further BiotSolver options, e.g. the preconditioner)."""
     s = BiotSolver(problems if len(problems) > 1 else problems[0], schedule="wavefront",
-                   depth=depth, wg_per_cu=wpc, precision=precision, device=device, omega=omega)
+                   depth=depth, wg_per_cu=wpc, precision=precision, device=device, omega=omega,
+                   **(solver_kw or {}))
     try:
         s.sweep(depth)                      # captures the graphs
         torch.cuda.synchronize()
@@ -107,12 +116,12 @@ def time_solve(problems, depth: int, wpc: int, precision: str, rtol: float,
 
 def tune_batch(problems, precision: str = "mixed", rtol: float = 2e-9,
                depths=(64, 72, 80, 88, 96), wpcs=(0, 4), use_cache: bool = True, device="cuda:0",
-               device_name: str | None = None, omega: float = 0.6) -> dict:
+               device_name: str | None = None, omega: float = 0.6, solver_kw=None) -> dict:
     """Best (depth, wg_per_cu) for one handle over all samples; returns the
     choice, every candidate's solve time and whether it came from the cache."""
     if device_name is None:
         device_name = torch.cuda.get_device_name(device).replace(" ", "_")
-    key = batch_key(problems, precision, rtol, device_name, omega=omega)
+    key = batch_key(problems, precision, rtol, device_name, omega=omega, solver_kw=solver_kw)
     cache = _load_cache() if use_cache else {}
     if key in cache:
         out = dict(cache[key])
@@ -122,7 +131,8 @@ def tune_batch(problems, precision: str = "mixed", rtol: float = 2e-9,
     trials = []
     for depth in depths:
         for wpc in wpcs:
-            t = time_solve(problems, depth, wpc, precision, rtol, device=device, omega=omega)
+            t = time_solve(problems, depth, wpc, precision, rtol, device=device, omega=omega,
+                           solver_kw=solver_kw)
             trials.append({"depth": depth, "wg_per_cu": wpc, "solve_s": t})
     best = min(trials, key=lambda r: r["solve_s"])
     out = {"key": key, "depth": best["depth"], "wg_per_cu": best["wg_per_cu"],
