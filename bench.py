@@ -51,7 +51,9 @@ TRAFFIC = {
 METRIC = "dof-timestep updates/s to 1e-8 rel err; HBM GB/s fraction; adjoint grad s"
 # candidate wavefront depths of the variants' Richardson solves (the headline's
 # come from --depths)
-VARIANT_DEPTHS = (40, 48, 56, 60, 64, 72, 80, 96)
+VARIANT_DEPTHS = (32, 40, 48, 56, 60, 64, 72, 80, 96)
+ADJOINT_DEPTHS = (64, 72, 80, 88)
+CUBE_DEPTHS = (56, 60, 64, 72)
 
 
 def log(msg):
@@ -194,7 +196,7 @@ def run_variant(BiotSolver, pb, golden_name, precision, args, reps=2, **kw):
     tuned = None
     if args.depth_auto and args.schedule == "wavefront" and "depth" not in kw:
         # Richardson units: the depth tuned like the headline's, over depths
-        # that cover these variants' sweep counts (about 40-96)
+        # that cover these variants' sweep counts (about 32-96)
         from paper_2310_10430_amd import autotune
         extra = {k: v for k, v in kw.items() if k != "omega"}
         ch = autotune.tune_batch([pb], precision=precision, rtol=args.rtol,
@@ -258,17 +260,40 @@ def run_adjoint(BiotSolver, args, reps=2):
                        "observations from reference field seed 41; gradient w.r.t. 32768 "
                        "log K_e and lambda_e, mu_e",
            "rtol": args.rtol}
+
+    def make(depth, stride):
+        return BiotSolver(pb, schedule=args.schedule, depth=depth, omega=args.omega,
+                          wg_per_cu=args.wg_per_cu, adjoint=True, ckpt_stride=stride,
+                          replay_segments=4, max_sensors=64)
+
+    def grad_of(s):
+        s.reset()
+        st = s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
+        out = s.adjoint(sensors, p_obs, rtol=args.rtol, max_sweeps=args.max_sweeps)
+        return st, out
+
+    depth = args.variant_depth
+    if args.depth_auto and args.schedule == "wavefront":
+        # one depth for the forward and the adjoint solve (80 and 76 sweeps at
+        # depth 64): the fastest gradient with checkpoints, timed
+        trials = []
+        for d in ADJOINT_DEPTHS:
+            s = make(d, 16)
+            grad_of(s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            grad_of(s)
+            torch.cuda.synchronize()
+            trials.append({"depth": d, "seconds": time.perf_counter() - t0})
+            s.close()
+        depth = min(trials, key=lambda r: r["seconds"])["depth"]
+        res["depth_tuned"] = {"over": list(ADJOINT_DEPTHS), "trials": trials}
+    res["depth"] = depth
     for stride in (16, 0):
-        s = BiotSolver(pb, schedule=args.schedule, depth=args.variant_depth, omega=args.omega,
-                       wg_per_cu=args.wg_per_cu, adjoint=True, ckpt_stride=stride,
-                       replay_segments=4, max_sensors=64)
+        s = make(depth, stride)
 
         def grad():
-            s.reset()
-            st = s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps,
-                                check_every=args.check_every)
-            out = s.adjoint(sensors, p_obs, rtol=args.rtol, max_sweeps=args.max_sweeps)
-            return st, out
+            return grad_of(s)
         grad()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -379,8 +404,14 @@ def run_cube(args):
     golden = np.load(gpath) if os.path.exists(gpath) else None
     res["oracle_golden"] = golden is not None
     for prec in ("fp64", "mixed"):
+        depth, tuned = args.variant_depth, None
+        if args.depth_auto:
+            from paper_2310_10430_amd import autotune
+            ch = autotune.tune_batch([pb], precision=prec, rtol=args.rtol, depths=CUBE_DEPTHS,
+                                     wpcs=(args.wg_per_cu,), omega=args.omega)
+            depth, tuned = ch["depth"], {"over": list(CUBE_DEPTHS), "trials": ch.get("trials")}
         t0 = time.perf_counter()
-        s = BiotSolver(pb, schedule="wavefront", depth=args.variant_depth, omega=args.omega,
+        s = BiotSolver(pb, schedule="wavefront", depth=depth, omega=args.omega,
                        precision=prec)
         setup = time.perf_counter() - t0
         s.solve_to_tol(args.rtol, max_sweeps=args.max_sweeps, check_every=args.check_every)
@@ -393,7 +424,8 @@ def run_cube(args):
         X = s.trajectory()
         s.close()
         res[prec] = {"seconds": per, "value": pb.n_dof * pb.n_steps / per, "setup_s": setup,
-                     "sweeps": st["sweeps"], "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"])}
+                     "depth": depth, "depth_tuned": tuned, "sweeps": st["sweeps"],
+                     "rel_resid": max(st["rel_resid_u"], st["rel_resid_p"])}
         Xn = X.cpu().numpy()
         acc = {"final_step_vs_steady_state": steady_state_error(Xn, pb)}
         if golden is not None:
@@ -506,8 +538,8 @@ def main():
         log(f"bench: counter run done (1 Jacobi sweep in batches of {cols} columns)")
         return
     depth_choice = None
-    # the adjoint and cube legs keep depth 64 unless one is given; the variants'
-    # Richardson solves tune theirs
+    # with --depth 0 the variants' Richardson solves, the adjoint and the cube
+    # tune their depths too; a given depth applies to every leg
     args.variant_depth = args.depth if args.depth > 0 else 64
     args.depth_auto = args.depth <= 0
     if args.schedule == "wavefront" and args.depth <= 0:
