@@ -10,6 +10,8 @@ backward Euler (<= 1e-8 per field), through the C ABI:
 * a zero load: the zero trajectory is the exact solution and is reached at
   once, with a finite residual;
 * a one-sample batch through the batch entry point equals the single handle;
+* eight copies of one sample in a batch, whose tail launches take 256-thread
+  workgroups, equal the single handle (1024-thread tails) bit for bit;
 * smoother degree 3, where the stored increment d is used between steps;
 * the fused two-step post-smoothing against the two separate steps
   (options.fuse_post = 0), bit for bit, for a single sample and for a batch;
@@ -99,6 +101,26 @@ def test_one_sample_batch_equals_single_handle():
     a.close()
     b.close()
     assert np.array_equal(Xa, Xb)
+
+
+def test_batch_tail_with_small_workgroups_equals_single_handle():
+    """Eight copies of one sample with 32 columns per full wave launch 256 tail
+    workgroups, enough for the tail's 256-thread instantiation; the sample
+    alone (32 per launch) takes the 1024-thread one.  Same arithmetic (and the
+    same smoother bounds: a batch takes the largest of its samples'): every
+    copy equals the single handle bit for bit.  (Samples that differ share
+    the batch's bounds and so differ from their single handles.)"""
+    pb = W.heterogeneous_problem(16, 40, field_seed=50, young_seed=60)
+    b = BiotSolver([pb] * 8, schedule="wavefront", depth=32)
+    b.sweep(32)
+    Xb = [b.sample_trajectory(i).cpu().numpy() for i in range(8)]
+    b.close()
+    a = BiotSolver(pb, schedule="wavefront", depth=32)
+    a.sweep(32)
+    Xa = a.trajectory().cpu().numpy()
+    a.close()
+    for i in range(8):
+        assert np.array_equal(Xa, Xb[i]), i
 
 
 @pytest.mark.parametrize("schedule", ["jacobi", "wavefront"])
